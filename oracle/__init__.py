@@ -1,0 +1,28 @@
+"""FP64 CPU oracle for the one-shot generalized winding number.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product library may import, call or
+link this package; only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` use it.  It shares no code, headers,
+tables or constants with the HIP path; the only common module is ``synth``
+(seeded input generators, no method arithmetic).
+
+Contents
+--------
+- ``wn3d``   : 3D meshes.  Boundary half-edges (Sec. 4 "Multiple Boundaries";
+               Sec. 5 preprocessing), brute-force signed crossing count
+               (Eq. chi; Alg. 1 lines 6-7), boundary line integral relative to
+               one fixed ray direction (Eq. wn_discrete_sum with Lemma 2, see
+               the module docstring), degeneracy margins.
+- ``wn2d``   : 2D cubic Bezier loops (Sec. 3 definition of w_C, Sec. 6 "2D
+               parametric geometry"): crossings of the +d ray with every cubic,
+               plus the open-loop endpoint angles.
+- ``grad3d`` : closed-form derivatives of the boundary integral with respect to
+               the query point and the boundary vertices (the crossing count is
+               piecewise constant, so it contributes nothing).
+- ``pool``   : a multiprocessing map used to time the oracle on host cores.
+
+Every floating-point computation is float64 on inputs promoted exactly from
+the kernel's float32 arrays.  Parity status of each function is stated in its
+module header ("pinned by ..." or "parity unpinned").
+"""
+from . import wn3d, wn2d, grad3d  # noqa: F401
