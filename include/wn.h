@@ -1,0 +1,222 @@
+/*
+ * wn.h -- C ABI of the one-shot generalized winding number library (libwn.so)
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Sec. 3, Alg. 1 of Martens & Bessmeltsev, "One-Shot Method for
+ * Computing Generalized Winding Numbers"): given an oriented surface M with
+ * boundary dM and query points p, return the generalized winding number
+ * w_M(p) = (1/4pi) int_M dOmega(p) (2D: (1/2pi) int_C dtheta(p)).
+ *
+ * Method as implemented here.  One fixed unit direction d is shared by every
+ * query.  Eq. wn_chi and Lemmas 1-2 give
+ *
+ *     w(p) = chi_d(p) + (1/2pi) * sum over boundary edges of theta_e(p)
+ *
+ * where chi_d(p) is the signed number of crossings of the ray p + t d,
+ * t > 0, with M (Eq. chi: +1 when the ray runs along the face normal
+ * (v1-v0)x(v2-v0)), and theta_e is half the signed solid angle of the
+ * spherical triangle (-d, a-p, b-p) for boundary edge a->b, i.e. the region
+ * areas of Eq. wn_discrete_sum written as a boundary line integral with d's
+ * region as the BFS seed of Alg. 1.  2D: chi_d plus the open-curve end-point
+ * angles measured from d.
+ *
+ * Conventions for every call
+ *  - "device" pointers are HIP device memory owned by the caller; "host"
+ *    pointers are ordinary CPU memory read before the call returns.
+ *  - Every call enqueues work on `stream` (a hipStream_t passed as void*,
+ *    NULL = the null stream) and returns without synchronising; the caller
+ *    keeps every buffer alive until the stream reaches that point.
+ *  - Inputs are never modified.  Outputs are fully overwritten (never
+ *    accumulated) and must not alias inputs.  Arrays are tightly packed,
+ *    little-endian, 4-byte aligned (16-byte preferred).
+ *  - Errors are returned, never thrown.  Arguments are validated on the host
+ *    before anything is enqueued; on error nothing is enqueued and handles
+ *    are unchanged.  wn_last_error() gives a per-thread message.
+ *  - A query exactly on M or its boundary has no defined w (Sec. 3); the
+ *    result there is unspecified but finite unless the query itself is
+ *    non-finite, in which case w = NaN and chi = WN_CHI_INVALID.
+ *  - A zero-size batch (nq == 0) is a no-op returning WN_OK.
+ */
+#ifndef WN_H
+#define WN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t wn_status;
+#define WN_OK                    0
+#define WN_ERR_INVALID_ARGUMENT  1
+#define WN_ERR_UNSUPPORTED       2
+#define WN_ERR_OUT_OF_MEMORY     3
+#define WN_ERR_HIP               4
+#define WN_ERR_INTERNAL          5
+
+typedef int32_t wn_dtype;
+#define WN_F32 0
+#define WN_F64 1
+
+/* chi value written for a query whose input is not finite */
+#define WN_CHI_INVALID ((int32_t)0x80000000)
+
+/* Most boundary loops one wn_eval_3d / wn_backward / wn_eval_2d call takes
+ * (the loop table travels in the kernel arguments). */
+#define WN_MAX_LOOPS 256
+
+typedef struct wn_bvh wn_bvh;       /* opaque: frame, rotated vertices, BVH */
+typedef struct wn_batch wn_batch;   /* opaque: many surfaces, one launch   */
+
+/* Library version (major*10000 + minor*100 + patch). */
+int32_t wn_version(void);
+
+/* Human-readable name of a status code (static string). */
+const char* wn_status_string(wn_status s);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* wn_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * wn_boundary_loops -- boundary of an oriented triangle mesh (host, topology).
+ *
+ * Sec. 4 "Multiple Boundaries" / Sec. 5 preprocessing: the boundary consists
+ * of the edges used by exactly one face.  Each boundary half-edge keeps the
+ * orientation it has in its face; half-edges are chained head to tail into
+ * closed loops.
+ *
+ *  F         host [nf][3] int32 vertex indices, each in [0, nv).
+ *  bnd_idx   host [cap] int32 out: boundary vertex ids, loop after loop; loop
+ *            l occupies [loop_off[l], loop_off[l+1]) and has edges
+ *            v_i -> v_{i+1} plus the closing edge last -> first.
+ *  loop_off  host [cap + 1] int64 out.
+ *  cap       capacity of bnd_idx (3*nf always suffices).
+ *  nb_out, nloops_out  host out: number of boundary vertices and loops.
+ * Loops are ordered by their smallest vertex id and start there.
+ * Errors: INVALID_ARGUMENT for out-of-range indices, a non-manifold boundary
+ * (a vertex with two outgoing boundary edges) or cap too small.
+ * ------------------------------------------------------------------------- */
+wn_status wn_boundary_loops(const int32_t* F, int64_t nf, int64_t nv,
+                            int32_t* bnd_idx, int64_t* loop_off, int64_t cap,
+                            int64_t* nb_out, int32_t* nloops_out);
+
+/* ---------------------------------------------------------------------------
+ * wn_build_bvh -- prepare a triangle mesh for chi_d (Eq. chi; Alg. 1 line 6).
+ *
+ * Builds, on the GPU, the rotated frame of d (rows e1, e2, d; det +1; scaled
+ * by a power of two so that coordinates are O(1)), the float64 rotated
+ * vertices and a binary LBVH over the triangles' projections along d (every
+ * ray of one call is parallel to d, so a node is a 2D box plus the largest
+ * coordinate along d).  The handle owns its device memory and does not keep
+ * V or F.
+ *
+ *  V    device [nv][3] float32; F device [nf][3] int32 (indices must lie in
+ *       [0, nv): they are not checked on the device).
+ *  dir  host [3] float64, finite and nonzero (normalised here in float64).
+ *  out  receives the handle on success.
+ * The build is enqueued on `stream`; the handle may be used on that stream
+ * at once and on other streams after synchronising with it.
+ * Errors: INVALID_ARGUMENT (null pointers with nonzero counts, bad dir,
+ * nv or nf above 2^31-2), OUT_OF_MEMORY, HIP.
+ * ------------------------------------------------------------------------- */
+wn_status wn_build_bvh(const float* V, int64_t nv, const int32_t* F, int64_t nf,
+                       const double dir[3], void* stream, wn_bvh** out);
+
+/* Release a handle (waits for nothing; the caller synchronises first). */
+wn_status wn_free_bvh(wn_bvh* bvh);
+
+/* The unit direction (float64, host [3]) a handle was built for. */
+wn_status wn_bvh_direction(const wn_bvh* bvh, double dir[3]);
+
+/* ---------------------------------------------------------------------------
+ * wn_eval_3d -- w_M(p) for triangle meshes (Alg. 1 with one shared ray
+ * direction; Eq. wn_discrete_sum as a boundary line integral).
+ *
+ *  bvh        from wn_build_bvh for this mesh.
+ *  bnd_xyz    device [nb][3] float32 boundary vertices in loop order; they
+ *             must be bit-identical copies of the mesh vertices (e.g.
+ *             V[bnd_idx] from wn_boundary_loops), so that the crossing count
+ *             and the boundary term flip together where the ray meets dM.
+ *  loop_off   host [nloops + 1] int64, nondecreasing, loop_off[0] = 0,
+ *             every loop with >= 3 vertices; nb = loop_off[nloops].
+ *             nloops = 0 (closed mesh) is allowed.  nloops <= WN_MAX_LOOPS.
+ *  qx, qy, qz device [nq] float32 query coordinates (structure of arrays).
+ *  w_out      device [nq] float32 out.
+ *  chi_out    device [nq] int32 out (chi_d), or NULL.
+ * Errors: INVALID_ARGUMENT, UNSUPPORTED (too many loops), HIP.
+ * ------------------------------------------------------------------------- */
+wn_status wn_eval_3d(const wn_bvh* bvh, const float* bnd_xyz,
+                     const int64_t* loop_off, int32_t nloops,
+                     const float* qx, const float* qy, const float* qz, int64_t nq,
+                     float* w_out, int32_t* chi_out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * wn_eval_3d_boundary -- boundary term only: w_out = chi_in + S/(2pi), in the
+ * frame of `bvh`.  Same arguments as wn_eval_3d except that chi_d comes from
+ * the caller (device [nq] int32).  A WN_CHI_INVALID entry gives w = NaN.
+ * ------------------------------------------------------------------------- */
+wn_status wn_eval_3d_boundary(const wn_bvh* bvh, const float* bnd_xyz,
+                              const int64_t* loop_off, int32_t nloops,
+                              const float* qx, const float* qy, const float* qz,
+                              int64_t nq, const int32_t* chi_in, float* w_out,
+                              void* stream);
+
+/* ---------------------------------------------------------------------------
+ * wn_crossings_3d -- chi_d only (Eq. chi; Alg. 1 lines 6-7) through the BVH.
+ *  chi_out device [nq] int32 out.
+ * ------------------------------------------------------------------------- */
+wn_status wn_crossings_3d(const wn_bvh* bvh, const float* qx, const float* qy,
+                          const float* qz, int64_t nq, int32_t* chi_out,
+                          void* stream);
+
+/* ---------------------------------------------------------------------------
+ * wn_backward -- adjoint of w with respect to the query points and the
+ * boundary vertices for a loss L with dL/dw = grad_w.  chi_d is piecewise
+ * constant, so only the boundary integral contributes; its derivatives are
+ * the Biot-Savart field of dM and its hat-weighted edge integrals, which do
+ * not depend on d.
+ *
+ *  bnd_xyz, loop_off, nloops as in wn_eval_3d (nloops = 0: all outputs 0).
+ *  grad_w     device [nq] float32 (dL/dw per query).
+ *  grad_q     device [nq][3] float32 out: dL/dp, or NULL.
+ *  grad_bnd   device [nb][3] float32 out: dL/d(bnd_xyz), or NULL.  Reduced
+ *             over queries in a fixed order (float64 partial sums), so the
+ *             result is bitwise reproducible.
+ * Errors: INVALID_ARGUMENT, UNSUPPORTED, OUT_OF_MEMORY (workspace), HIP.
+ * ------------------------------------------------------------------------- */
+wn_status wn_backward(const float* bnd_xyz, const int64_t* loop_off, int32_t nloops,
+                      const float* qx, const float* qy, const float* qz, int64_t nq,
+                      const float* grad_w, float* grad_q, float* grad_bnd,
+                      void* stream);
+
+/* ---------------------------------------------------------------------------
+ * wn_eval_2d -- w_C(p) for loops of cubic Bezier curves (Sec. 3 2D
+ * definition; Sec. 6 2D parametric geometry).  The ray direction is +x.
+ *
+ *  dtype      WN_F32 or WN_F64: type of ctrl, the query coordinates and w.
+ *  ctrl       device [nseg][4][2] control points; the segments of a loop are
+ *             C0-joined (segment i's last point equals segment i+1's first,
+ *             bit for bit).
+ *  loop_off   host [nloops + 1] int64 segment offsets; loop_closed host
+ *             [nloops] uint8 (nonzero: the loop's last point equals its
+ *             first point; zero: open, its two end points add
+ *             (phi(end-p) - phi(start-p))/(2pi), phi in [0, 2pi) measured
+ *             counter-clockwise from +x).
+ *  kind       0 = points: x[n], y[n] (n = nx, ny ignored);
+ *             1 = grid: x[nx] ascending, y[ny]; outputs row-major [ny][nx]
+ *             (one ray per row, the paper's one-shot reuse of Sec. 4).
+ *  w_out      device out, dtype, [n] or [ny][nx]; chi_out device int32 or NULL.
+ * A point on the ray's line counts as lying above it, so chi and the end
+ * point angles change together where a row passes exactly through a joint.
+ * Errors: INVALID_ARGUMENT, UNSUPPORTED, HIP.
+ * ------------------------------------------------------------------------- */
+wn_status wn_eval_2d(wn_dtype dtype, const void* ctrl, int64_t nseg,
+                     const int64_t* loop_off, const uint8_t* loop_closed, int32_t nloops,
+                     int32_t kind, const void* x, const void* y, int64_t nx, int64_t ny,
+                     void* w_out, int32_t* chi_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WN_H */

@@ -54,7 +54,13 @@ import math
 import numpy as np
 
 TWO_PI = 2.0 * math.pi
-BAND = 2.0 ** -16      # relative margin below which a query is degenerate
+# Relative margin below which a query is degenerate.  Margins are normalised
+# edge values d.(a x b)/(|a_perp||b_perp|), vertex offsets |a_perp|/|a| and
+# depths |t|/max(|a|,|b|,|c|); a float32 evaluation of the same predicates
+# relative to p (coordinates rounded once, two rounded products and one
+# difference) errs by at most about 2^-22 in these units, so a band of 2^-20
+# leaves a factor of four.
+BAND = 2.0 ** -20
 
 
 # ----------------------------------------------------------------------------
@@ -137,9 +143,12 @@ def crossings(V, F, P, d, margins: bool = False):
     relative to p share one strict sign (that sign is then sign(d . n)); it
     meets it in front of p iff t = (n . a)/(d . n) > 0.
 
-    With ``margins`` also returns, per query, the smallest normalised edge
-    value |d.(a x b)| / (|a||b|) and the smallest |t| / max(|a|,|b|,|c|) over
-    triangles that the ray hits or misses by less than BAND.
+    With ``margins`` also returns, per query, over the triangles that the ray
+    hits or misses by less than BAND: the smallest normalised edge value
+    |d.(a x b)| / (|a_perp||b_perp|) (the sine of the angle at the ray between
+    the projected vertices; a_perp is a's component perpendicular to d) or
+    vertex offset |a_perp| / |a|, whichever is smaller, and the smallest
+    |t| / max(|a|,|b|,|c|).
     """
     V = np.asarray(V, np.float64)
     F = np.asarray(F, np.int64)
@@ -168,16 +177,22 @@ def crossings(V, F, P, d, margins: bool = False):
             la = np.linalg.norm(a, axis=1)
             lb = np.linalg.norm(b, axis=1)
             lc = np.linalg.norm(c, axis=1)
+            # distances of the vertices from the ray's line (projections
+            # perpendicular to d)
+            pa = np.linalg.norm(a - np.outer(a @ d, d), axis=1)
+            pb = np.linalg.norm(b - np.outer(b @ d, d), axis=1)
+            pc = np.linalg.norm(c - np.outer(c @ d, d), axis=1)
             with np.errstate(divide="ignore", invalid="ignore"):
-                ab = e_ab / (la * lb)
-                bc = e_bc / (lb * lc)
-                ca = e_ca / (lc * la)
+                ab = e_ab / (pa * pb)
+                bc = e_bc / (pb * pc)
+                ca = e_ca / (pc * pa)
             near = (((ab > -BAND) & (bc > -BAND) & (ca > -BAND))
                     | ((ab < BAND) & (bc < BAND) & (ca < BAND)))
             near &= np.isfinite(t) & (t > -BAND * np.maximum(np.maximum(la, lb), lc))
             if np.any(near):
                 em = np.minimum(np.minimum(np.abs(ab[near]), np.abs(bc[near])), np.abs(ca[near]))
-                m_edge[i] = float(em.min())
+                vm = np.minimum(np.minimum(pa[near] / la[near], pb[near] / lb[near]), pc[near] / lc[near])
+                m_edge[i] = float(min(np.nan_to_num(em, nan=0.0).min(), vm.min()))
                 sc = np.maximum(np.maximum(la[near], lb[near]), lc[near])
                 m_t[i] = float((np.abs(t[near]) / sc).min())
     if margins:

@@ -1,0 +1,18 @@
+"""One-shot generalized winding numbers on AMD Instinct MI355X.
+
+Thin Python binding over ``libwn.so`` (C ABI in ``include/wn.h``): argument
+checks and marshalling of torch device tensors and the current HIP stream.
+All computation runs in the library's HIP kernels.
+"""
+from .api import (  # noqa: F401
+    BVH,
+    WindingNumber3D,
+    backward,
+    boundary_loops,
+    crossings_3d,
+    eval_2d,
+    eval_3d,
+    eval_3d_boundary,
+    winding_number,
+)
+from ._lib import WN_CHI_INVALID, WN_MAX_LOOPS, WnError, lib  # noqa: F401

@@ -1,0 +1,232 @@
+"""Python entry points: marshal torch tensors and the current stream into the
+C ABI of ``libwn.so``.  No arithmetic of the method happens here."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from ._lib import check, lib, WN_MAX_LOOPS
+
+__all__ = ["boundary_loops", "BVH", "eval_3d", "eval_3d_boundary", "crossings_3d",
+           "backward", "WindingNumber3D", "winding_number", "eval_2d"]
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, name: str, shape=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return C.c_void_p(t.data_ptr()) if t.numel() else C.c_void_p(0)
+
+
+def _loops(loop_off) -> tuple[np.ndarray, int]:
+    lo = np.ascontiguousarray(np.asarray(loop_off, dtype=np.int64))
+    n = max(lo.size - 1, 0)
+    if n > WN_MAX_LOOPS:
+        raise ValueError(f"at most {WN_MAX_LOOPS} loops per call")
+    return lo, n
+
+
+def _ptr64(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int64)) if a.size else None
+
+
+def boundary_loops(F) -> tuple[np.ndarray, np.ndarray]:
+    """Boundary loops of an oriented triangle mesh (host).  Returns
+    (bnd_idx int32 [nb], loop_off int64 [nloops + 1])."""
+    if isinstance(F, torch.Tensor):
+        F = F.detach().cpu().numpy()
+    F = np.ascontiguousarray(np.asarray(F, dtype=np.int32))
+    nf = F.shape[0]
+    nv = int(F.max()) + 1 if nf else 0
+    cap = 3 * nf
+    idx = np.zeros(max(cap, 1), np.int32)
+    off = np.zeros(max(cap, 1) + 1, np.int64)
+    nb = C.c_int64(0)
+    nl = C.c_int32(0)
+    st = lib().wn_boundary_loops(F.ctypes.data_as(C.c_void_p) if nf else None, nf, nv,
+                                 idx.ctypes.data_as(C.c_void_p), off.ctypes.data_as(C.c_void_p),
+                                 cap, C.byref(nb), C.byref(nl))
+    check(st, "wn_boundary_loops")
+    return idx[: nb.value].copy(), off[: nl.value + 1].copy()
+
+
+class BVH:
+    """Handle of ``wn_build_bvh``: frame of the ray direction and the BVH of
+    the mesh projections.  ``V`` float32 [nv, 3], ``F`` int32 [nf, 3] on the
+    GPU.  The build synchronises the current stream once."""
+
+    def __init__(self, V: torch.Tensor, F: torch.Tensor, direction, stream=None):
+        nv, nf = V.shape[0], F.shape[0]
+        pv = _dev(V, torch.float32, "V", (nv, 3))
+        pf = _dev(F, torch.int32, "F", (nf, 3))
+        d = (C.c_double * 3)(*[float(x) for x in np.asarray(direction, np.float64).ravel()[:3]])
+        h = C.c_void_p()
+        check(lib().wn_build_bvh(pv, nv, pf, nf, d, _stream(stream), C.byref(h)), "wn_build_bvh")
+        self._h = h
+        self.nv, self.nf = nv, nf
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("BVH already freed")
+        return self._h
+
+    @property
+    def direction(self) -> np.ndarray:
+        d = (C.c_double * 3)()
+        check(lib().wn_bvh_direction(self.handle, d), "wn_bvh_direction")
+        return np.array(d[:])
+
+    def free(self):
+        if getattr(self, "_h", None) is not None:
+            torch.cuda.synchronize()
+            lib().wn_free_bvh(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) is not None:
+                lib().wn_free_bvh(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+def _queries(qx, qy, qz):
+    nq = qx.shape[0]
+    return (_dev(qx, torch.float32, "qx", (nq,)), _dev(qy, torch.float32, "qy", (nq,)),
+            _dev(qz, torch.float32, "qz", (nq,)), nq)
+
+
+def eval_3d(bvh: BVH, bnd_xyz: torch.Tensor, loop_off, qx, qy, qz, want_chi: bool = True,
+            w_out=None, chi_out=None, stream=None):
+    """w (and chi) for queries (qx, qy, qz) against the mesh of ``bvh`` whose
+    boundary is ``bnd_xyz`` [nb, 3] with host loop offsets ``loop_off``."""
+    lo, nl = _loops(loop_off)
+    nb = int(lo[-1]) if nl else 0
+    pb = _dev(bnd_xyz, torch.float32, "bnd_xyz", (nb, 3))
+    px, py, pz, nq = _queries(qx, qy, qz)
+    w = torch.empty(nq, dtype=torch.float32, device=qx.device) if w_out is None else w_out
+    chi = None
+    if want_chi:
+        chi = torch.empty(nq, dtype=torch.int32, device=qx.device) if chi_out is None else chi_out
+    pw = _dev(w, torch.float32, "w_out", (nq,))
+    pc = _dev(chi, torch.int32, "chi_out", (nq,)) if chi is not None else None
+    check(lib().wn_eval_3d(bvh.handle, pb, _ptr64(lo), nl, px, py, pz, nq, pw, pc, _stream(stream)),
+          "wn_eval_3d")
+    return w, chi
+
+
+def eval_3d_boundary(bvh: BVH, bnd_xyz, loop_off, qx, qy, qz, chi_in, stream=None):
+    lo, nl = _loops(loop_off)
+    nb = int(lo[-1]) if nl else 0
+    pb = _dev(bnd_xyz, torch.float32, "bnd_xyz", (nb, 3))
+    px, py, pz, nq = _queries(qx, qy, qz)
+    pc = _dev(chi_in, torch.int32, "chi_in", (nq,))
+    w = torch.empty(nq, dtype=torch.float32, device=qx.device)
+    check(lib().wn_eval_3d_boundary(bvh.handle, pb, _ptr64(lo), nl, px, py, pz, nq, pc,
+                                    _dev(w, torch.float32, "w"), _stream(stream)),
+          "wn_eval_3d_boundary")
+    return w
+
+
+def crossings_3d(bvh: BVH, qx, qy, qz, stream=None):
+    px, py, pz, nq = _queries(qx, qy, qz)
+    chi = torch.empty(nq, dtype=torch.int32, device=qx.device)
+    check(lib().wn_crossings_3d(bvh.handle, px, py, pz, nq, _dev(chi, torch.int32, "chi"),
+                                _stream(stream)), "wn_crossings_3d")
+    return chi
+
+
+def backward(bnd_xyz, loop_off, qx, qy, qz, grad_w, want_q: bool = True, want_bnd: bool = True,
+             stream=None):
+    """(dL/dq [nq, 3] or None, dL/d bnd_xyz [nb, 3] or None) for dL/dw = grad_w."""
+    lo, nl = _loops(loop_off)
+    nb = int(lo[-1]) if nl else 0
+    pb = _dev(bnd_xyz, torch.float32, "bnd_xyz", (nb, 3))
+    px, py, pz, nq = _queries(qx, qy, qz)
+    pg = _dev(grad_w, torch.float32, "grad_w", (nq,))
+    dev = qx.device
+    gq = torch.empty((nq, 3), dtype=torch.float32, device=dev) if want_q else None
+    gb = torch.empty((nb, 3), dtype=torch.float32, device=dev) if want_bnd else None
+    check(lib().wn_backward(pb, _ptr64(lo), nl, px, py, pz, nq, pg,
+                            _dev(gq, torch.float32, "grad_q") if gq is not None else None,
+                            _dev(gb, torch.float32, "grad_bnd") if gb is not None else None,
+                            _stream(stream)), "wn_backward")
+    return gq, gb
+
+
+class WindingNumber3D(torch.autograd.Function):
+    """w = winding number of the mesh of ``bvh`` at the queries; gradients
+    flow to the boundary vertices ``bnd_xyz`` and to the query coordinates
+    (chi_d is piecewise constant and contributes none)."""
+
+    @staticmethod
+    def forward(ctx, bnd_xyz, qx, qy, qz, bvh, loop_off):
+        w, _ = eval_3d(bvh, bnd_xyz.detach(), loop_off, qx.detach(), qy.detach(), qz.detach(),
+                       want_chi=False)
+        ctx.save_for_backward(bnd_xyz, qx, qy, qz)
+        ctx.loop_off = loop_off
+        return w
+
+    @staticmethod
+    def backward(ctx, grad_w):
+        bnd_xyz, qx, qy, qz = ctx.saved_tensors
+        need_b = ctx.needs_input_grad[0]
+        need_q = any(ctx.needs_input_grad[1:4])
+        gq, gb = backward(bnd_xyz.detach(), ctx.loop_off, qx.detach(), qy.detach(), qz.detach(),
+                          grad_w.contiguous().float(), want_q=need_q, want_bnd=need_b)
+        gx = gy = gz = None
+        if gq is not None:
+            gx, gy, gz = gq[:, 0], gq[:, 1], gq[:, 2]
+        return gb, gx, gy, gz, None, None
+
+
+def winding_number(bvh, bnd_xyz, loop_off, qx, qy, qz):
+    return WindingNumber3D.apply(bnd_xyz, qx, qy, qz, bvh, loop_off)
+
+
+def eval_2d(ctrl: torch.Tensor, loop_off, loop_closed, x: torch.Tensor, y: torch.Tensor,
+            grid: bool = False, want_chi: bool = True, stream=None):
+    """w (and chi) of loops of cubic Beziers ``ctrl`` [nseg, 4, 2] (float32 or
+    float64) at points (x[i], y[i]) or on the grid x[nx] by y[ny] (row-major
+    [ny, nx] output).  Ray direction +x."""
+    if ctrl.dtype == torch.float64:
+        dt, code = torch.float64, 1
+    elif ctrl.dtype == torch.float32:
+        dt, code = torch.float32, 0
+    else:
+        raise TypeError("ctrl must be float32 or float64")
+    nseg = ctrl.shape[0]
+    pc = _dev(ctrl, dt, "ctrl", (nseg, 4, 2))
+    lo, nl = _loops(loop_off)
+    cl = np.ascontiguousarray(np.asarray(loop_closed, np.uint8))
+    if cl.size != nl:
+        raise ValueError("loop_closed must have one entry per loop")
+    nx = x.shape[0]
+    ny = y.shape[0]
+    px = _dev(x, dt, "x", (nx,))
+    py = _dev(y, dt, "y", (ny,))
+    if not grid and nx != ny:
+        raise ValueError("points mode needs len(x) == len(y)")
+    shape = (ny, nx) if grid else (nx,)
+    w = torch.empty(shape, dtype=dt, device=x.device)
+    chi = torch.empty(shape, dtype=torch.int32, device=x.device) if want_chi else None
+    check(lib().wn_eval_2d(code, pc, nseg, _ptr64(lo), cl.ctypes.data_as(C.c_void_p) if cl.size else None,
+                           nl, 1 if grid else 0, px, py, nx, ny if grid else nx,
+                           _dev(w, dt, "w"), _dev(chi, torch.int32, "chi") if chi is not None else None,
+                           _stream(stream)), "wn_eval_2d")
+    return w, chi

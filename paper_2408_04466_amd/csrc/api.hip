@@ -1,0 +1,490 @@
+// Host side of the C ABI declared in include/wn.h: argument validation,
+// handles, the frame of the ray direction, boundary extraction, and the
+// launch sequence of each entry point.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "bvh_build.hpp"
+#include "kernels.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+wn_status fail(wn_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+wn_status hip_fail(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+    return fail(WN_ERR_OUT_OF_MEMORY, "%s: %s", what, hipGetErrorString(e));
+  return fail(WN_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define WN_HIP(call, what)                       \
+  do {                                           \
+    hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Unit direction and orthonormal frame (rows e1, e2, d; det +1) in float64.
+bool make_rotation(const double dir[3], double d[3], double R[9]) {
+  if (!dir) return false;
+  const double n = std::sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+  if (!std::isfinite(n) || n == 0.0) return false;
+  for (int k = 0; k < 3; ++k) d[k] = dir[k] / n;
+  int m = 0;
+  for (int k = 1; k < 3; ++k)
+    if (std::fabs(d[k]) < std::fabs(d[m])) m = k;
+  double ax[3] = {0, 0, 0};
+  ax[m] = 1.0;
+  double e1[3] = {d[1] * ax[2] - d[2] * ax[1], d[2] * ax[0] - d[0] * ax[2], d[0] * ax[1] - d[1] * ax[0]};
+  const double l1 = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+  for (int k = 0; k < 3; ++k) e1[k] /= l1;
+  const double e2[3] = {d[1] * e1[2] - d[2] * e1[1], d[2] * e1[0] - d[0] * e1[2], d[0] * e1[1] - d[1] * e1[0]};
+  for (int k = 0; k < 3; ++k) {
+    R[k] = e1[k];
+    R[3 + k] = e2[k];
+    R[6 + k] = d[k];
+  }
+  return true;
+}
+
+// Validate a host loop table and copy it into the kernel-argument form.
+wn_status make_loops(const int64_t* loop_off, int32_t nloops, int32_t min_len, int64_t* nb_out,
+                     wn::LoopTable* L) {
+  if (nloops < 0) return fail(WN_ERR_INVALID_ARGUMENT, "nloops must be >= 0 (got %d)", nloops);
+  if (nloops > WN_MAX_LOOPS)
+    return fail(WN_ERR_UNSUPPORTED, "at most %d boundary loops per call (got %d)", WN_MAX_LOOPS, nloops);
+  std::memset(L, 0, sizeof *L);
+  L->n = nloops;
+  if (nloops == 0) {
+    *nb_out = 0;
+    return WN_OK;
+  }
+  if (!loop_off) return fail(WN_ERR_INVALID_ARGUMENT, "loop_off is NULL with nloops = %d", nloops);
+  if (loop_off[0] != 0) return fail(WN_ERR_INVALID_ARGUMENT, "loop_off[0] must be 0");
+  for (int32_t l = 0; l < nloops; ++l) {
+    const int64_t len = loop_off[l + 1] - loop_off[l];
+    if (len < min_len)
+      return fail(WN_ERR_INVALID_ARGUMENT, "loop %d has %lld entries (need >= %d)", l, (long long)len, min_len);
+  }
+  if (loop_off[nloops] > INT32_MAX - 1)
+    return fail(WN_ERR_UNSUPPORTED, "too many boundary vertices (%lld)", (long long)loop_off[nloops]);
+  for (int32_t l = 0; l <= nloops; ++l) L->off[l] = (int32_t)loop_off[l];
+  *nb_out = loop_off[nloops];
+  return WN_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+namespace {
+
+__global__ void k_bbox_f32(const float* __restrict__ V, int32_t nv, unsigned* __restrict__ out) {
+  __shared__ unsigned red[6][256];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int c = 0; c < 3; ++c) {
+    unsigned lo = 0xffffffffu, hi = 0u;
+    if (i < nv) {
+      const unsigned u = __float_as_uint(V[3 * i + c]);
+      const unsigned o = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+      lo = o;
+      hi = o;
+    }
+    red[2 * c][threadIdx.x] = lo;
+    red[2 * c + 1][threadIdx.x] = hi;
+  }
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int c = 0; c < 3; ++c) {
+        red[2 * c][threadIdx.x] = min(red[2 * c][threadIdx.x], red[2 * c][threadIdx.x + s]);
+        red[2 * c + 1][threadIdx.x] = max(red[2 * c + 1][threadIdx.x], red[2 * c + 1][threadIdx.x + s]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) {
+    if (threadIdx.x & 1) atomicMax(&out[threadIdx.x], red[threadIdx.x][0]);
+    else atomicMin(&out[threadIdx.x], red[threadIdx.x][0]);
+  }
+}
+
+float ord_to_float(unsigned o) {
+  const unsigned u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+template <class T>
+hipError_t dalloc(T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) return hipSuccess;
+  return hipMalloc((void**)p, n * sizeof(T));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+struct wn_bvh {
+  wn::Frame F;
+  double dir[3];
+  int32_t nv = 0, nf = 0;
+  double4* Vr = nullptr;
+  int4* tris = nullptr;
+  wn::BvhNode* nodes = nullptr;
+  float4* leafbox = nullptr;
+  float* leafz = nullptr;
+};
+
+extern "C" {
+
+int32_t wn_version(void) { return 10000; }
+
+const char* wn_status_string(wn_status s) {
+  switch (s) {
+    case WN_OK: return "WN_OK";
+    case WN_ERR_INVALID_ARGUMENT: return "WN_ERR_INVALID_ARGUMENT";
+    case WN_ERR_UNSUPPORTED: return "WN_ERR_UNSUPPORTED";
+    case WN_ERR_OUT_OF_MEMORY: return "WN_ERR_OUT_OF_MEMORY";
+    case WN_ERR_HIP: return "WN_ERR_HIP";
+    case WN_ERR_INTERNAL: return "WN_ERR_INTERNAL";
+    default: return "WN_ERR_UNKNOWN";
+  }
+}
+
+const char* wn_last_error(void) { return g_err.c_str(); }
+
+wn_status wn_boundary_loops(const int32_t* F, int64_t nf, int64_t nv, int32_t* bnd_idx,
+                            int64_t* loop_off, int64_t cap, int64_t* nb_out, int32_t* nloops_out) {
+  g_err.clear();
+  if (nf < 0 || nv < 0) return fail(WN_ERR_INVALID_ARGUMENT, "negative count");
+  if (nf > 0 && !F) return fail(WN_ERR_INVALID_ARGUMENT, "F is NULL");
+  if (!nb_out || !nloops_out) return fail(WN_ERR_INVALID_ARGUMENT, "NULL output count");
+  if (cap < 0 || (cap > 0 && (!bnd_idx || !loop_off)))
+    return fail(WN_ERR_INVALID_ARGUMENT, "bad output capacity/buffers");
+  // undirected edge key (lo, hi) -> (count, directed a->b of the first use)
+  struct HE { int64_t key; int32_t a, b; };
+  std::vector<HE> he;
+  he.reserve((size_t)(3 * nf));
+  for (int64_t f = 0; f < nf; ++f) {
+    for (int k = 0; k < 3; ++k) {
+      const int32_t a = F[3 * f + k], b = F[3 * f + (k + 1) % 3];
+      if (a < 0 || a >= nv || b < 0 || b >= nv)
+        return fail(WN_ERR_INVALID_ARGUMENT, "face %lld has an index outside [0, %lld)", (long long)f, (long long)nv);
+      const int64_t lo = std::min(a, b), hi = std::max(a, b);
+      he.push_back({lo * (nv + 1) + hi, a, b});
+    }
+  }
+  std::stable_sort(he.begin(), he.end(), [](const HE& x, const HE& y) { return x.key < y.key; });
+  std::vector<int32_t> next((size_t)nv, -1);
+  size_t i = 0;
+  int64_t nbe = 0;
+  while (i < he.size()) {
+    size_t j = i + 1;
+    while (j < he.size() && he[j].key == he[i].key) ++j;
+    if (j - i == 1) {
+      const int32_t a = he[i].a, b = he[i].b;
+      if (next[(size_t)a] != -1)
+        return fail(WN_ERR_INVALID_ARGUMENT, "vertex %d has two outgoing boundary edges", a);
+      next[(size_t)a] = b;
+      ++nbe;
+    }
+    i = j;
+  }
+  *nb_out = nbe;
+  std::vector<char> seen((size_t)nv, 0);
+  int64_t pos = 0;
+  int32_t nl = 0;
+  if (cap > 0) loop_off[0] = 0;
+  for (int64_t s = 0; s < nv; ++s) {
+    if (next[(size_t)s] < 0 || seen[(size_t)s]) continue;
+    int64_t v = s;
+    do {
+      if (seen[(size_t)v] || next[(size_t)v] < 0)
+        return fail(WN_ERR_INVALID_ARGUMENT, "boundary half-edges do not close into loops");
+      seen[(size_t)v] = 1;
+      if (pos >= cap) return fail(WN_ERR_INVALID_ARGUMENT, "capacity %lld too small", (long long)cap);
+      bnd_idx[pos++] = (int32_t)v;
+      v = next[(size_t)v];
+    } while (v != s);
+    ++nl;
+    if (nl > cap) return fail(WN_ERR_INVALID_ARGUMENT, "capacity %lld too small", (long long)cap);
+    loop_off[nl] = pos;
+  }
+  *nloops_out = nl;
+  return WN_OK;
+}
+
+wn_status wn_build_bvh(const float* V, int64_t nv, const int32_t* F, int64_t nf, const double dir[3],
+                       void* stream, wn_bvh** out) {
+  g_err.clear();
+  if (!out) return fail(WN_ERR_INVALID_ARGUMENT, "out is NULL");
+  if (nv < 0 || nf < 0) return fail(WN_ERR_INVALID_ARGUMENT, "negative count");
+  if (nv > INT32_MAX - 2 || nf > INT32_MAX - 2) return fail(WN_ERR_INVALID_ARGUMENT, "mesh too large");
+  if ((nv > 0 && !V) || (nf > 0 && !F)) return fail(WN_ERR_INVALID_ARGUMENT, "NULL mesh pointer");
+  if (nf > 0 && nv == 0) return fail(WN_ERR_INVALID_ARGUMENT, "faces without vertices");
+  double d[3], R[9];
+  if (!make_rotation(dir, d, R)) return fail(WN_ERR_INVALID_ARGUMENT, "dir must be finite and nonzero");
+  hipStream_t s = as_stream(stream);
+
+  wn_bvh* h = new wn_bvh();
+  std::memcpy(h->dir, d, sizeof d);
+  h->nv = (int32_t)nv;
+  h->nf = (int32_t)nf;
+
+  // bounding box of V -> centre and power-of-two scale of the frame
+  double c[3] = {0, 0, 0};
+  double half = 1.0;
+  if (nv > 0) {
+    unsigned* dbb = nullptr;
+    unsigned hbb[6];
+    hipError_t e = hipMalloc((void**)&dbb, 6 * sizeof(unsigned));
+    if (e != hipSuccess) { delete h; return hip_fail(e, "hipMalloc"); }
+    const unsigned init[6] = {0xffffffffu, 0u, 0xffffffffu, 0u, 0xffffffffu, 0u};
+    e = hipMemcpyAsync(dbb, init, sizeof init, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_bbox_f32, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, V, (int32_t)nv, dbb);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(hbb, dbb, sizeof hbb, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(dbb);
+    if (e != hipSuccess) { delete h; return hip_fail(e, "bounding box"); }
+    double m2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double lo = ord_to_float(hbb[2 * k]), hi = ord_to_float(hbb[2 * k + 1]);
+      if (!std::isfinite(lo) || !std::isfinite(hi)) { delete h; return fail(WN_ERR_INVALID_ARGUMENT, "non-finite vertex"); }
+      c[k] = (double)(float)(0.5 * (lo + hi));
+      const double hk = 0.5 * (hi - lo);
+      m2 += hk * hk;
+    }
+    half = std::sqrt(m2);
+    if (!(half > 0.0)) half = 1.0;
+  }
+  const double scale = std::ldexp(1.0, -std::ilogb(half) - 1);   // half*scale in [0.5, 1)
+  for (int k = 0; k < 9; ++k) h->F.r[k] = R[k] * scale;
+  for (int k = 0; k < 3; ++k) h->F.c[k] = c[k];
+
+  const int64_t nint = nf > 1 ? nf - 1 : 0;
+  wn::BuildBufs b{};
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+  chk(dalloc(&h->Vr, (size_t)nv));
+  chk(dalloc(&h->tris, (size_t)nf));
+  chk(dalloc(&h->nodes, (size_t)nint));
+  chk(dalloc(&h->leafbox, (size_t)nf));
+  chk(dalloc(&h->leafz, (size_t)nf));
+  b.Vr = h->Vr;
+  b.tris = h->tris;
+  b.nodes = h->nodes;
+  b.leafbox = h->leafbox;
+  b.leafz = h->leafz;
+  chk(dalloc(&b.box, (size_t)nf));
+  chk(dalloc(&b.zmax, (size_t)nf));
+  chk(dalloc(&b.cen, (size_t)nf));
+  chk(dalloc(&b.cbounds, 4));
+  chk(dalloc(&b.keys, (size_t)nf));
+  chk(dalloc(&b.vals, (size_t)nf));
+  chk(dalloc(&b.keys2, (size_t)nf));
+  chk(dalloc(&b.vals2, (size_t)nf));
+  chk(dalloc((char**)&b.sort_tmp, nf > 1 ? wn::radix_sort_tmp_bytes(nf) : 0));
+  chk(dalloc(&b.left, (size_t)nint));
+  chk(dalloc(&b.right, (size_t)nint));
+  chk(dalloc(&b.parent_int, (size_t)nint));
+  chk(dalloc(&b.parent_leaf, (size_t)nf));
+  chk(dalloc(&b.ibox, (size_t)nint));
+  chk(dalloc(&b.iz, (size_t)nint));
+  chk(dalloc(&b.flags, (size_t)nint));
+  // pad: scaled coordinates are O(1); 2^-19 covers float32 rounding of
+  // queries and vertices near the mesh with a wide margin
+  const float pad = std::ldexp(1.0f, -19);
+  if (e == hipSuccess) chk(wn::build_bvh_device(b, h->F, V, (int32_t)nv, F, (int32_t)nf, pad, s));
+  if (e == hipSuccess) chk(hipStreamSynchronize(s));
+  hipFree(b.box); hipFree(b.zmax); hipFree(b.cen); hipFree(b.cbounds);
+  hipFree(b.keys); hipFree(b.vals); hipFree(b.keys2); hipFree(b.vals2); hipFree(b.sort_tmp);
+  hipFree(b.left); hipFree(b.right); hipFree(b.parent_int); hipFree(b.parent_leaf);
+  hipFree(b.ibox); hipFree(b.iz); hipFree(b.flags);
+  if (e != hipSuccess) {
+    wn_free_bvh(h);
+    return hip_fail(e, "wn_build_bvh");
+  }
+  *out = h;
+  return WN_OK;
+}
+
+wn_status wn_free_bvh(wn_bvh* h) {
+  g_err.clear();
+  if (!h) return WN_OK;
+  hipFree(h->Vr);
+  hipFree(h->tris);
+  hipFree(h->nodes);
+  hipFree(h->leafbox);
+  hipFree(h->leafz);
+  delete h;
+  return WN_OK;
+}
+
+wn_status wn_bvh_direction(const wn_bvh* h, double dir[3]) {
+  g_err.clear();
+  if (!h || !dir) return fail(WN_ERR_INVALID_ARGUMENT, "NULL argument");
+  std::memcpy(dir, h->dir, sizeof h->dir);
+  return WN_OK;
+}
+
+static wn_status check_queries(const float* qx, const float* qy, const float* qz, int64_t nq) {
+  if (nq < 0) return fail(WN_ERR_INVALID_ARGUMENT, "nq must be >= 0");
+  if (nq > 0 && (!qx || !qy || !qz)) return fail(WN_ERR_INVALID_ARGUMENT, "NULL query pointer");
+  return WN_OK;
+}
+
+static wn::CrossArgs cross_args(const wn_bvh* h, const float* qx, const float* qy, const float* qz,
+                                int64_t nq, int32_t* chi) {
+  wn::CrossArgs a;
+  a.F = h->F;
+  a.nodes = h->nodes;
+  a.tris = h->tris;
+  a.Vr = h->Vr;
+  a.leafbox = h->leafbox;
+  a.leafz = h->leafz;
+  a.nf = h->nf;
+  a.qx = qx;
+  a.qy = qy;
+  a.qz = qz;
+  a.nq = nq;
+  a.chi = chi;
+  return a;
+}
+
+wn_status wn_crossings_3d(const wn_bvh* h, const float* qx, const float* qy, const float* qz,
+                          int64_t nq, int32_t* chi_out, void* stream) {
+  g_err.clear();
+  if (!h) return fail(WN_ERR_INVALID_ARGUMENT, "bvh is NULL");
+  wn_status st = check_queries(qx, qy, qz, nq);
+  if (st) return st;
+  if (nq == 0) return WN_OK;
+  if (!chi_out) return fail(WN_ERR_INVALID_ARGUMENT, "chi_out is NULL");
+  WN_HIP(wn::launch_cross3d(cross_args(h, qx, qy, qz, nq, chi_out), as_stream(stream)), "crossings");
+  return WN_OK;
+}
+
+static wn_status eval_boundary(const wn::Frame& F, const float* bnd, const wn::LoopTable& L, int64_t nb,
+                               const float* qx, const float* qy, const float* qz, int64_t nq,
+                               const int32_t* chi, float* w, hipStream_t s) {
+  wn::BndArgs a;
+  a.F = F;
+  a.bnd = bnd;
+  a.nb = (int32_t)nb;
+  a.qx = qx;
+  a.qy = qy;
+  a.qz = qz;
+  a.nq = nq;
+  a.chi_in = chi;
+  a.w_out = w;
+  WN_HIP(wn::launch_bnd3d(a, L, s), "boundary integral");
+  return WN_OK;
+}
+
+wn_status wn_eval_3d(const wn_bvh* h, const float* bnd_xyz, const int64_t* loop_off, int32_t nloops,
+                     const float* qx, const float* qy, const float* qz, int64_t nq, float* w_out,
+                     int32_t* chi_out, void* stream) {
+  g_err.clear();
+  if (!h) return fail(WN_ERR_INVALID_ARGUMENT, "bvh is NULL");
+  wn::LoopTable L;
+  int64_t nb = 0;
+  wn_status st = make_loops(loop_off, nloops, 3, &nb, &L);
+  if (st) return st;
+  if (nb > 0 && !bnd_xyz) return fail(WN_ERR_INVALID_ARGUMENT, "bnd_xyz is NULL");
+  if ((st = check_queries(qx, qy, qz, nq))) return st;
+  if (nq == 0) return WN_OK;
+  if (!w_out) return fail(WN_ERR_INVALID_ARGUMENT, "w_out is NULL");
+  hipStream_t s = as_stream(stream);
+  // chi goes to chi_out, or is parked in w_out (int bits) until the boundary
+  // kernel replaces each entry by w
+  int32_t* chi = chi_out ? chi_out : reinterpret_cast<int32_t*>(w_out);
+  WN_HIP(wn::launch_cross3d(cross_args(h, qx, qy, qz, nq, chi), s), "crossings");
+  return eval_boundary(h->F, bnd_xyz, L, nb, qx, qy, qz, nq, chi, w_out, s);
+}
+
+wn_status wn_eval_3d_boundary(const wn_bvh* h, const float* bnd_xyz, const int64_t* loop_off,
+                              int32_t nloops, const float* qx, const float* qy, const float* qz,
+                              int64_t nq, const int32_t* chi_in, float* w_out, void* stream) {
+  g_err.clear();
+  if (!h) return fail(WN_ERR_INVALID_ARGUMENT, "bvh is NULL");
+  wn::LoopTable L;
+  int64_t nb = 0;
+  wn_status st = make_loops(loop_off, nloops, 3, &nb, &L);
+  if (st) return st;
+  if (nb > 0 && !bnd_xyz) return fail(WN_ERR_INVALID_ARGUMENT, "bnd_xyz is NULL");
+  if ((st = check_queries(qx, qy, qz, nq))) return st;
+  if (nq == 0) return WN_OK;
+  if (!w_out || !chi_in) return fail(WN_ERR_INVALID_ARGUMENT, "w_out or chi_in is NULL");
+  return eval_boundary(h->F, bnd_xyz, L, nb, qx, qy, qz, nq, chi_in, w_out, as_stream(stream));
+}
+
+wn_status wn_backward(const float* bnd_xyz, const int64_t* loop_off, int32_t nloops, const float* qx,
+                      const float* qy, const float* qz, int64_t nq, const float* grad_w, float* grad_q,
+                      float* grad_bnd, void* stream) {
+  g_err.clear();
+  wn::LoopTable L;
+  int64_t nb = 0;
+  wn_status st = make_loops(loop_off, nloops, 3, &nb, &L);
+  if (st) return st;
+  if (nb > 0 && !bnd_xyz) return fail(WN_ERR_INVALID_ARGUMENT, "bnd_xyz is NULL");
+  if ((st = check_queries(qx, qy, qz, nq))) return st;
+  if (nq > 0 && !grad_w) return fail(WN_ERR_INVALID_ARGUMENT, "grad_w is NULL");
+  hipStream_t s = as_stream(stream);
+  const int64_t nblocks = wn::adj3d_blocks(nq);
+  const int64_t rows = wn::adj3d_rows(nblocks);
+  float* pv = nullptr;
+  float* pl = nullptr;
+  if (grad_bnd && nb > 0) {
+    if (rows == 0) {
+      WN_HIP(wn::fill_u32(reinterpret_cast<unsigned*>(grad_bnd), nb * 3, 0u, s), "zero grad_bnd");
+    } else {
+      WN_HIP(hipMallocAsync((void**)&pv, (size_t)(rows * nb * 3) * sizeof(float), s), "partials");
+      hipError_t e = hipMallocAsync((void**)&pl, (size_t)(rows * nloops * 3) * sizeof(float), s);
+      if (e != hipSuccess) { hipFreeAsync(pv, s); return hip_fail(e, "partials"); }
+    }
+  }
+  if (nq > 0 && (grad_q || pv)) {
+    if (nb == 0) {
+      if (grad_q) WN_HIP(wn::fill_u32(reinterpret_cast<unsigned*>(grad_q), nq * 3, 0u, s), "zero grad_q");
+    } else {
+      wn::AdjArgs a;
+      a.bnd = bnd_xyz;
+      a.nb = (int32_t)nb;
+      a.qx = qx;
+      a.qy = qy;
+      a.qz = qz;
+      a.nq = nq;
+      a.gw = grad_w;
+      a.gq = grad_q;
+      a.partial = pv;
+      a.partial_loop = pl;
+      hipError_t e = wn::launch_adj3d(a, L, nblocks, s);
+      if (e == hipSuccess && pv) e = wn::launch_reduce_partials(pv, pl, rows, (int32_t)nb, L, grad_bnd, s);
+      if (pv) { hipFreeAsync(pv, s); hipFreeAsync(pl, s); }
+      if (e != hipSuccess) return hip_fail(e, "backward");
+    }
+  }
+  return WN_OK;
+}
+
+}  // extern "C"

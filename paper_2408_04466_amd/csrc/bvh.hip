@@ -1,0 +1,410 @@
+// Crossing count chi_d (Eq. chi; Alg. 1 lines 6-7) through a linear BVH
+// built on the GPU.
+//
+// All rays of one call are parallel to d, so in the frame of d (rows e1, e2,
+// d) every ray is the vertical half line above (X_p, Y_p, Z_p).  A node
+// therefore stores, for each child, the 2D box of the children's projections
+// and the largest Z: a ray can reach the child only if its (X, Y) lies in the
+// box and Z_p is below that largest Z.  The paper uses a k-d tree for its
+// ray/mesh intersections (Sec. 4, Meshes); the tree here is a linear BVH
+// (Karras 2012) over 2D Morton codes of the projected centroids, built with
+// a project-written LSD radix sort, and traversed with a short stack held in
+// registers.
+#include "kernels.hpp"
+#include "bvh_build.hpp"
+
+namespace wn {
+
+// ---------------------------------------------------------------------------
+// Triangle test (shared predicates with the boundary kernel)
+// ---------------------------------------------------------------------------
+
+// +1 / -1 when the ray p + t d (t > 0) passes through the triangle's
+// interior along / against its normal (v1-v0)x(v2-v0), 0 otherwise.
+__device__ __forceinline__ int tri_crossing(const int4 t, const double4* __restrict__ Vr,
+                                            double Xp, double Yp, double Zp) {
+  const double4 A = Vr[t.x];
+  const double4 B = Vr[t.y];
+  const double4 C = Vr[t.z];
+  const VQ a = vertex_q(A.x, A.y, A.z, Xp, Yp, Zp);
+  const VQ b = vertex_q(B.x, B.y, B.z, Xp, Yp, Zp);
+  const VQ c = vertex_q(C.x, C.y, C.z, Xp, Yp, Zp);
+  float n01 = edge_n(a, b);
+  float n12 = edge_n(b, c);
+  float n20 = edge_n(c, a);
+  if (n01 == 0.0f) n01 = tie_zero(lex_less(A.x, A.y, A.z, B.x, B.y, B.z));
+  if (n12 == 0.0f) n12 = tie_zero(lex_less(B.x, B.y, B.z, C.x, C.y, C.z));
+  if (n20 == 0.0f) n20 = tie_zero(lex_less(C.x, C.y, C.z, A.x, A.y, A.z));
+  const unsigned s01 = __float_as_uint(n01) >> 31;
+  const unsigned s12 = __float_as_uint(n12) >> 31;
+  const unsigned s20 = __float_as_uint(n20) >> 31;
+  if (s01 != s12 || s12 != s20) return 0;
+  // Height of the crossing above p: barycentric weights are the edge values
+  // opposite each vertex (divided by the vertex scales), so the crossing is
+  // above p iff sum(N_opp * lam * Z) has the sign of the N's.
+  const float num = __fmaf_rn(n12, a.lz, __fmaf_rn(n20, b.lz, __fmul_rn(n01, c.lz)));
+  const bool neg = s01 != 0u;
+  const bool hit = neg ? (num < 0.0f) : (num > 0.0f);
+  return hit ? (neg ? 1 : -1) : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Traversal with a short stack in registers
+// ---------------------------------------------------------------------------
+
+// Fixed-depth stack kept in registers: push shifts every entry down by one
+// (plain register moves, no indexed addressing, so no scratch memory).
+template <int S>
+struct RegStack {
+  int32_t e[S];
+  int n;
+  __device__ __forceinline__ void init() { n = 0; }
+  __device__ __forceinline__ bool push(int32_t v) {
+#pragma unroll
+    for (int i = S - 1; i > 0; --i) e[i] = e[i - 1];
+    e[0] = v;
+    ++n;
+    return n <= S;
+  }
+  __device__ __forceinline__ int32_t pop() {
+    const int32_t v = e[0];
+#pragma unroll
+    for (int i = 0; i < S - 1; ++i) e[i] = e[i + 1];
+    --n;
+    return v;
+  }
+};
+
+__device__ __forceinline__ bool in_box(const float4 b, float bz, float x, float y, float z) {
+  return (x >= b.x) & (x <= b.y) & (y >= b.z) & (y <= b.w) & (z <= bz);
+}
+
+// chi for one query; returns kChiOverflow when the stack overflowed.
+template <int S>
+__device__ int traverse(const CrossArgs& a, double Xp, double Yp, double Zp) {
+  if (a.nf == 0) return 0;
+  const float x = (float)Xp, y = (float)Yp, z = (float)Zp;
+  if (a.nf == 1) {
+    return in_box(a.leafbox[0], a.leafz[0], x, y, z) ? tri_crossing(a.tris[0], a.Vr, Xp, Yp, Zp) : 0;
+  }
+  int chi = 0;
+  RegStack<S> st;
+  st.init();
+  int32_t node = 0;
+  const int32_t nint = a.nf - 1;
+  // a valid tree visits each node at most once per query
+  for (int32_t it = 0;; ++it) {
+    if (it > nint || (uint32_t)node >= (uint32_t)nint) return WN_CHI_INVALID;
+    const BvhNode nd = a.nodes[node];
+    bool hl = in_box(nd.lbox, nd.lzmax, x, y, z);
+    bool hr = in_box(nd.rbox, nd.rzmax, x, y, z);
+    if (hl && nd.left < 0) {
+      if (~nd.left >= a.nf) return WN_CHI_INVALID;
+      chi += tri_crossing(a.tris[~nd.left], a.Vr, Xp, Yp, Zp);
+      hl = false;
+    }
+    if (hr && nd.right < 0) {
+      if (~nd.right >= a.nf) return WN_CHI_INVALID;
+      chi += tri_crossing(a.tris[~nd.right], a.Vr, Xp, Yp, Zp);
+      hr = false;
+    }
+    if (hl && hr) {
+      if (!st.push(nd.right)) return kChiOverflow;   // deepest entry lost: redo deeper
+      node = nd.left;
+    } else if (hl) {
+      node = nd.left;
+    } else if (hr) {
+      node = nd.right;
+    } else {
+      if (st.n == 0) break;
+      node = st.pop();
+    }
+  }
+  return chi;
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_cross3d(CrossArgs a) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= a.nq) return;
+  const float px = a.qx[q], py = a.qy[q], pz = a.qz[q];
+  if (!(isfinite(px) && isfinite(py) && isfinite(pz))) {
+    a.chi[q] = WN_CHI_INVALID;
+    return;
+  }
+  double Xp, Yp, Zp;
+  rotate(a.F, px, py, pz, Xp, Yp, Zp);
+  a.chi[q] = traverse<S>(a, Xp, Yp, Zp);
+}
+
+// Second pass over the few queries whose short stack overflowed: a deeper
+// register stack (the tree depth bounds the number of pending siblings).
+template <int S>
+__global__ __launch_bounds__(64) void k_cross3d_retry(CrossArgs a) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= a.nq) return;
+  if (a.chi[q] != kChiOverflow) return;
+  double Xp, Yp, Zp;
+  rotate(a.F, a.qx[q], a.qy[q], a.qz[q], Xp, Yp, Zp);
+  const int r = traverse<S>(a, Xp, Yp, Zp);
+  a.chi[q] = (r == kChiOverflow) ? WN_CHI_INVALID : r;
+}
+
+hipError_t launch_cross3d(const CrossArgs& a, hipStream_t s) {
+  if (a.nq == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((a.nq + 255) / 256);
+  hipLaunchKernelGGL(k_cross3d<kShortStack>, dim3(blocks), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const unsigned b2 = (unsigned)((a.nq + 63) / 64);
+  hipLaunchKernelGGL(k_cross3d_retry<kDeepStack>, dim3(b2), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Build
+// ---------------------------------------------------------------------------
+
+namespace {
+
+__device__ __forceinline__ unsigned f2ord(float f) {
+  const unsigned u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float ord2f(unsigned o) {
+  const unsigned u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+  return __uint_as_float(u);
+}
+
+// float32 not above / not below a float64 value
+__device__ __forceinline__ float f_down(double x) {
+  float f = (float)x;
+  if ((double)f > x) f = nextafterf(f, -INFINITY);
+  return f;
+}
+__device__ __forceinline__ float f_up(double x) {
+  float f = (float)x;
+  if ((double)f < x) f = nextafterf(f, INFINITY);
+  return f;
+}
+
+__global__ void k_rotate_vertices(Frame F, const float* __restrict__ V, int32_t nv,
+                                  double4* __restrict__ Vr) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv) return;
+  double X, Y, Z;
+  rotate(F, V[3 * i], V[3 * i + 1], V[3 * i + 2], X, Y, Z);
+  Vr[i] = make_double4(X, Y, Z, 0.0);
+}
+
+// Projected box (+ pad) of each triangle, its centroid, and the centroid
+// bounds of the scene (ordered-int atomics).
+__global__ void k_tri_boxes(const double4* __restrict__ Vr, const int32_t* __restrict__ Fc,
+                            int32_t nf, float pad, float4* __restrict__ box,
+                            float* __restrict__ zmax, float2* __restrict__ cen,
+                            unsigned* __restrict__ cb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  float cx = 0.f, cy = 0.f;
+  bool ok = i < nf;
+  if (ok) {
+    const double4 A = Vr[Fc[3 * i]];
+    const double4 B = Vr[Fc[3 * i + 1]];
+    const double4 C = Vr[Fc[3 * i + 2]];
+    const double x0 = fmin(A.x, fmin(B.x, C.x)), x1 = fmax(A.x, fmax(B.x, C.x));
+    const double y0 = fmin(A.y, fmin(B.y, C.y)), y1 = fmax(A.y, fmax(B.y, C.y));
+    const double z1 = fmax(A.z, fmax(B.z, C.z));
+    box[i] = make_float4(f_down(x0) - pad, f_up(x1) + pad, f_down(y0) - pad, f_up(y1) + pad);
+    zmax[i] = f_up(z1) + pad;
+    cx = (float)(0.5 * (x0 + x1));
+    cy = (float)(0.5 * (y0 + y1));
+    cen[i] = make_float2(cx, cy);
+  }
+  // block reduction of centroid bounds, then one atomic per block
+  __shared__ unsigned red[4][256];
+  red[0][threadIdx.x] = ok ? f2ord(cx) : 0xffffffffu;
+  red[1][threadIdx.x] = ok ? f2ord(cx) : 0u;
+  red[2][threadIdx.x] = ok ? f2ord(cy) : 0xffffffffu;
+  red[3][threadIdx.x] = ok ? f2ord(cy) : 0u;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      red[0][threadIdx.x] = min(red[0][threadIdx.x], red[0][threadIdx.x + s]);
+      red[1][threadIdx.x] = max(red[1][threadIdx.x], red[1][threadIdx.x + s]);
+      red[2][threadIdx.x] = min(red[2][threadIdx.x], red[2][threadIdx.x + s]);
+      red[3][threadIdx.x] = max(red[3][threadIdx.x], red[3][threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicMin(&cb[0], red[0][0]);
+    atomicMax(&cb[1], red[1][0]);
+    atomicMin(&cb[2], red[2][0]);
+    atomicMax(&cb[3], red[3][0]);
+  }
+}
+
+__device__ __forceinline__ unsigned spread16(unsigned v) {
+  v &= 0xffffu;
+  v = (v | (v << 8)) & 0x00ff00ffu;
+  v = (v | (v << 4)) & 0x0f0f0f0fu;
+  v = (v | (v << 2)) & 0x33333333u;
+  v = (v | (v << 1)) & 0x55555555u;
+  return v;
+}
+
+__global__ void k_morton(const float2* __restrict__ cen, int32_t nf, const unsigned* __restrict__ cb,
+                         unsigned* __restrict__ keys, int32_t* __restrict__ vals) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nf) return;
+  const float x0 = ord2f(cb[0]), x1 = ord2f(cb[1]), y0 = ord2f(cb[2]), y1 = ord2f(cb[3]);
+  const float sx = (x1 > x0) ? 65535.0f / (x1 - x0) : 0.0f;
+  const float sy = (y1 > y0) ? 65535.0f / (y1 - y0) : 0.0f;
+  const float2 c = cen[i];
+  const unsigned ix = (unsigned)fminf(fmaxf((c.x - x0) * sx, 0.0f), 65535.0f);
+  const unsigned iy = (unsigned)fminf(fmaxf((c.y - y0) * sy, 0.0f), 65535.0f);
+  keys[i] = spread16(ix) | (spread16(iy) << 1);
+  vals[i] = i;
+}
+
+// Karras 2012: internal node i of n-1 covers a key range found from the
+// common-prefix lengths of its neighbours; duplicate keys are split by index.
+__device__ __forceinline__ int delta(const unsigned* __restrict__ k, int n, int i, int j) {
+  if (j < 0 || j >= n) return -1;
+  const unsigned long long a = ((unsigned long long)k[i] << 32) | (unsigned)i;
+  const unsigned long long b = ((unsigned long long)k[j] << 32) | (unsigned)j;
+  return __clzll(a ^ b);
+}
+
+__global__ void k_karras(const unsigned* __restrict__ keys, int32_t n, int32_t* __restrict__ left,
+                         int32_t* __restrict__ right, int32_t* __restrict__ parent_int,
+                         int32_t* __restrict__ parent_leaf) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n - 1) return;
+  const int d = (delta(keys, n, i, i + 1) - delta(keys, n, i, i - 1)) >= 0 ? 1 : -1;
+  const int dmin = delta(keys, n, i, i - d);
+  int lmax = 2;
+  while (delta(keys, n, i, i + lmax * d) > dmin) lmax <<= 1;
+  int l = 0;
+  for (int t = lmax >> 1; t >= 1; t >>= 1)
+    if (delta(keys, n, i, i + (l + t) * d) > dmin) l += t;
+  const int j = i + l * d;
+  const int dnode = delta(keys, n, i, j);
+  int s = 0;
+  int t = l;
+  do {
+    t = (t + 1) >> 1;
+    if (delta(keys, n, i, i + (s + t) * d) > dnode) s += t;
+  } while (t > 1);
+  const int gamma = i + s * d + min(d, 0);
+  const int lo = min(i, j), hi = max(i, j);
+  const int32_t lc = (lo == gamma) ? ~gamma : gamma;
+  const int32_t rc = (hi == gamma + 1) ? ~(gamma + 1) : gamma + 1;
+  left[i] = lc;
+  right[i] = rc;
+  if (lc < 0) parent_leaf[~lc] = i; else parent_int[lc] = i;
+  if (rc < 0) parent_leaf[~rc] = i; else parent_int[rc] = i;
+  if (i == 0) parent_int[0] = -1;
+}
+
+// Sorted triangle records and leaf boxes in sorted order.
+__global__ void k_gather_leaves(const int32_t* __restrict__ Fc, const int32_t* __restrict__ order,
+                                int32_t nf, const float4* __restrict__ box,
+                                const float* __restrict__ zmax, int4* __restrict__ tris,
+                                float4* __restrict__ lbox, float* __restrict__ lz) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nf) return;
+  int f = order[i];
+  if (f < 0 || f >= nf) f = 0;   // never taken for a permutation
+  tris[i] = make_int4(Fc[3 * f], Fc[3 * f + 1], Fc[3 * f + 2], f);
+  lbox[i] = box[f];
+  lz[i] = zmax[f];
+}
+
+// Bottom-up: the second child to arrive at a node writes the node.  The
+// agent-scope fence before the counter increment publishes this thread's
+// writes; the one after it makes the sibling's writes visible (it
+// invalidates the compute unit's vector L1).
+__global__ void k_refit(int32_t nf, const int32_t* __restrict__ left, const int32_t* __restrict__ right,
+                        const int32_t* __restrict__ parent_int, const int32_t* __restrict__ parent_leaf,
+                        const float4* __restrict__ lbox, const float* __restrict__ lz,
+                        float4* ibox, float* iz, int32_t* flags, BvhNode* __restrict__ nodes) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nf) return;
+  int node = parent_leaf[i];
+  while (node >= 0 && node < nf - 1) {
+    __threadfence();
+    if (atomicAdd(&flags[node], 1) == 0) return;
+    __threadfence();
+    const int32_t lc = left[node], rc = right[node];
+    if (lc >= nf - 1 || rc >= nf - 1 || ~lc >= nf || ~rc >= nf) return;
+    float4 bl, br;
+    float zl, zr;
+    if (lc < 0) { bl = lbox[~lc]; zl = lz[~lc]; }
+    else { bl = ibox[lc]; zl = iz[lc]; }
+    if (rc < 0) { br = lbox[~rc]; zr = lz[~rc]; }
+    else { br = ibox[rc]; zr = iz[rc]; }
+    BvhNode nd;
+    nd.lbox = bl;
+    nd.rbox = br;
+    nd.lzmax = zl;
+    nd.rzmax = zr;
+    nd.left = lc;
+    nd.right = rc;
+    nodes[node] = nd;
+    const float4 u = make_float4(fminf(bl.x, br.x), fmaxf(bl.y, br.y), fminf(bl.z, br.z), fmaxf(bl.w, br.w));
+    ibox[node] = u;
+    iz[node] = fmaxf(zl, zr);
+    node = parent_int[node];
+  }
+}
+
+__global__ void k_fill_u32(unsigned* p, int64_t n, unsigned v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+hipError_t fill_u32(unsigned* p, int64_t n, unsigned v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t build_bvh_device(const BuildBufs& b, const Frame& F, const float* V, int32_t nv,
+                            const int32_t* Fc, int32_t nf, float pad, hipStream_t s) {
+  hipError_t e;
+  const unsigned bv = (unsigned)((nv + 255) / 256);
+  const unsigned bf = (unsigned)((nf + 255) / 256);
+  if (nv > 0) {
+    hipLaunchKernelGGL(k_rotate_vertices, dim3(bv), dim3(256), 0, s, F, V, nv, b.Vr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (nf == 0) return hipSuccess;
+  unsigned init[4] = {0xffffffffu, 0u, 0xffffffffu, 0u};
+  for (int k = 0; k < 4; ++k)
+    if ((e = fill_u32(b.cbounds + k, 1, init[k], s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tri_boxes, dim3(bf), dim3(256), 0, s, b.Vr, Fc, nf, pad, b.box, b.zmax,
+                     b.cen, b.cbounds);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_morton, dim3(bf), dim3(256), 0, s, b.cen, nf, b.cbounds, b.keys, b.vals);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = radix_sort_pairs(b.keys, b.vals, b.keys2, b.vals2, nf, b.sort_tmp, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gather_leaves, dim3(bf), dim3(256), 0, s, Fc, b.vals, nf, b.box, b.zmax,
+                     b.tris, b.leafbox, b.leafz);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (nf == 1) return hipSuccess;
+  if ((e = fill_u32((unsigned*)b.parent_leaf, nf, 0xffffffffu, s)) != hipSuccess) return e;
+  if ((e = fill_u32((unsigned*)b.parent_int, nf - 1, 0xffffffffu, s)) != hipSuccess) return e;
+  // unwritten nodes would read as NaN boxes (never entered)
+  if ((e = fill_u32((unsigned*)b.nodes, (int64_t)(nf - 1) * (sizeof(BvhNode) / 4), 0xffffffffu, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_karras, dim3(bf), dim3(256), 0, s, b.keys, nf, b.left, b.right,
+                     b.parent_int, b.parent_leaf);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = fill_u32((unsigned*)b.flags, nf - 1, 0u, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_refit, dim3(bf), dim3(256), 0, s, nf, b.left, b.right, b.parent_int,
+                     b.parent_leaf, b.leafbox, b.leafz, b.ibox, b.iz, b.flags, b.nodes);
+  return hipGetLastError();
+}
+
+}  // namespace wn

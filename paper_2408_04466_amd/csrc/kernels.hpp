@@ -1,0 +1,80 @@
+// Kernel argument structures and launch helpers shared by the host API and
+// the kernels (plain structs passed by value as kernel arguments).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "geom.hpp"
+#include "wn.h"
+
+namespace wn {
+
+// Boundary loops of one call: loop l covers vertices [off[l], off[l+1]).
+struct LoopTable {
+  int32_t n;
+  int32_t off[WN_MAX_LOOPS + 1];
+};
+
+// Binary BVH node: the boxes of both children (projected x/y range and the
+// largest coordinate along d) and the children (>= 0 internal node index,
+// < 0 leaf ~index into the sorted triangle array).  48 bytes.
+struct alignas(16) BvhNode {
+  float4 lbox;   // xmin, xmax, ymin, ymax of the left child
+  float4 rbox;   // same for the right child
+  float lzmax, rzmax;
+  int32_t left, right;
+};
+
+constexpr int32_t kChiOverflow = (int32_t)0x80000001;  // internal: retry deeper
+
+struct CrossArgs {
+  Frame F;
+  const BvhNode* nodes;
+  const int4* tris;        // sorted triangles: v0, v1, v2, original face id
+  const double4* Vr;       // rotated vertices: X, Y, Z, 0
+  const float4* leafbox;   // used when the tree is a single leaf
+  const float* leafz;
+  int32_t nf;
+  const float* qx;
+  const float* qy;
+  const float* qz;
+  int64_t nq;
+  int32_t* chi;
+};
+
+struct BndArgs {
+  Frame F;
+  const float* bnd;        // [nb][3]
+  int32_t nb;
+  const float* qx;
+  const float* qy;
+  const float* qz;
+  int64_t nq;
+  const int32_t* chi_in;   // may alias w_out
+  float* w_out;
+};
+
+struct AdjArgs {
+  const float* bnd;
+  int32_t nb;
+  const float* qx;
+  const float* qy;
+  const float* qz;
+  int64_t nq;
+  const float* gw;
+  float* gq;               // [nq][3] or null
+  float* partial;          // [rows][nb][3] or null (rows = workgroups * 4)
+  float* partial_loop;     // [rows][nloops][3] (with partial)
+};
+
+// host-side launchers (defined next to their kernels)
+hipError_t launch_bnd3d(const BndArgs& a, const LoopTable& L, hipStream_t s);
+hipError_t launch_cross3d(const CrossArgs& a, hipStream_t s);
+hipError_t launch_adj3d(const AdjArgs& a, const LoopTable& L, int64_t nblocks, hipStream_t s);
+int64_t adj3d_blocks(int64_t nq);
+int64_t adj3d_rows(int64_t nblocks);
+hipError_t launch_reduce_partials(const float* pv, const float* pl, int64_t rows, int32_t nb,
+                                  const LoopTable& L, float* out, hipStream_t s);
+
+}  // namespace wn

@@ -1,0 +1,192 @@
+"""GPU parity of the 3D path (crossings + boundary integral) against the FP64
+oracle, through the C ABI.  chi bit-exact on non-degenerate queries, w within
+1e-4 away from the boundary (Alg. 1; Eq. chi; Eq. wn_discrete_sum)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import wn3d as O
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    import paper_2408_04466_amd as W
+    from gpu_util import DevMesh, compare_3d, W_TOL
+
+
+def _rand_queries(M, n, seed, scale=1.2):
+    P = synth.box_queries(M.V, n, seed, scale=scale)
+    ext = np.ptp(M.V.astype(np.float64), axis=0)
+    if ext.min() < 1e-3 * ext.max():
+        # flat mesh: spread the queries off its plane as well
+        k = int(np.argmin(ext))
+        P[:, k] = synth.rng(seed + 1).uniform(-0.6, 0.6, n) * ext.max()
+    return P
+
+
+SMALL = {
+    "bumpy_cap": lambda: synth.bumpy_cap(),
+    "twisted_sheet": lambda: synth.random_open_mesh(3, n=6),
+    "coons": lambda: synth.coons_surface(11, 2000, 96),
+    "disk": lambda: synth.disk_fan(64),
+    "sphere_small": lambda: synth.open_sphere(4, n_lon=48, n_rings=40, top_refine=2),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+@pytest.mark.parametrize("dseed", [3, 17])
+def test_small_meshes_match_oracle(name, dseed):
+    M = SMALL[name]()
+    dm = DevMesh(M, synth.random_direction(dseed))
+    P = _rand_queries(M, 1500, 100 + dseed)
+    w, chi = dm.eval(P)
+    compare_3d(dm, P, w, chi)
+
+
+def test_closed_mesh_inside_outside():
+    M = synth.icosphere(3)
+    dm = DevMesh(M, synth.random_direction(5))
+    assert len(dm.loop_off) == 1     # no boundary loops
+    P = synth.rng(3).uniform(-1.5, 1.5, (20000, 3)).astype(np.float32)
+    w, chi = dm.eval(P)
+    r = np.linalg.norm(P.astype(np.float64), axis=1)
+    far = np.abs(r - 1.0) > 0.02
+    assert np.array_equal(w[far], (r[far] < 1.0).astype(np.float32))
+    assert np.array_equal(chi[far], (r[far] < 1.0).astype(np.int32))
+
+
+@pytest.fixture(scope="module")
+def c3():
+    """The 3D open-mesh workload: noise-displaced unit sphere (amplitude 0.05)
+    with a 30 degree polar cap removed, 512 x 1024 rings (1,048,064
+    triangles, one boundary loop of 512 edges), 2^20 queries uniform in 1.2x
+    its bounding box, seeded random direction."""
+    M = synth.open_sphere(3)
+    d = synth.random_direction(3)
+    dm = DevMesh(M, d)
+    P = _rand_queries(M, 1 << 20, 7)
+    w, chi = dm.eval(P)
+    return dm, P, w, chi
+
+
+def test_c3_full_size_sampled_parity(c3):
+    dm, P, w, chi = c3
+    assert dm.M.F.shape[0] == 1048064 and len(dm.bnd_idx) == 512
+    sample = synth.rng(11).choice(len(P), 40, replace=False)
+    sample = np.concatenate([sample, [0, len(P) - 1]])
+    info = compare_3d(dm, P, w, chi, sample)
+    print("c3 sample", info)
+
+
+def test_c3_properties_at_full_size(c3):
+    dm, P, w, chi = c3
+    assert np.all(np.isfinite(w))
+    assert chi.min() >= -2 and chi.max() <= 3
+    # a second direction gives the same w (d-invariance) everywhere except
+    # next to the boundary curve
+    dm2 = DevMesh(dm.M, synth.random_direction(99))
+    w2, chi2 = dm2.eval(P)
+    from scipy.spatial import cKDTree
+    L = dm.M.V[dm.bnd_idx].astype(np.float64)
+    t = np.linspace(0, 1, 64, endpoint=False)[:, None, None]
+    dense = (L[None] * (1 - t) + np.roll(L, -1, 0)[None] * t).reshape(-1, 3)
+    dist, _ = cKDTree(dense).query(P.astype(np.float64), distance_upper_bound=1e-4)
+    far = np.isinf(dist)
+    diff = np.abs(w - w2)
+    assert diff[far].max() <= 2 * W_TOL, diff[far].max()
+    # the crossing counts differ, the winding numbers agree
+    assert np.any(chi != chi2)
+
+
+def test_near_boundary_queries():
+    M = synth.open_sphere(3, n_lon=128, n_rings=64)
+    d = synth.random_direction(21)
+    dm = DevMesh(M, d)
+    V = M.V.astype(np.float64)
+    L = dm.bnd_idx
+    g = synth.rng(5)
+    pts = []
+    for k, dist in enumerate([1e-5, 3e-5, 1e-4, 1e-3, 1e-2]):
+        for _ in range(40):
+            i = int(g.integers(len(L)))
+            a, b = V[L[i]], V[L[(i + 1) % len(L)]]
+            m = a + g.uniform(0.1, 0.9) * (b - a)
+            e = (b - a) / np.linalg.norm(b - a)
+            u = g.normal(size=3)
+            u -= (u @ e) * e
+            u /= np.linalg.norm(u)
+            pts.append(m + dist * u * 1.5)
+    P = np.array(pts, np.float32)
+    w, chi = dm.eval(P)
+    compare_3d(dm, P, w, chi, max_degenerate_frac=0.2)
+
+
+def test_w_continuous_across_boundary_crossing():
+    M = synth.bumpy_cap()
+    d = synth.random_direction(17)
+    dm = DevMesh(M, d)
+    V = M.V.astype(np.float64)
+    L = dm.bnd_idx
+    pts = []
+    for i in range(len(L)):
+        a, b = V[L[i]], V[L[(i + 1) % len(L)]]
+        mid = 0.5 * (a + b)
+        side = np.cross(d, b - a)
+        side /= np.linalg.norm(side)
+        base = mid - 0.7 * d
+        for s in (1e-5, -1e-5):
+            pts.append(base + s * side)
+    P = np.array(pts, np.float32)
+    w, chi = dm.eval(P)
+    w, chi = w.reshape(-1, 2), chi.reshape(-1, 2)
+    assert np.all(np.abs(chi[:, 0] - chi[:, 1]) == 1)
+    assert np.abs(w[:, 0] - w[:, 1]).max() < 1e-3
+
+
+def test_entry_points_agree_and_are_deterministic():
+    M = synth.coons_surface(5, 5000, 256)
+    dm = DevMesh(M, synth.random_direction(8))
+    P = _rand_queries(M, 50000, 9)
+    qx, qy, qz = dm.queries(P)
+    w1, chi1 = W.eval_3d(dm.bvh, dm.bnd, dm.loop_off, qx, qy, qz)
+    w2, _ = W.eval_3d(dm.bvh, dm.bnd, dm.loop_off, qx, qy, qz, want_chi=False)
+    chi3 = W.crossings_3d(dm.bvh, qx, qy, qz)
+    w4 = W.eval_3d_boundary(dm.bvh, dm.bnd, dm.loop_off, qx, qy, qz, chi3)
+    torch.cuda.synchronize()
+    assert torch.equal(w1, w2) and torch.equal(chi1, chi3) and torch.equal(w1, w4)
+
+
+def test_edge_cases():
+    M = synth.bumpy_cap()
+    dm = DevMesh(M, synth.random_direction(4))
+    # empty query set
+    e = torch.empty(0, dtype=torch.float32, device="cuda")
+    w, chi = W.eval_3d(dm.bvh, dm.bnd, dm.loop_off, e, e, e)
+    assert w.numel() == 0
+    # non-finite queries
+    P = np.array([[np.nan, 0, 0], [0, np.inf, 0], [0.1, 0.2, 0.3]], np.float32)
+    w, chi = dm.eval(P)
+    assert np.isnan(w[0]) and np.isnan(w[1]) and np.isfinite(w[2])
+    assert chi[0] == W.WN_CHI_INVALID and chi[1] == W.WN_CHI_INVALID
+    # far away: w -> 0
+    w, chi = dm.eval(np.array([[300.0, -200.0, 500.0]], np.float32))
+    assert abs(w[0]) < 1e-4
+    # one triangle
+    T = synth.Mesh(np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float32), np.array([[0, 1, 2]], np.int32))
+    dmt = DevMesh(T, synth.random_direction(6))
+    P = synth.rng(1).uniform(-1, 2, (500, 3)).astype(np.float32)
+    w, chi = dmt.eval(P)
+    compare_3d(dmt, P, w, chi)
+
+
+def test_invalid_arguments_raise():
+    M = synth.bumpy_cap()
+    dm = DevMesh(M, synth.random_direction(4))
+    q = torch.zeros(4, dtype=torch.float32, device="cuda")
+    with pytest.raises(W.WnError):
+        W.eval_3d(dm.bvh, dm.bnd[:2].contiguous(), np.array([0, 2]), q, q, q)   # a 2-vertex loop
+    with pytest.raises(TypeError):
+        W.eval_3d(dm.bvh, dm.bnd, dm.loop_off, q.double(), q, q)

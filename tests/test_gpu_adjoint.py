@@ -1,0 +1,122 @@
+"""GPU parity of the adjoint (wn_backward and the autograd Function) against
+the FP64 closed-form gradient oracle, itself pinned by finite differences.
+Gradients within 1e-3 relative (normwise per tensor) at queries more than
+1e-2 from the surface."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import grad3d as G
+from oracle import wn3d as O
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    import paper_2408_04466_amd as W
+    from gpu_util import DevMesh
+
+
+def _far_from_surface(M, P, dist):
+    from scipy.spatial import cKDTree
+    V = M.V.astype(np.float64)
+    F = M.F
+    # dense samples of every triangle (vertices, edge midpoints, centroids)
+    pts = np.concatenate([V, 0.5 * (V[F[:, 0]] + V[F[:, 1]]), 0.5 * (V[F[:, 1]] + V[F[:, 2]]),
+                          0.5 * (V[F[:, 2]] + V[F[:, 0]]), V[F].mean(1)], 0)
+    edge = np.linalg.norm(V[F[:, 0]] - V[F[:, 1]], axis=1).max()
+    dd, _ = cKDTree(pts).query(np.asarray(P, np.float64), distance_upper_bound=dist + edge)
+    return np.isinf(dd)
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
+
+
+@pytest.mark.parametrize("mesh", ["bumpy_cap", "coons"])
+def test_backward_matches_oracle_small(mesh):
+    M = synth.bumpy_cap() if mesh == "bumpy_cap" else synth.coons_surface(2, 3000, 200)
+    dm = DevMesh(M, synth.random_direction(3))
+    P = synth.box_queries(M.V, 20000, 4)
+    keep = _far_from_surface(M, P, 1e-2)
+    P = P[keep]
+    g = synth.rng(5).normal(size=len(P)).astype(np.float32)
+    qx, qy, qz = dm.queries(P)
+    gq, gb = W.backward(dm.bnd, dm.loop_off, qx, qy, qz, torch.from_numpy(g).cuda())
+    torch.cuda.synchronize()
+    Lx = [M.V[dm.bnd_idx[dm.loop_off[i]:dm.loop_off[i + 1]]] for i in range(len(dm.loop_off) - 1)]
+    rq, rv = G.grad3d(Lx, P.astype(np.float64), g.astype(np.float64))
+    assert _rel(gq.cpu().numpy(), rq) <= 1e-3
+    assert _rel(gb.cpu().numpy(), np.concatenate(rv, 0)) <= 1e-3
+
+
+def test_adjoint_workload_parity_and_fd():
+    """C3's surface with its boundary refined to 2048 edges, 2^18 queries,
+    L = sum (w - t)^2 with seeded targets t in {0, 1}."""
+    M = synth.open_sphere(3, top_refine=4)
+    d = synth.random_direction(3)
+    dm = DevMesh(M, d)
+    assert len(dm.bnd_idx) == 2048
+    P = synth.box_queries(M.V, 1 << 18, 13)
+    t = synth.targets01(len(P), 14)
+    qx, qy, qz = dm.queries(P)
+    bnd = dm.bnd.clone().requires_grad_(True)
+    qx.requires_grad_(True); qy.requires_grad_(True); qz.requires_grad_(True)
+    w = W.winding_number(dm.bvh, bnd, dm.loop_off, qx, qy, qz)
+    tt = torch.from_numpy(t).cuda()
+    # the loss covers a seeded subset of 16384 queries away from the surface
+    # (the kernels still process all 2^18; the others get dL/dw = 0)
+    sub = np.zeros(len(P), bool)
+    sub[synth.rng(15).choice(len(P), 16384, replace=False)] = True
+    far = torch.from_numpy(_far_from_surface(M, P, 1e-2) & sub).cuda()
+    loss = (((w - tt) ** 2) * far).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    gq = torch.stack([qx.grad, qy.grad, qz.grad], 1).cpu().numpy()
+    gb = bnd.grad.cpu().numpy()
+    wn = w.detach().cpu().numpy()
+    farn = far.cpu().numpy()
+    g = (2.0 * (wn.astype(np.float64) - t) * farn)
+    L = M.V[dm.bnd_idx].astype(np.float64)
+    # oracle gradient for every query (closed form, chunked)
+    rq = np.zeros((len(P), 3))
+    rv = np.zeros((len(L), 3))
+    sel_all = np.nonzero(farn)[0]
+    for s in range(0, len(sel_all), 2048):
+        ii = sel_all[s:s + 2048]
+        a, b = G.grad3d([L], P[ii].astype(np.float64), g[ii])
+        rq[ii] = a
+        rv += b[0]
+    assert _rel(gq[farn], rq[farn]) <= 1e-3
+    assert _rel(gb, rv) <= 1e-3
+    # the oracle's closed form against FP64 central differences (h = 1e-4)
+    sel = np.nonzero(farn)[0][:4]
+    h = 1e-4
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        fd = (O.wn3d(M.V, M.F, P[sel] + e, d, margins=False)["w"]
+              - O.wn3d(M.V, M.F, P[sel] - e, d, margins=False)["w"]) / (2 * h)
+        ref = G.grad3d([L], P[sel].astype(np.float64))[0][:, k]
+        assert np.abs(fd - ref).max() <= 1e-3 * max(np.abs(ref).max(), 1e-6)
+
+
+def test_backward_deterministic_and_edge_cases():
+    M = synth.coons_surface(7, 4000, 300)
+    dm = DevMesh(M, synth.random_direction(2))
+    P = synth.box_queries(M.V, 30000, 3)
+    qx, qy, qz = dm.queries(P)
+    g = torch.from_numpy(synth.rng(1).normal(size=len(P)).astype(np.float32)).cuda()
+    a = W.backward(dm.bnd, dm.loop_off, qx, qy, qz, g)
+    b = W.backward(dm.bnd, dm.loop_off, qx, qy, qz, g)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    # no queries: grad_bnd is all zeros
+    e = torch.empty(0, dtype=torch.float32, device="cuda")
+    gq, gb = W.backward(dm.bnd, dm.loop_off, e, e, e, e)
+    torch.cuda.synchronize()
+    assert gq.numel() == 0 and torch.count_nonzero(gb) == 0
+    # translation identity: sum of vertex grads + sum of query grads = 0
+    gq, gb = a
+    tot = gq.double().sum(0) + gb.double().sum(0)
+    assert tot.abs().max().item() <= 1e-3 * gb.double().abs().sum().item()
