@@ -15,9 +15,9 @@
 // done); it is summed over the lane's queries in registers, over the
 // wavefront with cross-lane adds, and written once per (workgroup,
 // wavefront, vertex) as a float32 partial.  The closing edge's share of each
-// loop's first vertex goes to a separate per-loop partial.  A second kernel
-// adds all partials in a fixed order in float64, so grad_bnd is bitwise
-// reproducible (no floating-point atomics).
+// loop's first vertex goes to a separate per-loop partial.  Two more kernels
+// add all partials in a fixed order in float64 (groups of rows, then the
+// groups), so grad_bnd is bitwise reproducible (no floating-point atomics).
 #include "kernels.hpp"
 
 namespace wn {
@@ -30,9 +30,21 @@ constexpr int kQPL = 4;
 constexpr int kChunk = 512;
 constexpr float kInv4Pi = 0.07957747154594767f;
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+
+// Sum over the 64 lanes of a wavefront, left in lane 63, with DPP moves
+// (no LDS traffic): butterflies inside quads, rotations inside rows of 16,
+// then the row broadcasts of lanes 15 and 31.
+__device__ __forceinline__ float wave_sum_last(float v) {
+  v += dpp<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  v += dpp<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  v += dpp<0x124, 0xF>(v);   // row_ror:4
+  v += dpp<0x128, 0xF>(v);   // row_ror:8  -> every lane holds its row's sum
+  v += dpp<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
   return v;
 }
 
@@ -64,10 +76,10 @@ __device__ __forceinline__ void edge_grad(QState& s, float ax, float ay, float a
 }
 
 __device__ __forceinline__ void put3(float* dst, const float acc[3], int lane) {
-  const float r0 = wave_sum(acc[0]);
-  const float r1 = wave_sum(acc[1]);
-  const float r2 = wave_sum(acc[2]);
-  if (lane == 0) {
+  const float r0 = wave_sum_last(acc[0]);
+  const float r1 = wave_sum_last(acc[1]);
+  const float r2 = wave_sum_last(acc[2]);
+  if (lane == 63) {
     dst[0] = r0;
     dst[1] = r1;
     dst[2] = r2;
@@ -171,11 +183,12 @@ __global__ __launch_bounds__(kThreads) void k_adj3d(AdjArgs a, LoopTable L) {
   }
 }
 
-// out[v][c] = -(1/4pi) * (sum over partial rows of partial[row][v][c]
-//             + for a loop's first vertex, sum over rows of the loop share),
-// added in row order in float64.
-__global__ void k_reduce_partials(const float* __restrict__ pv, const float* __restrict__ pl,
-                                  int64_t rows, int32_t nb, LoopTable L, float* __restrict__ out) {
+constexpr int kRowsPerGroup = 32;
+
+// Stage 1: g-th group of kRowsPerGroup partial rows, summed per column in
+// float64 (for a loop's first vertex the per-loop closing shares as well).
+__global__ void k_reduce_rows(const float* __restrict__ pv, const float* __restrict__ pl,
+                              int64_t rows, int32_t nb, LoopTable L, double* __restrict__ tmp) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = (int64_t)nb * 3;
   if (t >= n) return;
@@ -183,11 +196,23 @@ __global__ void k_reduce_partials(const float* __restrict__ pv, const float* __r
   int lf = -1;
   for (int l = 0; l < L.n; ++l)
     if (L.off[l] == v && L.off[l + 1] > v) lf = l;
+  const int64_t r0 = (int64_t)blockIdx.y * kRowsPerGroup;
+  const int64_t r1 = min(rows, r0 + kRowsPerGroup);
   double s = 0.0;
-  for (int64_t r = 0; r < rows; ++r) {
+  for (int64_t r = r0; r < r1; ++r) {
     s += (double)pv[r * n + t];
     if (lf >= 0) s += (double)pl[(r * L.n + lf) * 3 + c];
   }
+  tmp[(int64_t)blockIdx.y * n + t] = s;
+}
+
+// Stage 2: out = -(1/4pi) * sum over groups, in group order.
+__global__ void k_reduce_groups(const double* __restrict__ tmp, int64_t groups, int64_t n,
+                                float* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double s = 0.0;
+  for (int64_t g = 0; g < groups; ++g) s += tmp[g * n + t];
   out[t] = (float)(-s * 0.07957747154594767 + 0.0);
 }
 
@@ -206,12 +231,18 @@ hipError_t launch_adj3d(const AdjArgs& a, const LoopTable& L, int64_t nblocks, h
   return hipGetLastError();
 }
 
+int64_t reduce_groups(int64_t rows) { return (rows + kRowsPerGroup - 1) / kRowsPerGroup; }
+
 hipError_t launch_reduce_partials(const float* pv, const float* pl, int64_t rows, int32_t nb,
-                                  const LoopTable& L, float* out, hipStream_t s) {
+                                  const LoopTable& L, double* tmp, float* out, hipStream_t s) {
   const int64_t n = (int64_t)nb * 3;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pv, pl,
-                     rows, nb, L, out);
+  const int64_t groups = reduce_groups(rows);
+  const unsigned bx = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_reduce_rows, dim3(bx, (unsigned)groups), dim3(256), 0, s, pv, pl, rows, nb, L, tmp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_groups, dim3(bx), dim3(256), 0, s, tmp, groups, n, out);
   return hipGetLastError();
 }
 

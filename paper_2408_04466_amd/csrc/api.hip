@@ -454,13 +454,20 @@ wn_status wn_backward(const float* bnd_xyz, const int64_t* loop_off, int32_t nlo
   const int64_t rows = wn::adj3d_rows(nblocks);
   float* pv = nullptr;
   float* pl = nullptr;
+  double* tmp = nullptr;
   if (grad_bnd && nb > 0) {
     if (rows == 0) {
       WN_HIP(wn::fill_u32(reinterpret_cast<unsigned*>(grad_bnd), nb * 3, 0u, s), "zero grad_bnd");
     } else {
       WN_HIP(hipMallocAsync((void**)&pv, (size_t)(rows * nb * 3) * sizeof(float), s), "partials");
       hipError_t e = hipMallocAsync((void**)&pl, (size_t)(rows * nloops * 3) * sizeof(float), s);
-      if (e != hipSuccess) { hipFreeAsync(pv, s); return hip_fail(e, "partials"); }
+      if (e == hipSuccess)
+        e = hipMallocAsync((void**)&tmp, (size_t)(wn::reduce_groups(rows) * nb * 3) * sizeof(double), s);
+      if (e != hipSuccess) {
+        hipFreeAsync(pv, s);
+        if (pl) hipFreeAsync(pl, s);
+        return hip_fail(e, "partials");
+      }
     }
   }
   if (nq > 0 && (grad_q || pv)) {
@@ -479,8 +486,8 @@ wn_status wn_backward(const float* bnd_xyz, const int64_t* loop_off, int32_t nlo
       a.partial = pv;
       a.partial_loop = pl;
       hipError_t e = wn::launch_adj3d(a, L, nblocks, s);
-      if (e == hipSuccess && pv) e = wn::launch_reduce_partials(pv, pl, rows, (int32_t)nb, L, grad_bnd, s);
-      if (pv) { hipFreeAsync(pv, s); hipFreeAsync(pl, s); }
+      if (e == hipSuccess && pv) e = wn::launch_reduce_partials(pv, pl, rows, (int32_t)nb, L, tmp, grad_bnd, s);
+      if (pv) { hipFreeAsync(pv, s); hipFreeAsync(pl, s); hipFreeAsync(tmp, s); }
       if (e != hipSuccess) return hip_fail(e, "backward");
     }
   }

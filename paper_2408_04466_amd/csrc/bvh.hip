@@ -26,26 +26,21 @@ __device__ __forceinline__ int tri_crossing(const int4 t, const double4* __restr
   const double4 A = Vr[t.x];
   const double4 B = Vr[t.y];
   const double4 C = Vr[t.z];
-  const VQ a = vertex_q(A.x, A.y, A.z, Xp, Yp, Zp);
-  const VQ b = vertex_q(B.x, B.y, B.z, Xp, Yp, Zp);
-  const VQ c = vertex_q(C.x, C.y, C.z, Xp, Yp, Zp);
-  float n01 = edge_n(a, b);
-  float n12 = edge_n(b, c);
-  float n20 = edge_n(c, a);
-  if (n01 == 0.0f) n01 = tie_zero(lex_less(A.x, A.y, A.z, B.x, B.y, B.z));
-  if (n12 == 0.0f) n12 = tie_zero(lex_less(B.x, B.y, B.z, C.x, C.y, C.z));
-  if (n20 == 0.0f) n20 = tie_zero(lex_less(C.x, C.y, C.z, A.x, A.y, A.z));
-  const unsigned s01 = __float_as_uint(n01) >> 31;
-  const unsigned s12 = __float_as_uint(n12) >> 31;
-  const unsigned s20 = __float_as_uint(n20) >> 31;
+  float za, zb, zc;
+  const VQ a = vertex_q(A.x, A.y, A.z, Xp, Yp, Zp, &za);
+  const VQ b = vertex_q(B.x, B.y, B.z, Xp, Yp, Zp, &zb);
+  const VQ c = vertex_q(C.x, C.y, C.z, Xp, Yp, Zp, &zc);
+  const double n01 = edge_tie(edge_n(a, b), tie_offset(lex_less(A.x, A.y, A.z, B.x, B.y, B.z)));
+  const double n12 = edge_tie(edge_n(b, c), tie_offset(lex_less(B.x, B.y, B.z, C.x, C.y, C.z)));
+  const double n20 = edge_tie(edge_n(c, a), tie_offset(lex_less(C.x, C.y, C.z, A.x, A.y, A.z)));
+  const bool s01 = n01 < 0.0, s12 = n12 < 0.0, s20 = n20 < 0.0;
   if (s01 != s12 || s12 != s20) return 0;
   // Height of the crossing above p: barycentric weights are the edge values
   // opposite each vertex (divided by the vertex scales), so the crossing is
   // above p iff sum(N_opp * lam * Z) has the sign of the N's.
-  const float num = __fmaf_rn(n12, a.lz, __fmaf_rn(n20, b.lz, __fmul_rn(n01, c.lz)));
-  const bool neg = s01 != 0u;
-  const bool hit = neg ? (num < 0.0f) : (num > 0.0f);
-  return hit ? (neg ? 1 : -1) : 0;
+  const double num = __fma_rn(n12, (double)za, __fma_rn(n20, (double)zb, __dmul_rn(n01, (double)zc)));
+  const bool hit = s01 ? (num < 0.0) : (num > 0.0);
+  return hit ? (s01 ? 1 : -1) : 0;
 }
 
 // ---------------------------------------------------------------------------

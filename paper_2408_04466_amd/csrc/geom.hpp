@@ -42,14 +42,15 @@ __device__ __forceinline__ void rotate(const Frame& F, float x, float y, float z
 //   (alpha = u).  The edge terms are homogeneous of degree one in each
 //   vertex's (X, Y, alpha), so a positive per-vertex scale changes neither
 //   the angle of an edge nor the sign of any predicate.
+// The scaled values are float32 numbers held in float64 registers, so the
+// products of two of them in the edge terms below are exact.
 struct VQ {
-  float x, y;   // lam * X, lam * Y
-  float a;      // lam * alpha
-  float lz;     // lam * Z   (used by the depth test of the crossing kernel)
+  double x, y;  // lam * X, lam * Y
+  double a;     // lam * alpha
 };
 
 __device__ __forceinline__ VQ vertex_q(double Xv, double Yv, double Zv,
-                                       double Xp, double Yp, double Zp) {
+                                       double Xp, double Yp, double Zp, float* lz = nullptr) {
   const float X = (float)(Xv - Xp);
   const float Y = (float)(Yv - Yp);
   const float Z = (float)(Zv - Zp);
@@ -60,21 +61,22 @@ __device__ __forceinline__ VQ vertex_q(double Xv, double Yv, double Zv,
   const bool front = Z > 0.0f;
   const float lam = front ? u : 1.0f;
   VQ q;
-  q.x = __fmul_rn(lam, X);
-  q.y = __fmul_rn(lam, Y);
-  q.a = front ? rho2 : u;
-  q.lz = __fmul_rn(lam, Z);
+  q.x = (double)__fmul_rn(lam, X);
+  q.y = (double)__fmul_rn(lam, Y);
+  q.a = (double)(front ? rho2 : u);
+  if (lz) *lz = __fmul_rn(lam, Z);
   return q;
 }
 
 // Edge predicate N(a, b) = Y_a X_b - X_a Y_b of the projected edge a->b
-// relative to the ray (proportional to d.(b' x a')).  Both products are
-// rounded before the subtraction, so N(b, a) = -N(a, b) bit for bit (IEEE
-// round-to-nearest is symmetric); an exact zero is then resolved by the
-// caller with `tie_zero`, which is antisymmetric as well.  Every triangle
-// edge and every boundary edge goes through this one function.
-__device__ __forceinline__ float edge_n(const VQ& a, const VQ& b) {
-  return __fsub_rn(__fmul_rn(a.y, b.x), __fmul_rn(a.x, b.y));
+// relative to the ray (proportional to d.(b' x a')).  The inputs are float32
+// values, so X_a*Y_b is exact in float64 and the fused multiply-add rounds
+// the exact difference once: N is correctly rounded, N(b, a) = -N(a, b) bit
+// for bit, and N == 0 exactly when the two projected vertices are collinear
+// with the ray.  Every triangle edge and every boundary edge goes through
+// this one function followed by `edge_tie`.
+__device__ __forceinline__ double edge_n(const VQ& a, const VQ& b) {
+  return __fma_rn(a.y, b.x, -__dmul_rn(a.x, b.y));
 }
 
 // Lexicographic order of two rotated vertices; distinct float32 vertices
@@ -84,44 +86,60 @@ __device__ __forceinline__ bool lex_less(double ax, double ay, double az,
   return ax < bx || (ax == bx && (ay < by || (ay == by && az < bz)));
 }
 
-// Signed zero that an exact N(a, b) == 0 is replaced with: the ray counts as
-// passing on the side of the edge that its lexicographically smaller end
-// point picks, which is opposite for the two orientations of the edge.
-__device__ __forceinline__ float tie_zero(bool a_less_b) {
-  return a_less_b ? -0.0f : 0.0f;
+// Tie offset of the directed edge a->b: -2^-1022 if a precedes b
+// lexicographically, +2^-1022 otherwise (antisymmetric in a, b).  A nonzero
+// N is at least 2^-298 in magnitude (a difference of products of float32
+// values), so adding the offset changes nothing but an exact zero, which
+// becomes a value whose sign picks the side of the lexicographically smaller
+// end point.  N(a,b) + tie(a,b) stays exactly antisymmetric, so of two
+// triangles sharing an edge exactly one claims a ray through it, and the
+// boundary term breaks the tie the same way.
+constexpr double kTie = 2.2250738585072014e-308;   // 2^-1022
+__device__ __forceinline__ double tie_offset(bool a_less_b) {
+  return a_less_b ? -kTie : kTie;
+}
+
+__device__ __forceinline__ double edge_tie(double n, double tie) {
+  return __dadd_rn(n, tie);
 }
 
 // Edge factor D + iN (up to the positive scale lam_a*lam_b): the angle
 // theta_e = atan2(N, D) is half the signed solid angle of the spherical
 // triangle (-d, a - p, b - p), i.e. the per-edge boundary term.
-__device__ __forceinline__ float edge_d(const VQ& a, const VQ& b) {
-  return __fmaf_rn(a.y, b.y, __fmaf_rn(a.x, b.x, __fmul_rn(a.a, b.a)));
+__device__ __forceinline__ double edge_d(const VQ& a, const VQ& b) {
+  return __fma_rn(a.y, b.y, __fma_rn(a.x, b.x, __dmul_rn(a.a, b.a)));
 }
 
 // Running product of the edge factors with an exact count of turns:
-// sum_e theta_e = arg(zr + i zi) + 2 pi k.  Multiplying by a factor whose
-// angle lies in (-pi, pi] can carry the argument across the negative real
-// axis; that happens exactly when the old product and the factor lie in the
-// same closed half plane (by sign bit) and the new product in the other one.
-// Using sign bits makes a signed-zero N select its branch the same way
-// atan2 does.
+// sum_e theta_e = arg(zr + i zi) + 2 pi k.  The product is kept in float64
+// (its magnitude changes by the factors' magnitudes; float64 range allows
+// rescaling only every few edges).  Multiplying by a factor whose angle lies
+// in (-pi, pi] carries the argument across the negative real axis exactly
+// when the old product and the factor lie in the same closed half plane (by
+// sign bit) and the new product in the other one; the sign bits make the
+// count agree with atan2's branch.  The tie offset keeps N nonzero, so the
+// product starts from 1 without losing the sign of a zero.
 struct Turns {
-  float zr, zi;
+  double zr, zi;
   int k;
 };
 
-__device__ __forceinline__ void turns_init(Turns& t, float D, float N) {
-  t.zr = D;
-  t.zi = N;
+__device__ __forceinline__ void turns_init(Turns& t) {
+  t.zr = 1.0;
+  t.zi = 0.0;
   t.k = 0;
 }
 
-__device__ __forceinline__ void turns_mul(Turns& t, float D, float N) {
-  const float nr = __fmaf_rn(t.zr, D, -__fmul_rn(t.zi, N));
-  const float ni = __fmaf_rn(t.zr, N, __fmul_rn(t.zi, D));
-  const int A = __float_as_int(t.zi);
-  const int B = __float_as_int(N);
-  const int C = __float_as_int(ni);
+__device__ __forceinline__ int hi_word(double x) {
+  return (int)(__double_as_longlong(x) >> 32);
+}
+
+__device__ __forceinline__ void turns_mul(Turns& t, double D, double N) {
+  const double nr = __fma_rn(t.zr, D, -__dmul_rn(t.zi, N));
+  const double ni = __fma_rn(t.zr, N, __dmul_rn(t.zi, D));
+  const int A = hi_word(t.zi);
+  const int B = hi_word(N);
+  const int C = hi_word(ni);
   const int up = (~A & ~B & C) >> 31;   // -1: turned forward past pi
   const int dn = (A & B & ~C) >> 31;    // -1: turned backward past -pi
   t.k += dn - up;
@@ -131,19 +149,18 @@ __device__ __forceinline__ void turns_mul(Turns& t, float D, float N) {
 
 // Rescale by a power of two (exact; keeps signs and zeros).
 __device__ __forceinline__ void turns_norm(Turns& t) {
-  const float m = fmaxf(fabsf(t.zr), fabsf(t.zi));
-  const int e = __builtin_amdgcn_frexp_expf(m);
-  t.zr = __builtin_amdgcn_ldexpf(t.zr, -e);
-  t.zi = __builtin_amdgcn_ldexpf(t.zi, -e);
+  const int e = max(__builtin_amdgcn_frexp_exp(t.zr), __builtin_amdgcn_frexp_exp(t.zi));
+  t.zr = __builtin_amdgcn_ldexp(t.zr, -e);
+  t.zi = __builtin_amdgcn_ldexp(t.zi, -e);
 }
 
 // Combine two partial products (edge chunks of one query).
 __device__ __forceinline__ void turns_join(Turns& t, const Turns& o) {
-  const float nr = __fmaf_rn(t.zr, o.zr, -__fmul_rn(t.zi, o.zi));
-  const float ni = __fmaf_rn(t.zr, o.zi, __fmul_rn(t.zi, o.zr));
-  const int A = __float_as_int(t.zi);
-  const int B = __float_as_int(o.zi);
-  const int C = __float_as_int(ni);
+  const double nr = __fma_rn(t.zr, o.zr, -__dmul_rn(t.zi, o.zi));
+  const double ni = __fma_rn(t.zr, o.zi, __dmul_rn(t.zi, o.zr));
+  const int A = hi_word(t.zi);
+  const int B = hi_word(o.zi);
+  const int C = hi_word(ni);
   const int up = (~A & ~B & C) >> 31;
   const int dn = (A & B & ~C) >> 31;
   t.k += o.k + dn - up;
@@ -155,7 +172,7 @@ constexpr float kInv2Pi = 0.15915494309189535f;
 
 // w = chi + k + atan2(zi, zr) / (2 pi).
 __device__ __forceinline__ float turns_to_w(const Turns& t, int chi) {
-  return (float)(chi + t.k) + atan2f(t.zi, t.zr) * kInv2Pi;
+  return (float)(chi + t.k) + (float)atan2(t.zi, t.zr) * kInv2Pi;
 }
 
 }  // namespace wn

@@ -74,7 +74,8 @@ hipError_t launch_cross3d(const CrossArgs& a, hipStream_t s);
 hipError_t launch_adj3d(const AdjArgs& a, const LoopTable& L, int64_t nblocks, hipStream_t s);
 int64_t adj3d_blocks(int64_t nq);
 int64_t adj3d_rows(int64_t nblocks);
+int64_t reduce_groups(int64_t rows);
 hipError_t launch_reduce_partials(const float* pv, const float* pl, int64_t rows, int32_t nb,
-                                  const LoopTable& L, float* out, hipStream_t s);
+                                  const LoopTable& L, double* tmp, float* out, hipStream_t s);
 
 }  // namespace wn

@@ -46,6 +46,33 @@ def test_small_meshes_match_oracle(name, dseed):
     compare_3d(dm, P, w, chi)
 
 
+def _union(meshes, offsets):
+    Vs, Fs, n = [], [], 0
+    for M, o in zip(meshes, offsets):
+        Vs.append(M.V + np.asarray(o, np.float32))
+        Fs.append(M.F + n)
+        n += len(M.V)
+    return synth.Mesh(np.concatenate(Vs), np.concatenate(Fs).astype(np.int32))
+
+
+def test_many_loops_across_lds_chunks():
+    # five disjoint patches: 5 boundary loops of 200-260 edges, so loops
+    # straddle the 512-vertex LDS chunks of the boundary kernel
+    parts = [synth.coons_surface(40 + k, 1500, 200 + 16 * k) for k in range(5)]
+    M = _union(parts, [(1.3 * k, 0.2 * k, 0.0) for k in range(5)])
+    dm = DevMesh(M, synth.random_direction(23))
+    assert len(dm.loop_off) == 6 and dm.loop_off[-1] > 1024
+    P = _rand_queries(M, 2000, 24)
+    w, chi = dm.eval(P)
+    compare_3d(dm, P, w, chi)
+    # and the union equals the sum of the parts (Sec. 6: union = sum of w)
+    tot = np.zeros(len(P))
+    for Mk, o in zip(parts, [(1.3 * k, 0.2 * k, 0.0) for k in range(5)]):
+        Mk = synth.Mesh(Mk.V + np.asarray(o, np.float32), Mk.F)
+        tot += DevMesh(Mk, synth.random_direction(23)).eval(P)[0]
+    assert np.abs(tot - w).max() <= 5 * W_TOL
+
+
 def test_closed_mesh_inside_outside():
     M = synth.icosphere(3)
     dm = DevMesh(M, synth.random_direction(5))
