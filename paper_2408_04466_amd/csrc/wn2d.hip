@@ -1,7 +1,365 @@
-// 2D cubic Bezier loops (placeholder until the kernels land).
+// Winding numbers of loops of cubic Bezier curves (2D), ray direction +x.
+//
+// Sec. 3 defines w_C(p) = (1/2pi) int_C dtheta(p).  With one ray direction
+// d = +x for every query (the seed region of Alg. 1 is the one containing
+// d), w = chi(p) + (1/2pi) sum over open loops [phi(end - p) - phi(start - p)]
+// where chi is the signed number of crossings of the ray p + t (1, 0), t > 0,
+// with the curves (Eq. chi) and phi measures the angle of a vector
+// counter-clockwise from +x in [0, 2pi).  A point on the ray's line counts as
+// lying above it (y >= p_y), on the same side that phi in [0, 2pi) puts it.
+//
+// Steps:
+//  * k_pieces: split every cubic at the roots of y'(t) into at most three
+//    y-monotone pieces (the subdivision the paper performs per ray).
+//  * points mode: one lane per query walks the pieces (staged in LDS): a
+//    piece is crossed iff its end ordinates lie on different sides; the
+//    crossing counts if it lies right of p, decided by the piece's x bounds
+//    or, when p_x falls inside them, by solving y(t) = p_y on the piece
+//    (safeguarded Newton) and comparing x(t*).
+//  * grid mode: the paper's one-shot reuse (Sec. 4 "Optimization"; Sec. 6,
+//    2D results): one workgroup per (row, column tile) solves each piece that
+//    crosses the row once, bins the crossing by the number of grid columns
+//    left of it (an LDS histogram of integer counts), and a suffix scan gives
+//    chi for every column of the row.
+// Both modes decide "crossing right of p" as p_x < clamp(x*, xmin, xmax) with
+// the same solver, so they agree bit for bit.
+#include <cmath>
+
 #include "kernels.hpp"
 
-extern "C" wn_status wn_eval_2d(wn_dtype, const void*, int64_t, const int64_t*, const uint8_t*, int32_t,
-                                int32_t, const void*, const void*, int64_t, int64_t, void*, int32_t*, void*) {
-  return WN_ERR_UNSUPPORTED;
+namespace wn {
+
+namespace {
+
+template <class T>
+struct Piece {
+  T cx[4];        // x(t) = ((cx3 t + cx2) t + cx1) t + cx0   (segment power basis)
+  T cy[4];        // y(t) likewise
+  T t0, t1;       // parameter range of the monotone piece
+  T y0, y1;       // y(t0), y(t1) (exact control values at segment ends)
+  T xmin, xmax;   // x bounds of the segment's control polygon
+};
+
+struct Loops2D {
+  int32_t n;
+  int32_t off[WN_MAX_LOOPS + 1];
+  uint8_t closed[WN_MAX_LOOPS];
+};
+
+template <class T> __device__ __forceinline__ T fma_t(T a, T b, T c);
+template <> __device__ __forceinline__ float fma_t<float>(float a, float b, float c) { return __fmaf_rn(a, b, c); }
+template <> __device__ __forceinline__ double fma_t<double>(double a, double b, double c) { return __fma_rn(a, b, c); }
+
+template <class T>
+__device__ __forceinline__ T horner(const T c[4], T t) {
+  return fma_t(fma_t(fma_t(c[3], t, c[2]), t, c[1]), t, c[0]);
 }
+template <class T>
+__device__ __forceinline__ T horner_d(const T c[4], T t) {
+  return fma_t(fma_t((T)3 * c[3], t, (T)2 * c[2]), t, c[1]);
+}
+
+template <class T>
+__device__ __forceinline__ void power_basis(T p0, T p1, T p2, T p3, T c[4]) {
+  c[0] = p0;
+  c[1] = (T)3 * (p1 - p0);
+  c[2] = (T)3 * (p0 - (T)2 * p1 + p2);
+  c[3] = (p3 - p0) + (T)3 * (p1 - p2);
+}
+
+template <class T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+
+// Split segment s into three pieces (empty pieces have t0 == t1, y0 == y1);
+// yr gets the end ordinates of every piece for the straddle tests.
+template <class T>
+__global__ void k_pieces(const T* __restrict__ ctrl, int32_t nseg, Piece<T>* __restrict__ out,
+                         typename Vec2<T>::type* __restrict__ yr) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg) return;
+  const T* P = ctrl + 8 * (int64_t)s;
+  T cx[4], cy[4];
+  power_basis(P[0], P[2], P[4], P[6], cx);
+  power_basis(P[1], P[3], P[5], P[7], cy);
+  // roots of y'(t) = 3 c3 t^2 + 2 c2 t + c1 in (0, 1)
+  const T a = (T)3 * cy[3], b = (T)2 * cy[2], c = cy[1];
+  T r[2];
+  int nr = 0;
+  if (a != (T)0) {
+    const T disc = b * b - (T)4 * a * c;
+    if (disc > (T)0) {
+      const T sq = sqrt(disc);
+      // numerically stable pair
+      const T q = (b >= (T)0) ? -(T)0.5 * (b + sq) : -(T)0.5 * (b - sq);
+      T u = q / a, v = (q != (T)0) ? c / q : u;
+      if (u > v) { const T w = u; u = v; v = w; }
+      if (u > (T)0 && u < (T)1) r[nr++] = u;
+      if (v > (T)0 && v < (T)1 && v != u) r[nr++] = v;
+    }
+  } else if (b != (T)0) {
+    const T u = -c / b;
+    if (u > (T)0 && u < (T)1) r[nr++] = u;
+  }
+  T ts[4];
+  T ys[4];
+  int m = 0;
+  ts[m] = (T)0; ys[m++] = P[1];
+  for (int k = 0; k < nr; ++k) { ts[m] = r[k]; ys[m++] = horner(cy, r[k]); }
+  ts[m] = (T)1; ys[m++] = P[7];
+  const T xmin = fmin(fmin(P[0], P[2]), fmin(P[4], P[6]));
+  const T xmax = fmax(fmax(P[0], P[2]), fmax(P[4], P[6]));
+  for (int k = 0; k < 3; ++k) {
+    Piece<T> pc;
+    for (int i = 0; i < 4; ++i) { pc.cx[i] = cx[i]; pc.cy[i] = cy[i]; }
+    if (k + 1 < m) {
+      pc.t0 = ts[k]; pc.t1 = ts[k + 1]; pc.y0 = ys[k]; pc.y1 = ys[k + 1];
+    } else {
+      pc.t0 = pc.t1 = (T)1; pc.y0 = pc.y1 = P[7];
+    }
+    pc.xmin = xmin;
+    pc.xmax = xmax;
+    out[3 * (int64_t)s + k] = pc;
+    yr[3 * (int64_t)s + k] = {pc.y0, pc.y1};
+  }
+}
+
+// x(t*) for the t* in [t0, t1] with y(t*) = yq on a monotone piece whose end
+// ordinates straddle yq (y >= yq counts as above).  Safeguarded Newton: the
+// bracket [lo, hi] keeps lo below and hi above; a Newton step that leaves it
+// is replaced by bisection.
+template <class T>
+__device__ T solve_x(const Piece<T>& pc, T yq) {
+  const bool up = pc.y1 >= yq;      // piece goes from below (at t0) to above (at t1)
+  T lo = up ? pc.t0 : pc.t1;        // parameter where y is below yq
+  T hi = up ? pc.t1 : pc.t0;        // parameter where y is above (or on) yq
+  // regula falsi start between the end ordinates
+  T t = pc.t0 + (pc.t1 - pc.t0) * ((yq - pc.y0) / (pc.y1 - pc.y0));
+  if (!(t >= fmin(lo, hi) && t <= fmax(lo, hi))) t = (T)0.5 * (lo + hi);
+  const int maxit = sizeof(T) == 4 ? 40 : 80;
+  for (int it = 0; it < maxit; ++it) {
+    const T f = horner(pc.cy, t) - yq;
+    if (f >= (T)0) hi = t; else lo = t;
+    const T fp = horner_d(pc.cy, t);
+    T tn = (fp != (T)0) ? t - f / fp : (T)0.5 * (lo + hi);
+    const T a = fmin(lo, hi), b = fmax(lo, hi);
+    if (!(tn > a && tn < b)) tn = (T)0.5 * (lo + hi);
+    if (tn == t || b - a <= (T)4 * (sizeof(T) == 4 ? (T)1.2e-7 : (T)2.3e-16) * fmax((T)1, fabs(b))) {
+      t = tn;
+      break;
+    }
+    t = tn;
+  }
+  return horner(pc.cx, t);
+}
+
+// The crossing of piece pc with the row yq lies right of px.
+template <class T>
+__device__ __forceinline__ bool right_of(const Piece<T>& pc, T yq, T px) {
+  if (px < pc.xmin) return true;
+  if (px >= pc.xmax) return false;
+  return solve_x(pc, yq) > px;
+}
+
+template <class T> __device__ __forceinline__ T atan2_t(T y, T x);
+template <> __device__ __forceinline__ float atan2_t<float>(float y, float x) { return atan2f(y, x); }
+template <> __device__ __forceinline__ double atan2_t<double>(double y, double x) { return atan2(y, x); }
+
+// angle of v counter-clockwise from +x, in [0, 2pi); an exact +0 ordinate
+// counts as above
+template <class T>
+__device__ __forceinline__ T phi(T vx, T vy) {
+  const T a = atan2_t(vy, vx);
+  return a < (T)0 ? a + (T)6.283185307179586 : a;
+}
+
+// sum over open loops of phi(end - p) - phi(start - p)
+template <class T>
+__device__ T endpoint_term(const T* __restrict__ ctrl, const Loops2D& L, T px, T py) {
+  T e = (T)0;
+  for (int l = 0; l < L.n; ++l) {
+    if (L.closed[l] || L.off[l + 1] <= L.off[l]) continue;
+    const T* s = ctrl + 8 * (int64_t)L.off[l];
+    const T* f = ctrl + 8 * (int64_t)(L.off[l + 1] - 1);
+    e += phi(f[6] - px, f[7] - py) - phi(s[0] - px, s[1] - py);
+  }
+  return e;
+}
+
+constexpr int kThreads = 256;
+constexpr int kPieceChunk = 256;
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_points(const Piece<T>* __restrict__ pcs, int32_t npc,
+                                                     const T* __restrict__ ctrl, Loops2D L,
+                                                     const T* __restrict__ x, const T* __restrict__ y,
+                                                     int64_t n, T* __restrict__ w, int32_t* __restrict__ chi) {
+  __shared__ Piece<T> sp[kPieceChunk];
+  const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const bool ok = q < n;
+  const T px = ok ? x[q] : (T)0, py = ok ? y[q] : (T)0;
+  int c = 0;
+  for (int p0 = 0; p0 < npc; p0 += kPieceChunk) {
+    const int cnt = min(kPieceChunk, npc - p0);
+    __syncthreads();
+    for (int j = threadIdx.x; j < cnt; j += kThreads) sp[j] = pcs[p0 + j];
+    __syncthreads();
+    for (int j = 0; j < cnt; ++j) {
+      const T y0 = sp[j].y0, y1 = sp[j].y1;
+      const bool s0 = y0 >= py, s1 = y1 >= py;
+      if (s0 == s1) continue;
+      if (right_of(sp[j], py, px)) c += s1 ? 1 : -1;
+    }
+  }
+  if (!ok) return;
+  if (!(isfinite(px) && isfinite(py))) {
+    w[q] = (T)NAN;
+    if (chi) chi[q] = WN_CHI_INVALID;
+    return;
+  }
+  const T e = endpoint_term(ctrl, L, px, py);
+  w[q] = (T)c + e * (T)0.15915494309189535;
+  if (chi) chi[q] = c;
+}
+
+constexpr int kColTile = 4096;
+
+// One workgroup per (row, column tile).  Histogram slot c (0..ncol) counts the
+// crossings with exactly c tile columns left of them; columns at or beyond
+// the tile end get every crossing right of the whole tile through `base`.
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_grid(const Piece<T>* __restrict__ pcs,
+                                                   const typename Vec2<T>::type* __restrict__ yr, int32_t npc,
+                                                   const T* __restrict__ ctrl, Loops2D L,
+                                                   const T* __restrict__ x, int64_t nx,
+                                                   const T* __restrict__ y, int64_t ny,
+                                                   T* __restrict__ w, int32_t* __restrict__ chi) {
+  __shared__ T sx[kColTile];
+  __shared__ int hist[kColTile + 1];
+  __shared__ int sscan[kThreads];
+  const int64_t row = blockIdx.y;
+  const int64_t i0 = (int64_t)blockIdx.x * kColTile;
+  const int ncol = (int)min((int64_t)kColTile, nx - i0);
+  const T yq = y[row];
+  for (int i = threadIdx.x; i < ncol; i += kThreads) sx[i] = x[i0 + i];
+  for (int i = threadIdx.x; i <= ncol; i += kThreads) hist[i] = 0;
+  __syncthreads();
+  const T xlo = sx[0], xhi = sx[ncol - 1];
+  int base = 0;   // crossings right of every column of the tile
+  for (int j = threadIdx.x; j < npc; j += kThreads) {
+    const typename Vec2<T>::type e = yr[j];
+    const bool s0 = e.x >= yq, s1 = e.y >= yq;
+    if (s0 == s1) continue;
+    const int sg = s1 ? 1 : -1;
+    const Piece<T>& pc = pcs[j];
+    int cpos;
+    if (xhi < pc.xmin) {
+      cpos = ncol;                       // right of every column
+    } else if (xlo >= pc.xmax) {
+      cpos = 0;                          // right of none
+    } else {
+      const T xs = solve_x(pc, yq);
+      const T xe = fmin(fmax(xs, pc.xmin), pc.xmax);
+      // number of tile columns with x_i < xe (x ascending)
+      int a = 0, b = ncol;
+      while (a < b) {
+        const int mid = (a + b) >> 1;
+        if (sx[mid] < xe) a = mid + 1; else b = mid;
+      }
+      cpos = a;
+    }
+    if (cpos == ncol) base += sg;
+    else if (cpos > 0) atomicAdd(&hist[cpos], sg);
+  }
+  // block-wide sum of `base`
+  sscan[threadIdx.x] = base;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sscan[threadIdx.x] += sscan[threadIdx.x + s];
+    __syncthreads();
+  }
+  const int btot = sscan[0];
+  __syncthreads();
+  // chi(col i) = btot + sum_{c > i} hist[c]: suffix sums over [1, ncol),
+  // each thread owning a contiguous block of columns
+  const int per = (ncol + kThreads - 1) / kThreads;
+  const int a0 = threadIdx.x * per;
+  const int a1 = min(a0 + per, ncol);
+  int part = 0;
+  for (int c = a0 + 1; c <= a1 && c < ncol; ++c) part += hist[c];
+  sscan[threadIdx.x] = part;
+  __syncthreads();
+  // exclusive suffix offsets: sum of parts of later threads
+  for (int s = 1; s < kThreads; s <<= 1) {
+    const int v = ((int)threadIdx.x + s < kThreads) ? sscan[threadIdx.x + s] : 0;
+    __syncthreads();
+    sscan[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = btot + (((int)threadIdx.x + 1 < kThreads) ? sscan[threadIdx.x + 1] : 0);
+  // walk this thread's columns from the right
+  for (int i = a1 - 1; i >= a0; --i) {
+    if (i + 1 < ncol) run += hist[i + 1];
+    const int64_t o = row * nx + i0 + i;
+    const T px = sx[i];
+    if (!(isfinite(px) && isfinite(yq))) {
+      w[o] = (T)NAN;
+      if (chi) chi[o] = WN_CHI_INVALID;
+      continue;
+    }
+    const T e = endpoint_term(ctrl, L, px, yq);
+    w[o] = (T)run + e * (T)0.15915494309189535;
+    if (chi) chi[o] = run;
+  }
+}
+
+template <class T>
+hipError_t run2d(const T* ctrl, int64_t nseg, const Loops2D& L, int32_t kind, const T* x, const T* y,
+                 int64_t nx, int64_t ny, T* w, int32_t* chi, hipStream_t s) {
+  using V2 = typename Vec2<T>::type;
+  const int64_t npc = 3 * nseg;
+  Piece<T>* pcs = nullptr;
+  V2* yr = nullptr;
+  hipError_t e = hipSuccess;
+  if (npc > 0) {
+    e = hipMallocAsync((void**)&pcs, (size_t)npc * (sizeof(Piece<T>) + sizeof(V2)), s);
+    if (e != hipSuccess) return e;
+    yr = reinterpret_cast<V2*>(pcs + npc);
+    hipLaunchKernelGGL(k_pieces<T>, dim3((unsigned)((nseg + 127) / 128)), dim3(128), 0, s, ctrl,
+                       (int32_t)nseg, pcs, yr);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    if (kind == 0) {
+      hipLaunchKernelGGL(k_points<T>, dim3((unsigned)((nx + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                         pcs, (int32_t)npc, ctrl, L, x, y, nx, w, chi);
+    } else {
+      hipLaunchKernelGGL(k_grid<T>, dim3((unsigned)((nx + kColTile - 1) / kColTile), (unsigned)ny), dim3(kThreads),
+                         0, s, pcs, yr, (int32_t)npc, ctrl, L, x, nx, y, ny, w, chi);
+    }
+    e = hipGetLastError();
+  }
+  if (pcs) {
+    const hipError_t e2 = hipFreeAsync(pcs, s);
+    if (e == hipSuccess) e = e2;
+  }
+  return e;
+}
+
+}  // namespace
+
+hipError_t eval_2d(int32_t dtype, const void* ctrl, int64_t nseg, const int64_t* loop_off,
+                   const uint8_t* closed, int32_t nloops, int32_t kind, const void* x, const void* y,
+                   int64_t nx, int64_t ny, void* w, int32_t* chi, hipStream_t s) {
+  Loops2D L;
+  L.n = nloops;
+  for (int l = 0; l <= nloops; ++l) L.off[l] = (int32_t)loop_off[l];
+  for (int l = 0; l < nloops; ++l) L.closed[l] = closed[l] ? 1 : 0;
+  if (dtype == WN_F64)
+    return run2d<double>((const double*)ctrl, nseg, L, kind, (const double*)x, (const double*)y, nx, ny,
+                         (double*)w, chi, s);
+  return run2d<float>((const float*)ctrl, nseg, L, kind, (const float*)x, (const float*)y, nx, ny, (float*)w,
+                      chi, s);
+}
+
+}  // namespace wn

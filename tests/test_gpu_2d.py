@@ -1,0 +1,135 @@
+"""GPU parity of the 2D path (cubic Bezier loops, ray +x) against the FP64
+oracle: chi bit-exact on non-degenerate queries; w within 1e-10 (float64
+inputs) or 1e-4 (float32) away from open-curve end points; grid mode (one ray
+per row, Sec. 4 "Optimization") equal bit for bit to points mode."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import wn2d as O2
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    import paper_2408_04466_amd as W
+
+
+def _dev(C, dtype):
+    t = torch.float64 if dtype == np.float64 else torch.float32
+    return torch.from_numpy(np.ascontiguousarray(C.ctrl.astype(dtype))).cuda(), t
+
+
+def _eval(C, xs, ys, dtype, grid):
+    ctrl, t = _dev(C, dtype)
+    x = torch.from_numpy(np.ascontiguousarray(xs.astype(dtype))).cuda()
+    y = torch.from_numpy(np.ascontiguousarray(ys.astype(dtype))).cuda()
+    w, chi = W.eval_2d(ctrl, C.loop_off, C.closed, x, y, grid=grid)
+    torch.cuda.synchronize()
+    return w.cpu().numpy(), chi.cpu().numpy()
+
+
+def _endpoint_dist(C, P):
+    d = np.full(len(P), np.inf)
+    for l in range(len(C.closed)):
+        if C.closed[l]:
+            continue
+        for pt in (C.ctrl[C.loop_off[l], 0], C.ctrl[C.loop_off[l + 1] - 1, 3]):
+            d = np.minimum(d, np.linalg.norm(P - pt.astype(np.float64), axis=1))
+    return d
+
+
+def _check(C, P, w, chi, tol):
+    P = np.asarray(P, np.float64)
+    r = O2.wn2d(C.ctrl.astype(np.float64), C.loop_off, C.closed, P)
+    ok = ~r.degenerate
+    assert ok.mean() > 0.95
+    bad = np.nonzero(chi[ok] != r["chi"][ok])[0]
+    assert bad.size == 0, f"chi mismatch at {P[ok][bad][:5]}: {chi[ok][bad][:5]} vs {r['chi'][ok][bad][:5]}"
+    far = ok & (_endpoint_dist(C, P) > 1e-5)
+    err = np.abs(w - r["w"])[far]
+    assert err.max() <= tol, err.max()
+    return int((~ok).sum())
+
+
+def test_star_fp64_grid_and_points():
+    """One closed curve of 16 cubics (star, radii U[0.5, 1]); 128 x 128 grid
+    over [-1.5, 1.5]^2; float64."""
+    C = synth.star2d()
+    xs = synth.grid_axis(-1.5, 1.5, 128)
+    wg, cg = _eval(C, xs, xs, np.float64, grid=True)
+    X, Y = np.meshgrid(xs, xs)
+    P = np.stack([X.ravel(), Y.ravel()], 1)
+    wp, cp = _eval(C, P[:, 0], P[:, 1], np.float64, grid=False)
+    assert np.array_equal(wg.ravel(), wp) and np.array_equal(cg.ravel(), cp)
+    _check(C, P, wp, cp, 1e-10)
+    assert set(np.unique(wp)) <= {0.0, 1.0}
+
+
+@pytest.fixture(scope="module")
+def c2():
+    """16 loops x 64 cubics (12 closed, 4 open with gaps 0.01-0.05), control
+    points in [-1, 1]^2; 2048 x 2048 grid over [-1.2, 1.2]^2; float32."""
+    C = synth.loops2d()
+    xs = synth.grid_axis(-1.2, 1.2, 2048, np.float32)
+    w, chi = _eval(C, xs, xs, np.float32, grid=True)
+    return C, xs, w, chi
+
+
+def test_c2_full_rows(c2):
+    C, xs, w, chi = c2
+    assert w.shape == (2048, 2048)
+    for r in (0, 517, 1024, 2047):
+        P = np.stack([xs.astype(np.float64), np.full(2048, float(xs[r]))], 1)
+        _check(C, P, w[r], chi[r], 1e-4)
+
+
+def test_c2_random_points_and_points_mode(c2):
+    C, xs, w, chi = c2
+    g = synth.rng(4)
+    ii = g.integers(0, 2048, 3000)
+    jj = g.integers(0, 2048, 3000)
+    P = np.stack([xs[jj].astype(np.float64), xs[ii].astype(np.float64)], 1)
+    _check(C, P, w[ii, jj], chi[ii, jj], 1e-4)
+    wp, cp = _eval(C, xs[jj], xs[ii], np.float32, grid=False)
+    assert np.array_equal(wp, w[ii, jj]) and np.array_equal(cp, chi[ii, jj])
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-10), (np.float32, 1e-4)])
+def test_rows_through_end_points(dtype, tol):
+    # the paper's 2D setup (Sec. 6): random cubics with control points in the
+    # unit square, a regular grid in each curve's bounding box; the first and
+    # last rows and columns pass exactly through extremes and end points
+    g = synth.rng(5)
+    for _ in range(6):
+        c = g.uniform(0.0, 1.0, (1, 4, 2)).astype(dtype)
+        C = synth.Curves2D(c, np.array([0, 1], np.int64), np.array([0], np.uint8))
+        lo, hi = c[0].min(0), c[0].max(0)
+        xs = np.linspace(lo[0], hi[0], 64).astype(dtype)
+        ys = np.linspace(lo[1], hi[1], 64).astype(dtype)
+        w, chi = _eval(C, xs, ys, dtype, grid=True)
+        X, Y = np.meshgrid(xs, ys)
+        P = np.stack([X.ravel(), Y.ravel()], 1).astype(np.float64)
+        _check(C, P, w.ravel(), chi.ravel(), tol)
+        wp, cp = _eval(C, P[:, 0], P[:, 1], dtype, grid=False)
+        assert np.array_equal(wp, w.ravel()) and np.array_equal(cp, chi.ravel())
+
+
+def test_2d_edge_cases():
+    C = synth.loops2d(9, n_loops=3, seg_per_loop=5, n_open=2, dtype=np.float64)
+    e = np.zeros(0)
+    w, chi = _eval(C, e, e, np.float64, grid=False)
+    assert w.size == 0
+    w, chi = _eval(C, np.zeros(5), e, np.float64, grid=True)
+    assert w.size == 0
+    # straight segments and a horizontal one
+    a, b = np.array([0.1, 0.2]), np.array([0.9, 0.7])
+    seg = np.stack([a, a + (b - a) / 3, a + 2 * (b - a) / 3, b])
+    hor = np.array([[0.0, 0.5], [0.3, 0.5], [0.6, 0.5], [1.0, 0.5]])
+    Cs = synth.Curves2D(np.stack([seg, hor]), np.array([0, 1, 2], np.int64), np.array([0, 0], np.uint8))
+    P = synth.rng(6).uniform(-0.2, 1.2, (500, 2))
+    w, chi = _eval(Cs, P[:, 0], P[:, 1], np.float64, grid=False)
+    _check(Cs, P, w, chi, 1e-10)
+    # non-finite queries
+    w, chi = _eval(C, np.array([np.nan, 0.1]), np.array([0.0, 0.2]), np.float64, grid=False)
+    assert np.isnan(w[0]) and chi[0] == W.WN_CHI_INVALID and np.isfinite(w[1])
