@@ -215,6 +215,70 @@ wn_status wn_eval_2d(wn_dtype dtype, const void* ctrl, int64_t nseg,
                      int32_t kind, const void* x, const void* y, int64_t nx, int64_t ny,
                      void* w_out, int32_t* chi_out, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched evaluation: many surfaces of uneven size, each with its own query
+ * set, evaluated in one persistent launch replayed from a hipGraph.
+ *
+ * One surface of a batch.  V, F, bnd_xyz are device pointers as in
+ * wn_build_bvh / wn_eval_3d (bnd_xyz bit-identical copies of boundary
+ * vertices of V); loop_off is a host array [nloops + 1]; nq is the number of
+ * this surface's queries.  The batch copies what it needs at creation.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  const float* V;
+  int64_t nv;
+  const int32_t* F;
+  int64_t nf;
+  const float* bnd_xyz;
+  const int64_t* loop_off;
+  int32_t nloops;
+  int64_t nq;
+} wn_surface;
+
+/* ---------------------------------------------------------------------------
+ * wn_batch_create -- build the BVH of every surface (one shared ray direction
+ * `dir`), a descriptor table, the boundary arena and a work list of
+ * (surface, query tile) items in longest-processing-time-first order.
+ *  tune_mode  0: default tile (1024 queries) and 4 workgroups per compute
+ *             unit; 1: quick autotune, 2: full autotune of (tile, workgroups
+ *             per CU), run on the first wn_eval_batched with its real inputs;
+ *             results are cached in the JSON file named by $WN_TUNE_CACHE.
+ * Synchronises `stream`.  Errors: INVALID_ARGUMENT (naming the surface),
+ * UNSUPPORTED, OUT_OF_MEMORY, HIP.
+ * ------------------------------------------------------------------------- */
+wn_status wn_batch_create(const wn_surface* surfs, int32_t ns, const double dir[3],
+                          int32_t tune_mode, void* stream, wn_batch** out);
+
+/* Release a batch (the caller synchronises first). */
+wn_status wn_batch_free(wn_batch* batch);
+
+/* ---------------------------------------------------------------------------
+ * wn_eval_batched -- w (and chi) for every query of every surface.
+ *  qx, qy, qz  device [sum nq] float32, the surfaces' queries concatenated in
+ *              surface order.
+ *  w_out       device [sum nq] float32 out; chi_out device int32 or NULL.
+ * The first call captures a counter-reset kernel and the persistent kernel
+ * into a hipGraph (after autotuning when requested); later calls replay it,
+ * patching the kernel arguments when the pointers change.  Set
+ * $WN_FORCE_NO_GRAPH to launch directly (identical results).
+ * ------------------------------------------------------------------------- */
+wn_status wn_eval_batched(wn_batch* batch, const float* qx, const float* qy, const float* qz,
+                          float* w_out, int32_t* chi_out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * wn_backward_batched -- adjoint of the batch for dL/dw = grad_w (device
+ * [sum nq]): grad_q device [sum nq][3] or NULL; grad_bnd device
+ * [sum nb][3] or NULL, the surfaces' boundary vertices concatenated in
+ * surface order.  Fixed-order float64 reduction (bitwise reproducible).
+ * ------------------------------------------------------------------------- */
+wn_status wn_backward_batched(wn_batch* batch, const float* qx, const float* qy, const float* qz,
+                              const float* grad_w, float* grad_q, float* grad_bnd, void* stream);
+
+/* info[0..7] = total queries, total boundary vertices, total (query, edge)
+ * pairs, forward work items, tile size, workgroups per CU, graph in use
+ * (0/1), autotuning time in microseconds. */
+wn_status wn_batch_info(const wn_batch* batch, int64_t info[8]);
+
 #ifdef __cplusplus
 }
 #endif

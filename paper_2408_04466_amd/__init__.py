@@ -6,6 +6,7 @@ All computation runs in the library's HIP kernels.
 """
 from .api import (  # noqa: F401
     BVH,
+    Batch,
     WindingNumber3D,
     backward,
     boundary_loops,

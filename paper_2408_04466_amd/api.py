@@ -10,7 +10,7 @@ import torch
 from ._lib import check, lib, WN_MAX_LOOPS
 
 __all__ = ["boundary_loops", "BVH", "eval_3d", "eval_3d_boundary", "crossings_3d",
-           "backward", "WindingNumber3D", "winding_number", "eval_2d"]
+           "backward", "WindingNumber3D", "winding_number", "eval_2d", "Batch"]
 
 
 def _stream(stream=None):
@@ -230,3 +230,87 @@ def eval_2d(ctrl: torch.Tensor, loop_off, loop_closed, x: torch.Tensor, y: torch
                            _dev(w, dt, "w"), _dev(chi, torch.int32, "chi") if chi is not None else None,
                            _stream(stream)), "wn_eval_2d")
     return w, chi
+
+
+class Batch:
+    """Many surfaces, each with its own queries, in one persistent launch
+    (``wn_batch_create`` / ``wn_eval_batched`` / ``wn_backward_batched``).
+
+    ``surfaces`` is a list of dicts with device tensors ``V`` [nv, 3]
+    float32, ``F`` [nf, 3] int32, ``bnd`` [nb, 3] float32 (copies of
+    boundary vertices), host ``loop_off`` and the query count ``nq``.
+    Queries are passed concatenated in surface order."""
+
+    def __init__(self, surfaces, direction, tune_mode: int = 0, stream=None):
+        from ._lib import Surface
+        self._keep = []
+        arr = (Surface * max(len(surfaces), 1))()
+        nb_tot = 0
+        for i, s in enumerate(surfaces):
+            V, F, bnd = s["V"], s["F"], s["bnd"]
+            lo, nl = _loops(s["loop_off"])
+            nb = int(lo[-1]) if nl else 0
+            self._keep.append(lo)
+            arr[i].V = _dev(V, torch.float32, "V", (V.shape[0], 3))
+            arr[i].nv = V.shape[0]
+            arr[i].F = _dev(F, torch.int32, "F", (F.shape[0], 3))
+            arr[i].nf = F.shape[0]
+            arr[i].bnd_xyz = _dev(bnd, torch.float32, "bnd", (nb, 3))
+            arr[i].loop_off = _ptr64(lo)
+            arr[i].nloops = nl
+            arr[i].nq = int(s["nq"])
+            nb_tot += nb
+        d = (C.c_double * 3)(*[float(x) for x in np.asarray(direction, np.float64).ravel()[:3]])
+        h = C.c_void_p()
+        check(lib().wn_batch_create(arr, len(surfaces), d, int(tune_mode), _stream(stream), C.byref(h)),
+              "wn_batch_create")
+        self._h = h
+        self.total_q = sum(int(s["nq"]) for s in surfaces)
+        self.total_b = nb_tot
+
+    def info(self) -> dict:
+        v = (C.c_int64 * 8)()
+        check(lib().wn_batch_info(self._h, v), "wn_batch_info")
+        keys = ["total_q", "total_b", "total_pairs", "n_items", "tile", "wg_per_cu", "graph", "tune_us"]
+        return dict(zip(keys, v[:]))
+
+    def eval(self, qx, qy, qz, want_chi: bool = True, w_out=None, chi_out=None, stream=None):
+        nq = self.total_q
+        px = _dev(qx, torch.float32, "qx", (nq,))
+        py = _dev(qy, torch.float32, "qy", (nq,))
+        pz = _dev(qz, torch.float32, "qz", (nq,))
+        w = torch.empty(nq, dtype=torch.float32, device=qx.device) if w_out is None else w_out
+        chi = None
+        if want_chi:
+            chi = torch.empty(nq, dtype=torch.int32, device=qx.device) if chi_out is None else chi_out
+        check(lib().wn_eval_batched(self._h, px, py, pz, _dev(w, torch.float32, "w_out", (nq,)),
+                                    _dev(chi, torch.int32, "chi_out", (nq,)) if chi is not None else None,
+                                    _stream(stream)), "wn_eval_batched")
+        return w, chi
+
+    def backward(self, qx, qy, qz, grad_w, want_q: bool = True, want_bnd: bool = True, stream=None):
+        nq = self.total_q
+        dev = qx.device
+        gq = torch.empty((nq, 3), dtype=torch.float32, device=dev) if want_q else None
+        gb = torch.empty((self.total_b, 3), dtype=torch.float32, device=dev) if want_bnd else None
+        check(lib().wn_backward_batched(
+            self._h, _dev(qx, torch.float32, "qx", (nq,)), _dev(qy, torch.float32, "qy", (nq,)),
+            _dev(qz, torch.float32, "qz", (nq,)), _dev(grad_w, torch.float32, "grad_w", (nq,)),
+            _dev(gq, torch.float32, "grad_q") if gq is not None else None,
+            _dev(gb, torch.float32, "grad_bnd") if gb is not None else None, _stream(stream)),
+            "wn_backward_batched")
+        return gq, gb
+
+    def free(self):
+        if getattr(self, "_h", None) is not None:
+            torch.cuda.synchronize()
+            lib().wn_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) is not None:
+                lib().wn_batch_free(self._h)
+                self._h = None
+        except Exception:
+            pass

@@ -10,9 +10,11 @@
 #include <vector>
 
 #include "bvh_build.hpp"
+#include "host.hpp"
 #include "kernels.hpp"
 
-namespace {
+namespace wn {
+namespace host {
 
 thread_local std::string g_err;
 
@@ -30,37 +32,6 @@ wn_status hip_fail(hipError_t e, const char* what) {
   if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
     return fail(WN_ERR_OUT_OF_MEMORY, "%s: %s", what, hipGetErrorString(e));
   return fail(WN_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
-}
-
-#define WN_HIP(call, what)                       \
-  do {                                           \
-    hipError_t e_ = (call);                      \
-    if (e_ != hipSuccess) return hip_fail(e_, what); \
-  } while (0)
-
-inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
-
-// Unit direction and orthonormal frame (rows e1, e2, d; det +1) in float64.
-bool make_rotation(const double dir[3], double d[3], double R[9]) {
-  if (!dir) return false;
-  const double n = std::sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
-  if (!std::isfinite(n) || n == 0.0) return false;
-  for (int k = 0; k < 3; ++k) d[k] = dir[k] / n;
-  int m = 0;
-  for (int k = 1; k < 3; ++k)
-    if (std::fabs(d[k]) < std::fabs(d[m])) m = k;
-  double ax[3] = {0, 0, 0};
-  ax[m] = 1.0;
-  double e1[3] = {d[1] * ax[2] - d[2] * ax[1], d[2] * ax[0] - d[0] * ax[2], d[0] * ax[1] - d[1] * ax[0]};
-  const double l1 = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
-  for (int k = 0; k < 3; ++k) e1[k] /= l1;
-  const double e2[3] = {d[1] * e1[2] - d[2] * e1[1], d[2] * e1[0] - d[0] * e1[2], d[0] * e1[1] - d[1] * e1[0]};
-  for (int k = 0; k < 3; ++k) {
-    R[k] = e1[k];
-    R[3 + k] = e2[k];
-    R[6 + k] = d[k];
-  }
-  return true;
 }
 
 // Validate a host loop table and copy it into the kernel-argument form.
@@ -87,6 +58,40 @@ wn_status make_loops(const int64_t* loop_off, int32_t nloops, int32_t min_len, i
   for (int32_t l = 0; l <= nloops; ++l) L->off[l] = (int32_t)loop_off[l];
   *nb_out = loop_off[nloops];
   return WN_OK;
+}
+
+}  // namespace host
+}  // namespace wn
+
+using wn::host::fail;
+using wn::host::hip_fail;
+using wn::host::g_err;
+using wn::host::as_stream;
+using wn::host::make_loops;
+
+namespace {
+
+// Unit direction and orthonormal frame (rows e1, e2, d; det +1) in float64.
+bool make_rotation(const double dir[3], double d[3], double R[9]) {
+  if (!dir) return false;
+  const double n = std::sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+  if (!std::isfinite(n) || n == 0.0) return false;
+  for (int k = 0; k < 3; ++k) d[k] = dir[k] / n;
+  int m = 0;
+  for (int k = 1; k < 3; ++k)
+    if (std::fabs(d[k]) < std::fabs(d[m])) m = k;
+  double ax[3] = {0, 0, 0};
+  ax[m] = 1.0;
+  double e1[3] = {d[1] * ax[2] - d[2] * ax[1], d[2] * ax[0] - d[0] * ax[2], d[0] * ax[1] - d[1] * ax[0]};
+  const double l1 = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+  for (int k = 0; k < 3; ++k) e1[k] /= l1;
+  const double e2[3] = {d[1] * e1[2] - d[2] * e1[1], d[2] * e1[0] - d[0] * e1[2], d[0] * e1[1] - d[1] * e1[0]};
+  for (int k = 0; k < 3; ++k) {
+    R[k] = e1[k];
+    R[3 + k] = e2[k];
+    R[6 + k] = d[k];
+  }
+  return true;
 }
 
 }  // namespace
@@ -141,17 +146,6 @@ hipError_t dalloc(T** p, size_t n) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
-
-struct wn_bvh {
-  wn::Frame F;
-  double dir[3];
-  int32_t nv = 0, nf = 0;
-  double4* Vr = nullptr;
-  int4* tris = nullptr;
-  wn::BvhNode* nodes = nullptr;
-  float4* leafbox = nullptr;
-  float* leafz = nullptr;
-};
 
 extern "C" {
 

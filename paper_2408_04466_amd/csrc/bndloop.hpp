@@ -1,0 +1,162 @@
+// Boundary line integral of the one-shot winding number: the per-lane walk
+// over the boundary loops, shared by the plain boundary kernel and the
+// batched persistent kernel.
+//
+// S(p) = sum over boundary edges a->b of theta_e, theta_e = atan2(N, D): half
+// the signed solid angle of the spherical triangle (-d, a - p, b - p).  This
+// is Eq. wn_discrete_sum with the region of d as the seed of Alg. 1: by
+// Lemma 2 every other region differs from it by the number of boundary
+// crossings in between, so the region areas collapse into one line integral
+// over the boundary (the paper evaluates region areas from boundary
+// integrals as well, Sec. 4 "Exact Computations").
+//
+// Layout: the workgroup stages the boundary loops into LDS (rotated float64
+// coordinates plus the tie offset of the edge leaving each vertex) in chunks
+// of kChunk vertices, and every lane walks the same vertex sequence, so the
+// LDS reads are broadcasts.  Per (query, vertex) the frame quantities are
+// formed once and reused by the two edges that share the vertex.  Instead of
+// one atan2 per edge, the edge factors D + iN are multiplied into a running
+// complex product whose half-plane changes count whole turns exactly
+// (wn::Turns); one atan2 per query remains.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace wn {
+namespace bnd {
+
+constexpr int kThreads = 256;
+constexpr int kChunk = 512;      // vertices per LDS stage: 512 * 32 B = 16 KB
+constexpr int kUnroll = 8;       // vertices per main-loop step (one rescale per step)
+
+// Loop table accessors: loops in the kernel arguments, or in device memory.
+struct KernargLoops {
+  const LoopTable& L;
+  __device__ __forceinline__ int n() const { return L.n; }
+  __device__ __forceinline__ int off(int l) const { return L.off[l]; }
+};
+struct DeviceLoops {
+  const int32_t* o;   // [n + 1], relative to the surface's first vertex
+  int nl;
+  __device__ __forceinline__ int n() const { return nl; }
+  __device__ __forceinline__ int off(int l) const { return o[l]; }
+};
+
+// Loop containing flat vertex index i (binary search over the loop table).
+template <class Loops>
+__device__ __forceinline__ int loop_of(const Loops& L, int i) {
+  int lo = 0, hi = L.n() - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (L.off(mid) <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Stage vertices [c0, c0 + cnt) into LDS: rotated coordinates and, in .w,
+// the tie offset of the edge v_i -> v_next(i).
+template <class Loops>
+__device__ __forceinline__ void stage_chunk(const Frame& F, const float* __restrict__ bnd, const Loops& L,
+                                            int c0, int cnt, double4* sv) {
+  for (int j = threadIdx.x; j < cnt; j += kThreads) {
+    const int i = c0 + j;
+    const int l = loop_of(L, i);
+    const int nxt = (i + 1 < L.off(l + 1)) ? i + 1 : L.off(l);
+    double X, Y, Z, Xn, Yn, Zn;
+    rotate(F, bnd[3 * i], bnd[3 * i + 1], bnd[3 * i + 2], X, Y, Z);
+    rotate(F, bnd[3 * nxt], bnd[3 * nxt + 1], bnd[3 * nxt + 2], Xn, Yn, Zn);
+    sv[j] = make_double4(X, Y, Z, tie_offset(lex_less(X, Y, Z, Xn, Yn, Zn)));
+  }
+}
+
+template <int QPL>
+struct Lane {
+  double Xp[QPL], Yp[QPL], Zp[QPL];
+  Turns T[QPL];
+};
+
+template <int QPL>
+__device__ __forceinline__ void vert_q(const Lane<QPL>& s, const double4& v, VQ* out) {
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) out[k] = vertex_q(v.x, v.y, v.z, s.Xp[k], s.Yp[k], s.Zp[k]);
+}
+
+template <int QPL>
+__device__ __forceinline__ void edge_step(Lane<QPL>& s, const VQ* a, const VQ* b, double tie) {
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) {
+    const double N = edge_tie(edge_n(a[k], b[k]), tie);
+    const double D = edge_d(a[k], b[k]);
+    turns_mul(s.T[k], D, N);
+  }
+}
+
+template <int QPL>
+__device__ __forceinline__ void rescale(Lane<QPL>& s) {
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) turns_norm(s.T[k]);
+}
+
+// Multiply every boundary edge factor of the loops into the lane's turn
+// accumulators.  All threads of the workgroup must call this together.
+// `staged` tracks which chunk is in LDS (-1: none) so that a caller walking
+// the same boundary again (next tile of queries) skips restaging when the
+// whole boundary fits in one chunk.
+template <int QPL, class Loops>
+__device__ __forceinline__ void boundary_walk(Lane<QPL>& s, const Frame& F, const float* __restrict__ bnd,
+                                              int nb, const Loops& L, double4* sv, int& staged) {
+  VQ first[QPL], A[QPL], B[QPL];   // A holds the previous vertex between steps
+  double ptie = 0.0;               // uniform: tie offset of the edge leaving A
+  int l = 0;
+  for (int c0 = 0; c0 < nb; c0 += kChunk) {
+    const int c1 = min(c0 + kChunk, nb);
+    if (staged != c0) {
+      __syncthreads();
+      stage_chunk(F, bnd, L, c0, c1 - c0, sv);
+      __syncthreads();
+      staged = c0;
+    }
+    // the loops overlapping [c0, c1), each as a straight-line vertex range
+    for (; l < L.n() && L.off(l) < c1; ++l) {
+      const int ls = L.off(l), le = L.off(l + 1);
+      int j = max(ls, c0);
+      const int j1 = min(le, c1);
+      if (j == ls) {
+        const double4 v = sv[j - c0];
+        vert_q(s, v, first);
+#pragma unroll
+        for (int k = 0; k < QPL; ++k) A[k] = first[k];
+        ptie = v.w;
+        ++j;
+      }
+      // kUnroll vertices per step, the roles of A and B alternating
+      for (; j + kUnroll <= j1; j += kUnroll) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; u += 2) {
+          const double4 v0 = sv[j + u - c0];
+          vert_q(s, v0, B);
+          edge_step(s, A, B, ptie);
+          const double4 v1 = sv[j + u + 1 - c0];
+          vert_q(s, v1, A);
+          edge_step(s, B, A, v0.w);
+          ptie = v1.w;
+        }
+        rescale(s);
+      }
+      for (; j < j1; ++j) {
+        const double4 v = sv[j - c0];
+        vert_q(s, v, B);
+        edge_step(s, A, B, ptie);
+#pragma unroll
+        for (int k = 0; k < QPL; ++k) A[k] = B[k];
+        ptie = v.w;
+      }
+      rescale(s);
+      if (j1 < le) break;            // the loop continues in the next chunk
+      edge_step(s, A, first, ptie);  // closing edge last -> first
+    }
+  }
+}
+
+}  // namespace bnd
+}  // namespace wn

@@ -12,111 +12,9 @@
 // registers.
 #include "kernels.hpp"
 #include "bvh_build.hpp"
+#include "traverse.hpp"
 
 namespace wn {
-
-// ---------------------------------------------------------------------------
-// Triangle test (shared predicates with the boundary kernel)
-// ---------------------------------------------------------------------------
-
-// +1 / -1 when the ray p + t d (t > 0) passes through the triangle's
-// interior along / against its normal (v1-v0)x(v2-v0), 0 otherwise.
-__device__ __forceinline__ int tri_crossing(const int4 t, const double4* __restrict__ Vr,
-                                            double Xp, double Yp, double Zp) {
-  const double4 A = Vr[t.x];
-  const double4 B = Vr[t.y];
-  const double4 C = Vr[t.z];
-  float za, zb, zc;
-  const VQ a = vertex_q(A.x, A.y, A.z, Xp, Yp, Zp, &za);
-  const VQ b = vertex_q(B.x, B.y, B.z, Xp, Yp, Zp, &zb);
-  const VQ c = vertex_q(C.x, C.y, C.z, Xp, Yp, Zp, &zc);
-  const double n01 = edge_tie(edge_n(a, b), tie_offset(lex_less(A.x, A.y, A.z, B.x, B.y, B.z)));
-  const double n12 = edge_tie(edge_n(b, c), tie_offset(lex_less(B.x, B.y, B.z, C.x, C.y, C.z)));
-  const double n20 = edge_tie(edge_n(c, a), tie_offset(lex_less(C.x, C.y, C.z, A.x, A.y, A.z)));
-  const bool s01 = n01 < 0.0, s12 = n12 < 0.0, s20 = n20 < 0.0;
-  if (s01 != s12 || s12 != s20) return 0;
-  // Height of the crossing above p: barycentric weights are the edge values
-  // opposite each vertex (divided by the vertex scales), so the crossing is
-  // above p iff sum(N_opp * lam * Z) has the sign of the N's.
-  const double num = __fma_rn(n12, (double)za, __fma_rn(n20, (double)zb, __dmul_rn(n01, (double)zc)));
-  const bool hit = s01 ? (num < 0.0) : (num > 0.0);
-  return hit ? (s01 ? 1 : -1) : 0;
-}
-
-// ---------------------------------------------------------------------------
-// Traversal with a short stack in registers
-// ---------------------------------------------------------------------------
-
-// Fixed-depth stack kept in registers: push shifts every entry down by one
-// (plain register moves, no indexed addressing, so no scratch memory).
-template <int S>
-struct RegStack {
-  int32_t e[S];
-  int n;
-  __device__ __forceinline__ void init() { n = 0; }
-  __device__ __forceinline__ bool push(int32_t v) {
-#pragma unroll
-    for (int i = S - 1; i > 0; --i) e[i] = e[i - 1];
-    e[0] = v;
-    ++n;
-    return n <= S;
-  }
-  __device__ __forceinline__ int32_t pop() {
-    const int32_t v = e[0];
-#pragma unroll
-    for (int i = 0; i < S - 1; ++i) e[i] = e[i + 1];
-    --n;
-    return v;
-  }
-};
-
-__device__ __forceinline__ bool in_box(const float4 b, float bz, float x, float y, float z) {
-  return (x >= b.x) & (x <= b.y) & (y >= b.z) & (y <= b.w) & (z <= bz);
-}
-
-// chi for one query; returns kChiOverflow when the stack overflowed.
-template <int S>
-__device__ int traverse(const CrossArgs& a, double Xp, double Yp, double Zp) {
-  if (a.nf == 0) return 0;
-  const float x = (float)Xp, y = (float)Yp, z = (float)Zp;
-  if (a.nf == 1) {
-    return in_box(a.leafbox[0], a.leafz[0], x, y, z) ? tri_crossing(a.tris[0], a.Vr, Xp, Yp, Zp) : 0;
-  }
-  int chi = 0;
-  RegStack<S> st;
-  st.init();
-  int32_t node = 0;
-  const int32_t nint = a.nf - 1;
-  // a valid tree visits each node at most once per query
-  for (int32_t it = 0;; ++it) {
-    if (it > nint || (uint32_t)node >= (uint32_t)nint) return WN_CHI_INVALID;
-    const BvhNode nd = a.nodes[node];
-    bool hl = in_box(nd.lbox, nd.lzmax, x, y, z);
-    bool hr = in_box(nd.rbox, nd.rzmax, x, y, z);
-    if (hl && nd.left < 0) {
-      if (~nd.left >= a.nf) return WN_CHI_INVALID;
-      chi += tri_crossing(a.tris[~nd.left], a.Vr, Xp, Yp, Zp);
-      hl = false;
-    }
-    if (hr && nd.right < 0) {
-      if (~nd.right >= a.nf) return WN_CHI_INVALID;
-      chi += tri_crossing(a.tris[~nd.right], a.Vr, Xp, Yp, Zp);
-      hr = false;
-    }
-    if (hl && hr) {
-      if (!st.push(nd.right)) return kChiOverflow;   // deepest entry lost: redo deeper
-      node = nd.left;
-    } else if (hl) {
-      node = nd.left;
-    } else if (hr) {
-      node = nd.right;
-    } else {
-      if (st.n == 0) break;
-      node = st.pop();
-    }
-  }
-  return chi;
-}
 
 template <int S>
 __global__ __launch_bounds__(256) void k_cross3d(CrossArgs a) {
@@ -132,27 +30,10 @@ __global__ __launch_bounds__(256) void k_cross3d(CrossArgs a) {
   a.chi[q] = traverse<S>(a, Xp, Yp, Zp);
 }
 
-// Second pass over the few queries whose short stack overflowed: a deeper
-// register stack (the tree depth bounds the number of pending siblings).
-template <int S>
-__global__ __launch_bounds__(64) void k_cross3d_retry(CrossArgs a) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= a.nq) return;
-  if (a.chi[q] != kChiOverflow) return;
-  double Xp, Yp, Zp;
-  rotate(a.F, a.qx[q], a.qy[q], a.qz[q], Xp, Yp, Zp);
-  const int r = traverse<S>(a, Xp, Yp, Zp);
-  a.chi[q] = (r == kChiOverflow) ? WN_CHI_INVALID : r;
-}
-
 hipError_t launch_cross3d(const CrossArgs& a, hipStream_t s) {
   if (a.nq == 0) return hipSuccess;
   const unsigned blocks = (unsigned)((a.nq + 255) / 256);
   hipLaunchKernelGGL(k_cross3d<kShortStack>, dim3(blocks), dim3(256), 0, s, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const unsigned b2 = (unsigned)((a.nq + 63) / 64);
-  hipLaunchKernelGGL(k_cross3d_retry<kDeepStack>, dim3(b2), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

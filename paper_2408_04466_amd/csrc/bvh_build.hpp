@@ -8,8 +8,7 @@
 
 namespace wn {
 
-constexpr int kShortStack = 12;   // register stack of the main traversal
-constexpr int kDeepStack = 64;    // retry pass; the LBVH depth is < 64
+constexpr int kShortStack = 12;   // traversal stack entries kept in registers
 
 struct BuildBufs {
   double4* Vr;          // [nv]

@@ -26,8 +26,6 @@ struct alignas(16) BvhNode {
   int32_t left, right;
 };
 
-constexpr int32_t kChiOverflow = (int32_t)0x80000001;  // internal: retry deeper
-
 struct CrossArgs {
   Frame F;
   const BvhNode* nodes;

@@ -1,0 +1,123 @@
+// Ray/triangle crossing and BVH traversal for chi_d, shared by the plain
+// crossing kernel and the batched persistent kernel.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace wn {
+
+// ---------------------------------------------------------------------------
+// Triangle test (shared predicates with the boundary kernel)
+// ---------------------------------------------------------------------------
+
+// +1 / -1 when the ray p + t d (t > 0) passes through the triangle's
+// interior along / against its normal (v1-v0)x(v2-v0), 0 otherwise.
+__device__ __forceinline__ int tri_crossing(const int4 t, const double4* __restrict__ Vr,
+                                            double Xp, double Yp, double Zp) {
+  const double4 A = Vr[t.x];
+  const double4 B = Vr[t.y];
+  const double4 C = Vr[t.z];
+  float za, zb, zc;
+  const VQ a = vertex_q(A.x, A.y, A.z, Xp, Yp, Zp, &za);
+  const VQ b = vertex_q(B.x, B.y, B.z, Xp, Yp, Zp, &zb);
+  const VQ c = vertex_q(C.x, C.y, C.z, Xp, Yp, Zp, &zc);
+  const double n01 = edge_tie(edge_n(a, b), tie_offset(lex_less(A.x, A.y, A.z, B.x, B.y, B.z)));
+  const double n12 = edge_tie(edge_n(b, c), tie_offset(lex_less(B.x, B.y, B.z, C.x, C.y, C.z)));
+  const double n20 = edge_tie(edge_n(c, a), tie_offset(lex_less(C.x, C.y, C.z, A.x, A.y, A.z)));
+  const bool s01 = n01 < 0.0, s12 = n12 < 0.0, s20 = n20 < 0.0;
+  if (s01 != s12 || s12 != s20) return 0;
+  // Height of the crossing above p: barycentric weights are the edge values
+  // opposite each vertex (divided by the vertex scales), so the crossing is
+  // above p iff sum(N_opp * lam * Z) has the sign of the N's.
+  const double num = __fma_rn(n12, (double)za, __fma_rn(n20, (double)zb, __dmul_rn(n01, (double)zc)));
+  const bool hit = s01 ? (num < 0.0) : (num > 0.0);
+  return hit ? (s01 ? 1 : -1) : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Traversal with a short stack in registers
+// ---------------------------------------------------------------------------
+
+// Traversal stack: the top S entries live in registers (push and pop shift
+// them, plain moves, no indexed addressing); deeper entries spill to a
+// separate private array that only overflowing traversals touch.  The LBVH's
+// depth is below 64 (its split keys are 64-bit), which bounds the number of
+// pending siblings.
+constexpr int kSpill = 64;
+
+template <int S>
+struct RegStack {
+  int32_t e[S];   // e[0] = top
+  int n;
+  __device__ __forceinline__ void init() { n = 0; }
+  __device__ __forceinline__ bool push(int32_t v, int32_t* spill) {
+    if (n >= S) {
+      if (n - S >= kSpill) return false;
+      spill[n - S] = e[S - 1];
+    }
+#pragma unroll
+    for (int i = S - 1; i > 0; --i) e[i] = e[i - 1];
+    e[0] = v;
+    ++n;
+    return true;
+  }
+  __device__ __forceinline__ int32_t pop(const int32_t* spill) {
+    const int32_t v = e[0];
+#pragma unroll
+    for (int i = 0; i < S - 1; ++i) e[i] = e[i + 1];
+    --n;
+    if (n >= S) e[S - 1] = spill[n - S];
+    return v;
+  }
+};
+
+__device__ __forceinline__ bool in_box(const float4 b, float bz, float x, float y, float z) {
+  return (x >= b.x) & (x <= b.y) & (y >= b.z) & (y <= b.w) & (z <= bz);
+}
+
+// chi for one query (WN_CHI_INVALID if the tree is malformed).
+template <int S>
+__device__ int traverse(const CrossArgs& a, double Xp, double Yp, double Zp) {
+  if (a.nf == 0) return 0;
+  const float x = (float)Xp, y = (float)Yp, z = (float)Zp;
+  if (a.nf == 1) {
+    return in_box(a.leafbox[0], a.leafz[0], x, y, z) ? tri_crossing(a.tris[0], a.Vr, Xp, Yp, Zp) : 0;
+  }
+  int chi = 0;
+  RegStack<S> st;
+  int32_t spill[kSpill];
+  st.init();
+  int32_t node = 0;
+  const int32_t nint = a.nf - 1;
+  // a valid tree visits each node at most once per query
+  for (int32_t it = 0;; ++it) {
+    if (it > nint || (uint32_t)node >= (uint32_t)nint) return WN_CHI_INVALID;
+    const BvhNode nd = a.nodes[node];
+    bool hl = in_box(nd.lbox, nd.lzmax, x, y, z);
+    bool hr = in_box(nd.rbox, nd.rzmax, x, y, z);
+    if (hl && nd.left < 0) {
+      if (~nd.left >= a.nf) return WN_CHI_INVALID;
+      chi += tri_crossing(a.tris[~nd.left], a.Vr, Xp, Yp, Zp);
+      hl = false;
+    }
+    if (hr && nd.right < 0) {
+      if (~nd.right >= a.nf) return WN_CHI_INVALID;
+      chi += tri_crossing(a.tris[~nd.right], a.Vr, Xp, Yp, Zp);
+      hr = false;
+    }
+    if (hl && hr) {
+      if (!st.push(nd.right, spill)) return WN_CHI_INVALID;
+      node = nd.left;
+    } else if (hl) {
+      node = nd.left;
+    } else if (hr) {
+      node = nd.right;
+    } else {
+      if (st.n == 0) break;
+      node = st.pop(spill);
+    }
+  }
+  return chi;
+}
+
+}  // namespace wn

@@ -1,0 +1,181 @@
+"""GPU tests of the batched persistent path (many surfaces of uneven size in
+one launch, hipGraph replay, autotuner): bitwise agreement with the plain
+per-surface calls, oracle parity on samples, replay correctness."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import wn3d as O
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    import paper_2408_04466_amd as W
+    from gpu_util import W_TOL
+
+
+def _surfaces(seed, n, scale):
+    CB = synth.coons_batch(seed, n_surf=n, scale=scale)
+    meshes, queries = list(CB.meshes), list(CB.queries)
+    # a closed surface and a surface without queries ride along
+    meshes.append(synth.icosphere(2, radius=0.7))
+    queries.append(synth.box_queries(meshes[-1].V, 3000, 9))
+    meshes.append(synth.bumpy_cap())
+    queries.append(np.zeros((0, 3), np.float32))
+    return meshes, queries, CB.direction
+
+
+def _upload(meshes, queries):
+    surfs, plain = [], []
+    for M, Q in zip(meshes, queries):
+        V = torch.from_numpy(M.V).cuda()
+        F = torch.from_numpy(M.F).cuda()
+        idx, off = W.boundary_loops(M.F)
+        bnd = V[torch.from_numpy(idx.astype(np.int64)).cuda()].contiguous()
+        surfs.append({"V": V, "F": F, "bnd": bnd, "loop_off": off, "nq": len(Q), "idx": idx})
+    P = np.concatenate(queries, 0).astype(np.float32)
+    q = tuple(torch.from_numpy(np.ascontiguousarray(P[:, k])).cuda() for k in range(3))
+    return surfs, P, q
+
+
+def _plain(surfs, q, d):
+    ws, cs, o = [], [], 0
+    for s in surfs:
+        n = s["nq"]
+        if n == 0:
+            continue
+        bvh = W.BVH(s["V"], s["F"], d)
+        w, chi = W.eval_3d(bvh, s["bnd"], s["loop_off"], q[0][o:o + n], q[1][o:o + n], q[2][o:o + n])
+        torch.cuda.synchronize()
+        ws.append(w.cpu().numpy())
+        cs.append(chi.cpu().numpy())
+        o += n
+    return np.concatenate(ws), np.concatenate(cs)
+
+
+@pytest.fixture(scope="module")
+def small_batch():
+    meshes, queries, d = _surfaces(31, 12, 0.05)
+    surfs, P, q = _upload(meshes, queries)
+    return meshes, queries, d, surfs, P, q
+
+
+def test_batched_equals_plain_bitwise(small_batch):
+    meshes, queries, d, surfs, P, q = small_batch
+    B = W.Batch(surfs, d)
+    w, chi = B.eval(*q)
+    torch.cuda.synchronize()
+    wp, cp = _plain(surfs, q, d)
+    assert np.array_equal(chi.cpu().numpy(), cp)
+    assert np.array_equal(w.cpu().numpy(), wp)
+    info = B.info()
+    assert info["total_q"] == len(P) and info["graph"] == 1
+    B.free()
+
+
+def test_batched_oracle_samples(small_batch):
+    meshes, queries, d, surfs, P, q = small_batch
+    B = W.Batch(surfs, d)
+    w, chi = B.eval(*q)
+    torch.cuda.synchronize()
+    w, chi = w.cpu().numpy(), chi.cpu().numpy()
+    o = 0
+    g = synth.rng(2)
+    for M, Q in zip(meshes, queries):
+        n = len(Q)
+        if n == 0:
+            continue
+        sel = g.choice(n, min(n, 40), replace=False)
+        r = O.wn3d(M.V, M.F, Q[sel], d)
+        ok = ~r.degenerate
+        assert np.array_equal(chi[o + sel][ok], r["chi"][ok])
+        far = ok & (r["m_bnd"] > 1e-5)
+        assert np.abs(w[o + sel][far] - r["w"][far]).max() <= W_TOL
+        o += n
+
+
+def test_graph_replays_and_pointer_changes(small_batch):
+    meshes, queries, d, surfs, P, q = small_batch
+    B = W.Batch(surfs, d)
+    ref_w, ref_c = B.eval(*q)
+    torch.cuda.synchronize()
+    ref_w, ref_c = ref_w.clone(), ref_c.clone()
+    outs = [(torch.full_like(ref_w, float("nan")), torch.full_like(ref_c, -7)) for _ in range(3)]
+    for rep in range(4):
+        for w_o, c_o in outs:
+            # eager work between replays touches the same memory pool
+            junk = torch.randn(1 << 16, device="cuda").sum()
+            w_o.fill_(float("nan"))
+            B.eval(*q, w_out=w_o, chi_out=c_o)
+            torch.cuda.synchronize()
+            assert torch.equal(w_o, ref_w) and torch.equal(c_o, ref_c), f"replay {rep}"
+            del junk
+    # moved queries (new pointers): results follow the new inputs
+    q2 = tuple(t.clone() for t in q)
+    w2, c2 = B.eval(*q2)
+    torch.cuda.synchronize()
+    assert torch.equal(w2, ref_w) and torch.equal(c2, ref_c)
+    B.free()
+
+
+def test_direct_launch_mode_matches_graph(small_batch):
+    meshes, queries, d, surfs, P, q = small_batch
+    B = W.Batch(surfs, d)
+    wg, cg = B.eval(*q)
+    os.environ["WN_FORCE_NO_GRAPH"] = "1"
+    try:
+        B2 = W.Batch(surfs, d)
+    finally:
+        del os.environ["WN_FORCE_NO_GRAPH"]
+    wd, cd = B2.eval(*q)
+    torch.cuda.synchronize()
+    assert B2.info()["graph"] == 0
+    assert torch.equal(wg, wd) and torch.equal(cg, cd)
+
+
+def test_autotuner_and_cache(small_batch, tmp_path):
+    meshes, queries, d, surfs, P, q = small_batch
+    cache = tmp_path / "tune.json"
+    os.environ["WN_TUNE_CACHE"] = str(cache)
+    try:
+        B = W.Batch(surfs, d, tune_mode=1)
+        w, chi = B.eval(*q)
+        torch.cuda.synchronize()
+        info = B.info()
+        assert cache.exists() and info["tile"] in (512, 1024, 2048) and info["wg_per_cu"] in (2, 4, 8)
+        assert str(info["tile"]) in cache.read_text()
+        B2 = W.Batch(surfs, d, tune_mode=2)
+        w2, chi2 = B2.eval(*q)
+        torch.cuda.synchronize()
+        assert B2.info()["tile"] == info["tile"] and B2.info()["wg_per_cu"] == info["wg_per_cu"]
+    finally:
+        del os.environ["WN_TUNE_CACHE"]
+    B0 = W.Batch(surfs, d)
+    w0, c0 = B0.eval(*q)
+    torch.cuda.synchronize()
+    assert torch.equal(w, w0) and torch.equal(chi, c0) and torch.equal(w2, w0)
+
+
+def test_batched_backward_matches_plain(small_batch):
+    meshes, queries, d, surfs, P, q = small_batch
+    B = W.Batch(surfs, d)
+    g = torch.from_numpy(synth.rng(3).normal(size=len(P)).astype(np.float32)).cuda()
+    gq, gb = B.backward(*q, g)
+    gq2, gb2 = B.backward(*q, g)
+    torch.cuda.synchronize()
+    assert torch.equal(gq, gq2) and torch.equal(gb, gb2)
+    o, ob = 0, 0
+    for s in surfs:
+        n, nb = s["nq"], len(s["idx"])
+        if n > 0 and nb > 0:
+            pq, pb = W.backward(s["bnd"], s["loop_off"], q[0][o:o + n], q[1][o:o + n], q[2][o:o + n], g[o:o + n])
+            torch.cuda.synchronize()
+            assert torch.equal(gq[o:o + n], pq)
+            assert torch.allclose(gb[ob:ob + nb], pb, rtol=1e-5, atol=1e-6 * float(pb.abs().max()))
+        elif nb > 0:
+            assert torch.count_nonzero(gb[ob:ob + nb]) == 0
+        o += n
+        ob += nb
