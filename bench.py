@@ -1,16 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the one-shot winding number hot path on one MI355X.
 
-One step = one forward + backward pass over the 3D open-mesh workload:
-a noise-displaced unit sphere with a 30 degree polar cap removed (1,048,064
-triangles, one boundary loop of 512 edges), 2^20 query points uniform in 1.2x
-its bounding box, seeded ray direction.  Forward = crossing count through the
-BVH + boundary integral (w); backward = adjoint with respect to the queries
-and the boundary vertices for L = sum (w - t)^2.  Inputs are resident in HBM
-before the timed region; the BVH build is timed separately.
+Headline step: one forward + backward pass over the 3D open-mesh workload,
+through the batched persistent path (one hipGraph replay for the forward, one
+persistent adjoint launch): a noise-displaced unit sphere with a 30 degree
+polar cap removed (1,048,064 triangles, one boundary loop of 512 edges), 2^20
+query points uniform in 1.2x its bounding box, seeded ray direction.
+Forward = crossing count + boundary integral (w); backward = adjoint with
+respect to the queries and the boundary vertices for L = sum (w - t)^2.
+Inputs are resident in HBM before the timed region; BVH builds, graph
+capture and autotuning are timed separately.
 
-Prints one JSON line (see the keys below).  ``--gpus N`` with N > 1 exits:
-this build runs on one GPU.
+Also measured in the same run (reported beside the headline): the plain
+path on the same workload, the 256-surface batch (batched vs a loop of plain
+calls), the adjoint workload, and both 2D workloads.
+
+Prints one JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one
+GPU.
 """
 from __future__ import annotations
 
@@ -30,7 +36,6 @@ import synth  # noqa: E402
 FLOPS_PER_PAIR_FWD = 58      # boundary integral, per (query, boundary edge)
 FLOPS_PER_PAIR_BWD = 40      # adjoint, per (query, boundary edge)
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak
-PEAK_HBM_GBS = 8000.0
 
 
 def workload_c3():
@@ -47,8 +52,7 @@ def _oracle_chunk(args):
     from oracle import wn3d as O
     r = O.wn3d(V, F, P, d, margins=False, loops=L)
     g = 2.0 * (r["w"] - t)
-    Lx = O.loops_coords(V, L)
-    G.grad3d(Lx, P, g)
+    G.grad3d(O.loops_coords(V, L), P, g)
     return len(P)
 
 
@@ -68,9 +72,40 @@ def cpu_baseline(M, P, d, t, nsample=64):
         n = sum(pool.map(_oracle_chunk, jobs))
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "queries/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} random queries of the 2^20-query workload, forward w (brute-force "
-                      f"crossings over all triangles + boundary term) and closed-form gradients, "
-                      f"float64 numpy, multiprocessing over {cores} host cores; {dt:.1f} s wall"}
+            "sample": f"{n} random queries of the 2^20-query mesh workload, forward w (brute-force "
+                      f"crossings over all 1,048,064 triangles + boundary term) and closed-form "
+                      f"gradients, float64 numpy, multiprocessing over {cores} host cores; "
+                      f"{dt:.1f} s wall"}
+
+
+class Timer:
+    def __init__(self, torch, stream):
+        self.torch, self.stream = torch, stream
+
+    def ms(self, fn, reps, warm=1):
+        torch = self.torch
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(self.stream)
+        for _ in range(reps):
+            fn()
+        b.record(self.stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+
+def upload_mesh(torch, W, M, dev):
+    V = torch.from_numpy(np.ascontiguousarray(M.V)).to(dev)
+    F = torch.from_numpy(np.ascontiguousarray(M.F)).to(dev)
+    idx, off = W.boundary_loops(M.F)
+    bnd = V[torch.from_numpy(idx.astype(np.int64)).to(dev)].contiguous()
+    return V, F, bnd, off, idx
+
+
+def soa(torch, P, dev):
+    return tuple(torch.from_numpy(np.ascontiguousarray(P[:, k])).to(dev) for k in range(3))
 
 
 def main():
@@ -80,6 +115,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--parity-sample", type=int, default=12)
+    ap.add_argument("--only-c3", action="store_true", help="skip the other workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (got --gpus {args.gpus}); "
@@ -89,6 +125,7 @@ def main():
     M, P, d, t = workload_c3()
     nq = len(P)
     cpu = None if args.no_cpu_baseline else cpu_baseline(M, P, d, t)
+    others = None if args.only_c3 else {"c4": synth.coons_batch(4), "c5_mesh": synth.open_sphere(3, top_refine=4)}
 
     import torch
     import paper_2408_04466_amd as W
@@ -96,74 +133,81 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    V = torch.from_numpy(M.V).to(dev)
-    F = torch.from_numpy(M.F).to(dev)
+    stream = torch.cuda.current_stream()
+    T = Timer(torch, stream)
+    V, F, bnd, off, idx = upload_mesh(torch, W, M, dev)
+    nb = len(idx)
+    qx, qy, qz = soa(torch, P, dev)
+    tt = torch.from_numpy(t).to(dev)
     torch.cuda.synchronize()
+
     t0 = time.perf_counter()
     bvh = W.BVH(V, F, d)
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - t0) * 1e3
-    idx, off = W.boundary_loops(M.F)
-    nb = len(idx)
-    bnd = V[torch.from_numpy(idx.astype(np.int64)).to(dev)].contiguous()
-    qx, qy, qz = (torch.from_numpy(np.ascontiguousarray(P[:, k])).to(dev) for k in range(3))
-    tt = torch.from_numpy(t).to(dev)
+    t0 = time.perf_counter()
+    batch = W.Batch([{"V": V, "F": F, "bnd": bnd, "loop_off": off, "nq": nq}], d, tune_mode=1)
+    torch.cuda.synchronize()
+    batch_ms = (time.perf_counter() - t0) * 1e3
+
     w = torch.empty(nq, dtype=torch.float32, device=dev)
     chi = torch.empty(nq, dtype=torch.int32, device=dev)
-    stream = torch.cuda.current_stream()
+    wb = torch.empty(nq, dtype=torch.float32, device=dev)
 
-    def step():
+    # parity sample (the throughputs are reported only if it passes)
+    batch.eval(qx, qy, qz, w_out=wb, chi_out=chi)
+    W.eval_3d(bvh, bnd, off, qx, qy, qz, w_out=w, want_chi=False)
+    torch.cuda.synchronize()
+    sidx = synth.rng(31).choice(nq, args.parity_sample, replace=False)
+    r = O.wn3d(M.V, M.F, P[sidx], d)
+    wc, cc = wb.cpu().numpy(), chi.cpu().numpy()
+    ok = ~r.degenerate
+    chi_ok = bool(np.array_equal(cc[sidx][ok], r["chi"][ok]))
+    werr = float(np.abs(wc[sidx] - r["w"])[ok & (r["m_bnd"] > 1e-5)].max())
+    same = bool(torch.equal(w, wb))
+    parity = {"sample": int(len(sidx)), "chi_bit_exact": chi_ok, "max_abs_w_err": werr,
+              "degenerate": int((~ok).sum()), "batched_equals_plain": same,
+              "pass": bool(chi_ok and werr <= 1e-4 and same)}
+
+    def step_batched():
+        batch.eval(qx, qy, qz, w_out=wb, want_chi=False)
+        g = 2.0 * (wb - tt)
+        return batch.backward(qx, qy, qz, g)
+
+    def step_plain():
         W.eval_3d(bvh, bnd, off, qx, qy, qz, want_chi=False, w_out=w)
         g = 2.0 * (w - tt)
         return W.backward(bnd, off, qx, qy, qz, g)
 
-    # parity sample (the throughput below is reported only if it passes)
-    W.eval_3d(bvh, bnd, off, qx, qy, qz, w_out=w, chi_out=chi)
-    torch.cuda.synchronize()
-    sidx = synth.rng(31).choice(nq, args.parity_sample, replace=False)
-    r = O.wn3d(M.V, M.F, P[sidx], d)
-    wc, cc = w.cpu().numpy(), chi.cpu().numpy()
-    ok = ~r.degenerate
-    chi_ok = bool(np.array_equal(cc[sidx][ok], r["chi"][ok]))
-    werr = float(np.abs(wc[sidx] - r["w"])[ok & (r["m_bnd"] > 1e-5)].max())
-    parity = {"sample": int(len(sidx)), "chi_bit_exact": chi_ok, "max_abs_w_err": werr,
-              "degenerate": int((~ok).sum()), "pass": bool(chi_ok and werr <= 1e-4)}
-
     for _ in range(args.warmup):
-        step()
+        step_batched()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(args.steps):
-        step()
+        step_batched()
     e1.record(stream)
     torch.cuda.synchronize()
     ms_step = e0.elapsed_time(e1) / args.steps
+    ms_step_plain = T.ms(step_plain, args.steps, args.warmup)
 
     # per-kernel timings on the same stream (HIP events around K launches)
-    def timed(fn, reps):
-        fn()
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(reps):
-            fn()
-        b.record(stream)
-        torch.cuda.synchronize()
-        return a.elapsed_time(b) / reps
-
     reps = max(args.steps, 10)
-    chi_buf = torch.empty(nq, dtype=torch.int32, device=dev)
-    W.crossings_3d(bvh, qx, qy, qz)
-    ms_cross = timed(lambda: W.crossings_3d(bvh, qx, qy, qz), reps)
     chi_buf = W.crossings_3d(bvh, qx, qy, qz)
-    ms_bnd = timed(lambda: W.eval_3d_boundary(bvh, bnd, off, qx, qy, qz, chi_buf), reps)
+    ms_cross = T.ms(lambda: W.crossings_3d(bvh, qx, qy, qz), reps)
+    ms_bnd = T.ms(lambda: W.eval_3d_boundary(bvh, bnd, off, qx, qy, qz, chi_buf), reps)
     gw = torch.ones(nq, dtype=torch.float32, device=dev)
-    ms_bwd = timed(lambda: W.backward(bnd, off, qx, qy, qz, gw), reps)
-    ms_fwd = timed(lambda: W.eval_3d(bvh, bnd, off, qx, qy, qz, want_chi=False, w_out=w), reps)
+    ms_bwd = T.ms(lambda: W.backward(bnd, off, qx, qy, qz, gw), reps)
+    ms_fwd = T.ms(lambda: W.eval_3d(bvh, bnd, off, qx, qy, qz, want_chi=False, w_out=w), reps)
+    ms_fwd_b = T.ms(lambda: batch.eval(qx, qy, qz, w_out=wb, want_chi=False), reps)
+    ms_bwd_b = T.ms(lambda: batch.backward(qx, qy, qz, gw), reps)
 
     pairs = nq * nb
     achieved = pairs * FLOPS_PER_PAIR_FWD / (ms_bnd * 1e-3) / 1e12
+    extra = {}
+    if others is not None:
+        extra = run_others(torch, W, T, others, d, args, dev)
+
     out = {
         "metric": "winding queries/s fwd+bwd, batched vs plain, 3D mesh 2^20 pts at |err|<=1e-4",
         "value": nq / (ms_step * 1e-3),
@@ -177,19 +221,29 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "3D open mesh: noise-displaced sphere minus 30 deg cap, "
+        "config": {"workload": "3D open mesh: noise-displaced unit sphere minus a 30 deg polar cap, "
                                f"{M.F.shape[0]} triangles, {nb} boundary edges, 2^20 uniform queries "
-                               "in 1.2x bbox, seeded random ray direction; fwd (crossings + boundary "
-                               "integral) + bwd (adjoint w.r.t. queries and boundary vertices)",
+                               "in 1.2x bbox, seeded random ray direction; step = forward (crossings + "
+                               "boundary integral) + backward (adjoint w.r.t. queries and boundary "
+                               "vertices) through the batched persistent path",
                    "queries": nq, "triangles": int(M.F.shape[0]), "boundary_edges": nb,
-                   "path": "plain"},
+                   "path": "batched (1 surface, hipGraph forward)"},
         "roofline": {"bound": "alu", "kernel": "k_bnd3d (boundary integral)",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "flops_per_pair": FLOPS_PER_PAIR_FWD, "pairs": pairs, "ms": ms_bnd},
-        "kernels_ms": {"crossings": ms_cross, "boundary": ms_bnd, "forward": ms_fwd,
-                       "backward": ms_bwd, "bvh_build": build_ms},
-        "queries_per_s": {"fwd": nq / (ms_fwd * 1e-3), "fwd_bwd_plain": nq / (ms_step * 1e-3)},
+                     "flops_per_pair": FLOPS_PER_PAIR_FWD, "pairs_per_launch": pairs,
+                     "avg_launch_ms": ms_bnd},
+        "batched_vs_plain": {
+            "mesh_2^20": {"batched_fwd_bwd_qps": nq / (ms_step * 1e-3),
+                          "plain_fwd_bwd_qps": nq / (ms_step_plain * 1e-3),
+                          "batched_fwd_qps": nq / (ms_fwd_b * 1e-3),
+                          "plain_fwd_qps": nq / (ms_fwd * 1e-3),
+                          "ratio_fwd_bwd": ms_step_plain / ms_step},
+            **extra.get("c4", {})},
+        "kernels_ms": {"crossings": ms_cross, "boundary": ms_bnd, "plain_forward": ms_fwd,
+                       "plain_backward": ms_bwd, "batched_forward": ms_fwd_b, "batched_backward": ms_bwd_b,
+                       "bvh_build": build_ms, "batch_create": batch_ms},
+        "workloads": {k: v for k, v in extra.items() if k != "c4"},
         "parity": parity,
         "cpu_baseline": cpu,
     }
@@ -197,6 +251,97 @@ def main():
         out["value"] = None
         out["note"] = "parity sample failed: throughput withheld"
     print(json.dumps(out))
+
+
+def run_others(torch, W, T, others, d3, args, dev):
+    res = {}
+    reps = max(3, args.steps // 4)
+    # --- 256-surface batch: batched persistent launch vs a loop of plain calls
+    CB = others["c4"]
+    surfs, P = [], []
+    for Mk, Qk in zip(CB.meshes, CB.queries):
+        V, F, bnd, off, idx = upload_mesh(torch, W, Mk, dev)
+        surfs.append({"V": V, "F": F, "bnd": bnd, "loop_off": off, "nq": len(Qk), "nb": len(idx)})
+        P.append(Qk)
+    P = np.concatenate(P, 0)
+    q = soa(torch, P, dev)
+    nq = len(P)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B = W.Batch(surfs, CB.direction, tune_mode=1)
+    torch.cuda.synchronize()
+    create_ms = (time.perf_counter() - t0) * 1e3
+    w = torch.empty(nq, dtype=torch.float32, device=dev)
+    t0 = time.perf_counter()
+    B.eval(*q, w_out=w, want_chi=False)          # autotunes, then captures
+    torch.cuda.synchronize()
+    first_ms = (time.perf_counter() - t0) * 1e3
+    info = B.info()
+    bvhs = [W.BVH(s["V"], s["F"], CB.direction) for s in surfs]
+    offs = np.concatenate([[0], np.cumsum([s["nq"] for s in surfs])])
+    wp = torch.empty(nq, dtype=torch.float32, device=dev)
+    g = torch.ones(nq, dtype=torch.float32, device=dev)
+
+    def plain_fwd():
+        for k, s in enumerate(surfs):
+            a, b = int(offs[k]), int(offs[k + 1])
+            W.eval_3d(bvhs[k], s["bnd"], s["loop_off"], q[0][a:b], q[1][a:b], q[2][a:b],
+                      want_chi=False, w_out=wp[a:b])
+
+    def plain_bwd():
+        for k, s in enumerate(surfs):
+            a, b = int(offs[k]), int(offs[k + 1])
+            W.backward(s["bnd"], s["loop_off"], q[0][a:b], q[1][a:b], q[2][a:b], g[a:b])
+
+    ms_bf = T.ms(lambda: B.eval(*q, w_out=w, want_chi=False), reps)
+    ms_bb = T.ms(lambda: B.backward(*q, g), reps)
+    ms_pf = T.ms(plain_fwd, reps)
+    ms_pb = T.ms(plain_bwd, reps)
+    same = bool(torch.equal(w, wp))
+    pairs = info["total_pairs"]
+    res["c4"] = {"surfaces_256": {
+        "queries": nq, "pairs": pairs, "triangles": int(sum(m.F.shape[0] for m in CB.meshes)),
+        "batched_fwd_ms": ms_bf, "plain_fwd_ms": ms_pf, "batched_bwd_ms": ms_bb, "plain_bwd_ms": ms_pb,
+        "batched_fwd_bwd_qps": nq / ((ms_bf + ms_bb) * 1e-3), "plain_fwd_bwd_qps": nq / ((ms_pf + ms_pb) * 1e-3),
+        "ratio_fwd": ms_pf / ms_bf, "ratio_fwd_bwd": (ms_pf + ms_pb) / (ms_bf + ms_bb),
+        "boundary_TFLOPs_batched_fwd": pairs * FLOPS_PER_PAIR_FWD / (ms_bf * 1e-3) / 1e12,
+        "tile": info["tile"], "wg_per_cu": info["wg_per_cu"], "graph": info["graph"],
+        "create_ms": create_ms, "first_eval_ms_incl_tuning": first_ms, "tune_ms": info["tune_us"] / 1e3,
+        "batched_equals_plain": same}}
+    B.free()
+    del bvhs
+    # --- adjoint workload: boundary refined to 2048 edges, 2^18 queries
+    M5 = others["c5_mesh"]
+    P5 = synth.box_queries(M5.V, 1 << 18, 13)
+    t5 = torch.from_numpy(synth.targets01(len(P5), 14)).to(dev)
+    V, F, bnd, off, idx = upload_mesh(torch, W, M5, dev)
+    bvh5 = W.BVH(V, F, d3)
+    q5 = soa(torch, P5, dev)
+    w5 = torch.empty(len(P5), dtype=torch.float32, device=dev)
+
+    def step5():
+        W.eval_3d(bvh5, bnd, off, *q5, want_chi=False, w_out=w5)
+        return W.backward(bnd, off, *q5, 2.0 * (w5 - t5))
+
+    ms5 = T.ms(step5, reps)
+    gw5 = torch.ones(len(P5), dtype=torch.float32, device=dev)
+    ms5b = T.ms(lambda: W.backward(bnd, off, *q5, gw5), reps)
+    p5 = len(P5) * len(idx)
+    res["adjoint_2048_edges_2^18"] = {"fwd_bwd_ms": ms5, "bwd_ms": ms5b, "queries_per_s": len(P5) / (ms5 * 1e-3),
+                                      "bwd_TFLOPs": p5 * FLOPS_PER_PAIR_BWD / (ms5b * 1e-3) / 1e12}
+    # --- 2D workloads
+    C1 = synth.star2d()
+    ctrl = torch.from_numpy(C1.ctrl).to(dev)
+    xs = torch.from_numpy(synth.grid_axis(-1.5, 1.5, 128)).to(dev)
+    ms1 = T.ms(lambda: W.eval_2d(ctrl, C1.loop_off, C1.closed, xs, xs, grid=True), reps)
+    res["2d_star_fp64_grid_128^2"] = {"ms": ms1, "queries_per_s": 128 * 128 / (ms1 * 1e-3)}
+    C2 = synth.loops2d()
+    ctrl2 = torch.from_numpy(C2.ctrl).to(dev)
+    xs2 = torch.from_numpy(synth.grid_axis(-1.2, 1.2, 2048, np.float32)).to(dev)
+    ms2 = T.ms(lambda: W.eval_2d(ctrl2, C2.loop_off, C2.closed, xs2, xs2, grid=True), reps)
+    res["2d_loops_fp32_grid_2048^2"] = {"ms": ms2, "queries_per_s": 2048 * 2048 / (ms2 * 1e-3),
+                                        "hbm_GBs_outputs": 2048 * 2048 * 8 / (ms2 * 1e-3) / 1e9}
+    return res
 
 
 if __name__ == "__main__":

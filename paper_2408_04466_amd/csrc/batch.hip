@@ -46,8 +46,20 @@ struct SurfDesc {
   int64_t pv_off;      // backward: first float of its vertex partials
   int64_t pl_off;      // backward: first float of its loop partials
   int32_t tiles_bwd;   // backward tiles of this surface
+  int32_t groups;      // backward: groups of kRowsPerGroup partial rows
+  int64_t tmp_off;     // backward: first double of its group sums
+};
+
+// One workgroup of the first reduction stage: columns [col0, col0 + 256) of
+// row group `group` of surface `surf`.
+struct RBlock {
+  int32_t surf;
+  int32_t group;
+  int32_t col0;
   int32_t pad;
 };
+
+constexpr int kRowsPerGroup = 32;
 
 struct Item {
   int32_t surf;
@@ -161,29 +173,48 @@ __global__ __launch_bounds__(kThreads) void k_batch_bwd(BwdArgs a) {
   }
 }
 
-// out[3 * (bnd_off + v) + c] = -(1/4pi) * sum over the surface's partial rows
-// (+ the loop share for a loop's first vertex), in row order, float64.
-__global__ void k_batch_reduce(const SurfDesc* __restrict__ descs, const int32_t* __restrict__ surf_of,
-                               const int32_t* __restrict__ loops, const float* __restrict__ pv,
-                               const float* __restrict__ pl, int64_t total3, float* __restrict__ out) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= total3) return;
-  const int64_t gv = t / 3;
-  const int c = (int)(t % 3);
-  const SurfDesc D = descs[surf_of[gv]];
-  const int v = (int)(gv - D.bnd_off);
+// Boundary-vertex gradients from the per-(tile, wavefront) partial rows, in
+// two fixed-order float64 stages (the same grouping as the single-surface
+// adjoint, so both give identical bits).  Stage 1: one group of
+// kRowsPerGroup rows per column, plus the per-loop closing share at a loop's
+// first vertex.
+__global__ void k_batch_rows(const SurfDesc* __restrict__ descs, const RBlock* __restrict__ blocks,
+                             const int32_t* __restrict__ loops, const float* __restrict__ pv,
+                             const float* __restrict__ pl, double* __restrict__ tmp) {
+  const RBlock rb = blocks[blockIdx.x];
+  const SurfDesc D = descs[rb.surf];
   const int64_t n = (int64_t)D.nb * 3;
+  const int64_t t = (int64_t)rb.col0 + threadIdx.x;
+  if (t >= n) return;
+  const int v = (int)(t / 3), c = (int)(t % 3);
   const int32_t* lo = loops + D.loop_off;
   int lf = -1;
   for (int l = 0; l < D.nloops; ++l)
-    if (lo[l] == v) lf = l;
+    if (lo[l] == v && lo[l + 1] > v) lf = l;
   const int64_t rows = (int64_t)D.tiles_bwd * adj::kWaves;
-  const float* p = pv + D.pv_off + 3 * (int64_t)v + c;
+  const int64_t r0 = (int64_t)rb.group * kRowsPerGroup;
+  const int64_t r1 = min(rows, r0 + kRowsPerGroup);
+  const float* p = pv + D.pv_off;
+  const float* q = pl + D.pl_off;
   double s = 0.0;
-  for (int64_t r = 0; r < rows; ++r) {
-    s += (double)p[r * n];
-    if (lf >= 0) s += (double)pl[D.pl_off + (r * D.nloops + lf) * 3 + c];
+  for (int64_t r = r0; r < r1; ++r) {
+    s += (double)p[r * n + t];
+    if (lf >= 0) s += (double)q[(r * D.nloops + lf) * 3 + c];
   }
+  tmp[D.tmp_off + (int64_t)rb.group * n + t] = s;
+}
+
+// Stage 2: out[3 * (bnd_off + v) + c] = -(1/4pi) * sum over the surface's
+// groups, in group order.
+__global__ void k_batch_groups(const SurfDesc* __restrict__ descs, const int32_t* __restrict__ surf_of,
+                               const double* __restrict__ tmp, int64_t total3, float* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total3) return;
+  const SurfDesc D = descs[surf_of[t / 3]];
+  const int64_t n = (int64_t)D.nb * 3;
+  const int64_t col = t - 3 * D.bnd_off;
+  double s = 0.0;
+  for (int g = 0; g < D.groups; ++g) s += tmp[D.tmp_off + (int64_t)g * n + col];
   out[t] = (float)(-s * 0.07957747154594767 + 0.0);
 }
 
@@ -224,6 +255,10 @@ struct wn_batch {
   int32_t n_bitems = 0;
   float* d_pv = nullptr;
   float* d_pl = nullptr;
+  double* d_tmp = nullptr;
+  wn::RBlock* d_rblocks = nullptr;
+  int32_t n_rblocks = 0;
+  int64_t n_tmp = 0;
   // graph of the forward
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -537,6 +572,15 @@ wn_status wn_batch_create(const wn_surface* surfs, int32_t ns, const double dir[
     D.pl_off = pl;
     pv += (int64_t)D.tiles_bwd * wn::adj::kWaves * D.nb * 3;
     pl += (int64_t)D.tiles_bwd * wn::adj::kWaves * D.nloops * 3;
+    D.groups = (int32_t)(((int64_t)D.tiles_bwd * wn::adj::kWaves + wn::kRowsPerGroup - 1) / wn::kRowsPerGroup);
+    D.tmp_off = b->n_tmp;
+    b->n_tmp += (int64_t)D.groups * D.nb * 3;
+  }
+  std::vector<wn::RBlock> rblocks;
+  for (int32_t i = 0; i < ns; ++i) {
+    const wn::SurfDesc& D = b->desc[i];
+    for (int32_t g = 0; g < D.groups; ++g)
+      for (int64_t c0 = 0; c0 < (int64_t)D.nb * 3; c0 += 256) rblocks.push_back({i, g, (int32_t)c0, 0});
   }
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
@@ -555,6 +599,12 @@ wn_status wn_batch_create(const wn_surface* surfs, int32_t ns, const double dir[
     if (nbs[i] > 0)
       chk(hipMemcpyAsync(b->d_bnd + 3 * b->desc[i].bnd_off, surfs[i].bnd_xyz, (size_t)nbs[i] * 3 * sizeof(float),
                          hipMemcpyDeviceToDevice, s));
+  b->n_rblocks = (int32_t)rblocks.size();
+  if (e == hipSuccess && !rblocks.empty()) {
+    chk(hipMalloc((void**)&b->d_rblocks, rblocks.size() * sizeof(wn::RBlock)));
+    if (e == hipSuccess)
+      chk(hipMemcpy(b->d_rblocks, rblocks.data(), rblocks.size() * sizeof(wn::RBlock), hipMemcpyHostToDevice));
+  }
   if (e == hipSuccess) chk(hipStreamSynchronize(s));
   if (e != hipSuccess) return bail(hip_fail(e, "wn_batch_create"));
   wn_status st = upload_items(b, b->tile);
@@ -608,6 +658,8 @@ wn_status wn_batch_free(wn_batch* b) {
   hipFree(b->d_bitems);
   hipFree(b->d_pv);
   hipFree(b->d_pl);
+  hipFree(b->d_tmp);
+  hipFree(b->d_rblocks);
   delete b;
   return WN_OK;
 }
@@ -675,6 +727,7 @@ wn_status wn_backward_batched(wn_batch* b, const float* qx, const float* qy, con
     }
     WN_HIP(hipMalloc((void**)&b->d_pv, std::max<int64_t>(pv, 1) * sizeof(float)), "backward partials");
     WN_HIP(hipMalloc((void**)&b->d_pl, std::max<int64_t>(pl, 1) * sizeof(float)), "backward partials");
+    WN_HIP(hipMalloc((void**)&b->d_tmp, std::max<int64_t>(b->n_tmp, 1) * sizeof(double)), "backward partials");
   }
   wn::BwdArgs a;
   a.descs = b->d_desc;
@@ -697,8 +750,13 @@ wn_status wn_backward_batched(wn_batch* b, const float* qx, const float* qy, con
   WN_HIP(hipGetLastError(), "batched backward");
   if (grad_bnd && b->total_b > 0) {
     const int64_t n3 = 3 * b->total_b;
-    hipLaunchKernelGGL(wn::k_batch_reduce, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, b->d_desc,
-                       b->d_surf_of, b->d_loops, b->d_pv, b->d_pl, n3, grad_bnd);
+    if (b->n_rblocks > 0) {
+      hipLaunchKernelGGL(wn::k_batch_rows, dim3((unsigned)b->n_rblocks), dim3(256), 0, s, b->d_desc,
+                         b->d_rblocks, b->d_loops, b->d_pv, b->d_pl, b->d_tmp);
+      WN_HIP(hipGetLastError(), "batched reduce");
+    }
+    hipLaunchKernelGGL(wn::k_batch_groups, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, b->d_desc,
+                       b->d_surf_of, b->d_tmp, n3, grad_bnd);
     WN_HIP(hipGetLastError(), "batched reduce");
   }
   return WN_OK;
