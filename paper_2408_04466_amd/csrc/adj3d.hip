@@ -12,6 +12,7 @@ using namespace adj;
 
 __global__ __launch_bounds__(kThreads) void k_adj3d(AdjArgs a, LoopTable L) {
   __shared__ float4 sv[kChunk];
+  __shared__ float4 rsw[kWaves * kRowFloats / 4];
   const int wave = threadIdx.x >> 6;
   const int64_t bw = (int64_t)blockIdx.x * kWaves + wave;     // partial row
   float* pv = a.partial ? a.partial + bw * (int64_t)a.nb * 3 : nullptr;
@@ -21,7 +22,7 @@ __global__ __launch_bounds__(kThreads) void k_adj3d(AdjArgs a, LoopTable L) {
   bool ok[kQPL];
   const int64_t q0 = (int64_t)blockIdx.x * kTile;
   load_tile(S, a.qx, a.qy, a.qz, a.gw, q0, min((int64_t)kTile, a.nq - q0), qi, ok);
-  walk(S, a.bnd, a.nb, bnd::KernargLoops{L}, sv, pv, pl);
+  walk(S, a.bnd, a.nb, bnd::KernargLoops{L}, sv, reinterpret_cast<float*>(rsw), pv, pl);
   store_gq(S, qi, ok, a.gq);
 }
 

@@ -12,11 +12,13 @@
 // A lane holds kQPL queries; the workgroup stages the boundary in LDS and
 // every lane walks the same vertex sequence.  A vertex's gradient is complete
 // one step after the vertex is visited (its two edges are then done); it is
-// summed over the lane's queries in registers, over the wavefront with DPP
-// moves, and written once per (tile, wavefront, vertex) as a float32 partial.
-// The closing edge's share of each loop's first vertex goes to a separate
-// per-loop partial.  The partials are reduced in a fixed order in float64 by
-// separate kernels, so grad_bnd is bitwise reproducible.
+// summed over the lane's queries in registers and over each row of 16 lanes
+// with DPP moves; the four row sums wait in LDS until kBlk consecutive
+// vertices are complete, and one coalesced store then writes their sums as
+// float32 partials, one per (tile, wavefront, vertex).  The closing edge's
+// share of each loop's first vertex goes to a separate per-loop partial.  The
+// partials are reduced in a fixed order in float64 by separate kernels, so
+// grad_bnd is bitwise reproducible.
 #pragma once
 
 #include "bndloop.hpp"
@@ -30,6 +32,8 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kQPL = 4;
 constexpr int kChunk = 512;
 constexpr int kTile = kThreads * 4;   // queries per tile (kQPL per lane)
+constexpr int kBlk = 16;              // vertices per partial store
+constexpr int kRowFloats = kBlk * 12; // LDS row sums per wavefront: [kBlk][3][4 rows]
 constexpr float kInv4Pi = 0.07957747154594767f;
 
 template <int CTRL, int ROW_MASK>
@@ -50,31 +54,93 @@ __device__ __forceinline__ float wave_sum_last(float v) {
   return v;
 }
 
+// Sum over each row of 16 lanes (every lane of the row holds it).
+__device__ __forceinline__ float row_sum(float v) {
+  v += dpp<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  v += dpp<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  v += dpp<0x124, 0xF>(v);   // row_ror:4
+  v += dpp<0x128, 0xF>(v);   // row_ror:8
+  return v;
+}
+
+// Wavefront-scope ordering of the LDS row-sum block between the lanes that
+// write it and the lanes that read it.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Vertex va's partial (three values per lane): row sums into the wavefront's
+// LDS block at [va % kBlk][c][row]; once the block is full (or va is the
+// last vertex), lane t < 3 n adds the four row sums of entry t in row order
+// and stores the block's n vertices to pv with one coalesced store.
+__device__ __forceinline__ void park(float* rs, float* pv, int va, int nb, const float acc[3], int lane) {
+  const float r0 = row_sum(acc[0]);
+  const float r1 = row_sum(acc[1]);
+  const float r2 = row_sum(acc[2]);
+  const int slot = va % kBlk;
+  if ((lane & 15) == 15) {
+    float* d = rs + slot * 12 + (lane >> 4);
+    d[0] = r0;
+    d[4] = r1;
+    d[8] = r2;
+  }
+  if (slot == kBlk - 1 || va == nb - 1) {
+    wave_sync();
+    const int n = slot + 1;
+    if (lane < 3 * n) {
+      const float4 x = reinterpret_cast<const float4*>(rs)[lane];
+      pv[3 * (int64_t)(va - slot) + lane] = __fadd_rn(__fadd_rn(__fadd_rn(x.x, x.y), x.z), x.w);
+    }
+    wave_sync();
+  }
+}
+
 struct QState {
   float px, py, pz, g;
   float gx, gy, gz;          // sum_e g c_e (1/|a'| + 1/|b'|)
-  float ax, ay, az, ra, ia;  // previous vertex relative to p, |.|, 1/|.|
-  float fx, fy, fz, rf, iff; // first vertex of the current loop
 };
 
+// A boundary vertex seen from one query: v - p, |v - p|, 1/|v - p|.
+struct Rel {
+  float x, y, z, r, i;
+};
+
+__device__ __forceinline__ Rel rel(const QState& s, const float4& v) {
+  Rel q;
+  q.x = __fsub_rn(v.x, s.px);
+  q.y = __fsub_rn(v.y, s.py);
+  q.z = __fsub_rn(v.z, s.pz);
+  const float r2 = __fmaf_rn(q.x, q.x, __fmaf_rn(q.y, q.y, __fmul_rn(q.z, q.z)));
+  q.i = __builtin_amdgcn_rsqf(r2);
+  q.r = __fmul_rn(r2, q.i);
+  return q;
+}
+
 // Edge a->b for one query: c = g K (a' x b'); adds c (1/|a'| + 1/|b'|) to
-// the query gradient.
-__device__ __forceinline__ void edge_grad(QState& s, float ax, float ay, float az, float ra,
-                                          float ia, float bx, float by, float bz, float rb,
-                                          float ib, float& cx, float& cy, float& cz) {
-  const float crx = __fmaf_rn(ay, bz, -__fmul_rn(az, by));
-  const float cry = __fmaf_rn(az, bx, -__fmul_rn(ax, bz));
-  const float crz = __fmaf_rn(ax, by, -__fmul_rn(ay, bx));
-  const float dot = __fmaf_rn(ax, bx, __fmaf_rn(ay, by, __fmul_rn(az, bz)));
-  const float den = __fmaf_rn(ra, rb, dot);
+// the query gradient and c/|a'|, c/|b'| to the two vertex accumulators.
+__device__ __forceinline__ void edge_grad(QState& s, const Rel& a, const Rel& b, float* acc_a,
+                                          float* acc_b) {
+  const float crx = __fmaf_rn(a.y, b.z, -__fmul_rn(a.z, b.y));
+  const float cry = __fmaf_rn(a.z, b.x, -__fmul_rn(a.x, b.z));
+  const float crz = __fmaf_rn(a.x, b.y, -__fmul_rn(a.y, b.x));
+  const float dot = __fmaf_rn(a.x, b.x, __fmaf_rn(a.y, b.y, __fmul_rn(a.z, b.z)));
+  const float den = __fmaf_rn(a.r, b.r, dot);
   const float gk = __fmul_rn(s.g, __builtin_amdgcn_rcpf(den));
-  cx = __fmul_rn(gk, crx);
-  cy = __fmul_rn(gk, cry);
-  cz = __fmul_rn(gk, crz);
-  const float h = __fadd_rn(ia, ib);
+  const float cx = __fmul_rn(gk, crx);
+  const float cy = __fmul_rn(gk, cry);
+  const float cz = __fmul_rn(gk, crz);
+  const float h = __fadd_rn(a.i, b.i);
   s.gx = __fmaf_rn(cx, h, s.gx);
   s.gy = __fmaf_rn(cy, h, s.gy);
   s.gz = __fmaf_rn(cz, h, s.gz);
+  acc_a[0] = __fmaf_rn(cx, a.i, acc_a[0]);
+  acc_a[1] = __fmaf_rn(cy, a.i, acc_a[1]);
+  acc_a[2] = __fmaf_rn(cz, a.i, acc_a[2]);
+  acc_b[0] = __fmaf_rn(cx, b.i, acc_b[0]);
+  acc_b[1] = __fmaf_rn(cy, b.i, acc_b[1]);
+  acc_b[2] = __fmaf_rn(cz, b.i, acc_b[2]);
 }
 
 __device__ __forceinline__ void put3(float* dst, const float acc[3], int lane) {
@@ -104,70 +170,82 @@ __device__ __forceinline__ void load_tile(QState* S, const float* qx, const floa
   }
 }
 
+__device__ __forceinline__ void zero3(float* a) { a[0] = a[1] = a[2] = 0.f; }
+
+// Edge A->B for every query of the lane; the partial of vertex A is then
+// complete and goes out (summed over the wavefront) to row entry `va`.
+__device__ __forceinline__ void step(QState* S, const Rel* A, const Rel* B, float* accA, float* accB,
+                                     float* pv, float* rs, int va, int nb, int lane) {
+  zero3(accB);
+#pragma unroll
+  for (int k = 0; k < kQPL; ++k) edge_grad(S[k], A[k], B[k], accA, accB);
+  if (pv) park(rs, pv, va, nb, accA, lane);
+}
+
 // Walk the boundary for one tile.  pv: this wavefront's partial row
-// [nb][3] (or null), pl: its per-loop row [nloops][3].
+// [nb][3] (or null), pl: its per-loop row [nloops][3] (the closing edge's
+// share of each loop's first vertex), rsw: the workgroup's LDS row-sum
+// blocks [kWaves][kRowFloats].  Loops are taken as straight vertex ranges
+// (like the forward walk), two vertices per step; vertices complete in
+// increasing order 0 .. nb-1.
 template <class Loops>
 __device__ __forceinline__ void walk(QState* S, const float* __restrict__ bnd, int nb, const Loops& L,
-                                     float4* sv, float* pv, float* pl) {
+                                     float4* sv, float* rsw, float* pv, float* pl) {
   const int lane = threadIdx.x & 63;
-  float accp[3] = {0.f, 0.f, 0.f};   // previous vertex, summed over the lane's queries
-  int loop = 0;
+  float* rs = rsw + (threadIdx.x >> 6) * kRowFloats;
+  Rel F[kQPL], A[kQPL], B[kQPL];   // loop's first vertex; A = last vertex visited
+  float accA[3], accB[3];          // pending partial of vertex A (and scratch for B)
+  zero3(accA);
+  int l = 0;
   for (int c0 = 0; c0 < nb; c0 += kChunk) {
-    const int cnt = min(kChunk, nb - c0);
+    const int c1 = min(c0 + kChunk, nb);
     __syncthreads();
-    for (int j = threadIdx.x; j < cnt; j += kThreads) {
+    for (int j = threadIdx.x; j < c1 - c0; j += kThreads) {
       const int i = c0 + j;
       sv[j] = make_float4(bnd[3 * i], bnd[3 * i + 1], bnd[3 * i + 2], 0.f);
     }
     __syncthreads();
-    for (int j = 0; j < cnt; ++j) {
-      const int i = c0 + j;
-      const float4 v = sv[j];
-      while (L.off(loop + 1) <= i) ++loop;
-      const bool starts = (i == L.off(loop));
-      const bool ends = (i + 1 == L.off(loop + 1));
-      float accc[3] = {0.f, 0.f, 0.f};   // this vertex
-      float accf[3] = {0.f, 0.f, 0.f};   // closing-edge share of the loop's first vertex
+    for (; l < L.n() && L.off(l) < c1; ++l) {
+      const int ls = L.off(l), le = L.off(l + 1);
+      int j = max(ls, c0);
+      const int j1 = min(le, c1);
+      if (j == ls) {
+        const float4 v = sv[j - c0];
 #pragma unroll
-      for (int k = 0; k < kQPL; ++k) {
-        QState& s = S[k];
-        const float bx = __fsub_rn(v.x, s.px), by = __fsub_rn(v.y, s.py), bz = __fsub_rn(v.z, s.pz);
-        const float r2 = __fmaf_rn(bx, bx, __fmaf_rn(by, by, __fmul_rn(bz, bz)));
-        const float ib = __builtin_amdgcn_rsqf(r2);
-        const float rb = __fmul_rn(r2, ib);
-        if (starts) {
-          s.fx = bx; s.fy = by; s.fz = bz; s.rf = rb; s.iff = ib;
-        } else {
-          float cx, cy, cz;
-          edge_grad(s, s.ax, s.ay, s.az, s.ra, s.ia, bx, by, bz, rb, ib, cx, cy, cz);
-          accp[0] = __fmaf_rn(cx, s.ia, accp[0]);
-          accp[1] = __fmaf_rn(cy, s.ia, accp[1]);
-          accp[2] = __fmaf_rn(cz, s.ia, accp[2]);
-          accc[0] = __fmaf_rn(cx, ib, accc[0]);
-          accc[1] = __fmaf_rn(cy, ib, accc[1]);
-          accc[2] = __fmaf_rn(cz, ib, accc[2]);
+        for (int k = 0; k < kQPL; ++k) {
+          F[k] = rel(S[k], v);
+          A[k] = F[k];
         }
-        if (ends) {
-          // closing edge last -> first
-          float cx, cy, cz;
-          edge_grad(s, bx, by, bz, rb, ib, s.fx, s.fy, s.fz, s.rf, s.iff, cx, cy, cz);
-          accc[0] = __fmaf_rn(cx, ib, accc[0]);
-          accc[1] = __fmaf_rn(cy, ib, accc[1]);
-          accc[2] = __fmaf_rn(cz, ib, accc[2]);
-          accf[0] = __fmaf_rn(cx, s.iff, accf[0]);
-          accf[1] = __fmaf_rn(cy, s.iff, accf[1]);
-          accf[2] = __fmaf_rn(cz, s.iff, accf[2]);
-        }
-        s.ax = bx; s.ay = by; s.az = bz; s.ra = rb; s.ia = ib;
+        zero3(accA);
+        ++j;
       }
-      if (pv) {
-        if (!starts) put3(pv + 3 * (int64_t)(i - 1), accp, lane);   // vertex i-1 is complete
-        if (ends) {
-          put3(pv + 3 * (int64_t)i, accc, lane);
-          put3(pl + 3 * (int64_t)loop, accf, lane);
-        }
+      for (; j + 2 <= j1; j += 2) {
+        const float4 v0 = sv[j - c0];
+        const float4 v1 = sv[j + 1 - c0];
+#pragma unroll
+        for (int k = 0; k < kQPL; ++k) B[k] = rel(S[k], v0);
+        step(S, A, B, accA, accB, pv, rs, j - 1, nb, lane);
+#pragma unroll
+        for (int k = 0; k < kQPL; ++k) A[k] = rel(S[k], v1);
+        step(S, B, A, accB, accA, pv, rs, j, nb, lane);
       }
-      accp[0] = accc[0]; accp[1] = accc[1]; accp[2] = accc[2];
+      if (j < j1) {
+        const float4 v0 = sv[j - c0];
+#pragma unroll
+        for (int k = 0; k < kQPL; ++k) B[k] = rel(S[k], v0);
+        step(S, A, B, accA, accB, pv, rs, j - 1, nb, lane);
+#pragma unroll
+        for (int k = 0; k < kQPL; ++k) A[k] = B[k];
+        accA[0] = accB[0]; accA[1] = accB[1]; accA[2] = accB[2];
+        ++j;
+      }
+      if (j1 < le) break;            // the loop continues in the next chunk
+      // closing edge last -> first: completes the last vertex; the first
+      // vertex's share goes to the per-loop row
+      float accF[3];
+      step(S, A, F, accA, accF, pv, rs, le - 1, nb, lane);
+      if (pl) put3(pl + 3 * (int64_t)l, accF, lane);
+      zero3(accA);
     }
   }
 }

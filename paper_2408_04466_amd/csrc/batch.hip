@@ -153,6 +153,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_fwd(FwdArgs a) {
 
 __global__ __launch_bounds__(kThreads) void k_batch_bwd(BwdArgs a) {
   __shared__ float4 sv[adj::kChunk];
+  __shared__ float4 rsw[adj::kWaves * adj::kRowFloats / 4];
   __shared__ int s_item;
   const int wave = threadIdx.x >> 6;
   for (;;) {
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_bwd(BwdArgs a) {
     int64_t qi[adj::kQPL];
     bool ok[adj::kQPL];
     adj::load_tile(S, a.qx, a.qy, a.qz, a.gw, item.q0, item.cnt, qi, ok);
-    if (D.nb > 0) adj::walk(S, a.bnd + 3 * D.bnd_off, D.nb, L, sv, pv, pl);
+    if (D.nb > 0) adj::walk(S, a.bnd + 3 * D.bnd_off, D.nb, L, sv, reinterpret_cast<float*>(rsw), pv, pl);
     adj::store_gq(S, qi, ok, a.gq);
   }
 }
@@ -457,7 +458,7 @@ wn_status autotune(wn_batch* b, const wn::FwdArgs& base, hipStream_t s) {
       tiles = {256, 512, 1024, 2048, 4096};
       wgs = {1, 2, 4, 8};
     } else {
-      tiles = {512, 1024, 2048};
+      tiles = {256, 512, 1024, 2048};
       wgs = {2, 4, 8};
     }
     hipEvent_t e0, e1;

@@ -145,7 +145,7 @@ def test_autotuner_and_cache(small_batch, tmp_path):
         w, chi = B.eval(*q)
         torch.cuda.synchronize()
         info = B.info()
-        assert cache.exists() and info["tile"] in (512, 1024, 2048) and info["wg_per_cu"] in (2, 4, 8)
+        assert cache.exists() and info["tile"] in (256, 512, 1024, 2048) and info["wg_per_cu"] in (2, 4, 8)
         assert str(info["tile"]) in cache.read_text()
         B2 = W.Batch(surfs, d, tune_mode=2)
         w2, chi2 = B2.eval(*q)
