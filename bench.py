@@ -227,7 +227,8 @@ def main():
                                "boundary integral) + backward (adjoint w.r.t. queries and boundary "
                                "vertices) through the batched persistent path",
                    "queries": nq, "triangles": int(M.F.shape[0]), "boundary_edges": nb,
-                   "path": "batched (1 surface, hipGraph forward)"},
+                   "path": "batched (1 surface, hipGraph forward)",
+                   "batch_tuning": {k: batch.info()[k] for k in ("tile", "wg_per_cu", "mode")}},
         "roofline": {"bound": "alu", "kernel": "k_bnd3d (boundary integral)",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
@@ -306,6 +307,7 @@ def run_others(torch, W, T, others, d3, args, dev):
         "ratio_fwd": ms_pf / ms_bf, "ratio_fwd_bwd": (ms_pf + ms_pb) / (ms_bf + ms_bb),
         "boundary_TFLOPs_batched_fwd": pairs * FLOPS_PER_PAIR_FWD / (ms_bf * 1e-3) / 1e12,
         "tile": info["tile"], "wg_per_cu": info["wg_per_cu"], "graph": info["graph"],
+        "forward_mode": "split" if info["mode"] else "fused",
         "create_ms": create_ms, "first_eval_ms_incl_tuning": first_ms, "tune_ms": info["tune_us"] / 1e3,
         "batched_equals_plain": same}}
     B.free()

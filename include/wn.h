@@ -239,10 +239,11 @@ typedef struct {
  * wn_batch_create -- build the BVH of every surface (one shared ray direction
  * `dir`), a descriptor table, the boundary arena and a work list of
  * (surface, query tile) items in longest-processing-time-first order.
- *  tune_mode  0: default tile (1024 queries) and 4 workgroups per compute
- *             unit; 1: quick autotune, 2: full autotune of (tile, workgroups
- *             per CU), run on the first wn_eval_batched with its real inputs;
- *             results are cached in the JSON file named by $WN_TUNE_CACHE.
+ *  tune_mode  0: default tile (1024 queries), 4 workgroups per compute
+ *             unit, fused forward; 1: quick autotune, 2: full autotune of
+ *             (tile, workgroups per CU, fused or split forward), run on the
+ *             first wn_eval_batched with its real inputs; results are cached
+ *             in the JSON file named by $WN_TUNE_CACHE.
  * Synchronises `stream`.  Errors: INVALID_ARGUMENT (naming the surface),
  * UNSUPPORTED, OUT_OF_MEMORY, HIP.
  * ------------------------------------------------------------------------- */
@@ -257,9 +258,11 @@ wn_status wn_batch_free(wn_batch* batch);
  *  qx, qy, qz  device [sum nq] float32, the surfaces' queries concatenated in
  *              surface order.
  *  w_out       device [sum nq] float32 out; chi_out device int32 or NULL.
- * The first call captures a counter-reset kernel and the persistent kernel
- * into a hipGraph (after autotuning when requested); later calls replay it,
- * patching the kernel arguments when the pointers change.  Set
+ * The first call captures a counter-reset kernel and the persistent
+ * kernel(s) into a hipGraph (after autotuning when requested); later calls
+ * replay it, patching the kernel arguments when the pointers change.  The
+ * split forward without chi_out keeps the crossing counts in a buffer the
+ * batch allocates on first use (4 bytes per query).  Set
  * $WN_FORCE_NO_GRAPH to launch directly (identical results).
  * ------------------------------------------------------------------------- */
 wn_status wn_eval_batched(wn_batch* batch, const float* qx, const float* qy, const float* qz,
@@ -274,10 +277,12 @@ wn_status wn_eval_batched(wn_batch* batch, const float* qx, const float* qy, con
 wn_status wn_backward_batched(wn_batch* batch, const float* qx, const float* qy, const float* qz,
                               const float* grad_w, float* grad_q, float* grad_bnd, void* stream);
 
-/* info[0..7] = total queries, total boundary vertices, total (query, edge)
- * pairs, forward work items, tile size, workgroups per CU, graph in use
- * (0/1), autotuning time in microseconds. */
-wn_status wn_batch_info(const wn_batch* batch, int64_t info[8]);
+/* info[0..8] = total queries, total boundary vertices, total (query, edge)
+ * pairs, forward work items, tile size, workgroups per CU (0: one
+ * workgroup per item instead of a persistent grid), graph in use
+ * (0/1), autotuning time in microseconds, forward mode (0: fused kernel,
+ * 1: crossing kernel then boundary kernel). */
+wn_status wn_batch_info(const wn_batch* batch, int64_t info[9]);
 
 #ifdef __cplusplus
 }

@@ -269,9 +269,9 @@ class Batch:
         self.total_b = nb_tot
 
     def info(self) -> dict:
-        v = (C.c_int64 * 8)()
+        v = (C.c_int64 * 9)()
         check(lib().wn_batch_info(self._h, v), "wn_batch_info")
-        keys = ["total_q", "total_b", "total_pairs", "n_items", "tile", "wg_per_cu", "graph", "tune_us"]
+        keys = ["total_q", "total_b", "total_pairs", "n_items", "tile", "wg_per_cu", "graph", "tune_us", "mode"]
         return dict(zip(keys, v[:]))
 
     def eval(self, qx, qy, qz, want_chi: bool = True, w_out=None, chi_out=None, stream=None):

@@ -10,7 +10,10 @@ namespace {
 
 using namespace adj;
 
-__global__ __launch_bounds__(kThreads) void k_adj3d(AdjArgs a, LoopTable L) {
+// Four waves per SIMD: the register allocator then fits 128 registers,
+// spilling one pointer outside the walk.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_adj3d(AdjArgs a,
+                                                                                            LoopTable L) {
   __shared__ float4 sv[kChunk];
   __shared__ float4 rsw[kWaves * kRowFloats / 4];
   const int wave = threadIdx.x >> 6;

@@ -7,9 +7,12 @@
 // (tile size x (boundary edges + a crossing-count allowance)), the
 // longest-processing-time-first order, and a fixed grid of workgroups pulls
 // them from an atomic counter until the list is exhausted, so a few large
-// surfaces cannot leave most compute units idle at the end.  Tile size and
-// workgroups per compute unit come from a small autotuner that times
-// candidates on the first evaluation (optionally cached in a JSON file).
+// surfaces cannot leave most compute units idle at the end.  The forward
+// runs either fused (one kernel: traversal, then boundary walk, per query)
+// or split (a persistent crossing kernel, then a persistent boundary kernel,
+// each at its own register footprint).  Mode, tile size and workgroups per
+// compute unit come from a small autotuner that times candidates on the
+// first evaluation (optionally cached in a JSON file).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -73,8 +76,9 @@ struct FwdArgs {
   const SurfDesc* descs;
   const Item* items;
   int32_t n_items;
-  int32_t* counter;
-  const float* bnd;
+  int32_t* counter;        // [0]: fused or crossing kernel, [1]: boundary kernel
+  int32_t* chi_buf;        // split mode: crossing counts (chi_out or a batch buffer)
+  const double4* bndr;     // rotated boundary arena (bnd::stage_vertex of every vertex)
   const int32_t* loops;
   const float* qx;
   const float* qy;
@@ -102,35 +106,60 @@ struct BwdArgs {
 constexpr int kThreads = 256;
 
 __global__ void k_reset(int32_t* counter) {
-  if (threadIdx.x == 0) *counter = 0;
+  if (threadIdx.x < 2) counter[threadIdx.x] = 0;
 }
 
-// Pull the next item index (uniform across the workgroup).
+// Item lists and surface descriptors are written by the host before any
+// launch and only read by the kernels, so they are read through the
+// constant address space: with a wave-uniform index the compiler then uses
+// scalar loads and keeps the descriptor (frame, pointers, counts) in scalar
+// registers.
+template <class T>
+__device__ __forceinline__ T load_const(const T* p, int64_t i) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized records only");
+  const __attribute__((address_space(4))) uint32_t* src = (const __attribute__((address_space(4))) uint32_t*)(p + i);
+  T out;
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) dst[k] = src[k];
+  return out;
+}
+
+// Pull the next item index (uniform across the workgroup).  readfirstlane
+// tells the compiler so: the item and its surface descriptor are then read
+// with scalar loads into scalar registers instead of occupying vector
+// registers in every lane.
 __device__ __forceinline__ int next_item(int32_t* counter, int* s_item) {
   __syncthreads();
   if (threadIdx.x == 0) *s_item = atomicAdd(counter, 1);
   __syncthreads();
-  return *s_item;
+  return __builtin_amdgcn_readfirstlane(*s_item);
 }
 
+__device__ __forceinline__ CrossArgs cross_args(const SurfDesc& D) {
+  CrossArgs ca;
+  ca.F = D.F;
+  ca.nodes = D.nodes;
+  ca.tris = D.tris;
+  ca.Vr = D.Vr;
+  ca.leafbox = D.leafbox;
+  ca.leafz = D.leafz;
+  ca.nf = D.nf;
+  return ca;
+}
+
+// Fused mode: per query, the crossing count and then the boundary walk.
 __global__ __launch_bounds__(kThreads) void k_batch_fwd(FwdArgs a) {
   __shared__ double4 sv[bnd::kChunk];
   __shared__ int s_item;
   for (;;) {
     const int it = next_item(a.counter, &s_item);
     if (it >= a.n_items) return;
-    const Item item = a.items[it];
-    const SurfDesc D = a.descs[item.surf];
-    CrossArgs ca;
-    ca.F = D.F;
-    ca.nodes = D.nodes;
-    ca.tris = D.tris;
-    ca.Vr = D.Vr;
-    ca.leafbox = D.leafbox;
-    ca.leafz = D.leafz;
-    ca.nf = D.nf;
+    const Item item = load_const(a.items, it);
+    const SurfDesc D = load_const(a.descs, item.surf);
+    const CrossArgs ca = cross_args(D);
     const bnd::DeviceLoops L{a.loops + D.loop_off, D.nloops};
-    const float* bnd = a.bnd + 3 * D.bnd_off;
+    const bnd::StageCopy stage{a.bndr + D.bnd_off};
     int staged = -1;
     for (int r = 0; r < item.cnt; r += kThreads) {
       const bool ok = r + (int)threadIdx.x < item.cnt;
@@ -141,7 +170,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_fwd(FwdArgs a) {
       rotate(D.F, px, py, pz, s.Xp[0], s.Yp[0], s.Zp[0]);
       turns_init(s.T[0]);
       const int chi = (ok && fin) ? traverse<kShortStack>(ca, s.Xp[0], s.Yp[0], s.Zp[0]) : 0;
-      bnd::boundary_walk(s, D.F, bnd, D.nb, L, sv, staged);
+      bnd::boundary_walk(s, stage, D.nb, L, sv, staged);
       if (ok) {
         const bool valid = fin && chi != WN_CHI_INVALID;
         a.w[q] = valid ? turns_to_w(s.T[0], chi) : __int_as_float(0x7fc00000);
@@ -151,7 +180,60 @@ __global__ __launch_bounds__(kThreads) void k_batch_fwd(FwdArgs a) {
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_batch_bwd(BwdArgs a) {
+// Split mode, first kernel: crossing counts into chi_buf (WN_CHI_INVALID
+// for a non-finite query or an abandoned traversal).
+__global__ __launch_bounds__(kThreads) void k_batch_cross(FwdArgs a) {
+  __shared__ int s_item;
+  for (;;) {
+    const int it = next_item(a.counter, &s_item);
+    if (it >= a.n_items) return;
+    const Item item = load_const(a.items, it);
+    const SurfDesc D = load_const(a.descs, item.surf);
+    const CrossArgs ca = cross_args(D);
+    for (int r = threadIdx.x; r < item.cnt; r += kThreads) {
+      const int64_t q = item.q0 + r;
+      const float px = a.qx[q], py = a.qy[q], pz = a.qz[q];
+      int chi = WN_CHI_INVALID;
+      if (isfinite(px) && isfinite(py) && isfinite(pz)) {
+        double X, Y, Z;
+        rotate(D.F, px, py, pz, X, Y, Z);
+        chi = traverse<kShortStack>(ca, X, Y, Z);
+      }
+      a.chi_buf[q] = chi;
+    }
+  }
+}
+
+// Split mode, second kernel: boundary walk, combined with chi_buf into w.
+__global__ __launch_bounds__(kThreads) void k_batch_bnd(FwdArgs a) {
+  __shared__ double4 sv[bnd::kChunk];
+  __shared__ int s_item;
+  for (;;) {
+    const int it = next_item(a.counter + 1, &s_item);
+    if (it >= a.n_items) return;
+    const Item item = load_const(a.items, it);
+    const SurfDesc D = load_const(a.descs, item.surf);
+    const bnd::DeviceLoops L{a.loops + D.loop_off, D.nloops};
+    const bnd::StageCopy stage{a.bndr + D.bnd_off};
+    int staged = -1;
+    for (int r = 0; r < item.cnt; r += kThreads) {
+      const bool ok = r + (int)threadIdx.x < item.cnt;
+      const int64_t q = item.q0 + (ok ? r + (int)threadIdx.x : 0);
+      bnd::Lane<1> s;
+      rotate(D.F, a.qx[q], a.qy[q], a.qz[q], s.Xp[0], s.Yp[0], s.Zp[0]);
+      turns_init(s.T[0]);
+      bnd::boundary_walk(s, stage, D.nb, L, sv, staged);
+      if (ok) {
+        const int chi = a.chi_buf[q];
+        a.w[q] = chi != WN_CHI_INVALID ? turns_to_w(s.T[0], chi) : __int_as_float(0x7fc00000);
+      }
+    }
+  }
+}
+
+// Four waves per SIMD (128 registers): the few spills are per-item
+// addresses, outside the walk.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_bwd(BwdArgs a) {
   __shared__ float4 sv[adj::kChunk];
   __shared__ float4 rsw[adj::kWaves * adj::kRowFloats / 4];
   __shared__ int s_item;
@@ -159,8 +241,8 @@ __global__ __launch_bounds__(kThreads) void k_batch_bwd(BwdArgs a) {
   for (;;) {
     const int it = next_item(a.counter, &s_item);
     if (it >= a.n_items) return;
-    const Item item = a.items[it];
-    const SurfDesc D = a.descs[item.surf];
+    const Item item = load_const(a.items, it);
+    const SurfDesc D = load_const(a.descs, item.surf);
     const bnd::DeviceLoops L{a.loops + D.loop_off, D.nloops};
     const int64_t row = (int64_t)item.tile * adj::kWaves + wave;
     float* pv = a.pv ? a.pv + D.pv_off + row * (int64_t)D.nb * 3 : nullptr;
@@ -219,6 +301,18 @@ __global__ void k_batch_groups(const SurfDesc* __restrict__ descs, const int32_t
   out[t] = (float)(-s * 0.07957747154594767 + 0.0);
 }
 
+// Rotated boundary arena of a batch: vertex gv of the concatenated
+// boundaries, staged exactly as the plain kernels stage it.
+__global__ void k_rotate_bnd(const SurfDesc* __restrict__ descs, const int32_t* __restrict__ loops,
+                             const float* __restrict__ bnd, const int32_t* __restrict__ surf_of, int64_t nb_tot,
+                             double4* __restrict__ out) {
+  const int64_t gv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gv >= nb_tot) return;
+  const SurfDesc D = descs[surf_of[gv]];
+  const bnd::DeviceLoops L{loops + D.loop_off, D.nloops};
+  out[gv] = bnd::stage_vertex(D.F, bnd + 3 * D.bnd_off, L, (int)(gv - D.bnd_off));
+}
+
 __global__ void k_fill_f32(float* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0f;
@@ -242,12 +336,16 @@ struct wn_batch {
   wn::SurfDesc* d_desc = nullptr;
   int32_t* d_loops = nullptr;
   float* d_bnd = nullptr;
+  double4* d_bndr = nullptr;          // rotated boundary arena (forward)
   int32_t* d_surf_of = nullptr;       // boundary vertex -> surface
   int32_t* d_counter = nullptr;
   // forward work list
   wn::Item* d_items = nullptr;
   int32_t n_items = 0;
   int tile = 1024, wgpcu = 4;
+  int mode = 0;                       // forward: 0 fused, 1 split
+  int mode_fixed = -1;                // $WN_BATCH_MODE: the tuner keeps this mode
+  int32_t* d_chi = nullptr;           // split mode without chi_out
   int tune_mode = 0;
   bool tuned = false;
   double tune_ms = 0.0;
@@ -264,7 +362,8 @@ struct wn_batch {
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  hipGraphNode_t fwd_node = nullptr;
+  hipGraphNode_t fwd_node = nullptr;  // fused kernel, or the crossing kernel
+  hipGraphNode_t bnd_node = nullptr;  // split mode: the boundary kernel
   wn::FwdArgs graph_args{};
   bool use_graph = true;
 };
@@ -313,17 +412,22 @@ wn::FwdArgs fwd_args(const wn_batch* b, const float* qx, const float* qy, const 
   a.items = b->d_items;
   a.n_items = b->n_items;
   a.counter = b->d_counter;
-  a.bnd = b->d_bnd;
+  a.bndr = b->d_bndr;
   a.loops = b->d_loops;
   a.qx = qx;
   a.qy = qy;
   a.qz = qz;
   a.w = w;
   a.chi = chi;
+  a.chi_buf = chi ? chi : b->d_chi;
   return a;
 }
 
+// wgpcu > 0: a persistent grid of wgpcu workgroups per compute unit;
+// wgpcu == 0: one workgroup per item (the hardware dispatcher hands them out
+// in list order, which keeps the longest-first order of the items).
 int grid_of(const wn_batch* b, int n_items) {
+  if (b->wgpcu == 0) return std::max(1, n_items);
   return std::max(1, std::min(n_items, b->wgpcu * b->cus));
 }
 
@@ -332,8 +436,24 @@ hipError_t launch_fwd(const wn_batch* b, const wn::FwdArgs& a, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (a.n_items == 0) return hipSuccess;
-  hipLaunchKernelGGL(wn::k_batch_fwd, dim3(grid_of(b, a.n_items)), dim3(wn::kThreads), 0, s, a);
+  const dim3 grid(grid_of(b, a.n_items));
+  if (b->mode == 0) {
+    hipLaunchKernelGGL(wn::k_batch_fwd, grid, dim3(wn::kThreads), 0, s, a);
+    return hipGetLastError();
+  }
+  if (!a.chi_buf) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(wn::k_batch_cross, grid, dim3(wn::kThreads), 0, s, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(wn::k_batch_bnd, grid, dim3(wn::kThreads), 0, s, a);
   return hipGetLastError();
+}
+
+// Crossing-count buffer of the split mode when the caller passes no chi_out.
+wn_status ensure_chi(wn_batch* b) {
+  if (b->d_chi || b->total_q == 0) return WN_OK;
+  WN_HIP(hipMalloc((void**)&b->d_chi, (size_t)b->total_q * sizeof(int32_t)), "crossing buffer");
+  return WN_OK;
 }
 
 void drop_graph(wn_batch* b) {
@@ -342,6 +462,7 @@ void drop_graph(wn_batch* b) {
   b->exec = nullptr;
   b->graph = nullptr;
   b->fwd_node = nullptr;
+  b->bnd_node = nullptr;
 }
 
 // Capture reset + persistent forward into a graph (on a private stream).
@@ -364,9 +485,10 @@ wn_status capture(wn_batch* b, const wn::FwdArgs& a) {
     hipGraphNodeType t;
     if (hipGraphNodeGetType(nd, &t) != hipSuccess || t != hipGraphNodeTypeKernel) continue;
     hipKernelNodeParams p;
-    if (hipGraphKernelNodeGetParams(nd, &p) == hipSuccess &&
-        p.func == reinterpret_cast<void*>(wn::k_batch_fwd))
+    if (hipGraphKernelNodeGetParams(nd, &p) != hipSuccess) continue;
+    if (p.func == reinterpret_cast<void*>(wn::k_batch_fwd) || p.func == reinterpret_cast<void*>(wn::k_batch_cross))
       b->fwd_node = nd;
+    if (p.func == reinterpret_cast<void*>(wn::k_batch_bnd)) b->bnd_node = nd;
   }
   b->graph_args = a;
   return WN_OK;
@@ -392,7 +514,7 @@ std::string tune_key(const wn_batch* b) {
   return k;
 }
 
-bool cache_lookup(const std::string& key, int* tile, int* wgpcu) {
+bool cache_lookup(const std::string& key, int* tile, int* wgpcu, int* mode) {
   const char* path = std::getenv("WN_TUNE_CACHE");
   if (!path) return false;
   FILE* f = std::fopen(path, "r");
@@ -405,20 +527,19 @@ bool cache_lookup(const std::string& key, int* tile, int* wgpcu) {
   const std::string pat = "\"" + key + "\"";
   const size_t p = txt.find(pat);
   if (p == std::string::npos) return false;
-  int a = 0, c = 0;
-  if (std::sscanf(txt.c_str() + p + pat.size(), " : [%d , %d]", &a, &c) != 2 &&
-      std::sscanf(txt.c_str() + p + pat.size(), ": [%d, %d]", &a, &c) != 2)
-    return false;
-  if (a <= 0 || c <= 0) return false;
+  int a = 0, c = 0, m = -1;
+  if (std::sscanf(txt.c_str() + p + pat.size(), " : [ %d , %d , %d ]", &a, &c, &m) != 3) return false;
+  if (a <= 0 || c < 0 || m < 0 || m > 1) return false;
   *tile = a;
   *wgpcu = c;
+  *mode = m;
   return true;
 }
 
-void cache_store(const std::string& key, int tile, int wgpcu) {
+void cache_store(const std::string& key, int tile, int wgpcu, int mode) {
   const char* path = std::getenv("WN_TUNE_CACHE");
   if (!path) return;
-  // flat JSON object {"key": [tile, wg_per_cu], ...}; entries of other keys are kept
+  // flat JSON object {"key": [tile, wg_per_cu, mode], ...}; entries of other keys are kept
   std::vector<std::string> lines;
   if (FILE* f = std::fopen(path, "r")) {
     char buf[512];
@@ -435,7 +556,7 @@ void cache_store(const std::string& key, int tile, int wgpcu) {
     std::fclose(f);
   }
   char e[256];
-  std::snprintf(e, sizeof e, "  \"%s\": [%d, %d]", key.c_str(), tile, wgpcu);
+  std::snprintf(e, sizeof e, "  \"%s\": [%d, %d, %d]", key.c_str(), tile, wgpcu, mode);
   lines.push_back(e);
   if (FILE* f = std::fopen(path, "w")) {
     std::fprintf(f, "{\n");
@@ -450,16 +571,20 @@ void cache_store(const std::string& key, int tile, int wgpcu) {
 // run writes complete outputs, the last run uses the winner.
 wn_status autotune(wn_batch* b, const wn::FwdArgs& base, hipStream_t s) {
   const auto t0 = std::chrono::steady_clock::now();
-  int tile = b->tile, wg = b->wgpcu;
+  int tile = b->tile, wg = b->wgpcu, mode = b->mode;
   const std::string key = tune_key(b);
-  if (!cache_lookup(key, &tile, &wg)) {
+  if (!base.chi) {
+    wn_status st = ensure_chi(b);   // the split candidates need a crossing buffer
+    if (st) return st;
+  }
+  if (!cache_lookup(key, &tile, &wg, &mode) || (b->mode_fixed >= 0 && mode != b->mode_fixed)) {
     std::vector<int> tiles, wgs;
     if (b->tune_mode >= 2) {
       tiles = {256, 512, 1024, 2048, 4096};
-      wgs = {1, 2, 4, 8};
+      wgs = {1, 2, 4, 8, 0};
     } else {
       tiles = {256, 512, 1024, 2048};
-      wgs = {2, 4, 8};
+      wgs = {4, 8, 0};
     }
     hipEvent_t e0, e1;
     WN_HIP(hipEventCreate(&e0), "event");
@@ -468,28 +593,37 @@ wn_status autotune(wn_batch* b, const wn::FwdArgs& base, hipStream_t s) {
     for (int t : tiles) {
       wn_status st = upload_items(b, t);
       if (st) return st;
-      for (int w : wgs) {
-        b->wgpcu = w;
-        const wn::FwdArgs a = fwd_args(b, base.qx, base.qy, base.qz, base.w, base.chi);
-        WN_HIP(launch_fwd(b, a, s), "tune launch");   // warm-up
-        WN_HIP(hipEventRecord(e0, s), "event");
-        for (int r = 0; r < 2; ++r) WN_HIP(launch_fwd(b, a, s), "tune launch");
-        WN_HIP(hipEventRecord(e1, s), "event");
-        WN_HIP(hipEventSynchronize(e1), "event");
-        float ms = 0.f;
-        WN_HIP(hipEventElapsedTime(&ms, e0, e1), "event");
-        if (ms < best) {
-          best = ms;
-          tile = t;
-          wg = w;
+      for (int m = 0; m < 2; ++m) {
+        if (b->mode_fixed >= 0 && m != b->mode_fixed) continue;
+        for (int w : wgs) {
+          b->wgpcu = w;
+          b->mode = m;
+          const wn::FwdArgs a = fwd_args(b, base.qx, base.qy, base.qz, base.w, base.chi);
+          WN_HIP(launch_fwd(b, a, s), "tune launch");   // warm-up
+          WN_HIP(hipEventRecord(e0, s), "event");
+          for (int r = 0; r < 2; ++r) WN_HIP(launch_fwd(b, a, s), "tune launch");
+          WN_HIP(hipEventRecord(e1, s), "event");
+          WN_HIP(hipEventSynchronize(e1), "event");
+          float ms = 0.f;
+          WN_HIP(hipEventElapsedTime(&ms, e0, e1), "event");
+          if (std::getenv("WN_TUNE_LOG"))
+            std::fprintf(stderr, "wn tune: tile %d mode %s wg/cu %d: %.4f ms\n", t, m ? "split" : "fused", w,
+                         ms / 2);
+          if (ms < best) {
+            best = ms;
+            tile = t;
+            wg = w;
+            mode = m;
+          }
         }
       }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    cache_store(key, tile, wg);
+    cache_store(key, tile, wg, mode);
   }
   b->wgpcu = wg;
+  b->mode = mode;
   wn_status st = upload_items(b, tile);
   if (st) return st;
   b->tuned = true;
@@ -522,6 +656,11 @@ wn_status wn_batch_create(const wn_surface* surfs, int32_t ns, const double dir[
   b->ns = ns;
   b->tune_mode = tune_mode;
   b->use_graph = !std::getenv("WN_FORCE_NO_GRAPH");
+  if (const char* m = std::getenv("WN_BATCH_MODE")) {
+    if (!std::strcmp(m, "fused")) b->mode_fixed = 0;
+    else if (!std::strcmp(m, "split")) b->mode_fixed = 1;
+    if (b->mode_fixed >= 0) b->mode = b->mode_fixed;
+  }
   hipGetDevice(&b->dev);
   hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, b->dev);
   if (b->cus <= 0) b->cus = 256;
@@ -600,6 +739,12 @@ wn_status wn_batch_create(const wn_surface* surfs, int32_t ns, const double dir[
     if (nbs[i] > 0)
       chk(hipMemcpyAsync(b->d_bnd + 3 * b->desc[i].bnd_off, surfs[i].bnd_xyz, (size_t)nbs[i] * 3 * sizeof(float),
                          hipMemcpyDeviceToDevice, s));
+  if (e == hipSuccess) chk(hipMalloc((void**)&b->d_bndr, std::max<int64_t>(1, boff) * sizeof(double4)));
+  if (e == hipSuccess && boff > 0) {
+    hipLaunchKernelGGL(wn::k_rotate_bnd, dim3((unsigned)((boff + 255) / 256)), dim3(256), 0, s, b->d_desc,
+                       b->d_loops, b->d_bnd, b->d_surf_of, boff, b->d_bndr);
+    chk(hipGetLastError());
+  }
   b->n_rblocks = (int32_t)rblocks.size();
   if (e == hipSuccess && !rblocks.empty()) {
     chk(hipMalloc((void**)&b->d_rblocks, rblocks.size() * sizeof(wn::RBlock)));
@@ -653,6 +798,7 @@ wn_status wn_batch_free(wn_batch* b) {
   hipFree(b->d_desc);
   hipFree(b->d_loops);
   hipFree(b->d_bnd);
+  hipFree(b->d_bndr);
   hipFree(b->d_surf_of);
   hipFree(b->d_counter);
   hipFree(b->d_items);
@@ -661,6 +807,7 @@ wn_status wn_batch_free(wn_batch* b) {
   hipFree(b->d_pl);
   hipFree(b->d_tmp);
   hipFree(b->d_rblocks);
+  hipFree(b->d_chi);
   delete b;
   return WN_OK;
 }
@@ -677,6 +824,10 @@ wn_status wn_eval_batched(wn_batch* b, const float* qx, const float* qy, const f
     if (st) return st;
     drop_graph(b);
   }
+  if (b->mode == 1 && !chi_out) {
+    wn_status st = ensure_chi(b);
+    if (st) return st;
+  }
   const wn::FwdArgs a = fwd_args(b, qx, qy, qz, w_out, chi_out);
   if (!b->use_graph) {
     WN_HIP(launch_fwd(b, a, s), "batched forward");
@@ -691,17 +842,21 @@ wn_status wn_eval_batched(wn_batch* b, const float* qx, const float* qy, const f
       WN_HIP(launch_fwd(b, a, s), "batched forward");
       return WN_OK;
     }
-  } else if (!same_args(a, b->graph_args) && !b->fwd_node) {
-    wn_status st = capture(b, a);   // cannot patch the node: capture again
+  } else if (!same_args(a, b->graph_args) && (!b->fwd_node || (b->mode == 1 && !b->bnd_node))) {
+    wn_status st = capture(b, a);   // cannot patch the nodes: capture again
     if (st) return st;
   } else if (!same_args(a, b->graph_args)) {
-    hipKernelNodeParams p;
-    WN_HIP(hipGraphKernelNodeGetParams(b->fwd_node, &p), "graph params");
-    wn::FwdArgs na = a;
-    void* args[1] = {&na};
-    p.kernelParams = args;
-    p.extra = nullptr;
-    WN_HIP(hipGraphExecKernelNodeSetParams(b->exec, b->fwd_node, &p), "graph update");
+    hipGraphNode_t nodes[2] = {b->fwd_node, b->mode == 1 ? b->bnd_node : nullptr};
+    for (hipGraphNode_t nd : nodes) {
+      if (!nd) continue;
+      hipKernelNodeParams p;
+      WN_HIP(hipGraphKernelNodeGetParams(nd, &p), "graph params");
+      wn::FwdArgs na = a;
+      void* args[1] = {&na};
+      p.kernelParams = args;
+      p.extra = nullptr;
+      WN_HIP(hipGraphExecKernelNodeSetParams(b->exec, nd, &p), "graph update");
+    }
     b->graph_args = a;
   }
   WN_HIP(hipGraphLaunch(b->exec, s), "graph launch");
@@ -763,7 +918,7 @@ wn_status wn_backward_batched(wn_batch* b, const float* qx, const float* qy, con
   return WN_OK;
 }
 
-wn_status wn_batch_info(const wn_batch* b, int64_t info[8]) {
+wn_status wn_batch_info(const wn_batch* b, int64_t info[9]) {
   wn::host::g_err.clear();
   if (!b || !info) return fail(WN_ERR_INVALID_ARGUMENT, "NULL argument");
   info[0] = b->total_q;
@@ -774,6 +929,7 @@ wn_status wn_batch_info(const wn_batch* b, int64_t info[8]) {
   info[5] = b->wgpcu;
   info[6] = (b->use_graph && b->exec) ? 1 : 0;
   info[7] = (int64_t)std::llround(b->tune_ms * 1000.0);
+  info[8] = b->mode;
   return WN_OK;
 }
 

@@ -30,7 +30,8 @@ __global__ __launch_bounds__(kThreads) void k_bnd3d(BndArgs a, LoopTable L) {
   }
 
   int staged = -1;
-  boundary_walk(s, a.F, a.bnd, a.nb, KernargLoops{L}, sv, staged);
+  const KernargLoops KL{L};
+  boundary_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, staged);
 
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {

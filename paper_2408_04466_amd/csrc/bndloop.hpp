@@ -39,7 +39,12 @@ struct DeviceLoops {
   const int32_t* o;   // [n + 1], relative to the surface's first vertex
   int nl;
   __device__ __forceinline__ int n() const { return nl; }
-  __device__ __forceinline__ int off(int l) const { return o[l]; }
+  // The table is read-only for the whole launch: read through the constant
+  // address space, so a uniform index gives a scalar load and the loop
+  // bounds stay wave-uniform.
+  __device__ __forceinline__ int off(int l) const {
+    return ((const __attribute__((address_space(4))) int32_t*)(o))[l];
+  }
 };
 
 // Loop containing flat vertex index i (binary search over the loop table).
@@ -53,21 +58,45 @@ __device__ __forceinline__ int loop_of(const Loops& L, int i) {
   return lo;
 }
 
-// Stage vertices [c0, c0 + cnt) into LDS: rotated coordinates and, in .w,
-// the tie offset of the edge v_i -> v_next(i).
+// Boundary vertex i as staged: rotated coordinates and, in .w, the tie
+// offset of the edge v_i -> v_next(i).
+template <class Loops>
+__device__ __forceinline__ double4 stage_vertex(const Frame& F, const float* __restrict__ bnd, const Loops& L,
+                                                int i) {
+  const int l = loop_of(L, i);
+  const int nxt = (i + 1 < L.off(l + 1)) ? i + 1 : L.off(l);
+  double X, Y, Z, Xn, Yn, Zn;
+  rotate(F, bnd[3 * i], bnd[3 * i + 1], bnd[3 * i + 2], X, Y, Z);
+  rotate(F, bnd[3 * nxt], bnd[3 * nxt + 1], bnd[3 * nxt + 2], Xn, Yn, Zn);
+  return make_double4(X, Y, Z, tie_offset(lex_less(X, Y, Z, Xn, Yn, Zn)));
+}
+
+// Stage vertices [c0, c0 + cnt) into LDS.
 template <class Loops>
 __device__ __forceinline__ void stage_chunk(const Frame& F, const float* __restrict__ bnd, const Loops& L,
                                             int c0, int cnt, double4* sv) {
-  for (int j = threadIdx.x; j < cnt; j += kThreads) {
-    const int i = c0 + j;
-    const int l = loop_of(L, i);
-    const int nxt = (i + 1 < L.off(l + 1)) ? i + 1 : L.off(l);
-    double X, Y, Z, Xn, Yn, Zn;
-    rotate(F, bnd[3 * i], bnd[3 * i + 1], bnd[3 * i + 2], X, Y, Z);
-    rotate(F, bnd[3 * nxt], bnd[3 * nxt + 1], bnd[3 * nxt + 2], Xn, Yn, Zn);
-    sv[j] = make_double4(X, Y, Z, tie_offset(lex_less(X, Y, Z, Xn, Yn, Zn)));
-  }
+  for (int j = threadIdx.x; j < cnt; j += kThreads) sv[j] = stage_vertex(F, bnd, L, c0 + j);
 }
+
+// Stagers: fill LDS with vertices [c0, c0 + cnt) as (X, Y, Z, tie).
+// StageRotate rotates the float32 boundary on the fly; StageCopy copies a
+// boundary that was rotated beforehand with the same arithmetic (the batched
+// path rotates each surface's boundary once, when the batch is created).
+template <class Loops>
+struct StageRotate {
+  const Frame& F;
+  const float* __restrict__ bnd;
+  const Loops& L;
+  __device__ __forceinline__ void operator()(int c0, int cnt, double4* sv) const {
+    stage_chunk(F, bnd, L, c0, cnt, sv);
+  }
+};
+struct StageCopy {
+  const double4* __restrict__ src;
+  __device__ __forceinline__ void operator()(int c0, int cnt, double4* sv) const {
+    for (int j = threadIdx.x; j < cnt; j += kThreads) sv[j] = src[c0 + j];
+  }
+};
 
 template <int QPL>
 struct Lane {
@@ -102,9 +131,9 @@ __device__ __forceinline__ void rescale(Lane<QPL>& s) {
 // `staged` tracks which chunk is in LDS (-1: none) so that a caller walking
 // the same boundary again (next tile of queries) skips restaging when the
 // whole boundary fits in one chunk.
-template <int QPL, class Loops>
-__device__ __forceinline__ void boundary_walk(Lane<QPL>& s, const Frame& F, const float* __restrict__ bnd,
-                                              int nb, const Loops& L, double4* sv, int& staged) {
+template <int QPL, class Stager, class Loops>
+__device__ __forceinline__ void boundary_walk(Lane<QPL>& s, const Stager& stage, int nb, const Loops& L,
+                                              double4* sv, int& staged) {
   VQ first[QPL], A[QPL], B[QPL];   // A holds the previous vertex between steps
   double ptie = 0.0;               // uniform: tie offset of the edge leaving A
   int l = 0;
@@ -112,7 +141,7 @@ __device__ __forceinline__ void boundary_walk(Lane<QPL>& s, const Frame& F, cons
     const int c1 = min(c0 + kChunk, nb);
     if (staged != c0) {
       __syncthreads();
-      stage_chunk(F, bnd, L, c0, c1 - c0, sv);
+      stage(c0, c1 - c0, sv);
       __syncthreads();
       staged = c0;
     }
@@ -140,6 +169,10 @@ __device__ __forceinline__ void boundary_walk(Lane<QPL>& s, const Frame& F, cons
           vert_q(s, v1, A);
           edge_step(s, B, A, v0.w);
           ptie = v1.w;
+          // keep the scheduler from hoisting the LDS reads of later vertex
+          // pairs to the top of the step: that prefetch would hold up to
+          // 48 extra vector registers and cut occupancy from 8 to 5 waves
+          __builtin_amdgcn_sched_barrier(0);
         }
         rescale(s);
       }

@@ -170,9 +170,45 @@ __device__ __forceinline__ void turns_join(Turns& t, const Turns& o) {
 
 constexpr float kInv2Pi = 0.15915494309189535f;
 
-// w = chi + k + atan2(zi, zr) / (2 pi).
-__device__ __forceinline__ float turns_to_w(const Turns& t, int chi) {
-  return (float)(chi + t.k) + (float)atan2(t.zi, t.zr) * kInv2Pi;
+// atan2(y, x) in float32, written out operation by operation so that every
+// kernel including it produces the same bits (a library atan2f may lower its
+// internal division differently from one kernel to the next).  Octant
+// reduction to |t| <= tan(pi/8): t = a/b, or (a - b)/(a + b) with pi/4 added
+// back, where a <= b are |x| and |y|; then atan(t) = t P(t^2) with P of
+// degree 4, fitted here to atan(t)/t on that range by weighted least squares
+// (absolute error 4e-8 evaluated in float32).  One hardware reciprocal
+// replaces the division.  The sign of the result is the sign bit of y, so
+// on the negative real axis y = +0 gives +pi and y = -0 gives -pi.
+__device__ __forceinline__ float atan2_f32(float y, float x) {
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float a = fminf(ax, ay), b = fmaxf(ax, ay);
+  const bool big = a > __fmul_rn(0.41421356f, b);
+  const float num = big ? __fsub_rn(a, b) : a;
+  const float den = big ? __fadd_rn(a, b) : b;
+  const float t = den > 0.0f ? __fmul_rn(num, __builtin_amdgcn_rcpf(den)) : 0.0f;
+  const float s = __fmul_rn(t, t);
+  float p = 0.07993615418672562f;
+  p = __fmaf_rn(p, s, -0.1385444849729538f);
+  p = __fmaf_rn(p, s, 0.199747234582901f);
+  p = __fmaf_rn(p, s, -0.3333280682563782f);
+  p = __fmaf_rn(p, s, 1.0f);
+  float r = __fmul_rn(t, p);
+  if (big) r = __fadd_rn(r, 0.7853981633974483f);
+  if (ay > ax) r = __fsub_rn(1.5707963267948966f, r);
+  if (x < 0.0f) r = __fsub_rn(3.141592653589793f, r);
+  return copysignf(r, y);
+}
+
+// w = chi + k + atan2(zi, zr) / (2 pi).  After a power-of-two rescale the
+// larger component lies in [0.5, 1), so both round to float32 without
+// overflow; a component that underflows keeps its sign bit, so the branch
+// (+pi or -pi on the negative real axis) is the one the turn count assumed.
+// The float32 angle is off by about 1e-7 rad, below the float32 rounding of
+// w itself.
+__device__ __forceinline__ float turns_to_w(Turns t, int chi) {
+  turns_norm(t);
+  const float ang = atan2_f32((float)t.zi, (float)t.zr);
+  return __fadd_rn((float)(chi + t.k), __fmul_rn(ang, kInv2Pi));
 }
 
 }  // namespace wn

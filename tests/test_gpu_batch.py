@@ -136,6 +136,29 @@ def test_direct_launch_mode_matches_graph(small_batch):
     assert torch.equal(wg, wd) and torch.equal(cg, cd)
 
 
+@pytest.mark.parametrize("mode", ["fused", "split"])
+def test_forward_modes_match_plain(small_batch, mode):
+    """Both forward modes (one fused kernel; crossing kernel then boundary
+    kernel) give the plain path's bits, with and without chi_out, on graph
+    replays with changed output pointers."""
+    meshes, queries, d, surfs, P, q = small_batch
+    os.environ["WN_BATCH_MODE"] = mode
+    try:
+        B = W.Batch(surfs, d)
+    finally:
+        del os.environ["WN_BATCH_MODE"]
+    assert B.info()["mode"] == (1 if mode == "split" else 0)
+    wp, cp = _plain(surfs, q, d)
+    for rep in range(3):
+        w, chi = B.eval(*q)
+        w2, _ = B.eval(*q, want_chi=False)
+        torch.cuda.synchronize()
+        assert np.array_equal(chi.cpu().numpy(), cp), rep
+        assert np.array_equal(w.cpu().numpy(), wp), rep
+        assert np.array_equal(w2.cpu().numpy(), wp), rep
+    B.free()
+
+
 def test_autotuner_and_cache(small_batch, tmp_path):
     meshes, queries, d, surfs, P, q = small_batch
     cache = tmp_path / "tune.json"
@@ -145,12 +168,13 @@ def test_autotuner_and_cache(small_batch, tmp_path):
         w, chi = B.eval(*q)
         torch.cuda.synchronize()
         info = B.info()
-        assert cache.exists() and info["tile"] in (256, 512, 1024, 2048) and info["wg_per_cu"] in (2, 4, 8)
+        assert cache.exists() and info["tile"] in (256, 512, 1024, 2048) and info["wg_per_cu"] in (4, 8, 0)
         assert str(info["tile"]) in cache.read_text()
         B2 = W.Batch(surfs, d, tune_mode=2)
         w2, chi2 = B2.eval(*q)
         torch.cuda.synchronize()
         assert B2.info()["tile"] == info["tile"] and B2.info()["wg_per_cu"] == info["wg_per_cu"]
+        assert B2.info()["mode"] == info["mode"] and info["mode"] in (0, 1)
     finally:
         del os.environ["WN_TUNE_CACHE"]
     B0 = W.Batch(surfs, d)
