@@ -34,6 +34,9 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 FLOPS_PER_PAIR_FWD = 58      # boundary integral, per (query, boundary edge)
+COUNTERS = os.path.join(ROOT, "profiles", "k_bnd3d_mesh_2p20_counters.md")
+KERNEL_SOURCES = ("paper_2408_04466_amd/csrc/bnd3d.hip", "paper_2408_04466_amd/csrc/bndloop.hpp",
+                  "paper_2408_04466_amd/csrc/geom.hpp", "paper_2408_04466_amd/csrc/kernels.hpp")
 FLOPS_PER_PAIR_BWD = 40      # adjoint, per (query, boundary edge)
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak
 
@@ -78,6 +81,25 @@ def cpu_baseline(M, P, d, t, nsample=64):
                       f"{dt:.1f} s wall"}
 
 
+def measured_traffic():
+    """HBM bytes per k_bnd3d launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's counts), or
+    None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        txt = open(COUNTERS).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    vals = dict(line.split(": ", 1) for line in txt.splitlines()
+                if line.startswith(("traffic_bytes_per_launch k_bnd3d", "source_sha256 k_bnd3d")))
+    if vals.get("source_sha256 k_bnd3d", "").strip() != h.hexdigest():
+        return None
+    return int(vals["traffic_bytes_per_launch k_bnd3d"])
+
+
 class Timer:
     def __init__(self, torch, stream):
         self.torch, self.stream = torch, stream
@@ -108,6 +130,18 @@ def soa(torch, P, dev):
     return tuple(torch.from_numpy(np.ascontiguousarray(P[:, k])).to(dev) for k in range(3))
 
 
+def copy_calibration():
+    import torch
+    n = 1 << 28                      # 2^28 float32 = 1 GiB each way
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,7 +150,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--parity-sample", type=int, default=12)
     ap.add_argument("--only-c3", action="store_true", help="skip the other workloads")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 3 times (the reference kernel "
+                         "for scaling HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (got --gpus {args.gpus}); "
               "multi-GPU runs are not part of it", file=sys.stderr)
@@ -231,7 +271,9 @@ def main():
                    "batch_tuning": {k: batch.info()[k] for k in ("tile", "wg_per_cu", "mode")}},
         "roofline": {"bound": "alu", "kernel": "k_bnd3d (boundary integral)",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, "
+                                     "factors from a 1 GiB copy)",
                      "flops_per_pair": FLOPS_PER_PAIR_FWD, "pairs_per_launch": pairs,
                      "avg_launch_ms": ms_bnd},
         "batched_vs_plain": {

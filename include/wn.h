@@ -101,7 +101,7 @@ wn_status wn_boundary_loops(const int32_t* F, int64_t nf, int64_t nv,
                             int64_t* nb_out, int32_t* nloops_out);
 
 /* ---------------------------------------------------------------------------
- * wn_build_bvh -- prepare a triangle mesh for chi_d (Eq. chi; Alg. 1 line 6).
+ * wn_build_bvh -- prepare a triangle mesh for chi_d (Eq. chi; the ray-casting step of Alg. 1).
  *
  * Builds, on the GPU, the rotated frame of d (rows e1, e2, d; det +1; scaled
  * by a power of two so that coordinates are O(1)), the float64 rotated
@@ -162,7 +162,7 @@ wn_status wn_eval_3d_boundary(const wn_bvh* bvh, const float* bnd_xyz,
                               void* stream);
 
 /* ---------------------------------------------------------------------------
- * wn_crossings_3d -- chi_d only (Eq. chi; Alg. 1 lines 6-7) through the BVH.
+ * wn_crossings_3d -- chi_d only (Eq. chi; the ray-casting step of Alg. 1) through the BVH.
  *  chi_out device [nq] int32 out.
  * ------------------------------------------------------------------------- */
 wn_status wn_crossings_3d(const wn_bvh* bvh, const float* qx, const float* qy,

@@ -10,7 +10,7 @@ Contents
 --------
 - ``wn3d``   : 3D meshes.  Boundary half-edges (Sec. 4 "Multiple Boundaries";
                Sec. 5 preprocessing), brute-force signed crossing count
-               (Eq. chi; Alg. 1 lines 6-7), boundary line integral relative to
+               (Eq. chi; the ray-casting step of Alg. 1), boundary line integral relative to
                one fixed ray direction (Eq. wn_discrete_sum with Lemma 2, see
                the module docstring), degeneracy margins.
 - ``wn2d``   : 2D cubic Bezier loops (Sec. 3 definition of w_C, Sec. 6 "2D

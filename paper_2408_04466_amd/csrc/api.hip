@@ -408,12 +408,20 @@ wn_status wn_eval_3d(const wn_bvh* h, const float* bnd_xyz, const int64_t* loop_
   if ((st = check_queries(qx, qy, qz, nq))) return st;
   if (nq == 0) return WN_OK;
   if (!w_out) return fail(WN_ERR_INVALID_ARGUMENT, "w_out is NULL");
-  hipStream_t s = as_stream(stream);
-  // chi goes to chi_out, or is parked in w_out (int bits) until the boundary
-  // kernel replaces each entry by w
-  int32_t* chi = chi_out ? chi_out : reinterpret_cast<int32_t*>(w_out);
-  WN_HIP(wn::launch_cross3d(cross_args(h, qx, qy, qz, nq, chi), s), "crossings");
-  return eval_boundary(h->F, bnd_xyz, L, nb, qx, qy, qz, nq, chi, w_out, s);
+  // one fused kernel: traversal, boundary walk and combine per query
+  wn::BndArgs a;
+  a.F = h->F;
+  a.bnd = bnd_xyz;
+  a.nb = (int32_t)nb;
+  a.qx = qx;
+  a.qy = qy;
+  a.qz = qz;
+  a.nq = nq;
+  a.chi_in = nullptr;
+  a.w_out = w_out;
+  WN_HIP(wn::launch_fwd3d(cross_args(h, qx, qy, qz, nq, chi_out), a, L, chi_out, as_stream(stream)),
+         "forward");
+  return WN_OK;
 }
 
 wn_status wn_eval_3d_boundary(const wn_bvh* h, const float* bnd_xyz, const int64_t* loop_off,

@@ -5,6 +5,8 @@
 #include <cstdlib>
 
 #include "bndloop.hpp"
+#include "bvh_build.hpp"
+#include "traverse.hpp"
 
 namespace wn {
 
@@ -48,7 +50,38 @@ __global__ __launch_bounds__(kThreads) void k_bnd3d(BndArgs a, LoopTable L) {
   }
 }
 
+// Fused forward, one query per lane: the crossing count (BVH traversal),
+// then the boundary walk, then w.  While some waves wait on node fetches,
+// others keep the vector units busy with the boundary arithmetic.
+__global__ __launch_bounds__(kThreads) void k_fwd3d(CrossArgs c, BndArgs a, LoopTable L, int32_t* chi_out) {
+  __shared__ double4 sv[kChunk];
+  const int64_t qi = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const bool ok = qi < a.nq;
+  const int64_t q = ok ? qi : 0;
+  const float px = a.qx[q], py = a.qy[q], pz = a.qz[q];
+  const bool fin = isfinite(px) && isfinite(py) && isfinite(pz);
+  Lane<1> s;
+  rotate(a.F, px, py, pz, s.Xp[0], s.Yp[0], s.Zp[0]);
+  turns_init(s.T[0]);
+  const int chi = (ok && fin) ? traverse<kShortStack>(c, s.Xp[0], s.Yp[0], s.Zp[0]) : WN_CHI_INVALID;
+  int staged = -1;
+  const KernargLoops KL{L};
+  boundary_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, staged);
+  if (ok) {
+    a.w_out[q] = chi != WN_CHI_INVALID ? turns_to_w(s.T[0], chi) : __int_as_float(0x7fc00000);
+    if (chi_out) chi_out[q] = chi;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_fwd3d(const CrossArgs& c, const BndArgs& a, const LoopTable& L, int32_t* chi_out,
+                        hipStream_t s) {
+  const int64_t blocks = (a.nq + kThreads - 1) / kThreads;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fwd3d, dim3((unsigned)blocks), dim3(kThreads), 0, s, c, a, L, chi_out);
+  return hipGetLastError();
+}
 
 // Queries per lane: 1 or 2 (1 by default: 2 doubles the registers and
 // halves occupancy for no gain at the issue limit; WN_BND_QPL overrides).

@@ -1,4 +1,4 @@
-// Crossing count chi_d (Eq. chi; Alg. 1 lines 6-7) through a linear BVH
+// Crossing count chi_d (Eq. chi; the ray-casting step of Alg. 1) through a linear BVH
 // built on the GPU.
 //
 // All rays of one call are parallel to d, so in the frame of d (rows e1, e2,

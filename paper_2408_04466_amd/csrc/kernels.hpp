@@ -68,6 +68,9 @@ struct AdjArgs {
 
 // host-side launchers (defined next to their kernels)
 hipError_t launch_bnd3d(const BndArgs& a, const LoopTable& L, hipStream_t s);
+// Fused crossing count + boundary integral (chi_out may be null).
+hipError_t launch_fwd3d(const CrossArgs& c, const BndArgs& a, const LoopTable& L, int32_t* chi_out,
+                        hipStream_t s);
 hipError_t launch_cross3d(const CrossArgs& a, hipStream_t s);
 hipError_t launch_adj3d(const AdjArgs& a, const LoopTable& L, int64_t nblocks, hipStream_t s);
 int64_t adj3d_blocks(int64_t nq);
