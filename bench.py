@@ -209,14 +209,16 @@ def main():
               "degenerate": int((~ok).sum()), "batched_equals_plain": same,
               "pass": bool(chi_ok and werr <= 1e-4 and same)}
 
+    n2t = -2.0 * tt              # dL/dw = 2 (w - t) = 2 w + (-2 t): one fused kernel per step
+
     def step_batched():
         batch.eval(qx, qy, qz, w_out=wb, want_chi=False)
-        g = 2.0 * (wb - tt)
+        g = torch.add(n2t, wb, alpha=2.0)
         return batch.backward(qx, qy, qz, g)
 
     def step_plain():
         W.eval_3d(bvh, bnd, off, qx, qy, qz, want_chi=False, w_out=w)
-        g = 2.0 * (w - tt)
+        g = torch.add(n2t, w, alpha=2.0)
         return W.backward(bnd, off, qx, qy, qz, g)
 
     for _ in range(args.warmup):

@@ -45,9 +45,13 @@ __global__ void k_reduce_rows(const float* __restrict__ pv, const float* __restr
   const int64_t r0 = (int64_t)blockIdx.y * kRowsPerGroup;
   const int64_t r1 = min(rows, r0 + kRowsPerGroup);
   double s = 0.0;
-  for (int64_t r = r0; r < r1; ++r) {
-    s += (double)pv[r * n + t];
-    if (lf >= 0) s += (double)pl[(r * L.n + lf) * 3 + c];
+  if (lf < 0) {
+    s = ordered_sum(pv + r0 * n + t, n, r1 - r0, 0.0);
+  } else {
+    for (int64_t r = r0; r < r1; ++r) {
+      s += (double)pv[r * n + t];
+      s += (double)pl[(r * L.n + lf) * 3 + c];
+    }
   }
   tmp[(int64_t)blockIdx.y * n + t] = s;
 }
@@ -57,8 +61,7 @@ __global__ void k_reduce_groups(const double* __restrict__ tmp, int64_t groups, 
                                 float* __restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
-  double s = 0.0;
-  for (int64_t g = 0; g < groups; ++g) s += tmp[g * n + t];
+  const double s = ordered_sum(tmp + t, n, groups, 0.0);
   out[t] = (float)(-s * 0.07957747154594767 + 0.0);
 }
 

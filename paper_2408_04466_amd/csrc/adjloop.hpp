@@ -250,6 +250,23 @@ __device__ __forceinline__ void walk(QState* S, const float* __restrict__ bnd, i
   }
 }
 
+// x[0] + x[stride] + ... + x[(cnt - 1) stride] in float64, added in index
+// order, with the loads issued eight at a time (the partial reductions are
+// latency-bound: one dependent load per addition otherwise).
+template <class T>
+__device__ __forceinline__ double ordered_sum(const T* __restrict__ x, int64_t stride, int64_t cnt, double s) {
+  int64_t i = 0;
+  for (; i + 8 <= cnt; i += 8) {
+    T v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = x[(i + k) * stride];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += (double)v[k];
+  }
+  for (; i < cnt; ++i) s += (double)x[i * stride];
+  return s;
+}
+
 __device__ __forceinline__ void store_gq(const QState* S, const int64_t* qi, const bool* ok, float* gq) {
 #pragma unroll
   for (int k = 0; k < kQPL; ++k) {

@@ -76,6 +76,7 @@ struct FwdArgs {
   const SurfDesc* descs;
   const Item* items;
   int32_t n_items;
+  int32_t direct;          // 1: one workgroup per item (item = blockIdx.x, no counter)
   int32_t* counter;        // [0]: fused or crossing kernel, [1]: boundary kernel
   int32_t* chi_buf;        // split mode: crossing counts (chi_out or a batch buffer)
   const double4* bndr;     // rotated boundary arena (bnd::stage_vertex of every vertex)
@@ -136,6 +137,13 @@ __device__ __forceinline__ int next_item(int32_t* counter, int* s_item) {
   return __builtin_amdgcn_readfirstlane(*s_item);
 }
 
+// Item for this pass of the persistent loop: from the counter, or in direct
+// mode blockIdx.x on the first pass and none after it.
+__device__ __forceinline__ int item_for(int direct, int pass, int n_items, int32_t* counter, int* s_item) {
+  if (direct) return pass == 0 ? (int)blockIdx.x : n_items;
+  return next_item(counter, s_item);
+}
+
 __device__ __forceinline__ CrossArgs cross_args(const SurfDesc& D) {
   CrossArgs ca;
   ca.F = D.F;
@@ -152,8 +160,8 @@ __device__ __forceinline__ CrossArgs cross_args(const SurfDesc& D) {
 __global__ __launch_bounds__(kThreads) void k_batch_fwd(FwdArgs a) {
   __shared__ double4 sv[bnd::kChunk];
   __shared__ int s_item;
-  for (;;) {
-    const int it = next_item(a.counter, &s_item);
+  for (int pass = 0;; ++pass) {
+    const int it = item_for(a.direct, pass, a.n_items, a.counter, &s_item);
     if (it >= a.n_items) return;
     const Item item = load_const(a.items, it);
     const SurfDesc D = load_const(a.descs, item.surf);
@@ -184,8 +192,8 @@ __global__ __launch_bounds__(kThreads) void k_batch_fwd(FwdArgs a) {
 // for a non-finite query or an abandoned traversal).
 __global__ __launch_bounds__(kThreads) void k_batch_cross(FwdArgs a) {
   __shared__ int s_item;
-  for (;;) {
-    const int it = next_item(a.counter, &s_item);
+  for (int pass = 0;; ++pass) {
+    const int it = item_for(a.direct, pass, a.n_items, a.counter, &s_item);
     if (it >= a.n_items) return;
     const Item item = load_const(a.items, it);
     const SurfDesc D = load_const(a.descs, item.surf);
@@ -208,8 +216,8 @@ __global__ __launch_bounds__(kThreads) void k_batch_cross(FwdArgs a) {
 __global__ __launch_bounds__(kThreads) void k_batch_bnd(FwdArgs a) {
   __shared__ double4 sv[bnd::kChunk];
   __shared__ int s_item;
-  for (;;) {
-    const int it = next_item(a.counter + 1, &s_item);
+  for (int pass = 0;; ++pass) {
+    const int it = item_for(a.direct, pass, a.n_items, a.counter + 1, &s_item);
     if (it >= a.n_items) return;
     const Item item = load_const(a.items, it);
     const SurfDesc D = load_const(a.descs, item.surf);
@@ -238,8 +246,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
   __shared__ float4 rsw[adj::kWaves * adj::kRowFloats / 4];
   __shared__ int s_item;
   const int wave = threadIdx.x >> 6;
-  for (;;) {
-    const int it = next_item(a.counter, &s_item);
+  for (int pass = 0;; ++pass) {
+    const int it = item_for(1, pass, a.n_items, a.counter, &s_item);
     if (it >= a.n_items) return;
     const Item item = load_const(a.items, it);
     const SurfDesc D = load_const(a.descs, item.surf);
@@ -280,9 +288,13 @@ __global__ void k_batch_rows(const SurfDesc* __restrict__ descs, const RBlock* _
   const float* p = pv + D.pv_off;
   const float* q = pl + D.pl_off;
   double s = 0.0;
-  for (int64_t r = r0; r < r1; ++r) {
-    s += (double)p[r * n + t];
-    if (lf >= 0) s += (double)q[(r * D.nloops + lf) * 3 + c];
+  if (lf < 0) {
+    s = adj::ordered_sum(p + r0 * n + t, n, r1 - r0, 0.0);
+  } else {
+    for (int64_t r = r0; r < r1; ++r) {
+      s += (double)p[r * n + t];
+      s += (double)q[(r * D.nloops + lf) * 3 + c];
+    }
   }
   tmp[D.tmp_off + (int64_t)rb.group * n + t] = s;
 }
@@ -296,8 +308,7 @@ __global__ void k_batch_groups(const SurfDesc* __restrict__ descs, const int32_t
   const SurfDesc D = descs[surf_of[t / 3]];
   const int64_t n = (int64_t)D.nb * 3;
   const int64_t col = t - 3 * D.bnd_off;
-  double s = 0.0;
-  for (int g = 0; g < D.groups; ++g) s += tmp[D.tmp_off + (int64_t)g * n + col];
+  const double s = adj::ordered_sum(tmp + D.tmp_off + col, n, D.groups, 0.0);
   out[t] = (float)(-s * 0.07957747154594767 + 0.0);
 }
 
@@ -411,6 +422,7 @@ wn::FwdArgs fwd_args(const wn_batch* b, const float* qx, const float* qy, const 
   a.descs = b->d_desc;
   a.items = b->d_items;
   a.n_items = b->n_items;
+  a.direct = b->wgpcu == 0 ? 1 : 0;
   a.counter = b->d_counter;
   a.bndr = b->d_bndr;
   a.loops = b->d_loops;
@@ -432,9 +444,11 @@ int grid_of(const wn_batch* b, int n_items) {
 }
 
 hipError_t launch_fwd(const wn_batch* b, const wn::FwdArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(wn::k_reset, dim3(1), dim3(64), 0, s, b->d_counter);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  if (!a.direct) {
+    hipLaunchKernelGGL(wn::k_reset, dim3(1), dim3(64), 0, s, b->d_counter);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   if (a.n_items == 0) return hipSuccess;
   const dim3 grid(grid_of(b, a.n_items));
   if (b->mode == 0) {
@@ -902,10 +916,8 @@ wn_status wn_backward_batched(wn_batch* b, const float* qx, const float* qy, con
   a.gq = grad_q;
   a.pv = grad_bnd ? b->d_pv : nullptr;
   a.pl = grad_bnd ? b->d_pl : nullptr;
-  hipLaunchKernelGGL(wn::k_reset, dim3(1), dim3(64), 0, s, b->d_counter);
-  WN_HIP(hipGetLastError(), "batched backward");
-  const int grid = std::max(1, std::min(b->n_bitems, 4 * b->cus));
-  hipLaunchKernelGGL(wn::k_batch_bwd, dim3(grid), dim3(wn::kThreads), 0, s, a);
+  // one workgroup per item, dispatched in list (longest first) order
+  hipLaunchKernelGGL(wn::k_batch_bwd, dim3((unsigned)std::max(1, b->n_bitems)), dim3(wn::kThreads), 0, s, a);
   WN_HIP(hipGetLastError(), "batched backward");
   if (grad_bnd && b->total_b > 0) {
     const int64_t n3 = 3 * b->total_b;
