@@ -204,3 +204,46 @@ def test_batched_backward_matches_plain(small_batch):
             assert torch.count_nonzero(gb[ob:ob + nb]) == 0
         o += n
         ob += nb
+
+
+@pytest.mark.slow
+def test_full_size_batch_autotuned_parity():
+    """The 256-surface workload at full size (11.2M triangles, 17.5M queries),
+    in the configuration bench.py times (quick autotune, graph replay):
+    crossing counts bit-exact and |dw| <= 1e-4 against the oracle on one
+    seeded query of each of 128 surfaces; batched equals plain bit for bit on
+    every 16th surface; the batched backward is finite everywhere."""
+    CB = synth.coons_batch(4)
+    d = CB.direction
+    surfs, P, q = _upload(CB.meshes, CB.queries)
+    B = W.Batch(surfs, d, tune_mode=1)
+    w, chi = B.eval(*q)
+    w2, chi2 = B.eval(*q)                     # graph replay
+    torch.cuda.synchronize()
+    assert torch.equal(w, w2) and torch.equal(chi, chi2)
+    wc, cc = w.cpu().numpy(), chi.cpu().numpy()
+    offs = np.concatenate([[0], np.cumsum([len(Q) for Q in CB.queries])])
+    g = synth.rng(44)
+    n_deg = 0
+    for k in range(0, 256, 2):
+        M, Q = CB.meshes[k], CB.queries[k]
+        i = int(g.integers(len(Q)))
+        r = O.wn3d(M.V, M.F, Q[i:i + 1], d)
+        if r.degenerate[0]:
+            n_deg += 1
+            continue
+        assert cc[offs[k] + i] == r["chi"][0], k
+        if r["m_bnd"][0] > 1e-5:
+            assert abs(wc[offs[k] + i] - r["w"][0]) <= W_TOL, k
+    assert n_deg <= 2
+    for k in range(0, 256, 16):
+        s = surfs[k]
+        a, b = int(offs[k]), int(offs[k + 1])
+        bvh = W.BVH(s["V"], s["F"], d)
+        wp, cp = W.eval_3d(bvh, s["bnd"], s["loop_off"], q[0][a:b], q[1][a:b], q[2][a:b])
+        torch.cuda.synchronize()
+        assert torch.equal(wp, w[a:b]) and torch.equal(cp, chi[a:b]), k
+    gq, gb = B.backward(*q, torch.ones_like(w))
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(gq).all()) and bool(torch.isfinite(gb).all())
+    B.free()
