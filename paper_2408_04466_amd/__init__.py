@@ -14,6 +14,7 @@ from .api import (  # noqa: F401
     eval_2d,
     eval_3d,
     eval_3d_boundary,
+    eval_3d_grid,
     winding_number,
 )
 from ._lib import WN_CHI_INVALID, WN_MAX_LOOPS, WnError, lib  # noqa: F401

@@ -130,6 +130,25 @@ def eval_3d(bvh: BVH, bnd_xyz: torch.Tensor, loop_off, qx, qy, qz, want_chi: boo
     return w, chi
 
 
+def eval_3d_grid(bvh: BVH, bnd_xyz: torch.Tensor, loop_off, gx, gy, gz, want_chi: bool = True, stream=None):
+    """w (and chi) on the grid gx[nx] x gy[ny] x gz[nz] (float32 device
+    vectors), output shape [nx, ny, nz] (z fastest); the BVH must be built for
+    the direction +z (columns along the ray share it)."""
+    lo, nl = _loops(loop_off)
+    nb = int(lo[-1]) if nl else 0
+    pb = _dev(bnd_xyz, torch.float32, "bnd_xyz", (nb, 3))
+    nx, ny, nz = gx.shape[0], gy.shape[0], gz.shape[0]
+    px = _dev(gx, torch.float32, "gx", (nx,))
+    py = _dev(gy, torch.float32, "gy", (ny,))
+    pz = _dev(gz, torch.float32, "gz", (nz,))
+    w = torch.empty((nx, ny, nz), dtype=torch.float32, device=gx.device)
+    chi = torch.empty((nx, ny, nz), dtype=torch.int32, device=gx.device) if want_chi else None
+    check(lib().wn_eval_3d_grid(bvh.handle, pb, _ptr64(lo), nl, px, py, pz, nx, ny, nz,
+                                _dev(w, torch.float32, "w"), _dev(chi, torch.int32, "chi") if chi is not None else None,
+                                _stream(stream)), "wn_eval_3d_grid")
+    return w, chi
+
+
 def eval_3d_boundary(bvh: BVH, bnd_xyz, loop_off, qx, qy, qz, chi_in, stream=None):
     lo, nl = _loops(loop_off)
     nb = int(lo[-1]) if nl else 0

@@ -424,6 +424,48 @@ wn_status wn_eval_3d(const wn_bvh* h, const float* bnd_xyz, const int64_t* loop_
   return WN_OK;
 }
 
+wn_status wn_eval_3d_grid(const wn_bvh* h, const float* bnd_xyz, const int64_t* loop_off, int32_t nloops,
+                          const float* gx, const float* gy, const float* gz, int64_t nx, int64_t ny, int64_t nz,
+                          float* w_out, int32_t* chi_out, void* stream) {
+  g_err.clear();
+  if (!h) return fail(WN_ERR_INVALID_ARGUMENT, "bvh is NULL");
+  if (!(h->dir[0] == 0.0 && h->dir[1] == 0.0 && h->dir[2] > 0.0))
+    return fail(WN_ERR_UNSUPPORTED, "grid mode needs a BVH built for the direction +z");
+  wn::LoopTable L;
+  int64_t nb = 0;
+  wn_status st = make_loops(loop_off, nloops, 3, &nb, &L);
+  if (st) return st;
+  if (nb > 0 && !bnd_xyz) return fail(WN_ERR_INVALID_ARGUMENT, "bnd_xyz is NULL");
+  if (nx < 0 || ny < 0 || nz < 0) return fail(WN_ERR_INVALID_ARGUMENT, "negative grid size");
+  if (nx == 0 || ny == 0 || nz == 0) return WN_OK;
+  if (nx > (int64_t)1 << 40 || ny > ((int64_t)1 << 40) / nx || nz > ((int64_t)1 << 40) / (nx * ny))
+    return fail(WN_ERR_INVALID_ARGUMENT, "grid larger than 2^40 points");
+  if (nx * ny > (int64_t)INT32_MAX / wn::kGridCand)
+    return fail(WN_ERR_INVALID_ARGUMENT, "more than %d grid columns", (int)(INT32_MAX / wn::kGridCand));
+  if (!gx || !gy || !gz || !w_out) return fail(WN_ERR_INVALID_ARGUMENT, "NULL grid axis or output pointer");
+  const int64_t ncol = nx * ny, nq = ncol * nz;
+  hipStream_t s = as_stream(stream);
+  int32_t* buf = nullptr;   // column counts, then candidate lists
+  const size_t words = (size_t)ncol * (1 + wn::kGridCand);
+  WN_HIP(hipMallocAsync((void**)&buf, words * sizeof(int32_t), s), "grid candidate lists");
+  int32_t* cnt = buf;
+  int32_t* cand = buf + ncol;
+  wn::CrossArgs ca = cross_args(h, nullptr, nullptr, nullptr, 0, nullptr);
+  wn::BndArgs a;
+  a.F = h->F;
+  a.bnd = bnd_xyz;
+  a.nb = (int32_t)nb;
+  a.qx = a.qy = a.qz = nullptr;
+  a.nq = nq;
+  a.chi_in = nullptr;
+  a.w_out = w_out;
+  hipError_t e = wn::launch_grid3d_columns(ca, gx, gy, nx, ny, cnt, cand, s);
+  if (e == hipSuccess) e = wn::launch_grid3d_fwd(ca, a, L, gx, gy, gz, ny, nz, cnt, cand, chi_out, s);
+  hipFreeAsync(buf, s);
+  if (e != hipSuccess) return hip_fail(e, "grid forward");
+  return WN_OK;
+}
+
 wn_status wn_eval_3d_boundary(const wn_bvh* h, const float* bnd_xyz, const int64_t* loop_off,
                               int32_t nloops, const float* qx, const float* qy, const float* qz,
                               int64_t nq, const int32_t* chi_in, float* w_out, void* stream) {

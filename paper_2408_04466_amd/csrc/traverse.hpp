@@ -75,15 +75,18 @@ __device__ __forceinline__ bool in_box(const float4 b, float bz, float x, float 
   return (x >= b.x) & (x <= b.y) & (y >= b.z) & (y <= b.w) & (z <= bz);
 }
 
-// chi for one query (WN_CHI_INVALID if the tree is malformed).
-template <int S>
-__device__ int traverse(const CrossArgs& a, double Xp, double Yp, double Zp) {
+// Walk the tree for the vertical half line above (x, y, z) in the frame of
+// d and call leaf(t) for every sorted triangle t whose padded box contains
+// (x, y) with zmax >= z.  z = -inf visits every triangle whose projection box
+// contains (x, y), whatever its height (the column pass of the grid mode).
+// Returns 0, or WN_CHI_INVALID if the tree is malformed.
+template <int S, class Leaf>
+__device__ __forceinline__ int traverse_leaves(const CrossArgs& a, float x, float y, float z, Leaf&& leaf) {
   if (a.nf == 0) return 0;
-  const float x = (float)Xp, y = (float)Yp, z = (float)Zp;
   if (a.nf == 1) {
-    return in_box(a.leafbox[0], a.leafz[0], x, y, z) ? tri_crossing(a.tris[0], a.Vr, Xp, Yp, Zp) : 0;
+    if (in_box(a.leafbox[0], a.leafz[0], x, y, z)) leaf(0);
+    return 0;
   }
-  int chi = 0;
   RegStack<S> st;
   int32_t spill[kSpill];
   st.init();
@@ -97,12 +100,12 @@ __device__ int traverse(const CrossArgs& a, double Xp, double Yp, double Zp) {
     bool hr = in_box(nd.rbox, nd.rzmax, x, y, z);
     if (hl && nd.left < 0) {
       if (~nd.left >= a.nf) return WN_CHI_INVALID;
-      chi += tri_crossing(a.tris[~nd.left], a.Vr, Xp, Yp, Zp);
+      leaf(~nd.left);
       hl = false;
     }
     if (hr && nd.right < 0) {
       if (~nd.right >= a.nf) return WN_CHI_INVALID;
-      chi += tri_crossing(a.tris[~nd.right], a.Vr, Xp, Yp, Zp);
+      leaf(~nd.right);
       hr = false;
     }
     if (hl && hr) {
@@ -117,7 +120,16 @@ __device__ int traverse(const CrossArgs& a, double Xp, double Yp, double Zp) {
       node = st.pop(spill);
     }
   }
-  return chi;
+  return 0;
+}
+
+// chi for one query (WN_CHI_INVALID if the tree is malformed).
+template <int S>
+__device__ int traverse(const CrossArgs& a, double Xp, double Yp, double Zp) {
+  int chi = 0;
+  const int st = traverse_leaves<S>(a, (float)Xp, (float)Yp, (float)Zp,
+                                    [&](int t) { chi += tri_crossing(a.tris[t], a.Vr, Xp, Yp, Zp); });
+  return st ? st : chi;
 }
 
 }  // namespace wn
