@@ -375,6 +375,31 @@ def run_others(torch, W, T, others, d3, args, dev):
     p5 = len(P5) * len(idx)
     res["adjoint_2048_edges_2^18"] = {"fwd_bwd_ms": ms5, "bwd_ms": ms5b, "queries_per_s": len(P5) / (ms5 * 1e-3),
                                       "bwd_TFLOPs": p5 * FLOPS_PER_PAIR_BWD / (ms5b * 1e-3) / 1e12}
+    # --- 3D grid mode: 128^3 voxel grid over the mesh, d = +z, one ray per column
+    M3 = synth.open_sphere(3)
+    dz = np.array([0.0, 0.0, 1.0])
+    V, F, bnd, off, idx = upload_mesh(torch, W, M3, dev)
+    bvhz = W.BVH(V, F, dz)
+    lo, hi = M3.V.min(0).astype(np.float64), M3.V.max(0).astype(np.float64)
+    c, h = (lo + hi) / 2, (hi - lo) / 2 * 1.2
+    ax = [synth.grid_axis(c[k] - h[k], c[k] + h[k], 128, np.float32) for k in range(3)]
+    gx, gy, gz = (torch.from_numpy(a).to(dev) for a in ax)
+    Xg, Yg, Zg = np.meshgrid(*ax, indexing="ij")
+    qg = tuple(torch.from_numpy(np.ascontiguousarray(a.ravel())).to(dev) for a in (Xg, Yg, Zg))
+    wg = torch.empty(128 ** 3, dtype=torch.float32, device=dev)
+    perm = torch.from_numpy(synth.rng(17).permutation(128 ** 3)).to(dev)
+    qs = tuple(t[perm].contiguous() for t in qg)          # the same points in random order
+    ws = torch.empty_like(wg)
+    ms_g = T.ms(lambda: W.eval_3d_grid(bvhz, bnd, off, gx, gy, gz, want_chi=False), reps)
+    ms_gq = T.ms(lambda: W.eval_3d(bvhz, bnd, off, *qg, want_chi=False, w_out=wg), reps)
+    ms_gs = T.ms(lambda: W.eval_3d(bvhz, bnd, off, *qs, want_chi=False, w_out=ws), reps)
+    wgrid, _ = W.eval_3d_grid(bvhz, bnd, off, gx, gy, gz, want_chi=False)
+    torch.cuda.synchronize()
+    res["3d_voxel_grid_128^3_dz"] = {
+        "grid_ms": ms_g, "points_in_column_order_ms": ms_gq, "points_in_random_order_ms": ms_gs,
+        "queries_per_s": 128 ** 3 / (ms_g * 1e-3),
+        "grid_equals_per_query": bool(torch.equal(wgrid.view(-1), wg) and torch.equal(ws, wg[perm]))}
+    del bvhz
     # --- 2D workloads
     C1 = synth.star2d()
     ctrl = torch.from_numpy(C1.ctrl).to(dev)

@@ -154,17 +154,16 @@ wn_status wn_eval_3d(const wn_bvh* bvh, const float* bnd_xyz,
  * wn_eval_3d_grid -- w_M on a grid whose columns run along the ray: queries
  * (gx[i], gy[j], gz[k]), i < nx, j < ny, k < nz, for a BVH built for the
  * direction +z.  Sec. 4 ("Optimization"): points on one line parallel to
- * the ray share the ray; one traversal per column (x_i, y_j) lists the
- * triangles that can cross it and each point applies the exact triangle
- * test to that list only.  chi and w are bit-identical to wn_eval_3d on the
- * same float32 points.
+ * the ray share the ray.  The points of a column are consecutive lanes with
+ * identical frame coordinates X, Y, so a wavefront walks the tree once for
+ * its column and each point applies the exact triangle test at its own
+ * height; chi and w are bit-identical to wn_eval_3d on the same float32
+ * points, without materialising the point coordinates.
  *  gx, gy, gz device float32 [nx], [ny], [nz].
  *  w_out      device [nx][ny][nz] float32 out (z fastest); chi_out same
  *             layout int32, or NULL.
- * Allocates 4 (1 + 32) bytes per column on the stream for candidate lists
- * (stream-ordered allocation, released before the call returns).
  * Errors: UNSUPPORTED if the BVH's direction is not +z; INVALID_ARGUMENT
- * (negative sizes, more than 2^40 points or 2^26 columns); HIP.
+ * (negative sizes, 2^32 points or more); HIP.
  * ------------------------------------------------------------------------- */
 wn_status wn_eval_3d_grid(const wn_bvh* bvh, const float* bnd_xyz,
                           const int64_t* loop_off, int32_t nloops,

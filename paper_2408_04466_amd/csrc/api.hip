@@ -438,18 +438,11 @@ wn_status wn_eval_3d_grid(const wn_bvh* h, const float* bnd_xyz, const int64_t* 
   if (nb > 0 && !bnd_xyz) return fail(WN_ERR_INVALID_ARGUMENT, "bnd_xyz is NULL");
   if (nx < 0 || ny < 0 || nz < 0) return fail(WN_ERR_INVALID_ARGUMENT, "negative grid size");
   if (nx == 0 || ny == 0 || nz == 0) return WN_OK;
-  if (nx > (int64_t)1 << 40 || ny > ((int64_t)1 << 40) / nx || nz > ((int64_t)1 << 40) / (nx * ny))
-    return fail(WN_ERR_INVALID_ARGUMENT, "grid larger than 2^40 points");
-  if (nx * ny > (int64_t)INT32_MAX / wn::kGridCand)
-    return fail(WN_ERR_INVALID_ARGUMENT, "more than %d grid columns", (int)(INT32_MAX / wn::kGridCand));
+  if (nx > (int64_t)UINT32_MAX || ny > (int64_t)UINT32_MAX / nx || nz > (int64_t)UINT32_MAX / (nx * ny))
+    return fail(WN_ERR_INVALID_ARGUMENT, "grid of 2^32 points or more");
   if (!gx || !gy || !gz || !w_out) return fail(WN_ERR_INVALID_ARGUMENT, "NULL grid axis or output pointer");
-  const int64_t ncol = nx * ny, nq = ncol * nz;
+  const int64_t nq = nx * ny * nz;
   hipStream_t s = as_stream(stream);
-  int32_t* buf = nullptr;   // column counts, then candidate lists
-  const size_t words = (size_t)ncol * (1 + wn::kGridCand);
-  WN_HIP(hipMallocAsync((void**)&buf, words * sizeof(int32_t), s), "grid candidate lists");
-  int32_t* cnt = buf;
-  int32_t* cand = buf + ncol;
   wn::CrossArgs ca = cross_args(h, nullptr, nullptr, nullptr, 0, nullptr);
   wn::BndArgs a;
   a.F = h->F;
@@ -459,10 +452,7 @@ wn_status wn_eval_3d_grid(const wn_bvh* h, const float* bnd_xyz, const int64_t* 
   a.nq = nq;
   a.chi_in = nullptr;
   a.w_out = w_out;
-  hipError_t e = wn::launch_grid3d_columns(ca, gx, gy, nx, ny, cnt, cand, s);
-  if (e == hipSuccess) e = wn::launch_grid3d_fwd(ca, a, L, gx, gy, gz, ny, nz, cnt, cand, chi_out, s);
-  hipFreeAsync(buf, s);
-  if (e != hipSuccess) return hip_fail(e, "grid forward");
+  WN_HIP(wn::launch_grid3d_fwd(ca, a, L, gx, gy, gz, ny, nz, chi_out, s), "grid forward");
   return WN_OK;
 }
 

@@ -9,9 +9,6 @@
 namespace wn {
 
 constexpr int kShortStack = 12;   // traversal stack entries kept in registers
-// Candidate triangles kept per column in the 3D grid mode (more: the
-// column's queries traverse the tree one by one).
-constexpr int kGridCand = 32;
 
 struct BuildBufs {
   double4* Vr;          // [nv]

@@ -72,13 +72,10 @@ hipError_t launch_bnd3d(const BndArgs& a, const LoopTable& L, hipStream_t s);
 hipError_t launch_fwd3d(const CrossArgs& c, const BndArgs& a, const LoopTable& L, int32_t* chi_out,
                         hipStream_t s);
 hipError_t launch_cross3d(const CrossArgs& a, hipStream_t s);
-// 3D grid mode (grid3d.hip): candidate lists per column, then the forward
-// per query (z fastest); cnt [nx*ny], cand [nx*ny][kGridCand].
-hipError_t launch_grid3d_columns(const CrossArgs& c, const float* gx, const float* gy, int64_t nx, int64_t ny,
-                                 int32_t* cnt, int32_t* cand, hipStream_t s);
+// 3D grid mode (grid3d.hip): fused forward per query, z fastest.
 hipError_t launch_grid3d_fwd(const CrossArgs& c, const BndArgs& a, const LoopTable& L, const float* gx,
-                             const float* gy, const float* gz, int64_t ny, int64_t nz, const int32_t* cnt,
-                             const int32_t* cand, int32_t* chi_out, hipStream_t s);
+                             const float* gy, const float* gz, int64_t ny, int64_t nz, int32_t* chi_out,
+                             hipStream_t s);
 hipError_t launch_adj3d(const AdjArgs& a, const LoopTable& L, int64_t nblocks, hipStream_t s);
 int64_t adj3d_blocks(int64_t nq);
 int64_t adj3d_rows(int64_t nblocks);

@@ -1,8 +1,7 @@
-"""GPU tests of the 3D grid mode (queries on lines along the ray share one
-traversal per column, Sec. 4 "Optimization"): bit-identical to the
-per-query path on the same float32 points, oracle parity on samples, the
-candidate-list overflow fallback, edge cases, and the full-size voxel grid
-over the 1M-triangle mesh."""
+"""GPU tests of the 3D grid mode (queries on lines along the ray share the
+ray, Sec. 4 "Optimization"): bit-identical to the per-query path on the
+same float32 points, oracle parity on samples, deep stacks of surfaces,
+edge cases, and the full-size voxel grid over the 1M-triangle mesh."""
 import numpy as np
 import pytest
 import torch
@@ -62,8 +61,8 @@ def test_grid_equals_per_query_path_and_oracle(name):
     compare_3d(dm, P, wp, cp, sample)
 
 
-def test_candidate_overflow_falls_back_to_traversal():
-    # 40 stacked disks: every column through the stack has > 32 candidates
+def test_deep_stack_of_surfaces():
+    # 40 stacked disks: columns through the stack cross every layer
     M = _stack_of_disks(40)
     dm = DevMesh(M, DZ)
     ax = _axes(M, (10, 12, 30))
