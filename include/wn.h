@@ -281,7 +281,9 @@ wn_status wn_batch_free(wn_batch* batch);
  *  w_out       device [sum nq] float32 out; chi_out device int32 or NULL.
  * The first call captures a counter-reset kernel and the persistent
  * kernel(s) into a hipGraph (after autotuning when requested); later calls
- * replay it, patching the kernel arguments when the pointers change.  The
+ * replay it, patching the kernel arguments when the pointers change.  With
+ * autotuning the graph is kept only if its replay is not slower than direct
+ * launches of the same kernels (wn_batch_info reports which is in use).  The
  * split forward without chi_out keeps the crossing counts in a buffer the
  * batch allocates on first use (4 bytes per query).  Set
  * $WN_FORCE_NO_GRAPH to launch directly (identical results).

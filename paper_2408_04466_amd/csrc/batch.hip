@@ -512,6 +512,34 @@ bool same_args(const wn::FwdArgs& x, const wn::FwdArgs& y) {
   return std::memcmp(&x, &y, sizeof x) == 0;
 }
 
+// Best of two trials of three back-to-back graph replays, and the same for
+// direct launches, in ms per forward.
+wn_status time_graph_vs_direct(wn_batch* b, const wn::FwdArgs& a, hipStream_t s, float* tg, float* td) {
+  hipEvent_t e0, e1;
+  WN_HIP(hipEventCreate(&e0), "event");
+  WN_HIP(hipEventCreate(&e1), "event");
+  float best[2] = {1e30f, 1e30f};
+  for (int v = 0; v < 2; ++v) {
+    for (int r = 0; r < 3; ++r) {      // first pass warms up
+      WN_HIP(hipEventRecord(e0, s), "event");
+      for (int k = 0; k < 3; ++k) {
+        if (v == 0) WN_HIP(hipGraphLaunch(b->exec, s), "graph launch");
+        else WN_HIP(launch_fwd(b, a, s), "batched forward");
+      }
+      WN_HIP(hipEventRecord(e1, s), "event");
+      WN_HIP(hipEventSynchronize(e1), "event");
+      float ms = 0.f;
+      WN_HIP(hipEventElapsedTime(&ms, e0, e1), "event");
+      if (r > 0) best[v] = std::min(best[v], ms / 3.0f);
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *tg = best[0];
+  *td = best[1];
+  return WN_OK;
+}
+
 // --- autotuner ---------------------------------------------------------------
 
 std::string tune_key(const wn_batch* b) {
@@ -614,15 +642,17 @@ wn_status autotune(wn_batch* b, const wn::FwdArgs& base, hipStream_t s) {
           b->mode = m;
           const wn::FwdArgs a = fwd_args(b, base.qx, base.qy, base.qz, base.w, base.chi);
           WN_HIP(launch_fwd(b, a, s), "tune launch");   // warm-up
-          float ms = 1e30f;                              // best of three single launches
-          for (int r = 0; r < 3; ++r) {
+          // back-to-back launches as in use (a single launch after a sync
+          // ranks the candidates differently); best of two trials of three
+          float ms = 1e30f;
+          for (int r = 0; r < 2; ++r) {
             WN_HIP(hipEventRecord(e0, s), "event");
-            WN_HIP(launch_fwd(b, a, s), "tune launch");
+            for (int k = 0; k < 3; ++k) WN_HIP(launch_fwd(b, a, s), "tune launch");
             WN_HIP(hipEventRecord(e1, s), "event");
             WN_HIP(hipEventSynchronize(e1), "event");
-            float one = 0.f;
-            WN_HIP(hipEventElapsedTime(&one, e0, e1), "event");
-            ms = std::min(ms, one);
+            float three = 0.f;
+            WN_HIP(hipEventElapsedTime(&three, e0, e1), "event");
+            ms = std::min(ms, three / 3.0f);
           }
           if (std::getenv("WN_TUNE_LOG"))
             std::fprintf(stderr, "wn tune: tile %d mode %s wg/cu %d: %.4f ms\n", t, m ? "split" : "fused", w, ms);
@@ -836,7 +866,8 @@ wn_status wn_eval_batched(wn_batch* b, const float* qx, const float* qy, const f
   if (b->total_q == 0) return WN_OK;
   if (!qx || !qy || !qz || !w_out) return fail(WN_ERR_INVALID_ARGUMENT, "NULL query or output pointer");
   hipStream_t s = as_stream(stream);
-  if (b->tune_mode > 0 && !b->tuned) {
+  const bool tuning = b->tune_mode > 0 && !b->tuned;
+  if (tuning) {
     wn_status st = autotune(b, fwd_args(b, qx, qy, qz, w_out, chi_out), s);
     if (st) return st;
     drop_graph(b);
@@ -858,6 +889,21 @@ wn_status wn_eval_batched(wn_batch* b, const float* qx, const float* qy, const f
       b->use_graph = false;
       WN_HIP(launch_fwd(b, a, s), "batched forward");
       return WN_OK;
+    }
+    if (tuning) {
+      // the tuner also decides graph replay against direct launches of the
+      // winning configuration: a one-kernel graph saves no launch overhead,
+      // and its replay has measured slower on some runtimes
+      float tg = 0.f, td = 0.f;
+      st = time_graph_vs_direct(b, a, s, &tg, &td);
+      if (st) return st;
+      if (std::getenv("WN_TUNE_LOG")) std::fprintf(stderr, "wn tune: graph %.4f ms, direct %.4f ms\n", tg, td);
+      if (tg > 1.02f * td) {
+        drop_graph(b);
+        b->use_graph = false;
+        WN_HIP(launch_fwd(b, a, s), "batched forward");
+        return WN_OK;
+      }
     }
   } else if (!same_args(a, b->graph_args) && (!b->fwd_node || (b->mode == 1 && !b->bnd_node))) {
     wn_status st = capture(b, a);   // cannot patch the nodes: capture again
