@@ -25,6 +25,7 @@
 // the same solver, so they agree bit for bit.
 #include <cmath>
 
+#include "geom.hpp"
 #include "kernels.hpp"
 
 namespace wn {
@@ -162,15 +163,32 @@ __device__ __forceinline__ bool right_of(const Piece<T>& pc, T yq, T px) {
 }
 
 template <class T> __device__ __forceinline__ T atan2_t(T y, T x);
-template <> __device__ __forceinline__ float atan2_t<float>(float y, float x) { return atan2f(y, x); }
+template <> __device__ __forceinline__ float atan2_t<float>(float y, float x) { return atan2_f32(y, x); }
 template <> __device__ __forceinline__ double atan2_t<double>(double y, double x) { return atan2(y, x); }
 
-// angle of v counter-clockwise from +x, in [0, 2pi); an exact +0 ordinate
-// counts as above
+// phi(e) - phi(s) for the vectors s, e from p to an open loop's start and
+// end, with one atan2: the signed angle theta from s to e lies in (-pi, pi],
+// and phi (in [0, 2pi), cut along +x) differs from it by 2 pi exactly when
+// the chord s -> e crosses the ray p + t(1, 0), t > 0: upward (s below,
+// e on or above the ray's line) gives phi(e) - phi(s) = theta - 2 pi,
+// downward theta + 2 pi.  The crossing lies right of p iff s x e has the
+// direction's sign, the same sign theta takes, so the two decisions cannot
+// disagree through rounding.  p on the chord between s and e (s x e = 0,
+// s . e < 0) gives -pi when e is in [0, pi) (above, or on the +x side of
+// the line), +pi otherwise.
 template <class T>
-__device__ __forceinline__ T phi(T vx, T vy) {
-  const T a = atan2_t(vy, vx);
-  return a < (T)0 ? a + (T)6.283185307179586 : a;
+__device__ __forceinline__ T open_loop_angle(T sx, T sy, T ex, T ey) {
+  const T cr = fma_t(sx, ey, -(sy * ex));
+  const T dt = fma_t(sx, ex, sy * ey);
+  if (cr == (T)0 && dt < (T)0) {
+    const bool e_upper = ey > (T)0 || (ey == (T)0 && ex > (T)0);
+    return e_upper ? -(T)3.141592653589793 : (T)3.141592653589793;
+  }
+  const T th = atan2_t(cr, dt);
+  const bool s_above = sy >= (T)0, e_above = ey >= (T)0;
+  if (!s_above && e_above && cr > (T)0) return th - (T)6.283185307179586;
+  if (s_above && !e_above && cr < (T)0) return th + (T)6.283185307179586;
+  return th;
 }
 
 // sum over open loops of phi(end - p) - phi(start - p)
@@ -181,7 +199,7 @@ __device__ T endpoint_term(const T* __restrict__ ctrl, const Loops2D& L, T px, T
     if (L.closed[l] || L.off[l + 1] <= L.off[l]) continue;
     const T* s = ctrl + 8 * (int64_t)L.off[l];
     const T* f = ctrl + 8 * (int64_t)(L.off[l + 1] - 1);
-    e += phi(f[6] - px, f[7] - py) - phi(s[0] - px, s[1] - py);
+    e += open_loop_angle(s[0] - px, s[1] - py, f[6] - px, f[7] - py);
   }
   return e;
 }
@@ -223,41 +241,58 @@ __global__ __launch_bounds__(kThreads) void k_points(const Piece<T>* __restrict_
 }
 
 constexpr int kColTile = 4096;
+constexpr int kSolveChunk = 1024;   // pieces examined per pass (LDS list of those needing a solve)
 
 // One workgroup per (row, column tile).  Histogram slot c (0..ncol) counts the
 // crossings with exactly c tile columns left of them; columns at or beyond
 // the tile end get every crossing right of the whole tile through `base`.
+// Pieces are examined in chunks: a first pass settles the pieces that miss
+// the row or lie beside the whole tile and lists the others in LDS, so that
+// the Newton solves run on consecutive lanes without idle lanes in between.
+// All counts are integer additions, so their order does not matter.
 template <class T>
 __global__ __launch_bounds__(kThreads) void k_grid(const Piece<T>* __restrict__ pcs,
                                                    const typename Vec2<T>::type* __restrict__ yr, int32_t npc,
                                                    const T* __restrict__ ctrl, Loops2D L,
                                                    const T* __restrict__ x, int64_t nx,
                                                    const T* __restrict__ y, int64_t ny,
-                                                   T* __restrict__ w, int32_t* __restrict__ chi) {
-  __shared__ T sx[kColTile];
-  __shared__ int hist[kColTile + 1];
+                                                   T* __restrict__ w, int32_t* __restrict__ chi, int tile) {
+  // dynamic LDS sized to the tile: sx [tile] T, hist [tile + 1] int
+  extern __shared__ __align__(16) unsigned char dyn[];
+  T* sx = reinterpret_cast<T*>(dyn);
+  int* hist = reinterpret_cast<int*>(sx + tile);
   __shared__ int sscan[kThreads];
+  __shared__ int list[kSolveChunk];
+  __shared__ int nlist;
   const int64_t row = blockIdx.y;
-  const int64_t i0 = (int64_t)blockIdx.x * kColTile;
-  const int ncol = (int)min((int64_t)kColTile, nx - i0);
+  const int64_t i0 = (int64_t)blockIdx.x * tile;
+  const int ncol = (int)min((int64_t)tile, nx - i0);
   const T yq = y[row];
   for (int i = threadIdx.x; i < ncol; i += kThreads) sx[i] = x[i0 + i];
   for (int i = threadIdx.x; i <= ncol; i += kThreads) hist[i] = 0;
   __syncthreads();
   const T xlo = sx[0], xhi = sx[ncol - 1];
   int base = 0;   // crossings right of every column of the tile
-  for (int j = threadIdx.x; j < npc; j += kThreads) {
-    const typename Vec2<T>::type e = yr[j];
-    const bool s0 = e.x >= yq, s1 = e.y >= yq;
-    if (s0 == s1) continue;
-    const int sg = s1 ? 1 : -1;
-    const Piece<T>& pc = pcs[j];
-    int cpos;
-    if (xhi < pc.xmin) {
-      cpos = ncol;                       // right of every column
-    } else if (xlo >= pc.xmax) {
-      cpos = 0;                          // right of none
-    } else {
+  for (int c0 = 0; c0 < npc; c0 += kSolveChunk) {
+    const int c1 = min(c0 + kSolveChunk, npc);
+    if (threadIdx.x == 0) nlist = 0;
+    __syncthreads();
+    for (int j = c0 + threadIdx.x; j < c1; j += kThreads) {
+      const typename Vec2<T>::type e = yr[j];
+      const bool s0 = e.x >= yq, s1 = e.y >= yq;
+      if (s0 == s1) continue;
+      const int sg = s1 ? 1 : -1;
+      const T pxmin = pcs[j].xmin, pxmax = pcs[j].xmax;
+      if (xhi < pxmin) base += sg;                     // right of every column
+      else if (xlo < pxmax) list[atomicAdd(&nlist, 1)] = j;   // needs the solve
+      // else: right of no column
+    }
+    __syncthreads();
+    const int n = nlist;
+    for (int k = threadIdx.x; k < n; k += kThreads) {
+      const int j = list[k];
+      const Piece<T>& pc = pcs[j];
+      const int sg = yr[j].y >= yq ? 1 : -1;
       const T xs = solve_x(pc, yq);
       const T xe = fmin(fmax(xs, pc.xmin), pc.xmax);
       // number of tile columns with x_i < xe (x ascending)
@@ -266,10 +301,10 @@ __global__ __launch_bounds__(kThreads) void k_grid(const Piece<T>* __restrict__ 
         const int mid = (a + b) >> 1;
         if (sx[mid] < xe) a = mid + 1; else b = mid;
       }
-      cpos = a;
+      if (a == ncol) base += sg;
+      else if (a > 0) atomicAdd(&hist[a], sg);
     }
-    if (cpos == ncol) base += sg;
-    else if (cpos > 0) atomicAdd(&hist[cpos], sg);
+    __syncthreads();
   }
   // block-wide sum of `base`
   sscan[threadIdx.x] = base;
@@ -297,9 +332,16 @@ __global__ __launch_bounds__(kThreads) void k_grid(const Piece<T>* __restrict__ 
     __syncthreads();
   }
   int run = btot + (((int)threadIdx.x + 1 < kThreads) ? sscan[threadIdx.x + 1] : 0);
-  // walk this thread's columns from the right
+  // walk this thread's columns from the right; chi(i) replaces hist[i + 1],
+  // which no thread reads after this point (thread blocks are disjoint and
+  // the slot is read just before it is overwritten)
   for (int i = a1 - 1; i >= a0; --i) {
     if (i + 1 < ncol) run += hist[i + 1];
+    hist[i + 1] = run;
+  }
+  __syncthreads();
+  // coalesced output: consecutive lanes write consecutive columns
+  for (int i = threadIdx.x; i < ncol; i += kThreads) {
     const int64_t o = row * nx + i0 + i;
     const T px = sx[i];
     if (!(isfinite(px) && isfinite(yq))) {
@@ -307,9 +349,10 @@ __global__ __launch_bounds__(kThreads) void k_grid(const Piece<T>* __restrict__ 
       if (chi) chi[o] = WN_CHI_INVALID;
       continue;
     }
+    const int c = hist[i + 1];
     const T e = endpoint_term(ctrl, L, px, yq);
-    w[o] = (T)run + e * (T)0.15915494309189535;
-    if (chi) chi[o] = run;
+    w[o] = (T)c + e * (T)0.15915494309189535;
+    if (chi) chi[o] = c;
   }
 }
 
@@ -334,8 +377,12 @@ hipError_t run2d(const T* ctrl, int64_t nseg, const Loops2D& L, int32_t kind, co
       hipLaunchKernelGGL(k_points<T>, dim3((unsigned)((nx + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
                          pcs, (int32_t)npc, ctrl, L, x, y, nx, w, chi);
     } else {
-      hipLaunchKernelGGL(k_grid<T>, dim3((unsigned)((nx + kColTile - 1) / kColTile), (unsigned)ny), dim3(kThreads),
-                         0, s, pcs, yr, (int32_t)npc, ctrl, L, x, nx, y, ny, w, chi);
+      // tiles of at most kColTile columns, as even as possible; LDS sized to the tile
+      const int64_t ntiles = (nx + kColTile - 1) / kColTile;
+      const int tile = (int)((nx + ntiles - 1) / ntiles);
+      const size_t lds = ((size_t)tile * sizeof(T) + (size_t)(tile + 1) * sizeof(int) + 15) & ~(size_t)15;
+      hipLaunchKernelGGL(k_grid<T>, dim3((unsigned)ntiles, (unsigned)ny), dim3(kThreads), lds, s, pcs, yr,
+                         (int32_t)npc, ctrl, L, x, nx, y, ny, w, chi, tile);
     }
     e = hipGetLastError();
   }
