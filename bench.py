@@ -36,7 +36,7 @@ import synth  # noqa: E402
 FLOPS_PER_PAIR_FWD = 58      # boundary integral, per (query, boundary edge)
 COUNTERS = os.path.join(ROOT, "profiles", "k_bnd3d_mesh_2p20_counters.md")
 KERNEL_SOURCES = ("paper_2408_04466_amd/csrc/bnd3d.hip", "paper_2408_04466_amd/csrc/bndloop.hpp",
-                  "paper_2408_04466_amd/csrc/geom.hpp", "paper_2408_04466_amd/csrc/kernels.hpp")
+                  "paper_2408_04466_amd/csrc/geom.hpp")
 FLOPS_PER_PAIR_BWD = 40      # adjoint, per (query, boundary edge)
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak
 

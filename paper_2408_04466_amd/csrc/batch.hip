@@ -157,7 +157,8 @@ __device__ __forceinline__ CrossArgs cross_args(const SurfDesc& D) {
 }
 
 // Fused mode: per query, the crossing count and then the boundary walk.
-__global__ __launch_bounds__(kThreads) void k_batch_fwd(FwdArgs a) {
+// Seven waves per SIMD (71 registers; one 64-bit value spills in the prologue).
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_batch_fwd(FwdArgs a) {
   __shared__ double4 sv[bnd::kChunk];
   __shared__ int s_item;
   for (int pass = 0;; ++pass) {

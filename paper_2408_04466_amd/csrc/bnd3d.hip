@@ -53,7 +53,8 @@ __global__ __launch_bounds__(kThreads) void k_bnd3d(BndArgs a, LoopTable L) {
 // Fused forward, one query per lane: the crossing count (BVH traversal),
 // then the boundary walk, then w.  While some waves wait on node fetches,
 // others keep the vector units busy with the boundary arithmetic.
-__global__ __launch_bounds__(kThreads) void k_fwd3d(CrossArgs c, BndArgs a, LoopTable L, int32_t* chi_out) {
+// Eight waves per SIMD: fits in 64 registers without spilling.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_fwd3d(CrossArgs c, BndArgs a, LoopTable L, int32_t* chi_out) {
   __shared__ double4 sv[kChunk];
   const int64_t qi = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const bool ok = qi < a.nq;
