@@ -19,10 +19,11 @@ Contents
 - ``grad3d`` : closed-form derivatives of the boundary integral with respect to
                the query point and the boundary vertices (the crossing count is
                piecewise constant, so it contributes nothing).
-- ``pool``   : a multiprocessing map used to time the oracle on host cores.
+- ``grad2d`` : the same for 2D loops: only the open loops' end points (and the
+               query) carry a gradient.
 
 Every floating-point computation is float64 on inputs promoted exactly from
 the kernel's float32 arrays.  Parity status of each function is stated in its
 module header ("pinned by ..." or "parity unpinned").
 """
-from . import wn3d, wn2d, grad3d  # noqa: F401
+from . import wn3d, wn2d, grad3d, grad2d  # noqa: F401
