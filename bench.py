@@ -417,8 +417,12 @@ def run_others(torch, W, T, others, d3, args, dev):
     ctrl2 = torch.from_numpy(C2.ctrl).to(dev)
     xs2 = torch.from_numpy(synth.grid_axis(-1.2, 1.2, 2048, np.float32)).to(dev)
     ms2 = T.ms(lambda: W.eval_2d(ctrl2, C2.loop_off, C2.closed, xs2, xs2, grid=True), reps)
+    g2 = torch.ones(2048, 2048, dtype=torch.float32, device=dev)
+    ms2b = T.ms(lambda: W.backward_2d(ctrl2, C2.loop_off, C2.closed, xs2, xs2, g2, grid=True), reps)
     res["2d_loops_fp32_grid_2048^2"] = {"ms": ms2, "queries_per_s": 2048 * 2048 / (ms2 * 1e-3),
-                                        "hbm_GBs_outputs": 2048 * 2048 * 8 / (ms2 * 1e-3) / 1e9}
+                                        "hbm_GBs_outputs": 2048 * 2048 * 8 / (ms2 * 1e-3) / 1e9,
+                                        "backward_ms": ms2b,
+                                        "backward_hbm_GBs": 2048 * 2048 * 12 / (ms2b * 1e-3) / 1e9}
     return res
 
 

@@ -237,6 +237,30 @@ wn_status wn_eval_2d(wn_dtype dtype, const void* ctrl, int64_t nseg,
                      void* w_out, int32_t* chi_out, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * wn_backward_2d -- adjoint of wn_eval_2d for a loss L with dL/dw = grad_w.
+ * Away from the curves the crossing count is locally constant, so w moves
+ * only with the open loops' end-point angles (the 2D boundary of Sec. 4):
+ * with A(v) = (-v_y, v_x)/|v|^2 and c = grad_w/(2 pi) per query,
+ *   dL/dp = c (A(s - p) - A(e - p)) summed over open loops,
+ *   dL/ds = -sum_q c A(s - p),  dL/de = sum_q c A(e - p),
+ * s = ctrl[first segment][0], e = ctrl[last segment][3] of each open loop;
+ * every other control point gets 0.
+ *  Curves, loop table, kind, x, y, nx, ny as in wn_eval_2d.
+ *  grad_w     device [n] (points: n = nx; grid: [ny][nx]) of dtype.
+ *  grad_q     device [n][2] of dtype out, or NULL (NaN for non-finite
+ *             queries).
+ *  grad_ctrl  device [nseg][4][2] of dtype out (fully written), or NULL.
+ * The end-point sums are reduced in float64 in a fixed order (bitwise
+ * reproducible).  Allocates 32 bytes per (open loop, 256 queries) on the
+ * stream.  Errors as wn_eval_2d.
+ * ------------------------------------------------------------------------- */
+wn_status wn_backward_2d(wn_dtype dtype, const void* ctrl, int64_t nseg,
+                         const int64_t* loop_off, const uint8_t* loop_closed,
+                         int32_t nloops, int32_t kind, const void* x, const void* y,
+                         int64_t nx, int64_t ny, const void* grad_w, void* grad_q,
+                         void* grad_ctrl, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Batched evaluation: many surfaces of uneven size, each with its own query
  * set, evaluated in one persistent launch replayed from a hipGraph.
  *

@@ -7,7 +7,9 @@ All computation runs in the library's HIP kernels.
 from .api import (  # noqa: F401
     BVH,
     Batch,
+    WindingNumber2D,
     WindingNumber3D,
+    backward_2d,
     backward,
     boundary_loops,
     crossings_3d,
@@ -16,5 +18,6 @@ from .api import (  # noqa: F401
     eval_3d_boundary,
     eval_3d_grid,
     winding_number,
+    winding_number_2d,
 )
 from ._lib import WN_CHI_INVALID, WN_MAX_LOOPS, WnError, lib  # noqa: F401

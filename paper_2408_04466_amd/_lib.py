@@ -45,6 +45,7 @@ SIGNATURES = {
     "wn_crossings_3d": (I32, [P, P, P, P, I64, P, P]),
     "wn_backward": (I32, [P, PI64, I32, P, P, P, I64, P, P, P, P]),
     "wn_eval_2d": (I32, [I32, P, I64, PI64, P, I32, I32, P, P, I64, I64, P, P, P]),
+    "wn_backward_2d": (I32, [I32, P, I64, PI64, P, I32, I32, P, P, I64, I64, P, P, P, P]),
     "wn_batch_create": (I32, [P, I32, PD, I32, P, C.POINTER(P)]),
     "wn_batch_free": (I32, [P]),
     "wn_eval_batched": (I32, [P, P, P, P, P, P, P]),

@@ -251,6 +251,67 @@ def eval_2d(ctrl: torch.Tensor, loop_off, loop_closed, x: torch.Tensor, y: torch
     return w, chi
 
 
+def backward_2d(ctrl: torch.Tensor, loop_off, loop_closed, x: torch.Tensor, y: torch.Tensor,
+                grad_w: torch.Tensor, grid: bool = False, want_q: bool = True, want_ctrl: bool = True,
+                stream=None):
+    """(dL/dp, dL/dctrl) for dL/dw = grad_w on the queries of eval_2d (same
+    layout: points [n] or grid [ny, nx]); dL/dp has a trailing axis of 2, dL/dctrl
+    the shape of ctrl.  Only the open loops' end points get nonzero entries."""
+    if ctrl.dtype == torch.float64:
+        dt, code = torch.float64, 1
+    elif ctrl.dtype == torch.float32:
+        dt, code = torch.float32, 0
+    else:
+        raise TypeError("ctrl must be float32 or float64")
+    nseg = ctrl.shape[0]
+    pc = _dev(ctrl, dt, "ctrl", (nseg, 4, 2))
+    lo, nl = _loops(loop_off)
+    cl = np.ascontiguousarray(np.asarray(loop_closed, np.uint8))
+    if cl.size != nl:
+        raise ValueError("loop_closed must have one entry per loop")
+    nx, ny = x.shape[0], y.shape[0]
+    if not grid and nx != ny:
+        raise ValueError("points mode needs len(x) == len(y)")
+    shape = (ny, nx) if grid else (nx,)
+    pg = _dev(grad_w, dt, "grad_w", shape)
+    gq = torch.empty(shape + (2,), dtype=dt, device=x.device) if want_q else None
+    gc = torch.empty((nseg, 4, 2), dtype=dt, device=x.device) if want_ctrl else None
+    check(lib().wn_backward_2d(code, pc, nseg, _ptr64(lo), cl.ctypes.data_as(C.c_void_p) if cl.size else None, nl,
+                               1 if grid else 0, _dev(x, dt, "x", (nx,)), _dev(y, dt, "y", (ny,)), nx,
+                               ny if grid else nx, pg, _dev(gq, dt, "grad_q") if gq is not None else None,
+                               _dev(gc, dt, "grad_ctrl") if gc is not None else None, _stream(stream)),
+          "wn_backward_2d")
+    return gq, gc
+
+
+class WindingNumber2D(torch.autograd.Function):
+    """w of cubic Bezier loops at points (x[i], y[i]); gradients flow to the
+    control points (only open loops' end points move w) and to x, y."""
+
+    @staticmethod
+    def forward(ctx, ctrl, x, y, loop_off, loop_closed):
+        w, _ = eval_2d(ctrl.detach(), loop_off, loop_closed, x.detach(), y.detach(), want_chi=False)
+        ctx.save_for_backward(ctrl, x, y)
+        ctx.loops = (loop_off, loop_closed)
+        return w
+
+    @staticmethod
+    def backward(ctx, grad_w):
+        ctrl, x, y = ctx.saved_tensors
+        need_c = ctx.needs_input_grad[0]
+        need_q = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
+        gq, gc = backward_2d(ctrl.detach(), ctx.loops[0], ctx.loops[1], x.detach(), y.detach(),
+                             grad_w.contiguous().to(ctrl.dtype), want_q=need_q, want_ctrl=need_c)
+        gx = gy = None
+        if gq is not None:
+            gx, gy = gq[:, 0], gq[:, 1]
+        return gc, gx, gy, None, None
+
+
+def winding_number_2d(ctrl, loop_off, loop_closed, x, y):
+    return WindingNumber2D.apply(ctrl, x, y, loop_off, loop_closed)
+
+
 class Batch:
     """Many surfaces, each with its own queries, in one persistent launch
     (``wn_batch_create`` / ``wn_eval_batched`` / ``wn_backward_batched``).

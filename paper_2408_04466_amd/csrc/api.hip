@@ -528,6 +528,46 @@ wn_status wn_backward(const float* bnd_xyz, const int64_t* loop_off, int32_t nlo
   return WN_OK;
 }
 
+// Checks shared by the 2D entry points (curves, loop table, query layout).
+static wn_status check_2d(wn_dtype dtype, const void* ctrl, int64_t nseg, const int64_t* loop_off,
+                          const uint8_t* loop_closed, int32_t nloops, int32_t kind, int64_t nx, int64_t ny) {
+  if (dtype != WN_F32 && dtype != WN_F64) return fail(WN_ERR_UNSUPPORTED, "dtype must be WN_F32 or WN_F64");
+  if (kind != 0 && kind != 1) return fail(WN_ERR_INVALID_ARGUMENT, "kind must be 0 (points) or 1 (grid)");
+  if (nseg < 0 || nx < 0 || (kind == 1 && ny < 0)) return fail(WN_ERR_INVALID_ARGUMENT, "negative count");
+  if (nseg > (INT32_MAX - 3) / 3) return fail(WN_ERR_UNSUPPORTED, "too many segments");
+  if (nseg > 0 && !ctrl) return fail(WN_ERR_INVALID_ARGUMENT, "ctrl is NULL");
+  if (nloops < 0) return fail(WN_ERR_INVALID_ARGUMENT, "nloops must be >= 0");
+  if (nloops > WN_MAX_LOOPS) return fail(WN_ERR_UNSUPPORTED, "at most %d loops per call", WN_MAX_LOOPS);
+  if (nloops > 0 && (!loop_off || !loop_closed)) return fail(WN_ERR_INVALID_ARGUMENT, "loop table is NULL");
+  if (nloops > 0) {
+    if (loop_off[0] != 0) return fail(WN_ERR_INVALID_ARGUMENT, "loop_off[0] must be 0");
+    for (int32_t l = 0; l < nloops; ++l)
+      if (loop_off[l + 1] <= loop_off[l]) return fail(WN_ERR_INVALID_ARGUMENT, "loop %d is empty or reversed", l);
+    if (loop_off[nloops] != nseg) return fail(WN_ERR_INVALID_ARGUMENT, "loop_off[nloops] must equal nseg");
+  } else if (nseg > 0) {
+    return fail(WN_ERR_INVALID_ARGUMENT, "segments without loops");
+  }
+  return WN_OK;
+}
+
+wn_status wn_backward_2d(wn_dtype dtype, const void* ctrl, int64_t nseg, const int64_t* loop_off,
+                         const uint8_t* loop_closed, int32_t nloops, int32_t kind, const void* x, const void* y,
+                         int64_t nx, int64_t ny, const void* grad_w, void* grad_q, void* grad_ctrl, void* stream) {
+  g_err.clear();
+  wn_status st = check_2d(dtype, ctrl, nseg, loop_off, loop_closed, nloops, kind, nx, ny);
+  if (st) return st;
+  if (kind == 1 && nx > 0 && ny > INT64_MAX / nx) return fail(WN_ERR_INVALID_ARGUMENT, "grid too large");
+  const int64_t n = kind == 0 ? nx : nx * ny;
+  if (n > 0 && (!x || !y || !grad_w)) return fail(WN_ERR_INVALID_ARGUMENT, "query coordinates or grad_w are NULL");
+  if (!grad_q && !grad_ctrl) return WN_OK;
+  int64_t lo_local[1] = {0};
+  uint8_t cl_local[1] = {0};
+  WN_HIP(wn::backward_2d(dtype, ctrl, nseg, nloops ? loop_off : lo_local, nloops ? loop_closed : cl_local, nloops,
+                         kind, x, y, nx, ny, grad_w, grad_q, grad_ctrl, as_stream(stream)),
+         "wn_backward_2d");
+  return WN_OK;
+}
+
 wn_status wn_eval_2d(wn_dtype dtype, const void* ctrl, int64_t nseg, const int64_t* loop_off,
                      const uint8_t* loop_closed, int32_t nloops, int32_t kind, const void* x, const void* y,
                      int64_t nx, int64_t ny, void* w_out, int32_t* chi_out, void* stream) {

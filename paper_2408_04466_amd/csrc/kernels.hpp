@@ -80,6 +80,9 @@ hipError_t launch_adj3d(const AdjArgs& a, const LoopTable& L, int64_t nblocks, h
 int64_t adj3d_blocks(int64_t nq);
 int64_t adj3d_rows(int64_t nblocks);
 int64_t reduce_groups(int64_t rows);
+hipError_t backward_2d(int32_t dtype, const void* ctrl, int64_t nseg, const int64_t* loop_off,
+                       const uint8_t* closed, int32_t nloops, int32_t kind, const void* x, const void* y,
+                       int64_t nx, int64_t ny, const void* gw, void* gq, void* gc, hipStream_t s);
 hipError_t eval_2d(int32_t dtype, const void* ctrl, int64_t nseg, const int64_t* loop_off,
                    const uint8_t* closed, int32_t nloops, int32_t kind, const void* x, const void* y,
                    int64_t nx, int64_t ny, void* w, int32_t* chi, hipStream_t s);

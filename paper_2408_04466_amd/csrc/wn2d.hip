@@ -356,6 +356,144 @@ __global__ __launch_bounds__(kThreads) void k_grid(const Piece<T>* __restrict__ 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint.  Away from the curves chi is locally constant, so w moves only
+// with the open loops' end-point angles; with A(v) = (-v_y, v_x)/|v|^2 (the
+// gradient of the angle of v) and c = g/(2 pi) per query:
+//   dL/dp += c (A(s - p) - A(e - p)),  dL/ds -= c A(s - p),  dL/de += c A(e - p).
+// Interior control points and closed loops get zero.  Per workgroup the
+// end-point sums are reduced in LDS by a fixed-order tree in float64 and
+// stored value-major (part[value][block]); a second kernel adds the blocks
+// in a fixed order, so grad_ctrl is bitwise reproducible.
+// ---------------------------------------------------------------------------
+
+template <class T>
+__device__ __forceinline__ void angle_grad(T vx, T vy, T& ax, T& ay) {
+  const T r2 = fma_t(vx, vx, vy * vy);
+  const T inv = (T)1 / r2;
+  ax = -vy * inv;
+  ay = vx * inv;
+}
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_back2d(const T* __restrict__ ctrl, Loops2D L, int32_t kind,
+                                                     const T* __restrict__ x, const T* __restrict__ y, int64_t nx,
+                                                     int64_t n, const T* __restrict__ gw, T* __restrict__ gq,
+                                                     double* __restrict__ part, int64_t nblocks) {
+  __shared__ double red[4][kThreads];
+  const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const bool ok = q < n;
+  T px = (T)0, py = (T)0, g = (T)0;
+  if (ok) {
+    px = kind == 0 ? x[q] : x[q % nx];
+    py = kind == 0 ? y[q] : y[q / nx];
+    g = gw[q];
+  }
+  const bool fin = ok && isfinite(px) && isfinite(py);
+  const T c = fin ? g * (T)0.15915494309189535 : (T)0;
+  T gpx = (T)0, gpy = (T)0;
+  int k = 0;
+  for (int l = 0; l < L.n; ++l) {
+    if (L.closed[l] || L.off[l + 1] <= L.off[l]) continue;
+    const T* sp = ctrl + 8 * (int64_t)L.off[l];
+    const T* ep = ctrl + 8 * (int64_t)(L.off[l + 1] - 1);
+    T asx = (T)0, asy = (T)0, aex = (T)0, aey = (T)0;
+    if (fin) {
+      angle_grad(sp[0] - px, sp[1] - py, asx, asy);
+      angle_grad(ep[6] - px, ep[7] - py, aex, aey);
+      gpx += asx - aex;
+      gpy += asy - aey;
+    }
+    if (part) {   // uniform: end-point gradients requested
+      red[0][threadIdx.x] = -(double)(c * asx);
+      red[1][threadIdx.x] = -(double)(c * asy);
+      red[2][threadIdx.x] = (double)(c * aex);
+      red[3][threadIdx.x] = (double)(c * aey);
+      __syncthreads();
+      for (int h = kThreads / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + h];
+        __syncthreads();
+      }
+      if (threadIdx.x < 4) part[((int64_t)k * 4 + threadIdx.x) * nblocks + blockIdx.x] = red[threadIdx.x][0];
+      __syncthreads();
+    }
+    ++k;
+  }
+  if (ok && gq) {
+    if (fin) {
+      gq[2 * q] = c * gpx;
+      gq[2 * q + 1] = c * gpy;
+    } else {
+      gq[2 * q] = gq[2 * q + 1] = (T)NAN;
+    }
+  }
+}
+
+// One workgroup per end-point value v = 4 k + j (k-th open loop; j: start x,
+// start y, end x, end y): fixed-order sum over the blocks, into its grad_ctrl
+// entry.
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_back2d_sum(const double* __restrict__ part, int64_t nblocks,
+                                                         Loops2D L, T* __restrict__ gc) {
+  __shared__ double red[kThreads];
+  const double* p = part + (int64_t)blockIdx.x * nblocks;
+  double sacc = 0.0;
+  for (int64_t b = threadIdx.x; b < nblocks; b += kThreads) sacc += p[b];
+  red[threadIdx.x] = sacc;
+  __syncthreads();
+  for (int h = kThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int k = blockIdx.x / 4, j = blockIdx.x % 4;
+    int seen = -1, l = 0;
+    for (; l < L.n; ++l) {
+      if (L.closed[l] || L.off[l + 1] <= L.off[l]) continue;
+      if (++seen == k) break;
+    }
+    const int64_t at = j < 2 ? 8 * (int64_t)L.off[l] + j : 8 * (int64_t)(L.off[l + 1] - 1) + 6 + (j - 2);
+    gc[at] = (T)red[0];
+  }
+}
+
+template <class T>
+__global__ void k_zero(T* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (T)0;
+}
+
+template <class T>
+hipError_t back2d(const T* ctrl, int64_t nseg, const Loops2D& L, int32_t kind, const T* x, const T* y,
+                  int64_t nx, int64_t n, const T* gw, T* gq, T* gc, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (gc && nseg > 0) {
+    hipLaunchKernelGGL(k_zero<T>, dim3((unsigned)((8 * nseg + 255) / 256)), dim3(256), 0, s, gc, 8 * nseg);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (n == 0) return hipSuccess;
+  int nopen = 0;
+  for (int l = 0; l < L.n; ++l)
+    if (!L.closed[l] && L.off[l + 1] > L.off[l]) ++nopen;
+  const int64_t nblocks = (n + kThreads - 1) / kThreads;
+  double* part = nullptr;   // [4 nopen][nblocks] float64 partial sums
+  if (gc && nopen > 0) {
+    e = hipMallocAsync((void**)&part, (size_t)nopen * 4 * nblocks * sizeof(double), s);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_back2d<T>, dim3((unsigned)nblocks), dim3(kThreads), 0, s, ctrl, L, kind, x, y, nx, n, gw, gq,
+                     part, nblocks);
+  e = hipGetLastError();
+  if (e == hipSuccess && part) {
+    hipLaunchKernelGGL(k_back2d_sum<T>, dim3((unsigned)(4 * nopen)), dim3(kThreads), 0, s, part, nblocks, L, gc);
+    e = hipGetLastError();
+  }
+  if (part) hipFreeAsync(part, s);
+  return e;
+}
+
 template <class T>
 hipError_t run2d(const T* ctrl, int64_t nseg, const Loops2D& L, int32_t kind, const T* x, const T* y,
                  int64_t nx, int64_t ny, T* w, int32_t* chi, hipStream_t s) {
@@ -407,6 +545,21 @@ hipError_t eval_2d(int32_t dtype, const void* ctrl, int64_t nseg, const int64_t*
                          (double*)w, chi, s);
   return run2d<float>((const float*)ctrl, nseg, L, kind, (const float*)x, (const float*)y, nx, ny, (float*)w,
                       chi, s);
+}
+
+hipError_t backward_2d(int32_t dtype, const void* ctrl, int64_t nseg, const int64_t* loop_off,
+                       const uint8_t* closed, int32_t nloops, int32_t kind, const void* x, const void* y,
+                       int64_t nx, int64_t ny, const void* gw, void* gq, void* gc, hipStream_t s) {
+  Loops2D L;
+  L.n = nloops;
+  for (int l = 0; l <= nloops; ++l) L.off[l] = (int32_t)loop_off[l];
+  for (int l = 0; l < nloops; ++l) L.closed[l] = closed[l] ? 1 : 0;
+  const int64_t n = kind == 0 ? nx : nx * ny;
+  if (dtype == WN_F64)
+    return back2d<double>((const double*)ctrl, nseg, L, kind, (const double*)x, (const double*)y, nx, n,
+                          (const double*)gw, (double*)gq, (double*)gc, s);
+  return back2d<float>((const float*)ctrl, nseg, L, kind, (const float*)x, (const float*)y, nx, n,
+                       (const float*)gw, (float*)gq, (float*)gc, s);
 }
 
 }  // namespace wn
