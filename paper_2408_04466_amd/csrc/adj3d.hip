@@ -10,23 +10,25 @@ namespace {
 
 using namespace adj;
 
-// Four waves per SIMD: the register allocator then fits 128 registers,
-// spilling one pointer outside the walk.
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_adj3d(AdjArgs a,
-                                                                                            LoopTable L) {
+// QPL queries per lane.  With 4, four waves per SIMD: the register
+// allocator then fits 128 registers, spilling one pointer outside the walk.
+template <int QPL>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL == 4 ? 4 : (QPL == 2 ? 6 : 8)))) void k_adj3d(
+    AdjArgs a, LoopTable L) {
   __shared__ float4 sv[kChunk];
   __shared__ float4 rsw[kWaves * kRowFloats / 4];
   const int wave = threadIdx.x >> 6;
   const int64_t bw = (int64_t)blockIdx.x * kWaves + wave;     // partial row
   float* pv = a.partial ? a.partial + bw * (int64_t)a.nb * 3 : nullptr;
   float* pl = a.partial_loop ? a.partial_loop + bw * (int64_t)L.n * 3 : nullptr;
-  QState S[kQPL];
-  int64_t qi[kQPL];
-  bool ok[kQPL];
-  const int64_t q0 = (int64_t)blockIdx.x * kTile;
-  load_tile(S, a.qx, a.qy, a.qz, a.gw, q0, min((int64_t)kTile, a.nq - q0), qi, ok);
-  walk(S, a.bnd, a.nb, bnd::KernargLoops{L}, sv, reinterpret_cast<float*>(rsw), pv, pl);
-  store_gq(S, qi, ok, a.gq);
+  QState S[QPL];
+  int64_t qi[QPL];
+  bool ok[QPL];
+  const int64_t tile = (int64_t)kThreads * QPL;
+  const int64_t q0 = (int64_t)blockIdx.x * tile;
+  load_tile<QPL>(S, a.qx, a.qy, a.qz, a.gw, q0, min(tile, a.nq - q0), qi, ok);
+  walk<QPL>(S, a.bnd, a.nb, bnd::KernargLoops{L}, sv, reinterpret_cast<float*>(rsw), pv, pl);
+  store_gq<QPL>(S, qi, ok, a.gq);
 }
 
 constexpr int kRowsPerGroup = 32;
@@ -67,16 +69,33 @@ __global__ void k_reduce_groups(const double* __restrict__ tmp, int64_t groups, 
 
 }  // namespace
 
-int64_t adj3d_blocks(int64_t nq) {
-  const int64_t per = (int64_t)kThreads * kQPL;
+// Queries per lane for nq queries (measured on a 256-CU MI355X): 4 (the
+// cheapest per pair: the cross-lane sums are shared by four queries) once
+// that leaves four wavefronts per SIMD (nq >= 2^20); 2 down to one wavefront
+// per SIMD (nq >= 2^17; at 2^18 queries x 2048 edges 0.75 ms against 0.87
+// ms with 4 and 0.94 ms with 1); 1 below.
+int adj3d_qpl(int64_t nq) {
+  const int64_t simds = 4 * 256;
+  if (nq >= (int64_t)kThreads * 4 * simds) return 4;
+  if (nq >= (int64_t)kThreads * 2 * simds / 4) return 2;
+  return 1;
+}
+
+int64_t adj3d_blocks(int64_t nq, int qpl) {
+  const int64_t per = (int64_t)kThreads * qpl;
   return (nq + per - 1) / per;
 }
 
 int64_t adj3d_rows(int64_t nblocks) { return nblocks * kWaves; }
 
-hipError_t launch_adj3d(const AdjArgs& a, const LoopTable& L, int64_t nblocks, hipStream_t s) {
+hipError_t launch_adj3d(const AdjArgs& a, const LoopTable& L, int64_t nblocks, int qpl, hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_adj3d, dim3((unsigned)nblocks), dim3(kThreads), 0, s, a, L);
+  if (qpl == 4)
+    hipLaunchKernelGGL(k_adj3d<4>, dim3((unsigned)nblocks), dim3(kThreads), 0, s, a, L);
+  else if (qpl == 2)
+    hipLaunchKernelGGL(k_adj3d<2>, dim3((unsigned)nblocks), dim3(kThreads), 0, s, a, L);
+  else
+    hipLaunchKernelGGL(k_adj3d<1>, dim3((unsigned)nblocks), dim3(kThreads), 0, s, a, L);
   return hipGetLastError();
 }
 

@@ -9,7 +9,7 @@
 // (the same field integrated against each vertex's hat function along the
 // straight edge).  These vanish in sum: sum_v dw/dv + dw/dp = 0.
 //
-// A lane holds kQPL queries; the workgroup stages the boundary in LDS and
+// A lane holds QPL queries (a template parameter); the workgroup stages the boundary in LDS and
 // every lane walks the same vertex sequence.  A vertex's gradient is complete
 // one step after the vertex is visited (its two edges are then done); it is
 // summed over the lane's queries in registers and over each row of 16 lanes
@@ -29,9 +29,9 @@ namespace adj {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kQPL = 4;
+constexpr int kQPL = 4;              // queries per lane of the batched adjoint (plain: 1, 2 or 4)
 constexpr int kChunk = 512;
-constexpr int kTile = kThreads * 4;   // queries per tile (kQPL per lane)
+constexpr int kTile = kThreads * kQPL;   // queries per batched tile
 constexpr int kBlk = 16;              // vertices per partial store
 constexpr int kRowFloats = kBlk * 12; // LDS row sums per wavefront: [kBlk][3][4 rows]
 constexpr float kInv4Pi = 0.07957747154594767f;
@@ -154,11 +154,12 @@ __device__ __forceinline__ void put3(float* dst, const float acc[3], int lane) {
   }
 }
 
-// Load the tile's queries [q0, q0 + cnt) into the lane states.
+// Load the tile's queries [q0, q0 + cnt) into the lane states (QPL per lane).
+template <int QPL>
 __device__ __forceinline__ void load_tile(QState* S, const float* qx, const float* qy, const float* qz,
                                           const float* gw, int64_t q0, int64_t cnt, int64_t* qi, bool* ok) {
 #pragma unroll
-  for (int k = 0; k < kQPL; ++k) {
+  for (int k = 0; k < QPL; ++k) {
     const int64_t r = (int64_t)k * kThreads + threadIdx.x;
     ok[k] = r < cnt;
     qi[k] = q0 + (ok[k] ? r : 0);
@@ -174,11 +175,12 @@ __device__ __forceinline__ void zero3(float* a) { a[0] = a[1] = a[2] = 0.f; }
 
 // Edge A->B for every query of the lane; the partial of vertex A is then
 // complete and goes out (summed over the wavefront) to row entry `va`.
+template <int QPL>
 __device__ __forceinline__ void step(QState* S, const Rel* A, const Rel* B, float* accA, float* accB,
                                      float* pv, float* rs, int va, int nb, int lane) {
   zero3(accB);
 #pragma unroll
-  for (int k = 0; k < kQPL; ++k) edge_grad(S[k], A[k], B[k], accA, accB);
+  for (int k = 0; k < QPL; ++k) edge_grad(S[k], A[k], B[k], accA, accB);
   if (pv) park(rs, pv, va, nb, accA, lane);
 }
 
@@ -188,12 +190,12 @@ __device__ __forceinline__ void step(QState* S, const Rel* A, const Rel* B, floa
 // blocks [kWaves][kRowFloats].  Loops are taken as straight vertex ranges
 // (like the forward walk), two vertices per step; vertices complete in
 // increasing order 0 .. nb-1.
-template <class Loops>
+template <int QPL, class Loops>
 __device__ __forceinline__ void walk(QState* S, const float* __restrict__ bnd, int nb, const Loops& L,
                                      float4* sv, float* rsw, float* pv, float* pl) {
   const int lane = threadIdx.x & 63;
   float* rs = rsw + (threadIdx.x >> 6) * kRowFloats;
-  Rel F[kQPL], A[kQPL], B[kQPL];   // loop's first vertex; A = last vertex visited
+  Rel F[QPL], A[QPL], B[QPL];      // loop's first vertex; A = last vertex visited
   float accA[3], accB[3];          // pending partial of vertex A (and scratch for B)
   zero3(accA);
   int l = 0;
@@ -212,7 +214,7 @@ __device__ __forceinline__ void walk(QState* S, const float* __restrict__ bnd, i
       if (j == ls) {
         const float4 v = sv[j - c0];
 #pragma unroll
-        for (int k = 0; k < kQPL; ++k) {
+        for (int k = 0; k < QPL; ++k) {
           F[k] = rel(S[k], v);
           A[k] = F[k];
         }
@@ -223,19 +225,19 @@ __device__ __forceinline__ void walk(QState* S, const float* __restrict__ bnd, i
         const float4 v0 = sv[j - c0];
         const float4 v1 = sv[j + 1 - c0];
 #pragma unroll
-        for (int k = 0; k < kQPL; ++k) B[k] = rel(S[k], v0);
-        step(S, A, B, accA, accB, pv, rs, j - 1, nb, lane);
+        for (int k = 0; k < QPL; ++k) B[k] = rel(S[k], v0);
+        step<QPL>(S, A, B, accA, accB, pv, rs, j - 1, nb, lane);
 #pragma unroll
-        for (int k = 0; k < kQPL; ++k) A[k] = rel(S[k], v1);
-        step(S, B, A, accB, accA, pv, rs, j, nb, lane);
+        for (int k = 0; k < QPL; ++k) A[k] = rel(S[k], v1);
+        step<QPL>(S, B, A, accB, accA, pv, rs, j, nb, lane);
       }
       if (j < j1) {
         const float4 v0 = sv[j - c0];
 #pragma unroll
-        for (int k = 0; k < kQPL; ++k) B[k] = rel(S[k], v0);
-        step(S, A, B, accA, accB, pv, rs, j - 1, nb, lane);
+        for (int k = 0; k < QPL; ++k) B[k] = rel(S[k], v0);
+        step<QPL>(S, A, B, accA, accB, pv, rs, j - 1, nb, lane);
 #pragma unroll
-        for (int k = 0; k < kQPL; ++k) A[k] = B[k];
+        for (int k = 0; k < QPL; ++k) A[k] = B[k];
         accA[0] = accB[0]; accA[1] = accB[1]; accA[2] = accB[2];
         ++j;
       }
@@ -243,7 +245,7 @@ __device__ __forceinline__ void walk(QState* S, const float* __restrict__ bnd, i
       // closing edge last -> first: completes the last vertex; the first
       // vertex's share goes to the per-loop row
       float accF[3];
-      step(S, A, F, accA, accF, pv, rs, le - 1, nb, lane);
+      step<QPL>(S, A, F, accA, accF, pv, rs, le - 1, nb, lane);
       if (pl) put3(pl + 3 * (int64_t)l, accF, lane);
       zero3(accA);
     }
@@ -267,9 +269,10 @@ __device__ __forceinline__ double ordered_sum(const T* __restrict__ x, int64_t s
   return s;
 }
 
+template <int QPL>
 __device__ __forceinline__ void store_gq(const QState* S, const int64_t* qi, const bool* ok, float* gq) {
 #pragma unroll
-  for (int k = 0; k < kQPL; ++k) {
+  for (int k = 0; k < QPL; ++k) {
     if (!ok[k] || !gq) continue;
     const int64_t q = qi[k];
     gq[3 * q + 0] = S[k].gx * kInv4Pi;

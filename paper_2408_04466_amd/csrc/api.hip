@@ -484,7 +484,8 @@ wn_status wn_backward(const float* bnd_xyz, const int64_t* loop_off, int32_t nlo
   if ((st = check_queries(qx, qy, qz, nq))) return st;
   if (nq > 0 && !grad_w) return fail(WN_ERR_INVALID_ARGUMENT, "grad_w is NULL");
   hipStream_t s = as_stream(stream);
-  const int64_t nblocks = wn::adj3d_blocks(nq);
+  const int qpl = wn::adj3d_qpl(nq);
+  const int64_t nblocks = wn::adj3d_blocks(nq, qpl);
   const int64_t rows = wn::adj3d_rows(nblocks);
   float* pv = nullptr;
   float* pl = nullptr;
@@ -519,7 +520,7 @@ wn_status wn_backward(const float* bnd_xyz, const int64_t* loop_off, int32_t nlo
       a.gq = grad_q;
       a.partial = pv;
       a.partial_loop = pl;
-      hipError_t e = wn::launch_adj3d(a, L, nblocks, s);
+      hipError_t e = wn::launch_adj3d(a, L, nblocks, qpl, s);
       if (e == hipSuccess && pv) e = wn::launch_reduce_partials(pv, pl, rows, (int32_t)nb, L, tmp, grad_bnd, s);
       if (pv) { hipFreeAsync(pv, s); hipFreeAsync(pl, s); hipFreeAsync(tmp, s); }
       if (e != hipSuccess) return hip_fail(e, "backward");

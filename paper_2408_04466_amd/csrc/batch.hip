@@ -259,9 +259,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     adj::QState S[adj::kQPL];
     int64_t qi[adj::kQPL];
     bool ok[adj::kQPL];
-    adj::load_tile(S, a.qx, a.qy, a.qz, a.gw, item.q0, item.cnt, qi, ok);
-    if (D.nb > 0) adj::walk(S, a.bnd + 3 * D.bnd_off, D.nb, L, sv, reinterpret_cast<float*>(rsw), pv, pl);
-    adj::store_gq(S, qi, ok, a.gq);
+    adj::load_tile<adj::kQPL>(S, a.qx, a.qy, a.qz, a.gw, item.q0, item.cnt, qi, ok);
+    if (D.nb > 0) adj::walk<adj::kQPL>(S, a.bnd + 3 * D.bnd_off, D.nb, L, sv, reinterpret_cast<float*>(rsw), pv, pl);
+    adj::store_gq<adj::kQPL>(S, qi, ok, a.gq);
   }
 }
 

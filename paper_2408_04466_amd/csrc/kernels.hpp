@@ -76,8 +76,9 @@ hipError_t launch_cross3d(const CrossArgs& a, hipStream_t s);
 hipError_t launch_grid3d_fwd(const CrossArgs& c, const BndArgs& a, const LoopTable& L, const float* gx,
                              const float* gy, const float* gz, int64_t ny, int64_t nz, int32_t* chi_out,
                              hipStream_t s);
-hipError_t launch_adj3d(const AdjArgs& a, const LoopTable& L, int64_t nblocks, hipStream_t s);
-int64_t adj3d_blocks(int64_t nq);
+int adj3d_qpl(int64_t nq);   // queries per lane the plain adjoint uses for nq queries
+hipError_t launch_adj3d(const AdjArgs& a, const LoopTable& L, int64_t nblocks, int qpl, hipStream_t s);
+int64_t adj3d_blocks(int64_t nq, int qpl);
 int64_t adj3d_rows(int64_t nblocks);
 int64_t reduce_groups(int64_t rows);
 hipError_t backward_2d(int32_t dtype, const void* ctrl, int64_t nseg, const int64_t* loop_off,
