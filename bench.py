@@ -423,6 +423,30 @@ def run_others(torch, W, T, others, d3, args, dev):
                                         "hbm_GBs_outputs": 2048 * 2048 * 8 / (ms2 * 1e-3) / 1e9,
                                         "backward_ms": ms2b,
                                         "backward_hbm_GBs": 2048 * 2048 * 12 / (ms2b * 1e-3) / 1e9}
+    # --- the 2D experiment's shape: 1000 random cubics, each on its own 250^2
+    # grid, float64; one batched launch vs a loop of single-set calls
+    E1 = synth.random_cubics(seed=5, n=1000, res=250, dtype=np.float64)
+    ctrl3 = torch.from_numpy(np.concatenate([C.ctrl for C, _, _ in E1])).to(dev)
+    xe = torch.from_numpy(np.concatenate([xs for _, xs, _ in E1])).to(dev)
+    ye = torch.from_numpy(np.concatenate([ys for _, _, ys in E1])).to(dev)
+    b2 = W.Batch2D([(C.loop_off, C.closed, 250, 250) for C, _, _ in E1], torch.float64)
+    w3 = torch.empty(b2.nout, dtype=torch.float64, device=dev)
+    c3 = torch.empty(b2.nout, dtype=torch.int32, device=dev)
+    ms3 = T.ms(lambda: b2.eval(ctrl3, xe, ye, out=(w3, c3)), reps)
+    ms3w = T.ms(lambda: b2.eval(ctrl3, xe, ye, out=(w3, None)), reps)
+    singles = [(ctrl3[k:k + 1], C.loop_off, C.closed, xe[250 * k:250 * (k + 1)], ye[250 * k:250 * (k + 1)])
+               for k, (C, _, _) in enumerate(E1)]
+
+    def loop_e1():
+        for c, lo, cl, xk, yk in singles:
+            W.eval_2d(c, lo, cl, xk, yk, grid=True)
+    ms3l = T.ms(loop_e1, 2)
+    nq3 = 1000 * 250 * 250
+    res["2d_random_cubics_fp64_1000x250^2"] = {
+        "batched_ms": ms3, "queries_per_s": nq3 / (ms3 * 1e-3),
+        "hbm_GBs_outputs": nq3 * 12 / (ms3 * 1e-3) / 1e9,
+        "batched_w_only_ms": ms3w, "w_only_hbm_GBs": nq3 * 8 / (ms3w * 1e-3) / 1e9,
+        "loop_of_single_calls_ms": ms3l}
     return res
 
 

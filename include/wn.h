@@ -67,6 +67,7 @@ typedef int32_t wn_dtype;
 
 typedef struct wn_bvh wn_bvh;       /* opaque: frame, rotated vertices, BVH */
 typedef struct wn_batch wn_batch;   /* opaque: many surfaces, one launch   */
+typedef struct wn_batch2d wn_batch2d;   /* opaque: many 2D curve sets    */
 
 /* Library version (major*10000 + minor*100 + patch). */
 int32_t wn_version(void);
@@ -235,6 +236,60 @@ wn_status wn_eval_2d(wn_dtype dtype, const void* ctrl, int64_t nseg,
                      const int64_t* loop_off, const uint8_t* loop_closed, int32_t nloops,
                      int32_t kind, const void* x, const void* y, int64_t nx, int64_t ny,
                      void* w_out, int32_t* chi_out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched 2D grid mode: many independent curve sets, each on its own grid,
+ * in one launch (the 2D experiment of Sec. 6 evaluates 1000 random cubics,
+ * each on a 250 x 250 grid over its bounding box).
+ *
+ * One set of a batch: nseg segments (taken from the batch's ctrl array in set
+ * order), its loop table as in wn_eval_2d (host arrays, offsets relative to
+ * the set's first segment) and its grid size nx by ny.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int64_t nseg;
+  const int64_t* loop_off;
+  const uint8_t* loop_closed;
+  int32_t nloops;
+  int64_t nx, ny;
+} wn_curveset_2d;
+
+/* ---------------------------------------------------------------------------
+ * wn_batch2d_create -- copy the set descriptors and loop tables to the
+ * device and reserve room for the monotone pieces of every segment
+ * (192 (f32) or 384 (f64) bytes per segment).  `sets` is read during the
+ * call only.  A loop table of any length is accepted (no WN_MAX_LOOPS
+ * limit).  Sets of at most 21 segments run one wavefront per (row, tile of
+ * at most 512 columns), larger sets one workgroup per (row, tile of at most
+ * 4096 columns).  Synchronises `stream`.  Errors: INVALID_ARGUMENT (naming
+ * the set), UNSUPPORTED (a grid side over 2^31 - 1, or more than 2^24
+ * workgroup tiles or 2^26 wavefront tiles in one batch), OUT_OF_MEMORY,
+ * HIP.
+ * ------------------------------------------------------------------------- */
+wn_status wn_batch2d_create(wn_dtype dtype, const wn_curveset_2d* sets, int32_t nsets,
+                            void* stream, wn_batch2d** out);
+
+/* Release a 2D batch (the caller synchronises first). */
+wn_status wn_batch2d_free(wn_batch2d* batch);
+
+/* ---------------------------------------------------------------------------
+ * wn_eval_2d_batched -- wn_eval_2d in grid mode (kind 1) for every set of
+ * the batch: one launch splits every segment, then one launch per kernel
+ * kind runs the (set, row, column tile) items; every output equals the
+ * single-set wn_eval_2d grid call bit for bit.
+ *  ctrl    device [sum nseg][4][2] of the batch's dtype, the sets' segments
+ *          concatenated (may change between calls; the pieces are rebuilt).
+ *  x, y    device [sum nx], [sum ny]: each set's axes concatenated in set
+ *          order, each x axis ascending.
+ *  w_out   device [sum nx*ny] out: each set's [ny][nx] grid, row-major,
+ *          concatenated in set order; chi_out the same in int32, or NULL.
+ * A set without segments gets w = 0, chi = 0.  No allocation, no host
+ * copies: the call only enqueues the two kernels on `stream`; calls that
+ * overlap on one batch race on its piece buffer.  Errors: INVALID_ARGUMENT,
+ * HIP.
+ * ------------------------------------------------------------------------- */
+wn_status wn_eval_2d_batched(const wn_batch2d* batch, const void* ctrl, const void* x,
+                             const void* y, void* w_out, int32_t* chi_out, void* stream);
 
 /* ---------------------------------------------------------------------------
  * wn_backward_2d -- adjoint of wn_eval_2d for a loss L with dL/dw = grad_w.

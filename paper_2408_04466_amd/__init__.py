@@ -7,6 +7,7 @@ All computation runs in the library's HIP kernels.
 from .api import (  # noqa: F401
     BVH,
     Batch,
+    Batch2D,
     WindingNumber2D,
     WindingNumber3D,
     backward_2d,
@@ -14,6 +15,7 @@ from .api import (  # noqa: F401
     boundary_loops,
     crossings_3d,
     eval_2d,
+    eval_2d_batched,
     eval_3d,
     eval_3d_boundary,
     eval_3d_grid,

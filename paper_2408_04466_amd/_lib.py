@@ -46,6 +46,9 @@ SIGNATURES = {
     "wn_backward": (I32, [P, PI64, I32, P, P, P, I64, P, P, P, P]),
     "wn_eval_2d": (I32, [I32, P, I64, PI64, P, I32, I32, P, P, I64, I64, P, P, P]),
     "wn_backward_2d": (I32, [I32, P, I64, PI64, P, I32, I32, P, P, I64, I64, P, P, P, P]),
+    "wn_batch2d_create": (I32, [I32, P, I32, P, C.POINTER(P)]),
+    "wn_batch2d_free": (I32, [P]),
+    "wn_eval_2d_batched": (I32, [P, P, P, P, P, P, P]),
     "wn_batch_create": (I32, [P, I32, PD, I32, P, C.POINTER(P)]),
     "wn_batch_free": (I32, [P]),
     "wn_eval_batched": (I32, [P, P, P, P, P, P, P]),
@@ -58,6 +61,12 @@ class Surface(C.Structure):
     """Mirror of ``wn_surface`` in include/wn.h."""
     _fields_ = [("V", P), ("nv", I64), ("F", P), ("nf", I64), ("bnd_xyz", P),
                 ("loop_off", PI64), ("nloops", I32), ("nq", I64)]
+
+
+class CurveSet2D(C.Structure):
+    """Mirror of ``wn_curveset_2d`` in include/wn.h."""
+    _fields_ = [("nseg", I64), ("loop_off", PI64), ("loop_closed", P), ("nloops", I32),
+                ("nx", I64), ("ny", I64)]
 
 
 def lib():

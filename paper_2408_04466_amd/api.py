@@ -7,10 +7,11 @@ import ctypes as C
 import numpy as np
 import torch
 
-from ._lib import check, lib, WN_MAX_LOOPS
+from ._lib import CurveSet2D, check, lib, WN_MAX_LOOPS
 
-__all__ = ["boundary_loops", "BVH", "eval_3d", "eval_3d_boundary", "crossings_3d",
-           "backward", "WindingNumber3D", "winding_number", "eval_2d", "Batch"]
+__all__ = ["boundary_loops", "BVH", "eval_3d", "eval_3d_boundary", "eval_3d_grid", "crossings_3d",
+           "backward", "WindingNumber3D", "winding_number", "eval_2d", "eval_2d_batched", "Batch2D", "backward_2d",
+           "WindingNumber2D", "winding_number_2d", "Batch"]
 
 
 def _stream(stream=None):
@@ -249,6 +250,93 @@ def eval_2d(ctrl: torch.Tensor, loop_off, loop_closed, x: torch.Tensor, y: torch
                            _dev(w, dt, "w"), _dev(chi, torch.int32, "chi") if chi is not None else None,
                            _stream(stream)), "wn_eval_2d")
     return w, chi
+
+
+class Batch2D:
+    """Many 2D curve sets, each evaluated on its own grid in one launch.
+
+    ``sets`` is a sequence of ``(loop_off, loop_closed, nx, ny)`` (loop
+    offsets relative to the set's first segment).  The batch holds the set
+    descriptors and loop tables on the device; ``eval`` takes the segments of
+    every set concatenated (``ctrl`` [sum nseg, 4, 2]) and the axes
+    concatenated (``x`` [sum nx], ``y`` [sum ny]).  Every set's output equals
+    eval_2d(..., grid=True) on that set alone, bit for bit."""
+
+    def __init__(self, sets, dtype=torch.float32, stream=None):
+        if dtype == torch.float64:
+            self.dtype, self._code = torch.float64, 1
+        elif dtype == torch.float32:
+            self.dtype, self._code = torch.float32, 0
+        else:
+            raise TypeError("dtype must be float32 or float64")
+        self._h = None
+        n = len(sets)
+        desc = (CurveSet2D * max(n, 1))()
+        keep = []
+        self.shapes = []
+        self.nseg = self.nx = self.ny = 0
+        for k, (loop_off, loop_closed, nx, ny) in enumerate(sets):
+            lo = np.ascontiguousarray(np.asarray(loop_off, dtype=np.int64))
+            cl = np.ascontiguousarray(np.asarray(loop_closed, np.uint8))
+            nl = max(lo.size - 1, 0)
+            if cl.size != nl:
+                raise ValueError(f"set {k}: loop_closed must have one entry per loop")
+            nseg = int(lo[-1]) if lo.size else 0
+            keep += [lo, cl]
+            d = desc[k]
+            d.nseg, d.nloops, d.nx, d.ny = nseg, nl, int(nx), int(ny)
+            d.loop_off = _ptr64(lo)
+            d.loop_closed = cl.ctypes.data_as(C.c_void_p) if cl.size else None
+            self.nseg += nseg
+            self.nx += int(nx)
+            self.ny += int(ny)
+            self.shapes.append((int(ny), int(nx)))
+        self.nout = sum(a * b for a, b in self.shapes)
+        h = C.c_void_p()
+        check(lib().wn_batch2d_create(self._code, desc if n else None, n, _stream(stream), C.byref(h)),
+              "wn_batch2d_create")
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().wn_batch2d_free(self._h)
+            self._h = None
+
+    def eval(self, ctrl: torch.Tensor, x: torch.Tensor, y: torch.Tensor, want_chi: bool = True,
+             out=None, stream=None):
+        """(w, chi) as flat [sum nx*ny] tensors (each set's [ny, nx] grid in set
+        order; chi None if not wanted).  ``out`` may pass preallocated
+        (w, chi) tensors.  ``split`` turns them into per-set views."""
+        dt = self.dtype
+        pc = _dev(ctrl, dt, "ctrl", (self.nseg, 4, 2))
+        px = _dev(x, dt, "x", (self.nx,))
+        py = _dev(y, dt, "y", (self.ny,))
+        if out is not None:
+            w, chi = out
+        else:
+            w = torch.empty(self.nout, dtype=dt, device=x.device)
+            chi = torch.empty(self.nout, dtype=torch.int32, device=x.device) if want_chi else None
+        check(lib().wn_eval_2d_batched(self._h, pc, px, py, _dev(w, dt, "w", (self.nout,)),
+                                       _dev(chi, torch.int32, "chi", (self.nout,)) if chi is not None else None,
+                                       _stream(stream)), "wn_eval_2d_batched")
+        return w, chi
+
+    def split(self, flat: torch.Tensor):
+        """Per-set [ny, nx] views of a flat output."""
+        views, o = [], 0
+        for ny, nx in self.shapes:
+            views.append(flat[o:o + ny * nx].view(ny, nx))
+            o += ny * nx
+        return views
+
+
+def eval_2d_batched(ctrl: torch.Tensor, sets, x: torch.Tensor, y: torch.Tensor, want_chi: bool = True,
+                    stream=None):
+    """One-off Batch2D evaluation: lists of per-set [ny, nx] w (and chi)
+    views; see Batch2D for the layout of ``ctrl``, ``sets``, ``x``, ``y``."""
+    b = Batch2D(sets, ctrl.dtype, stream)
+    w, chi = b.eval(ctrl, x, y, want_chi, stream=stream)
+    return b.split(w), (b.split(chi) if chi is not None else None)
 
 
 def backward_2d(ctrl: torch.Tensor, loop_off, loop_closed, x: torch.Tensor, y: torch.Tensor,

@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/wn.h: argument validation,
 // handles, the frame of the ray direction, boundary extraction, and the
 // launch sequence of each entry point.
+#include <new>
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
@@ -599,6 +600,78 @@ wn_status wn_eval_2d(wn_dtype dtype, const void* ctrl, int64_t nseg, const int64
   WN_HIP(wn::eval_2d(dtype, ctrl, nseg, nloops ? loop_off : lo_local, nloops ? loop_closed : cl_local, nloops,
                      kind, x, y, nx, ny, w_out, chi_out, as_stream(stream)),
          "wn_eval_2d");
+  return WN_OK;
+}
+
+struct wn_batch2d {
+  wn::Batch2D b;
+};
+
+wn_status wn_batch2d_create(wn_dtype dtype, const wn_curveset_2d* sets, int32_t nsets, void* stream,
+                            wn_batch2d** out) {
+  g_err.clear();
+  if (!out) return fail(WN_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if (dtype != WN_F32 && dtype != WN_F64) return fail(WN_ERR_UNSUPPORTED, "dtype must be WN_F32 or WN_F64");
+  if (nsets < 0) return fail(WN_ERR_INVALID_ARGUMENT, "nsets must be >= 0");
+  if (nsets > 0 && !sets) return fail(WN_ERR_INVALID_ARGUMENT, "sets is NULL");
+  int64_t seg = 0, items_g = 0, items_w = 0, loops = 0;
+  for (int32_t k = 0; k < nsets; ++k) {
+    const wn_curveset_2d& c = sets[k];
+    if (c.nseg < 0 || c.nx < 0 || c.ny < 0 || c.nloops < 0)
+      return fail(WN_ERR_INVALID_ARGUMENT, "set %d: negative count", k);
+    if (c.nx > INT32_MAX || c.ny > INT32_MAX) return fail(WN_ERR_UNSUPPORTED, "set %d: grid side over 2^31 - 1", k);
+    if (c.nloops > 0 && (!c.loop_off || !c.loop_closed))
+      return fail(WN_ERR_INVALID_ARGUMENT, "set %d: loop table is NULL", k);
+    if (c.nloops > 0) {
+      if (c.loop_off[0] != 0) return fail(WN_ERR_INVALID_ARGUMENT, "set %d: loop_off[0] must be 0", k);
+      for (int32_t l = 0; l < c.nloops; ++l)
+        if (c.loop_off[l + 1] <= c.loop_off[l])
+          return fail(WN_ERR_INVALID_ARGUMENT, "set %d: loop %d is empty or reversed", k, l);
+      if (c.loop_off[c.nloops] != c.nseg)
+        return fail(WN_ERR_INVALID_ARGUMENT, "set %d: loop_off[nloops] must equal nseg", k);
+    } else if (c.nseg > 0) {
+      return fail(WN_ERR_INVALID_ARGUMENT, "set %d: segments without loops", k);
+    }
+    if (c.nx > 0 && c.ny > INT64_MAX / c.nx) return fail(WN_ERR_INVALID_ARGUMENT, "set %d: grid too large", k);
+    seg += c.nseg;
+    loops += c.nloops + 1;
+    if (seg > (INT32_MAX - 3) / 3 || loops > INT32_MAX / 2)
+      return fail(WN_ERR_UNSUPPORTED, "too many segments or loops");
+    if (3 * c.nseg <= wn::kRowPieces2D)
+      items_w += (c.nx + wn::kRowColTile2D - 1) / wn::kRowColTile2D * c.ny;
+    else
+      items_g += (c.nx + wn::kGridColTile2D - 1) / wn::kGridColTile2D * c.ny;
+    if (items_g > wn::kMaxItemsG2D || items_w > wn::kMaxItemsW2D)
+      return fail(WN_ERR_UNSUPPORTED, "batch too large for one launch (split it)");
+  }
+  wn_batch2d* h = new (std::nothrow) wn_batch2d();
+  if (!h) return fail(WN_ERR_OUT_OF_MEMORY, "host allocation");
+  const hipError_t e = wn::batch2d_create(dtype, sets, nsets, as_stream(stream), &h->b);
+  if (e != hipSuccess) {
+    delete h;
+    return hip_fail(e, "wn_batch2d_create");
+  }
+  *out = h;
+  return WN_OK;
+}
+
+wn_status wn_batch2d_free(wn_batch2d* batch) {
+  g_err.clear();
+  delete batch;
+  return WN_OK;
+}
+
+wn_status wn_eval_2d_batched(const wn_batch2d* batch, const void* ctrl, const void* x, const void* y, void* w_out,
+                             int32_t* chi_out, void* stream) {
+  g_err.clear();
+  if (!batch) return fail(WN_ERR_INVALID_ARGUMENT, "batch is NULL");
+  const wn::Batch2D& b = batch->b;
+  if (b.nseg > 0 && !ctrl) return fail(WN_ERR_INVALID_ARGUMENT, "ctrl is NULL");
+  if (b.nout == 0) return WN_OK;
+  if (!x || !y) return fail(WN_ERR_INVALID_ARGUMENT, "query coordinates are NULL");
+  if (!w_out) return fail(WN_ERR_INVALID_ARGUMENT, "w_out is NULL");
+  WN_HIP(wn::eval_2d_batched(b, ctrl, x, y, w_out, chi_out, as_stream(stream)), "wn_eval_2d_batched");
   return WN_OK;
 }
 

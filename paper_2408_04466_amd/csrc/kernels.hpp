@@ -84,6 +84,38 @@ int64_t reduce_groups(int64_t rows);
 hipError_t backward_2d(int32_t dtype, const void* ctrl, int64_t nseg, const int64_t* loop_off,
                        const uint8_t* closed, int32_t nloops, int32_t kind, const void* x, const void* y,
                        int64_t nx, int64_t ny, const void* gw, void* gq, void* gc, hipStream_t s);
+// Most columns one workgroup of the 2D grid mode handles (wider rows are split
+// into even tiles).
+constexpr int kGridColTile2D = 4096;
+// Batched 2D: sets with at most kRowPieces2D monotone pieces (3 per segment)
+// run one wavefront per row tile of at most kRowColTile2D columns.
+constexpr int kRowPieces2D = 64;
+constexpr int kRowColTile2D = 512;
+constexpr int kRowsPerWave2D = 8;   // rows per wavefront item (fewer if pieces x rows > 64)
+// Most work items of one 2D batch launch (a launch holds fewer than 2^32
+// work-items): 2^24 workgroup items, 2^26 wavefront items.
+constexpr int64_t kMaxItemsG2D = (int64_t)1 << 24;
+constexpr int64_t kMaxItemsW2D = (int64_t)1 << 26;
+// A 2D batch: the set descriptors and loop tables on the device, and room
+// for the monotone pieces of every segment.
+struct Batch2D {
+  int32_t dtype = 0;
+  int32_t nsets_g = 0, nsets_w = 0;    // sets on the workgroup / wavefront kernel
+  int64_t nseg = 0, nx = 0, ny = 0, nout = 0;
+  int64_t items_g = 0, items_w = 0;    // (row, column tile) items of each kernel
+  size_t lds = 0;
+  unsigned char* ws = nullptr;   // the one allocation below
+  unsigned char* desc_g = nullptr;
+  unsigned char* desc_w = nullptr;
+  unsigned char* loop_off = nullptr;
+  unsigned char* loop_closed = nullptr;
+  unsigned char* blk_set = nullptr;
+  unsigned char* pieces = nullptr;
+  ~Batch2D();
+};
+hipError_t batch2d_create(int32_t dtype, const wn_curveset_2d* sets, int32_t nsets, hipStream_t s, Batch2D* b);
+hipError_t eval_2d_batched(const Batch2D& b, const void* ctrl, const void* x, const void* y, void* w, int32_t* chi,
+                           hipStream_t s);
 hipError_t eval_2d(int32_t dtype, const void* ctrl, int64_t nseg, const int64_t* loop_off,
                    const uint8_t* closed, int32_t nloops, int32_t kind, const void* x, const void* y,
                    int64_t nx, int64_t ny, void* w, int32_t* chi, hipStream_t s);

@@ -23,7 +23,9 @@
 //    chi for every column of the row.
 // Both modes decide "crossing right of p" as p_x < clamp(x*, xmin, xmax) with
 // the same solver, so they agree bit for bit.
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "geom.hpp"
 #include "kernels.hpp"
@@ -75,11 +77,8 @@ template <> struct Vec2<double> { using type = double2; };
 // Split segment s into three pieces (empty pieces have t0 == t1, y0 == y1);
 // yr gets the end ordinates of every piece for the straddle tests.
 template <class T>
-__global__ void k_pieces(const T* __restrict__ ctrl, int32_t nseg, Piece<T>* __restrict__ out,
-                         typename Vec2<T>::type* __restrict__ yr) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nseg) return;
-  const T* P = ctrl + 8 * (int64_t)s;
+__device__ void split_segment(const T* __restrict__ P, Piece<T>* __restrict__ out,
+                              typename Vec2<T>::type* __restrict__ yr) {
   T cx[4], cy[4];
   power_basis(P[0], P[2], P[4], P[6], cx);
   power_basis(P[1], P[3], P[5], P[7], cy);
@@ -120,9 +119,17 @@ __global__ void k_pieces(const T* __restrict__ ctrl, int32_t nseg, Piece<T>* __r
     }
     pc.xmin = xmin;
     pc.xmax = xmax;
-    out[3 * (int64_t)s + k] = pc;
-    yr[3 * (int64_t)s + k] = {pc.y0, pc.y1};
+    out[k] = pc;
+    yr[k] = {pc.y0, pc.y1};
   }
+}
+
+template <class T>
+__global__ void k_pieces(const T* __restrict__ ctrl, int32_t nseg, Piece<T>* __restrict__ out,
+                         typename Vec2<T>::type* __restrict__ yr) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg) return;
+  split_segment(ctrl + 8 * (int64_t)s, out + 3 * (int64_t)s, yr + 3 * (int64_t)s);
 }
 
 // x(t*) for the t* in [t0, t1] with y(t*) = yq on a monotone piece whose end
@@ -191,9 +198,23 @@ __device__ __forceinline__ T open_loop_angle(T sx, T sy, T ex, T ey) {
   return th;
 }
 
-// sum over open loops of phi(end - p) - phi(start - p)
+// Loop table in device memory (batched calls): same members as Loops2D.
+struct DevLoops2D {
+  int32_t n;
+  const int32_t* off;
+  const uint8_t* closed;
+};
+
+// w from the crossing count and the end-point angle sum (every kernel
+// finishes with this one expression, so their results agree bit for bit).
 template <class T>
-__device__ T endpoint_term(const T* __restrict__ ctrl, const Loops2D& L, T px, T py) {
+__device__ __forceinline__ T finish_w(int c, T e) {
+  return (T)c + e * (T)0.15915494309189535;
+}
+
+// sum over open loops of phi(end - p) - phi(start - p)
+template <class T, class LoopsT>
+__device__ T endpoint_term(const T* __restrict__ ctrl, const LoopsT& L, T px, T py) {
   T e = (T)0;
   for (int l = 0; l < L.n; ++l) {
     if (L.closed[l] || L.off[l + 1] <= L.off[l]) continue;
@@ -236,11 +257,11 @@ __global__ __launch_bounds__(kThreads) void k_points(const Piece<T>* __restrict_
     return;
   }
   const T e = endpoint_term(ctrl, L, px, py);
-  w[q] = (T)c + e * (T)0.15915494309189535;
+  w[q] = finish_w(c, e);
   if (chi) chi[q] = c;
 }
 
-constexpr int kColTile = 4096;
+constexpr int kColTile = kGridColTile2D;
 constexpr int kSolveChunk = 1024;   // pieces examined per pass (LDS list of those needing a solve)
 
 // One workgroup per (row, column tile).  Histogram slot c (0..ncol) counts the
@@ -250,24 +271,11 @@ constexpr int kSolveChunk = 1024;   // pieces examined per pass (LDS list of tho
 // the row or lie beside the whole tile and lists the others in LDS, so that
 // the Newton solves run on consecutive lanes without idle lanes in between.
 // All counts are integer additions, so their order does not matter.
-template <class T>
-__global__ __launch_bounds__(kThreads) void k_grid(const Piece<T>* __restrict__ pcs,
-                                                   const typename Vec2<T>::type* __restrict__ yr, int32_t npc,
-                                                   const T* __restrict__ ctrl, Loops2D L,
-                                                   const T* __restrict__ x, int64_t nx,
-                                                   const T* __restrict__ y, int64_t ny,
-                                                   T* __restrict__ w, int32_t* __restrict__ chi, int tile) {
-  // dynamic LDS sized to the tile: sx [tile] T, hist [tile + 1] int
-  extern __shared__ __align__(16) unsigned char dyn[];
-  T* sx = reinterpret_cast<T*>(dyn);
-  int* hist = reinterpret_cast<int*>(sx + tile);
-  __shared__ int sscan[kThreads];
-  __shared__ int list[kSolveChunk];
-  __shared__ int nlist;
-  const int64_t row = blockIdx.y;
-  const int64_t i0 = (int64_t)blockIdx.x * tile;
-  const int ncol = (int)min((int64_t)tile, nx - i0);
-  const T yq = y[row];
+template <class T, class LoopsT>
+__device__ void grid_tile(const Piece<T>* __restrict__ pcs, const typename Vec2<T>::type* __restrict__ yr,
+                          int32_t npc, const T* __restrict__ ctrl, const LoopsT& L, const T* __restrict__ x,
+                          int64_t nx, T yq, int64_t row, int64_t i0, int ncol, T* __restrict__ w,
+                          int32_t* __restrict__ chi, T* sx, int* hist, int* sscan, int* list, int* nlist) {
   for (int i = threadIdx.x; i < ncol; i += kThreads) sx[i] = x[i0 + i];
   for (int i = threadIdx.x; i <= ncol; i += kThreads) hist[i] = 0;
   __syncthreads();
@@ -275,7 +283,7 @@ __global__ __launch_bounds__(kThreads) void k_grid(const Piece<T>* __restrict__ 
   int base = 0;   // crossings right of every column of the tile
   for (int c0 = 0; c0 < npc; c0 += kSolveChunk) {
     const int c1 = min(c0 + kSolveChunk, npc);
-    if (threadIdx.x == 0) nlist = 0;
+    if (threadIdx.x == 0) *nlist = 0;
     __syncthreads();
     for (int j = c0 + threadIdx.x; j < c1; j += kThreads) {
       const typename Vec2<T>::type e = yr[j];
@@ -283,12 +291,12 @@ __global__ __launch_bounds__(kThreads) void k_grid(const Piece<T>* __restrict__ 
       if (s0 == s1) continue;
       const int sg = s1 ? 1 : -1;
       const T pxmin = pcs[j].xmin, pxmax = pcs[j].xmax;
-      if (xhi < pxmin) base += sg;                     // right of every column
-      else if (xlo < pxmax) list[atomicAdd(&nlist, 1)] = j;   // needs the solve
+      if (xhi < pxmin) base += sg;                          // right of every column
+      else if (xlo < pxmax) list[atomicAdd(nlist, 1)] = j;  // needs the solve
       // else: right of no column
     }
     __syncthreads();
-    const int n = nlist;
+    const int n = *nlist;
     for (int k = threadIdx.x; k < n; k += kThreads) {
       const int j = list[k];
       const Piece<T>& pc = pcs[j];
@@ -351,8 +359,220 @@ __global__ __launch_bounds__(kThreads) void k_grid(const Piece<T>* __restrict__ 
     }
     const int c = hist[i + 1];
     const T e = endpoint_term(ctrl, L, px, yq);
-    w[o] = (T)c + e * (T)0.15915494309189535;
+    w[o] = finish_w(c, e);
     if (chi) chi[o] = c;
+  }
+}
+
+// One workgroup per (row, column tile).  Histogram slot c (0..ncol) counts the
+// crossings with exactly c tile columns left of them; columns at or beyond
+// the tile end get every crossing right of the whole tile through `base`.
+// Pieces are examined in chunks: a first pass settles the pieces that miss
+// the row or lie beside the whole tile and lists the others in LDS, so that
+// the Newton solves run on consecutive lanes without idle lanes in between.
+// All counts are integer additions, so their order does not matter.
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_grid(const Piece<T>* __restrict__ pcs,
+                                                   const typename Vec2<T>::type* __restrict__ yr, int32_t npc,
+                                                   const T* __restrict__ ctrl, Loops2D L,
+                                                   const T* __restrict__ x, int64_t nx,
+                                                   const T* __restrict__ y, int64_t ny,
+                                                   T* __restrict__ w, int32_t* __restrict__ chi, int tile) {
+  // dynamic LDS sized to the tile: sx [tile] T, hist [tile + 1] int
+  extern __shared__ __align__(16) unsigned char dyn[];
+  T* sx = reinterpret_cast<T*>(dyn);
+  int* hist = reinterpret_cast<int*>(sx + tile);
+  __shared__ int sscan[kThreads];
+  __shared__ int list[kSolveChunk];
+  __shared__ int nlist;
+  const int64_t row = blockIdx.y;
+  const int64_t i0 = (int64_t)blockIdx.x * tile;
+  const int ncol = (int)min((int64_t)tile, nx - i0);
+  grid_tile(pcs, yr, npc, ctrl, L, x, nx, y[row], row, i0, ncol, w, chi, sx, hist, sscan, list, &nlist);
+}
+
+// ---------------------------------------------------------------------------
+// Batched grid mode: many curve sets, each with its own grid, in one launch.
+// ---------------------------------------------------------------------------
+
+// One curve set of a batch; offsets index the batch's concatenated arrays.
+struct Set2D {
+  int64_t item_off;    // first (row, tile) workgroup of the set
+  int64_t x_off, y_off, out_off;
+  int32_t seg_off;     // first segment (pieces at 3 seg_off)
+  int32_t nseg;
+  int32_t off_base;    // first entry of the set's loop offsets in the batch table
+  int32_t closed_base; // first entry of the set's closed flags
+  int32_t nloops;
+  int32_t nx, ny;
+  int32_t ntiles, tile;
+  int32_t rows;        // rows per item (wavefront kernel; 1 for the workgroup kernel)
+};
+
+// Set containing index v of a per-set prefix (binary search).
+template <class F>
+__device__ __forceinline__ int find_set(const Set2D* __restrict__ sets, int nsets, int64_t v, F start) {
+  int lo = 0, hi = nsets - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start(sets[mid]) <= v) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_grid_batched(const Set2D* __restrict__ sets, int32_t nsets,
+                                                           const Piece<T>* __restrict__ pcs,
+                                                           const typename Vec2<T>::type* __restrict__ yr,
+                                                           const int32_t* __restrict__ loop_off,
+                                                           const uint8_t* __restrict__ loop_closed,
+                                                           const T* __restrict__ ctrl, const T* __restrict__ x,
+                                                           const T* __restrict__ y, T* __restrict__ w,
+                                                           int32_t* __restrict__ chi) {
+  extern __shared__ __align__(16) unsigned char dyn[];
+  __shared__ int sscan[kThreads];
+  __shared__ int list[kSolveChunk];
+  __shared__ int nlist;
+  const int64_t item = blockIdx.x;
+  const int k = find_set(sets, nsets, item, [](const Set2D& d) { return d.item_off; });
+  const Set2D d = sets[k];
+  const int64_t local = item - d.item_off;
+  const int64_t row = local / d.ntiles;
+  const int64_t i0 = (local % d.ntiles) * d.tile;
+  const int ncol = (int)min((int64_t)d.tile, (int64_t)d.nx - i0);
+  T* sx = reinterpret_cast<T*>(dyn);
+  int* hist = reinterpret_cast<int*>(sx + d.tile);
+  const DevLoops2D L{d.nloops, loop_off + d.off_base, loop_closed + d.closed_base};
+  grid_tile(pcs + 3 * (int64_t)d.seg_off, yr + 3 * (int64_t)d.seg_off, 3 * d.nseg, ctrl + 8 * (int64_t)d.seg_off,
+            L, x + d.x_off, (int64_t)d.nx, y[d.y_off + row], row, i0, ncol, w + d.out_off,
+            chi ? chi + d.out_off : nullptr, sx, hist, sscan, list, &nlist);
+}
+
+// Sets with at most 64 monotone pieces (21 segments): one wavefront per
+// (set, group of rows, column tile), four per workgroup.  Lane r*npc + j
+// takes piece j on row r of the group (rows = 64 / npc, at most
+// kRowsPerWave): a piece that straddles the row gets its crossing abscissa
+// xe, clamped to the piece's x range (pieces beside the whole tile take a
+// bound instead of a solve), and each row's crossings are compacted into the
+// wavefront's LDS list.  chi of a column is the signed count of its row's
+// entries with x_i < xe, which is what k_grid's histogram and suffix scan
+// count: a crossing lands in slot a = #{columns with x < xe} and adds to
+// every column i < a.  Columns left of a piece's x range always count it and
+// columns right of it never do, with or without the solve, so the two
+// kernels agree bit for bit.  The open loops' end points (the same for every
+// query of the set) are staged in LDS once, in loop order, and summed in the
+// order and arithmetic of endpoint_term.
+constexpr int kRowWaves = kThreads / 64;
+constexpr int kRowPieces = kRowPieces2D;
+constexpr int kRowLoops = kRowPieces2D / 3;   // a loop has at least one segment
+constexpr int kRowColTile = kRowColTile2D;
+constexpr int kRowsPerWave = kRowsPerWave2D;
+
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <class T>
+__global__ __launch_bounds__(kThreads) void k_rows_batched(const Set2D* __restrict__ sets, int32_t nsets,
+                                                           const int32_t* __restrict__ blk_set, int64_t nitems,
+                                                           const Piece<T>* __restrict__ pcs,
+                                                           const typename Vec2<T>::type* __restrict__ yr,
+                                                           const int32_t* __restrict__ loop_off,
+                                                           const uint8_t* __restrict__ loop_closed,
+                                                           const T* __restrict__ ctrl, const T* __restrict__ x,
+                                                           const T* __restrict__ y, T* __restrict__ w,
+                                                           int32_t* __restrict__ chi) {
+  using V4 = T[4];
+  __shared__ T sxe[kRowWaves][kRowPieces];
+  __shared__ int ssg[kRowWaves][kRowPieces];
+  __shared__ V4 sep[kRowWaves][kRowLoops];
+  const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int64_t item = (int64_t)blockIdx.x * kRowWaves + wv;
+  if (item >= nitems) return;   // whole wavefronts leave; no workgroup barrier below
+  // the set of the block's first item, then forward (sets may hold no items)
+  int k = blk_set[blockIdx.x];
+  while (k + 1 < nsets && sets[k + 1].item_off <= item) ++k;
+  const Set2D d = sets[k];
+  const int64_t local = item - d.item_off;
+  const int64_t r0 = (local / d.ntiles) * d.rows;
+  const int nr = (int)min((int64_t)d.rows, (int64_t)d.ny - r0);
+  const int64_t i0 = (local % d.ntiles) * d.tile;
+  const int ncol = (int)min((int64_t)d.tile, (int64_t)d.nx - i0);
+  const T* xs = x + d.x_off + i0;
+  const T* ys = y + d.y_off + r0;
+  const T xlo = xs[0], xhi = xs[ncol - 1];
+  const int npc = 3 * d.nseg;   // <= kRowPieces; rows * npc <= 64
+  // crossings: lane r * npc + j <-> (row r, piece j)
+  const int r = npc ? lane / npc : 0;
+  const int j = lane - r * npc;
+  int sg = 0;
+  T xe = (T)0;
+  if (npc && r < nr) {
+    const T yq = ys[r];
+    const int64_t pj = 3 * (int64_t)d.seg_off + j;
+    const typename Vec2<T>::type e = yr[pj];
+    const bool s0 = e.x >= yq, s1 = e.y >= yq;
+    if (s0 != s1) {
+      sg = s1 ? 1 : -1;
+      const Piece<T>& pc = pcs[pj];
+      if (xhi < pc.xmin) xe = pc.xmin;          // right of every column
+      else if (xlo >= pc.xmax) xe = pc.xmax;    // right of no column
+      else xe = fmin(fmax(solve_x(pc, yq), pc.xmin), pc.xmax);
+    }
+  }
+  const uint64_t m = __ballot(sg != 0);
+  const uint64_t rowbits = npc >= 64 ? ~0ull : ((1ull << npc) - 1);
+  if (sg != 0) {
+    const int at = __popcll(m & (rowbits << (r * npc)) & ((1ull << lane) - 1));
+    sxe[wv][r * npc + at] = xe;
+    ssg[wv][r * npc + at] = sg;
+  }
+  // open loops' end points, compacted in loop order
+  bool open = false;
+  T e4[4] = {(T)0, (T)0, (T)0, (T)0};
+  if (lane < d.nloops) {
+    const int o0 = loop_off[d.off_base + lane], o1 = loop_off[d.off_base + lane + 1];
+    open = !loop_closed[d.closed_base + lane] && o1 > o0;
+    if (open) {
+      const T* sp = ctrl + 8 * ((int64_t)d.seg_off + o0);
+      const T* fp = ctrl + 8 * ((int64_t)d.seg_off + o1 - 1);
+      e4[0] = sp[0];
+      e4[1] = sp[1];
+      e4[2] = fp[6];
+      e4[3] = fp[7];
+    }
+  }
+  const uint64_t mo = __ballot(open);
+  const int nopen = __popcll(mo);
+  if (open) {
+    const int at = __popcll(mo & ((1ull << lane) - 1));
+    for (int t = 0; t < 4; ++t) sep[wv][at][t] = e4[t];
+  }
+  wave_fence();
+  T* wr = w + d.out_off + r0 * d.nx + i0;
+  int32_t* cr = chi ? chi + d.out_off + r0 * d.nx + i0 : nullptr;
+  for (int rr = 0; rr < nr; ++rr, wr += d.nx, cr = cr ? cr + d.nx : nullptr) {
+    const T yq = ys[rr];
+    const int n = __popcll(m & (rowbits << (rr * npc)));
+    const T* lx = &sxe[wv][rr * npc];
+    const int* lg = &ssg[wv][rr * npc];
+    for (int i = lane; i < ncol; i += 64) {
+      const T px = xs[i];
+      if (!(isfinite(px) && isfinite(yq))) {
+        wr[i] = (T)NAN;
+        if (cr) cr[i] = WN_CHI_INVALID;
+        continue;
+      }
+      int c = 0;
+      for (int t = 0; t < n; ++t) c += px < lx[t] ? lg[t] : 0;
+      T e = (T)0;
+      for (int t = 0; t < nopen; ++t)
+        e += open_loop_angle(sep[wv][t][0] - px, sep[wv][t][1] - yq, sep[wv][t][2] - px, sep[wv][t][3] - yq);
+      wr[i] = finish_w(c, e);
+      if (cr) cr[i] = c;
+    }
   }
 }
 
@@ -532,6 +752,141 @@ hipError_t run2d(const T* ctrl, int64_t nseg, const Loops2D& L, int32_t kind, co
 }
 
 }  // namespace
+
+Batch2D::~Batch2D() {
+  if (ws) hipFree(ws);
+}
+
+hipError_t batch2d_create(int32_t dtype, const wn_curveset_2d* sets, int32_t nsets, hipStream_t s, Batch2D* b) {
+  // sets with few pieces go to the wavefront-per-row kernel, the others to
+  // the workgroup (histogram) kernel; each kernel numbers its own items
+  std::vector<Set2D> dg, dw;
+  std::vector<int32_t> offs;
+  std::vector<uint8_t> cls;
+  int64_t seg = 0, xo = 0, yo = 0, oo = 0, items_g = 0, items_w = 0;
+  int max_tile = 1;
+  for (int32_t k = 0; k < nsets; ++k) {
+    const wn_curveset_2d& c = sets[k];
+    const bool wave = 3 * c.nseg <= kRowPieces;
+    Set2D e;
+    e.x_off = xo;
+    e.y_off = yo;
+    e.out_off = oo;
+    e.seg_off = (int32_t)seg;
+    e.nseg = (int32_t)c.nseg;
+    e.off_base = (int32_t)offs.size();
+    e.closed_base = (int32_t)cls.size();
+    e.nloops = c.nloops;
+    for (int32_t l = 0; l <= c.nloops; ++l) offs.push_back(c.nloops ? (int32_t)c.loop_off[l] : 0);
+    for (int32_t l = 0; l < c.nloops; ++l) cls.push_back(c.loop_closed[l] ? 1 : 0);
+    e.nx = (int32_t)c.nx;
+    e.ny = (int32_t)c.ny;
+    // column tiles as even as possible (the workgroup kernel uses the
+    // single-set call's tiling)
+    const int64_t cap = wave ? kRowColTile : kColTile;
+    e.ntiles = (int32_t)((c.nx + cap - 1) / cap);
+    e.tile = e.ntiles ? (int32_t)((c.nx + e.ntiles - 1) / e.ntiles) : 1;
+    e.rows = wave ? (int32_t)std::min<int64_t>(kRowsPerWave, kRowPieces / std::max<int64_t>(3 * c.nseg, 1)) : 1;
+    int64_t& items = wave ? items_w : items_g;
+    e.item_off = items;
+    items += (int64_t)e.ntiles * ((c.ny + e.rows - 1) / e.rows);
+    if (!wave) max_tile = std::max(max_tile, (int)e.tile);
+    (wave ? dw : dg).push_back(e);
+    seg += c.nseg;
+    xo += c.nx;
+    yo += c.ny;
+    oo += c.nx * c.ny;
+  }
+  b->dtype = dtype;
+  b->nsets_g = (int32_t)dg.size();
+  b->nsets_w = (int32_t)dw.size();
+  b->nseg = seg;
+  b->nx = xo;
+  b->ny = yo;
+  b->nout = oo;
+  b->items_g = items_g;
+  b->items_w = items_w;
+  const size_t tsz = dtype == WN_F64 ? sizeof(double) : sizeof(float);
+  b->lds = ((size_t)max_tile * tsz + (size_t)(max_tile + 1) * sizeof(int) + 15) & ~(size_t)15;
+  // set of the first item of every wavefront-kernel workgroup
+  std::vector<int32_t> bs((size_t)((items_w + kRowWaves - 1) / kRowWaves));
+  for (size_t k = 0, blk = 0; blk < bs.size(); ++blk) {
+    const int64_t it = (int64_t)blk * kRowWaves;
+    while (k + 1 < dw.size() && dw[k + 1].item_off <= it) ++k;
+    bs[blk] = (int32_t)k;
+  }
+  // one device allocation: descriptors (workgroup sets, then wavefront
+  // sets) | loop offsets | closed flags | block -> set | pieces | y ranges
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t b_dg = up(dg.size() * sizeof(Set2D));
+  const size_t b_dw = up(dw.size() * sizeof(Set2D));
+  const size_t b_off = up(offs.size() * sizeof(int32_t));
+  const size_t b_cls = up(cls.size() + 1);
+  const size_t b_bs = up(bs.size() * sizeof(int32_t));
+  const size_t piece = dtype == WN_F64 ? sizeof(Piece<double>) + sizeof(double2) : sizeof(Piece<float>) + sizeof(float2);
+  const size_t bytes = b_dg + b_dw + b_off + b_cls + b_bs + (size_t)(3 * seg) * piece;
+  hipError_t e = hipMalloc((void**)&b->ws, std::max(bytes, (size_t)256));
+  if (e != hipSuccess) {
+    b->ws = nullptr;
+    return e;
+  }
+  b->desc_g = b->ws;
+  b->desc_w = b->ws + b_dg;
+  b->loop_off = b->ws + b_dg + b_dw;
+  b->loop_closed = b->loop_off + b_off;
+  b->blk_set = b->loop_closed + b_cls;
+  b->pieces = b->blk_set + b_bs;
+  auto put = [&](void* dst, const void* src, size_t n) {
+    if (n && e == hipSuccess) e = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s);
+  };
+  put(b->desc_g, dg.data(), dg.size() * sizeof(Set2D));
+  put(b->desc_w, dw.data(), dw.size() * sizeof(Set2D));
+  put(b->loop_off, offs.data(), offs.size() * sizeof(int32_t));
+  put(b->loop_closed, cls.data(), cls.size());
+  put(b->blk_set, bs.data(), bs.size() * sizeof(int32_t));
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(s);   // the host tables go out of scope
+}
+
+template <class T>
+hipError_t run2d_batched(const Batch2D& b, const T* ctrl, const T* x, const T* y, T* w, int32_t* chi,
+                         hipStream_t s) {
+  using V2 = typename Vec2<T>::type;
+  if (b.items_g + b.items_w == 0) return hipSuccess;
+  const int32_t* doff = reinterpret_cast<const int32_t*>(b.loop_off);
+  const uint8_t* dcl = b.loop_closed;
+  Piece<T>* pcs = reinterpret_cast<Piece<T>*>(b.pieces);
+  V2* yr = reinterpret_cast<V2*>(pcs + 3 * b.nseg);
+  if (b.nseg > 0) {
+    // the sets' segments are contiguous: split them all in one launch
+    hipLaunchKernelGGL(k_pieces<T>, dim3((unsigned)((b.nseg + 127) / 128)), dim3(128), 0, s, ctrl, (int32_t)b.nseg,
+                       pcs, yr);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (b.items_w > 0) {
+    const int64_t blocks = (b.items_w + kRowWaves - 1) / kRowWaves;
+    hipLaunchKernelGGL(k_rows_batched<T>, dim3((unsigned)blocks), dim3(kThreads), 0, s,
+                       reinterpret_cast<const Set2D*>(b.desc_w), b.nsets_w,
+                       reinterpret_cast<const int32_t*>(b.blk_set), b.items_w, pcs, yr, doff, dcl, ctrl, x, y, w,
+                       chi);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (b.items_g > 0) {
+    hipLaunchKernelGGL(k_grid_batched<T>, dim3((unsigned)b.items_g), dim3(kThreads), b.lds, s,
+                       reinterpret_cast<const Set2D*>(b.desc_g), b.nsets_g, pcs, yr, doff, dcl, ctrl, x, y, w, chi);
+    return hipGetLastError();
+  }
+  return hipSuccess;
+}
+
+hipError_t eval_2d_batched(const Batch2D& b, const void* ctrl, const void* x, const void* y, void* w, int32_t* chi,
+                           hipStream_t s) {
+  if (b.dtype == WN_F64)
+    return run2d_batched<double>(b, (const double*)ctrl, (const double*)x, (const double*)y, (double*)w, chi, s);
+  return run2d_batched<float>(b, (const float*)ctrl, (const float*)x, (const float*)y, (float*)w, chi, s);
+}
 
 hipError_t eval_2d(int32_t dtype, const void* ctrl, int64_t nseg, const int64_t* loop_off,
                    const uint8_t* closed, int32_t nloops, int32_t kind, const void* x, const void* y,

@@ -87,6 +87,23 @@ def loops2d(seed: int = 2, n_loops: int = 16, seg_per_loop: int = 64,
     return Curves2D(ctrl.astype(dtype), off, np.array(closed, np.uint8))
 
 
+def random_cubics(seed: int = 5, n: int = 1000, res: int = 250, dtype=np.float64):
+    """The 2D experiment's input shape: ``n`` independent cubic Beziers with
+    control points uniform in the unit square, each an open loop of one
+    segment, each with a ``res`` x ``res`` grid spanning the bounding box of
+    its control points (which contains the curve).  Returns a list of
+    ``(Curves2D, xs, ys)``."""
+    g = rng(seed)
+    out = []
+    for _ in range(n):
+        c = g.uniform(0.0, 1.0, (1, 4, 2)).astype(dtype)
+        lo, hi = c[0].min(0).astype(np.float64), c[0].max(0).astype(np.float64)
+        xs = grid_axis(lo[0], hi[0], res, dtype)
+        ys = grid_axis(lo[1], hi[1], res, dtype)
+        out.append((Curves2D(c, np.array([0, 1], np.int64), np.array([0], np.uint8)), xs, ys))
+    return out
+
+
 def grid_axis(lo: float, hi: float, n: int, dtype=np.float64) -> np.ndarray:
     """``numpy.linspace(lo, hi, n)`` (endpoints included) rounded once."""
     return np.linspace(lo, hi, n).astype(dtype)

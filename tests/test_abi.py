@@ -109,6 +109,31 @@ def test_validation_happens_on_the_host(W):
     assert L.wn_eval_2d(0, fake, 3, off.ctypes.data_as(C.POINTER(C.c_int64)), cl.ctypes.data_as(P), 1, 0,
                         fake, fake, 1, 1, fake, None, None) == 1
     assert "nseg" in _err(W)
+    # 2D batched: the failing set is named; an all-empty batch does nothing
+    from paper_2408_04466_amd._lib import CurveSet2D
+    sets = (CurveSet2D * 3)()
+    offs = [np.array([0, 1], np.int64), np.array([0, 2], np.int64), np.array([0, 1], np.int64)]
+    cls = np.array([0], np.uint8)
+    for k, o in enumerate(offs):
+        sets[k].nseg, sets[k].nloops, sets[k].nx, sets[k].ny = 1, 1, 4, 4
+        sets[k].loop_off = o.ctypes.data_as(C.POINTER(C.c_int64))
+        sets[k].loop_closed = cls.ctypes.data_as(P)
+    h = P()
+    assert L.wn_batch2d_create(1, sets, 3, None, C.byref(h)) == 1 and not h.value
+    assert "set 1" in _err(W) and "nseg" in _err(W)
+    sets[1].nseg = 2
+    sets[2].ny = -1
+    assert L.wn_batch2d_create(1, sets, 3, None, C.byref(h)) == 1
+    assert "set 2" in _err(W)
+    sets[2].ny = 1 << 40
+    assert L.wn_batch2d_create(1, sets, 3, None, C.byref(h)) == 2
+    sets[2].ny = 1 << 30                     # 2^30 wavefront tiles: more than one launch holds
+    assert L.wn_batch2d_create(1, sets, 3, None, C.byref(h)) == 2
+    assert "too large" in _err(W)
+    assert L.wn_batch2d_create(5, sets, 3, None, C.byref(h)) == 2
+    assert L.wn_eval_2d_batched(None, fake, fake, fake, fake, None, None) == 1
+    assert "batch" in _err(W)
+    assert L.wn_batch2d_free(None) == 0
 
 
 def test_missing_library_fails_loudly(tmp_path):
