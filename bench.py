@@ -423,6 +423,26 @@ def run_others(torch, W, T, others, d3, args, dev):
                                         "hbm_GBs_outputs": 2048 * 2048 * 8 / (ms2 * 1e-3) / 1e9,
                                         "backward_ms": ms2b,
                                         "backward_hbm_GBs": 2048 * 2048 * 12 / (ms2b * 1e-3) / 1e9}
+    # --- curved boundary: a Coons surface (~1M triangles) bounded by 4 cubic
+    # Beziers, 2^20 queries; boundary term along the curves vs the 512-edge
+    # polyline through the same boundary vertices
+    MC = synth.coons_surface(6, 1 << 20, 512)
+    dmc = synth.random_direction(106)
+    Vc = torch.from_numpy(MC.V).to(dev)
+    bvhc = W.BVH(Vc, torch.from_numpy(MC.F).to(dev), dmc)
+    idxc, offc = W.boundary_loops(MC.F)
+    bndc = Vc[torch.from_numpy(idxc.astype(np.int64)).to(dev)].contiguous()
+    Pc = synth.box_queries(MC.V, 1 << 20, 7)
+    qc = [torch.from_numpy(np.ascontiguousarray(Pc[:, k])).to(dev) for k in range(3)]
+    ctrlc = torch.from_numpy(np.ascontiguousarray(MC.info["curves"].astype(np.float32))).to(dev)
+    zc = torch.zeros(1 << 20, dtype=torch.int32, device=dev)
+    ms_cb = T.ms(lambda: W.eval_3d_curves(bvhc, ctrlc, *qc, chi_in=zc), reps)
+    ms_cw = T.ms(lambda: W.eval_3d_curves(bvhc, ctrlc, *qc), reps)
+    ms_pb = T.ms(lambda: W.eval_3d_boundary(bvhc, bndc, offc, *qc, zc), reps)
+    res["3d_curved_boundary_coons_2p20"] = {
+        "curves": 4, "curves_boundary_ms": ms_cb, "curves_with_bvh_chi_ms": ms_cw,
+        "polyline_512_boundary_ms": ms_pb, "queries_per_s": (1 << 20) / (ms_cw * 1e-3)}
+    del bvhc
     # --- the 2D experiment's shape: 1000 random cubics, each on its own 250^2
     # grid, float64; one batched launch vs a loop of single-set calls
     E1 = synth.random_cubics(seed=5, n=1000, res=250, dtype=np.float64)

@@ -184,6 +184,33 @@ wn_status wn_eval_3d_boundary(const wn_bvh* bvh, const float* bnd_xyz,
                               void* stream);
 
 /* ---------------------------------------------------------------------------
+ * wn_eval_3d_curves -- w for a surface whose boundary is a set of closed
+ * loops of cubic Bezier curves: w = chi_d + Theta/(2pi), Theta the line
+ * integral along the curves of the form whose integral along a straight edge
+ * is the polyline path's edge term (Sec. 4: region areas from boundary
+ * integrals, Gauss-Bonnet; Bezier boundaries are integrated numerically).
+ *  bvh        frame and direction d; also gives chi_d when chi_in is NULL
+ *             (the BVH of the surface's tessellation).
+ *  ctrl       device [ncurves][4][3] float32 control points, in the
+ *             orientation the surface induces on its boundary.
+ *  qx..nq     queries as in wn_eval_3d.
+ *  chi_in     device [nq] int32 chi_d from the caller (for example from an
+ *             exact ray-surface intersection), or NULL.
+ *  w_out      device [nq] float32 out; chi_out device int32 or NULL.
+ * Quadrature: per curve, dyadic panels integrated by 6-point Gauss-Legendre
+ * once they lie farther than 1.5 control-polygon lengths from the query,
+ * halved otherwise (at most 24 times; the chord's exact edge term then
+ * stands in).  With chi_d from a tessellation whose boundary vertices lie on
+ * the curves, chi_d and Theta jump at slightly different places: w can be
+ * off by one where the ray passes between a boundary chord and its curve.
+ * Errors: INVALID_ARGUMENT, UNSUPPORTED, HIP.
+ * ------------------------------------------------------------------------- */
+wn_status wn_eval_3d_curves(const wn_bvh* bvh, const float* ctrl, int64_t ncurves,
+                            const float* qx, const float* qy, const float* qz, int64_t nq,
+                            const int32_t* chi_in, float* w_out, int32_t* chi_out,
+                            void* stream);
+
+/* ---------------------------------------------------------------------------
  * wn_crossings_3d -- chi_d only (Eq. chi; the ray-casting step of Alg. 1) through the BVH.
  *  chi_out device [nq] int32 out.
  * ------------------------------------------------------------------------- */

@@ -18,6 +18,7 @@ from .api import (  # noqa: F401
     eval_2d_batched,
     eval_3d,
     eval_3d_boundary,
+    eval_3d_curves,
     eval_3d_grid,
     winding_number,
     winding_number_2d,

@@ -9,7 +9,7 @@ import torch
 
 from ._lib import CurveSet2D, check, lib, WN_MAX_LOOPS
 
-__all__ = ["boundary_loops", "BVH", "eval_3d", "eval_3d_boundary", "eval_3d_grid", "crossings_3d",
+__all__ = ["boundary_loops", "BVH", "eval_3d", "eval_3d_boundary", "eval_3d_grid", "eval_3d_curves", "crossings_3d",
            "backward", "WindingNumber3D", "winding_number", "eval_2d", "eval_2d_batched", "Batch2D", "backward_2d",
            "WindingNumber2D", "winding_number_2d", "Batch"]
 
@@ -128,6 +128,23 @@ def eval_3d(bvh: BVH, bnd_xyz: torch.Tensor, loop_off, qx, qy, qz, want_chi: boo
     pc = _dev(chi, torch.int32, "chi_out", (nq,)) if chi is not None else None
     check(lib().wn_eval_3d(bvh.handle, pb, _ptr64(lo), nl, px, py, pz, nq, pw, pc, _stream(stream)),
           "wn_eval_3d")
+    return w, chi
+
+
+def eval_3d_curves(bvh: BVH, ctrl: torch.Tensor, qx, qy, qz, chi_in=None, want_chi: bool = True, stream=None):
+    """w for a surface bounded by loops of cubic Beziers ``ctrl`` [nc, 4, 3]
+    (float32, boundary orientation): chi_d from ``chi_in`` (int32 [nq]) or,
+    if None, from ``bvh`` (the surface's tessellation), plus the boundary
+    integral along the curves in the frame of ``bvh``.  Returns (w, chi)."""
+    nc = ctrl.shape[0]
+    pcurve = _dev(ctrl, torch.float32, "ctrl", (nc, 4, 3))
+    px, py, pz, nq = _queries(qx, qy, qz)
+    pin = _dev(chi_in, torch.int32, "chi_in", (nq,)) if chi_in is not None else None
+    w = torch.empty(nq, dtype=torch.float32, device=qx.device)
+    chi = torch.empty(nq, dtype=torch.int32, device=qx.device) if want_chi else None
+    check(lib().wn_eval_3d_curves(bvh.handle, pcurve, nc, px, py, pz, nq, pin, _dev(w, torch.float32, "w"),
+                                  _dev(chi, torch.int32, "chi") if chi is not None else None, _stream(stream)),
+          "wn_eval_3d_curves")
     return w, chi
 
 

@@ -425,6 +425,24 @@ wn_status wn_eval_3d(const wn_bvh* h, const float* bnd_xyz, const int64_t* loop_
   return WN_OK;
 }
 
+wn_status wn_eval_3d_curves(const wn_bvh* h, const float* ctrl, int64_t ncurves, const float* qx, const float* qy,
+                            const float* qz, int64_t nq, const int32_t* chi_in, float* w_out, int32_t* chi_out,
+                            void* stream) {
+  g_err.clear();
+  if (!h) return fail(WN_ERR_INVALID_ARGUMENT, "bvh is NULL");
+  if (ncurves < 0) return fail(WN_ERR_INVALID_ARGUMENT, "ncurves must be >= 0");
+  if (ncurves > INT32_MAX / 12) return fail(WN_ERR_UNSUPPORTED, "too many curves");
+  if (ncurves > 0 && !ctrl) return fail(WN_ERR_INVALID_ARGUMENT, "ctrl is NULL");
+  wn_status st = check_queries(qx, qy, qz, nq);
+  if (st) return st;
+  if (nq == 0) return WN_OK;
+  if (!w_out) return fail(WN_ERR_INVALID_ARGUMENT, "w_out is NULL");
+  WN_HIP(wn::launch_curves3d(cross_args(h, qx, qy, qz, nq, chi_out), ctrl, ncurves, chi_in, w_out, chi_out,
+                             as_stream(stream)),
+         "wn_eval_3d_curves");
+  return WN_OK;
+}
+
 wn_status wn_eval_3d_grid(const wn_bvh* h, const float* bnd_xyz, const int64_t* loop_off, int32_t nloops,
                           const float* gx, const float* gy, const float* gz, int64_t nx, int64_t ny, int64_t nz,
                           float* w_out, int32_t* chi_out, void* stream) {

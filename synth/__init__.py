@@ -352,7 +352,10 @@ def coons_surface(seed: int, n_tri: int, n_bnd: int) -> Mesh:
     uv = np.concatenate([inner_uv, outer_uv], 0)
     V = _coons_eval(corners, sides, uv[:, 0], uv[:, 1])
     F = np.concatenate(faces, 0).astype(np.int32)
-    return Mesh(V.astype(np.float32), F, {"n_bnd": n_bnd, "m": m, "seed": seed})
+    # boundary curves in the orientation the (counter-clockwise) faces induce:
+    # bottom, right, then top and left reversed
+    curves = np.stack([sides["bottom"], sides["right"], sides["top"][::-1], sides["left"][::-1]])
+    return Mesh(V.astype(np.float32), F, {"n_bnd": n_bnd, "m": m, "seed": seed, "curves": curves})
 
 
 @dataclass
