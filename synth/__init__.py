@@ -256,6 +256,31 @@ def _coons_eval(corners, sides, u, v):
     return (1 - vv) * c0 + vv * c1 + (1 - uu) * d0 + uu * d1 - bil
 
 
+def _coons_net(corners, sides):
+    """The 4x4 Bernstein net (index [i][j]: i along u, j along v) of the
+    bilinearly blended Coons patch: its two ruled parts are cubic in one
+    parameter and linear (degree-elevated to cubic) in the other, and the
+    bilinear correction is degree-elevated in both."""
+    e = np.array([1.0, 2.0 / 3.0, 1.0 / 3.0, 0.0])          # (1 - t) in the cubic Bernstein basis
+    net = np.zeros((4, 4, 3))
+    for i in range(4):
+        for j in range(4):
+            net[i, j] = (e[j] * sides["bottom"][i] + (1 - e[j]) * sides["top"][i]
+                         + e[i] * sides["left"][j] + (1 - e[i]) * sides["right"][j]
+                         - (e[i] * e[j] * corners["c00"] + (1 - e[i]) * e[j] * corners["c10"]
+                            + e[i] * (1 - e[j]) * corners["c01"] + (1 - e[i]) * (1 - e[j]) * corners["c11"]))
+    return net
+
+
+def bezier_patch(net, u, v):
+    """Points of the bicubic Bezier patch ``net`` [4, 4, 3] at (u, v)."""
+    u = np.asarray(u, np.float64)[..., None]
+    v = np.asarray(v, np.float64)[..., None]
+    bu = [(1 - u) ** 3, 3 * u * (1 - u) ** 2, 3 * u * u * (1 - u), u ** 3]
+    bv = [(1 - v) ** 3, 3 * v * (1 - v) ** 2, 3 * v * v * (1 - v), v ** 3]
+    return sum(bu[i] * bv[j] * net[i, j] for i in range(4) for j in range(4))
+
+
 def _perim(u, v, eps):
     """Perimeter parameter in [0, 4) of a point on the square [eps, 1-eps]^2
     boundary, counter-clockwise from (eps, eps)."""
@@ -355,7 +380,8 @@ def coons_surface(seed: int, n_tri: int, n_bnd: int) -> Mesh:
     # boundary curves in the orientation the (counter-clockwise) faces induce:
     # bottom, right, then top and left reversed
     curves = np.stack([sides["bottom"], sides["right"], sides["top"][::-1], sides["left"][::-1]])
-    return Mesh(V.astype(np.float32), F, {"n_bnd": n_bnd, "m": m, "seed": seed, "curves": curves})
+    return Mesh(V.astype(np.float32), F, {"n_bnd": n_bnd, "m": m, "seed": seed, "curves": curves,
+                                          "net": _coons_net(corners, sides)})
 
 
 @dataclass
