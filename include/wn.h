@@ -211,6 +211,35 @@ wn_status wn_eval_3d_curves(const wn_bvh* bvh, const float* ctrl, int64_t ncurve
                             void* stream);
 
 /* ---------------------------------------------------------------------------
+ * wn_eval_3d_patches -- w of a parametric surface made of bicubic Bezier
+ * patches, without tessellation: chi_d from the exact ray-patch crossings
+ * (Eq. chi; Sec. 4, parametric surfaces) plus the boundary integral along
+ * the surface's boundary curves as in wn_eval_3d_curves.
+ *  dir        host [3] ray direction d (normalised here).
+ *  nets       device [npatch][4][4][3] float32 Bernstein control nets (index
+ *             [i][j]: i along u, j along v); a crossing counts
+ *             sign(d . (S_u x S_v)).
+ *  curves     device [ncurves][4][3] float32: the surface's boundary loops
+ *             as cubic Beziers, oriented as the patches induce (may be 0).
+ *  qx..nq     queries as in wn_eval_3d.
+ *  w_out      device [nq] float32 out, or NULL (crossings only);
+ *  chi_out    device [nq] int32 out, or NULL (then a temporary buffer of
+ *             4 bytes per query is allocated on the stream).
+ * Crossings: per query a depth-first walk over dyadic sub-squares of each
+ * patch; a sub-square is dropped when its net relative to the query excludes
+ * the ray (convex hull); when it lies wholly in front of the query and the
+ * hull of each of its boundary edges excludes the ray, its signed crossings
+ * are the winding number of its boundary's image around the ray; otherwise
+ * it is split, down to level 16 (where it is dropped).  Non-finite queries
+ * give NaN / WN_CHI_INVALID.
+ * Errors: INVALID_ARGUMENT, UNSUPPORTED, OUT_OF_MEMORY, HIP.
+ * ------------------------------------------------------------------------- */
+wn_status wn_eval_3d_patches(const double dir[3], const float* nets, int64_t npatch,
+                             const float* curves, int64_t ncurves,
+                             const float* qx, const float* qy, const float* qz, int64_t nq,
+                             float* w_out, int32_t* chi_out, void* stream);
+
+/* ---------------------------------------------------------------------------
  * wn_crossings_3d -- chi_d only (Eq. chi; the ray-casting step of Alg. 1) through the BVH.
  *  chi_out device [nq] int32 out.
  * ------------------------------------------------------------------------- */

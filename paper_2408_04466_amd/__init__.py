@@ -19,6 +19,7 @@ from .api import (  # noqa: F401
     eval_3d,
     eval_3d_boundary,
     eval_3d_curves,
+    eval_3d_patches,
     eval_3d_grid,
     winding_number,
     winding_number_2d,

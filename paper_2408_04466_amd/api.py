@@ -9,7 +9,7 @@ import torch
 
 from ._lib import CurveSet2D, check, lib, WN_MAX_LOOPS
 
-__all__ = ["boundary_loops", "BVH", "eval_3d", "eval_3d_boundary", "eval_3d_grid", "eval_3d_curves", "crossings_3d",
+__all__ = ["boundary_loops", "BVH", "eval_3d", "eval_3d_boundary", "eval_3d_grid", "eval_3d_curves", "eval_3d_patches", "crossings_3d",
            "backward", "WindingNumber3D", "winding_number", "eval_2d", "eval_2d_batched", "Batch2D", "backward_2d",
            "WindingNumber2D", "winding_number_2d", "Batch"]
 
@@ -145,6 +145,29 @@ def eval_3d_curves(bvh: BVH, ctrl: torch.Tensor, qx, qy, qz, chi_in=None, want_c
     check(lib().wn_eval_3d_curves(bvh.handle, pcurve, nc, px, py, pz, nq, pin, _dev(w, torch.float32, "w"),
                                   _dev(chi, torch.int32, "chi") if chi is not None else None, _stream(stream)),
           "wn_eval_3d_curves")
+    return w, chi
+
+
+def eval_3d_patches(direction, nets: torch.Tensor, curves, qx, qy, qz, want_w: bool = True,
+                    want_chi: bool = True, stream=None):
+    """w (and chi) of a surface of bicubic Bezier patches ``nets`` [np, 4, 4, 3]
+    (float32) with boundary curves ``curves`` [nc, 4, 3] (or None), for the
+    ray direction ``direction`` (3 floats): exact ray-patch crossings plus the
+    boundary integral along the curves.  Returns (w or None, chi or None)."""
+    npatch = nets.shape[0]
+    pn = _dev(nets, torch.float32, "nets", (npatch, 4, 4, 3))
+    nc = 0 if curves is None else curves.shape[0]
+    pcv = _dev(curves, torch.float32, "curves", (nc, 4, 3)) if curves is not None else None
+    px, py, pz, nq = _queries(qx, qy, qz)
+    if not (want_w or want_chi):
+        raise ValueError("nothing requested")
+    w = torch.empty(nq, dtype=torch.float32, device=qx.device) if want_w else None
+    chi = torch.empty(nq, dtype=torch.int32, device=qx.device) if want_chi else None
+    d = (C.c_double * 3)(*[float(x) for x in direction])
+    check(lib().wn_eval_3d_patches(d, pn, npatch, pcv, nc, px, py, pz, nq,
+                                   _dev(w, torch.float32, "w") if w is not None else None,
+                                   _dev(chi, torch.int32, "chi") if chi is not None else None, _stream(stream)),
+          "wn_eval_3d_patches")
     return w, chi
 
 

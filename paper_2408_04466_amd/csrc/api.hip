@@ -443,6 +443,47 @@ wn_status wn_eval_3d_curves(const wn_bvh* h, const float* ctrl, int64_t ncurves,
   return WN_OK;
 }
 
+wn_status wn_eval_3d_patches(const double dir[3], const float* nets, int64_t npatch, const float* curves,
+                             int64_t ncurves, const float* qx, const float* qy, const float* qz, int64_t nq,
+                             float* w_out, int32_t* chi_out, void* stream) {
+  g_err.clear();
+  double d[3], R[9];
+  if (!make_rotation(dir, d, R)) return fail(WN_ERR_INVALID_ARGUMENT, "dir must be finite and nonzero");
+  if (npatch < 0 || ncurves < 0) return fail(WN_ERR_INVALID_ARGUMENT, "negative patch or curve count");
+  if (npatch > INT32_MAX / 48 || ncurves > INT32_MAX / 12) return fail(WN_ERR_UNSUPPORTED, "too many patches or curves");
+  if (npatch > 0 && !nets) return fail(WN_ERR_INVALID_ARGUMENT, "nets is NULL");
+  if (ncurves > 0 && !curves) return fail(WN_ERR_INVALID_ARGUMENT, "curves is NULL");
+  wn_status st = check_queries(qx, qy, qz, nq);
+  if (st) return st;
+  if (nq == 0) return WN_OK;
+  if (!w_out && !chi_out) return fail(WN_ERR_INVALID_ARGUMENT, "w_out and chi_out are both NULL");
+  wn::Frame F;
+  for (int k = 0; k < 9; ++k) F.r[k] = R[k];
+  for (int k = 0; k < 3; ++k) F.c[k] = 0.0;
+  hipStream_t s = as_stream(stream);
+  int32_t* chi = chi_out;
+  if (!chi) {
+    const hipError_t e = hipMallocAsync((void**)&chi, (size_t)nq * sizeof(int32_t), s);
+    if (e != hipSuccess) return hip_fail(e, "hipMallocAsync");
+  }
+  hipError_t e = wn::launch_patches3d(F, nets, npatch, qx, qy, qz, nq, chi, s);
+  if (e == hipSuccess && w_out) {
+    wn::CrossArgs c{};
+    c.F = F;
+    c.qx = qx;
+    c.qy = qy;
+    c.qz = qz;
+    c.nq = nq;
+    e = wn::launch_curves3d(c, curves, ncurves, chi, w_out, nullptr, s);
+  }
+  if (!chi_out) {
+    const hipError_t e2 = hipFreeAsync(chi, s);
+    if (e == hipSuccess) e = e2;
+  }
+  if (e != hipSuccess) return hip_fail(e, "wn_eval_3d_patches");
+  return WN_OK;
+}
+
 wn_status wn_eval_3d_grid(const wn_bvh* h, const float* bnd_xyz, const int64_t* loop_off, int32_t nloops,
                           const float* gx, const float* gy, const float* gz, int64_t nx, int64_t ny, int64_t nz,
                           float* w_out, int32_t* chi_out, void* stream) {

@@ -134,6 +134,15 @@ def test_validation_happens_on_the_host(W):
     assert L.wn_eval_2d_batched(None, fake, fake, fake, fake, None, None) == 1
     assert "batch" in _err(W)
     assert L.wn_batch2d_free(None) == 0
+    # parametric path: bad direction, NULL nets, nothing requested
+    d0 = (C.c_double * 3)(0.0, 0.0, 0.0)
+    d1 = (C.c_double * 3)(0.0, 0.0, 1.0)
+    assert L.wn_eval_3d_patches(d0, fake, 1, None, 0, fake, fake, fake, 4, fake, None, None) == 1
+    assert L.wn_eval_3d_patches(d1, None, 1, None, 0, fake, fake, fake, 4, fake, None, None) == 1
+    assert "nets" in _err(W)
+    assert L.wn_eval_3d_patches(d1, fake, 1, None, 0, fake, fake, fake, 4, None, None, None) == 1
+    assert L.wn_eval_3d_patches(d1, fake, 1, None, 0, fake, fake, fake, 0, None, None, None) == 0
+    assert L.wn_eval_3d_curves(None, fake, 1, fake, fake, fake, 4, None, fake, None, None) == 1
 
 
 def test_missing_library_fails_loudly(tmp_path):
