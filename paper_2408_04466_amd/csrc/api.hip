@@ -137,12 +137,34 @@ float ord_to_float(unsigned o) {
   return f;
 }
 
-template <class T>
-hipError_t dalloc(T** p, size_t n) {
-  *p = nullptr;
-  if (n == 0) return hipSuccess;
-  return hipMalloc((void**)p, n * sizeof(T));
-}
+// Several device arrays carved out of one allocation (256-byte aligned).
+struct Carve {
+  struct Req {
+    void** p;
+    size_t bytes;
+  };
+  std::vector<Req> reqs;
+  template <class T>
+  void add(T** p, size_t n) {
+    reqs.push_back({(void**)p, n * sizeof(T)});
+  }
+  hipError_t alloc(void** base) {
+    size_t total = 0;
+    for (const Req& r : reqs) total += (r.bytes + 255) & ~(size_t)255;
+    *base = nullptr;
+    const hipError_t e = hipMalloc(base, total > 0 ? total : 256);
+    if (e != hipSuccess) {
+      *base = nullptr;
+      return e;
+    }
+    size_t o = 0;
+    for (const Req& r : reqs) {
+      *r.p = r.bytes ? (void*)((char*)*base + o) : nullptr;
+      o += (r.bytes + 255) & ~(size_t)255;
+    }
+    return hipSuccess;
+  }
+};
 
 }  // namespace
 
@@ -244,14 +266,50 @@ wn_status wn_build_bvh(const float* V, int64_t nv, const int32_t* F, int64_t nf,
   h->nv = (int32_t)nv;
   h->nf = (int32_t)nf;
 
+  // every temporary of the build in one allocation, the BVH's arrays in another
+  const int64_t nint = nf > 1 ? nf - 1 : 0;
+  wn::BuildBufs b{};
+  unsigned* dbb = nullptr;
+  Carve tc;
+  tc.add(&dbb, 6);
+  tc.add(&b.box, (size_t)nf);
+  tc.add(&b.zmax, (size_t)nf);
+  tc.add(&b.cen, (size_t)nf);
+  tc.add(&b.cbounds, 4);
+  tc.add(&b.keys, (size_t)nf);
+  tc.add(&b.vals, (size_t)nf);
+  tc.add(&b.keys2, (size_t)nf);
+  tc.add(&b.vals2, (size_t)nf);
+  tc.add((char**)&b.sort_tmp, nf > 1 ? wn::radix_sort_tmp_bytes(nf) : 0);
+  tc.add(&b.left, (size_t)nint);
+  tc.add(&b.right, (size_t)nint);
+  tc.add(&b.parent_int, (size_t)nint);
+  tc.add(&b.parent_leaf, (size_t)nf);
+  tc.add(&b.ibox, (size_t)nint);
+  tc.add(&b.iz, (size_t)nint);
+  tc.add(&b.flags, (size_t)nint);
+  void* tmp = nullptr;
+  hipError_t e = tc.alloc(&tmp);
+  if (e != hipSuccess) { delete h; return hip_fail(e, "hipMalloc"); }
+  Carve pc;
+  pc.add(&h->Vr, (size_t)nv);
+  pc.add(&h->tris, (size_t)nf);
+  pc.add(&h->nodes, (size_t)nint);
+  pc.add(&h->leafbox, (size_t)nf);
+  pc.add(&h->leafz, (size_t)nf);
+  e = pc.alloc(&h->mem);
+  if (e != hipSuccess) { hipFree(tmp); delete h; return hip_fail(e, "hipMalloc"); }
+  b.Vr = h->Vr;
+  b.tris = h->tris;
+  b.nodes = h->nodes;
+  b.leafbox = h->leafbox;
+  b.leafz = h->leafz;
+
   // bounding box of V -> centre and power-of-two scale of the frame
   double c[3] = {0, 0, 0};
   double half = 1.0;
   if (nv > 0) {
-    unsigned* dbb = nullptr;
     unsigned hbb[6];
-    hipError_t e = hipMalloc((void**)&dbb, 6 * sizeof(unsigned));
-    if (e != hipSuccess) { delete h; return hip_fail(e, "hipMalloc"); }
     const unsigned init[6] = {0xffffffffu, 0u, 0xffffffffu, 0u, 0xffffffffu, 0u};
     e = hipMemcpyAsync(dbb, init, sizeof init, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
@@ -260,12 +318,15 @@ wn_status wn_build_bvh(const float* V, int64_t nv, const int32_t* F, int64_t nf,
     }
     if (e == hipSuccess) e = hipMemcpyAsync(hbb, dbb, sizeof hbb, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    hipFree(dbb);
-    if (e != hipSuccess) { delete h; return hip_fail(e, "bounding box"); }
+    if (e != hipSuccess) { hipFree(tmp); wn_free_bvh(h); return hip_fail(e, "bounding box"); }
     double m2 = 0.0;
     for (int k = 0; k < 3; ++k) {
       const double lo = ord_to_float(hbb[2 * k]), hi = ord_to_float(hbb[2 * k + 1]);
-      if (!std::isfinite(lo) || !std::isfinite(hi)) { delete h; return fail(WN_ERR_INVALID_ARGUMENT, "non-finite vertex"); }
+      if (!std::isfinite(lo) || !std::isfinite(hi)) {
+        hipFree(tmp);
+        wn_free_bvh(h);
+        return fail(WN_ERR_INVALID_ARGUMENT, "non-finite vertex");
+      }
       c[k] = (double)(float)(0.5 * (lo + hi));
       const double hk = 0.5 * (hi - lo);
       m2 += hk * hk;
@@ -277,45 +338,13 @@ wn_status wn_build_bvh(const float* V, int64_t nv, const int32_t* F, int64_t nf,
   for (int k = 0; k < 9; ++k) h->F.r[k] = R[k] * scale;
   for (int k = 0; k < 3; ++k) h->F.c[k] = c[k];
 
-  const int64_t nint = nf > 1 ? nf - 1 : 0;
-  wn::BuildBufs b{};
-  hipError_t e = hipSuccess;
   auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
-  chk(dalloc(&h->Vr, (size_t)nv));
-  chk(dalloc(&h->tris, (size_t)nf));
-  chk(dalloc(&h->nodes, (size_t)nint));
-  chk(dalloc(&h->leafbox, (size_t)nf));
-  chk(dalloc(&h->leafz, (size_t)nf));
-  b.Vr = h->Vr;
-  b.tris = h->tris;
-  b.nodes = h->nodes;
-  b.leafbox = h->leafbox;
-  b.leafz = h->leafz;
-  chk(dalloc(&b.box, (size_t)nf));
-  chk(dalloc(&b.zmax, (size_t)nf));
-  chk(dalloc(&b.cen, (size_t)nf));
-  chk(dalloc(&b.cbounds, 4));
-  chk(dalloc(&b.keys, (size_t)nf));
-  chk(dalloc(&b.vals, (size_t)nf));
-  chk(dalloc(&b.keys2, (size_t)nf));
-  chk(dalloc(&b.vals2, (size_t)nf));
-  chk(dalloc((char**)&b.sort_tmp, nf > 1 ? wn::radix_sort_tmp_bytes(nf) : 0));
-  chk(dalloc(&b.left, (size_t)nint));
-  chk(dalloc(&b.right, (size_t)nint));
-  chk(dalloc(&b.parent_int, (size_t)nint));
-  chk(dalloc(&b.parent_leaf, (size_t)nf));
-  chk(dalloc(&b.ibox, (size_t)nint));
-  chk(dalloc(&b.iz, (size_t)nint));
-  chk(dalloc(&b.flags, (size_t)nint));
   // pad: scaled coordinates are O(1); 2^-19 covers float32 rounding of
   // queries and vertices near the mesh with a wide margin
   const float pad = std::ldexp(1.0f, -19);
   if (e == hipSuccess) chk(wn::build_bvh_device(b, h->F, V, (int32_t)nv, F, (int32_t)nf, pad, s));
   if (e == hipSuccess) chk(hipStreamSynchronize(s));
-  hipFree(b.box); hipFree(b.zmax); hipFree(b.cen); hipFree(b.cbounds);
-  hipFree(b.keys); hipFree(b.vals); hipFree(b.keys2); hipFree(b.vals2); hipFree(b.sort_tmp);
-  hipFree(b.left); hipFree(b.right); hipFree(b.parent_int); hipFree(b.parent_leaf);
-  hipFree(b.ibox); hipFree(b.iz); hipFree(b.flags);
+  hipFree(tmp);
   if (e != hipSuccess) {
     wn_free_bvh(h);
     return hip_fail(e, "wn_build_bvh");
@@ -327,11 +356,7 @@ wn_status wn_build_bvh(const float* V, int64_t nv, const int32_t* F, int64_t nf,
 wn_status wn_free_bvh(wn_bvh* h) {
   g_err.clear();
   if (!h) return WN_OK;
-  hipFree(h->Vr);
-  hipFree(h->tris);
-  hipFree(h->nodes);
-  hipFree(h->leafbox);
-  hipFree(h->leafz);
+  if (h->mem) hipFree(h->mem);
   delete h;
   return WN_OK;
 }

@@ -196,42 +196,76 @@ __global__ void k_gather_leaves(const int32_t* __restrict__ Fc, const int32_t* _
   lz[i] = zmax[f];
 }
 
-// Bottom-up: the second child to arrive at a node writes the node.  The
-// agent-scope fence before the counter increment publishes this thread's
-// writes; the one after it makes the sibling's writes visible (it
-// invalidates the compute unit's vector L1).
-__global__ void k_refit(int32_t nf, const int32_t* __restrict__ left, const int32_t* __restrict__ right,
-                        const int32_t* __restrict__ parent_int, const int32_t* __restrict__ parent_leaf,
-                        const float4* __restrict__ lbox, const float* __restrict__ lz,
-                        float4* ibox, float* iz, int32_t* flags, BvhNode* __restrict__ nodes) {
+// Depth of every internal node (distance to the root) by pointer jumping
+// over the parent links: after r rounds anc[i] is the 2^r-th ancestor (or -1)
+// and dep[i] the number of links walked.
+__global__ void k_depth_init(const int32_t* __restrict__ parent_int, int32_t n, int32_t* __restrict__ anc,
+                             int32_t* __restrict__ dep) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nf) return;
-  int node = parent_leaf[i];
-  while (node >= 0 && node < nf - 1) {
-    __threadfence();
-    if (atomicAdd(&flags[node], 1) == 0) return;
-    __threadfence();
-    const int32_t lc = left[node], rc = right[node];
-    if (lc >= nf - 1 || rc >= nf - 1 || ~lc >= nf || ~rc >= nf) return;
-    float4 bl, br;
-    float zl, zr;
-    if (lc < 0) { bl = lbox[~lc]; zl = lz[~lc]; }
-    else { bl = ibox[lc]; zl = iz[lc]; }
-    if (rc < 0) { br = lbox[~rc]; zr = lz[~rc]; }
-    else { br = ibox[rc]; zr = iz[rc]; }
-    BvhNode nd;
-    nd.lbox = bl;
-    nd.rbox = br;
-    nd.lzmax = zl;
-    nd.rzmax = zr;
-    nd.left = lc;
-    nd.right = rc;
-    nodes[node] = nd;
-    const float4 u = make_float4(fminf(bl.x, br.x), fmaxf(bl.y, br.y), fminf(bl.z, br.z), fmaxf(bl.w, br.w));
-    ibox[node] = u;
-    iz[node] = fmaxf(zl, zr);
-    node = parent_int[node];
+  if (i >= n) return;
+  const int32_t p = parent_int[i];
+  anc[i] = p;
+  dep[i] = p >= 0 ? 1 : 0;
+}
+
+__global__ void k_depth_jump(const int32_t* __restrict__ anc_in, const int32_t* __restrict__ dep_in, int32_t n,
+                             int32_t* __restrict__ anc_out, int32_t* __restrict__ dep_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t a = anc_in[i];
+  if (a >= 0 && a < n) {
+    dep_out[i] = dep_in[i] + dep_in[a];
+    anc_out[i] = anc_in[a];
+  } else {
+    dep_out[i] = dep_in[i];
+    anc_out[i] = -1;
   }
+}
+
+// res[0] = deepest level, res[1] = 1 if some node has not reached the root.
+__global__ void k_depth_max(const int32_t* __restrict__ anc, const int32_t* __restrict__ dep, int32_t n,
+                            int32_t* res) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int m = i < n ? dep[i] : 0;
+  int open = (i < n && anc[i] >= 0) ? 1 : 0;
+  // wavefront maximum first: one atomic per wavefront
+  for (int o = 32; o > 0; o >>= 1) {
+    m = max(m, __shfl_xor(m, o));
+    open = max(open, __shfl_xor(open, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(&res[0], m);
+    if (open) atomicMax(&res[1], 1);
+  }
+}
+
+// One level of the bottom-up refit: every node at depth `level` merges its
+// children, which are leaves or nodes of the level below (written by the
+// previous launch, so no fences are needed).
+__global__ void k_refit_level(int32_t nf, int32_t level, const int32_t* __restrict__ dep,
+                              const int32_t* __restrict__ left, const int32_t* __restrict__ right,
+                              const float4* __restrict__ lbox, const float* __restrict__ lz, float4* ibox, float* iz,
+                              BvhNode* __restrict__ nodes) {
+  const int node = blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= nf - 1 || dep[node] != level) return;
+  const int32_t lc = left[node], rc = right[node];
+  if (lc >= nf - 1 || rc >= nf - 1 || ~lc >= nf || ~rc >= nf) return;
+  float4 bl, br;
+  float zl, zr;
+  if (lc < 0) { bl = lbox[~lc]; zl = lz[~lc]; }
+  else { bl = ibox[lc]; zl = iz[lc]; }
+  if (rc < 0) { br = lbox[~rc]; zr = lz[~rc]; }
+  else { br = ibox[rc]; zr = iz[rc]; }
+  BvhNode nd;
+  nd.lbox = bl;
+  nd.rbox = br;
+  nd.lzmax = zl;
+  nd.rzmax = zr;
+  nd.left = lc;
+  nd.right = rc;
+  nodes[node] = nd;
+  ibox[node] = make_float4(fminf(bl.x, br.x), fmaxf(bl.y, br.y), fminf(bl.z, br.z), fmaxf(bl.w, br.w));
+  iz[node] = fmaxf(zl, zr);
 }
 
 __global__ void k_fill_u32(unsigned* p, int64_t n, unsigned v) {
@@ -277,10 +311,35 @@ hipError_t build_bvh_device(const BuildBufs& b, const Frame& F, const float* V, 
   hipLaunchKernelGGL(k_karras, dim3(bf), dim3(256), 0, s, b.keys, nf, b.left, b.right,
                      b.parent_int, b.parent_leaf);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = fill_u32((unsigned*)b.flags, nf - 1, 0u, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_refit, dim3(bf), dim3(256), 0, s, nf, b.left, b.right, b.parent_int,
-                     b.parent_leaf, b.leafbox, b.leafz, b.ibox, b.iz, b.flags, b.nodes);
-  return hipGetLastError();
+  // node depths (the sort and Morton buffers are free by now), then the
+  // refit one level per launch, deepest first
+  const int32_t ni = nf - 1;
+  const unsigned bi = (unsigned)((ni + 255) / 256);
+  int32_t* anc[2] = {(int32_t*)b.keys2, b.flags};
+  int32_t* dep[2] = {b.vals2, (int32_t*)b.keys};
+  hipLaunchKernelGGL(k_depth_init, dim3(bi), dim3(256), 0, s, b.parent_int, ni, anc[0], dep[0]);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // a Karras tree over 64-bit (key, index) codes is at most 64 levels deep:
+  // 7 rounds reach the root from every node
+  int cur = 0;
+  for (int r = 0; r < 7; ++r, cur ^= 1) {
+    hipLaunchKernelGGL(k_depth_jump, dim3(bi), dim3(256), 0, s, anc[cur], dep[cur], ni, anc[cur ^ 1], dep[cur ^ 1]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  int32_t* res = (int32_t*)b.cbounds;
+  if ((e = fill_u32(b.cbounds, 2, 0u, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_depth_max, dim3(bi), dim3(256), 0, s, anc[cur], dep[cur], ni, res);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  int32_t hres[2] = {0, 0};
+  if ((e = hipMemcpyAsync(hres, res, sizeof hres, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+  if (hres[1] != 0 || hres[0] < 0 || hres[0] > 128) return hipErrorUnknown;
+  for (int level = hres[0]; level >= 0; --level) {
+    hipLaunchKernelGGL(k_refit_level, dim3(bi), dim3(256), 0, s, nf, level, dep[cur], b.left, b.right, b.leafbox,
+                       b.leafz, b.ibox, b.iz, b.nodes);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace wn

@@ -36,5 +36,6 @@ struct wn_bvh {
   wn::BvhNode* nodes = nullptr;
   float4* leafbox = nullptr;
   float* leafz = nullptr;
+  void* mem = nullptr;   // the one allocation holding the arrays above
 };
 
