@@ -39,6 +39,7 @@ KERNEL_SOURCES = ("paper_2408_04466_amd/csrc/bnd3d.hip", "paper_2408_04466_amd/c
                   "paper_2408_04466_amd/csrc/geom.hpp")
 FLOPS_PER_PAIR_BWD = 40      # adjoint, per (query, boundary edge)
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak
+VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9   # vector lane-instructions/s without packed FP32
 
 
 def workload_c3():
@@ -81,23 +82,26 @@ def cpu_baseline(M, P, d, t, nsample=64):
                       f"{dt:.1f} s wall"}
 
 
-def measured_traffic():
-    """HBM bytes per k_bnd3d launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's counts), or
-    None when the kernel sources changed since the counters were taken."""
+def measured_counters():
+    """(HBM bytes, VALU wavefront instructions) per k_bnd3d launch from the
+    committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE scaled by
+    a plain copy's counts; SQ_INSTS_VALU), or (None, None) when the kernel
+    sources changed since the counters were taken."""
     import hashlib
     try:
         txt = open(COUNTERS).read()
     except OSError:
-        return None
+        return None, None
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     vals = dict(line.split(": ", 1) for line in txt.splitlines()
-                if line.startswith(("traffic_bytes_per_launch k_bnd3d", "source_sha256 k_bnd3d")))
+                if line.startswith(("traffic_bytes_per_launch k_bnd3d", "source_sha256 k_bnd3d",
+                                    "valu_wave_instructions_per_launch k_bnd3d")))
     if vals.get("source_sha256 k_bnd3d", "").strip() != h.hexdigest():
-        return None
-    return int(vals["traffic_bytes_per_launch k_bnd3d"])
+        return None, None
+    valu = vals.get("valu_wave_instructions_per_launch k_bnd3d")
+    return int(vals["traffic_bytes_per_launch k_bnd3d"]), (int(valu) if valu else None)
 
 
 class Timer:
@@ -256,6 +260,7 @@ def main():
     extra = {}
     if others is not None:
         extra = run_others(torch, W, T, others, d, args, dev)
+    traffic, valu = measured_counters()
 
     out = {
         "metric": "winding queries/s fwd+bwd, batched vs plain, 3D mesh 2^20 pts at |err|<=1e-4",
@@ -280,11 +285,19 @@ def main():
                    "batch_tuning": {k: batch.info()[k] for k in ("tile", "wg_per_cu", "mode", "graph")}},
         "roofline": {"bound": "alu", "kernel": "k_bnd3d (boundary integral)",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, "
                                      "factors from a 1 GiB copy)",
                      "flops_per_pair": FLOPS_PER_PAIR_FWD, "pairs_per_launch": pairs,
-                     "avg_launch_ms": ms_bnd},
+                     "avg_launch_ms": ms_bnd,
+                     # vector-ALU issue: the committed SQ_INSTS_VALU count per launch
+                     # (wavefront instructions x 64 lanes) over the live launch time,
+                     # against 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one wave64
+                     # instruction per SIMD every 4 cycles; packed FP32 excluded)
+                     "valu_issue": ({"achieved": valu * 64 / (ms_bnd * 1e-3), "peak": VALU_ISSUE_PEAK,
+                                     "unit": "lane-instructions/s",
+                                     "frac": valu * 64 / (ms_bnd * 1e-3) / VALU_ISSUE_PEAK}
+                                    if valu else None)},
         "batched_vs_plain": {
             "mesh_2^20": {"batched_fwd_bwd_qps": nq / (ms_step * 1e-3),
                           "plain_fwd_bwd_qps": nq / (ms_step_plain * 1e-3),
