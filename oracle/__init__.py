@@ -26,4 +26,4 @@ Every floating-point computation is float64 on inputs promoted exactly from
 the kernel's float32 arrays.  Parity status of each function is stated in its
 module header ("pinned by ..." or "parity unpinned").
 """
-from . import wn3d, wn2d, grad3d, grad2d, curves3d, patches3d  # noqa: F401
+from . import wn3d, wn2d, grad3d, grad2d, curves3d, patches3d, gradcurves  # noqa: F401
