@@ -453,6 +453,8 @@ def run_others(torch, W, T, others, d3, args, dev):
     ms_cw = T.ms(lambda: W.eval_3d_curves(bvhc, ctrlc, *qc), reps)
     ms_pb = T.ms(lambda: W.eval_3d_boundary(bvhc, bndc, offc, *qc, zc), reps)
     ms_tw = T.ms(lambda: W.eval_3d(bvhc, bndc, offc, *qc), reps)
+    gwc = torch.ones(1 << 20, dtype=torch.float32, device=dev)
+    ms_cbw = T.ms(lambda: W.backward_curves(ctrlc, *qc, gwc), reps)
     netc = torch.from_numpy(np.ascontiguousarray(MC.info["net"][None].astype(np.float32))).to(dev)
     ms_pc = T.ms(lambda: W.eval_3d_patches(dmc, netc, None, *qc, want_w=False), reps)
     ms_pw = T.ms(lambda: W.eval_3d_patches(dmc, netc, ctrlc, *qc), reps)
@@ -461,7 +463,8 @@ def run_others(torch, W, T, others, d3, args, dev):
         "tessellated_w_ms_1M_triangles": ms_tw, "queries_per_s": (1 << 20) / (ms_pw * 1e-3)}
     res["3d_curved_boundary_coons_2p20"] = {
         "curves": 4, "curves_boundary_ms": ms_cb, "curves_with_bvh_chi_ms": ms_cw,
-        "polyline_512_boundary_ms": ms_pb, "queries_per_s": (1 << 20) / (ms_cw * 1e-3)}
+        "polyline_512_boundary_ms": ms_pb, "curves_backward_ms": ms_cbw,
+        "queries_per_s": (1 << 20) / (ms_cw * 1e-3)}
     del bvhc
     # --- the 2D experiment's shape: 1000 random cubics, each on its own 250^2
     # grid, float64; one batched launch vs a loop of single-set calls

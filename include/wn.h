@@ -211,6 +211,30 @@ wn_status wn_eval_3d_curves(const wn_bvh* bvh, const float* ctrl, int64_t ncurve
                             void* stream);
 
 /* ---------------------------------------------------------------------------
+ * wn_backward_curves -- adjoint of the curve boundary term for a loss L with
+ * dL/dw = grad_w.  Away from the surface chi_d is locally constant, so
+ * (as for wn_backward) the derivatives come from the boundary alone and do
+ * not depend on d:
+ *   dL/dp   = +(g/4pi) int (gamma - p) x gamma'(t) / |gamma - p|^3 dt,
+ *   dL/dc_k = -sum_q (g_q/4pi) int B_k(t) (gamma - p) x gamma'(t) / |gamma - p|^3 dt
+ * over every curve (B_k the cubic Bernstein functions), integrated on the
+ * same dyadic panels as wn_eval_3d_curves (6-point Gauss-Legendre once a
+ * panel is 1.5 control-polygon lengths away).
+ *  ctrl       device [ncurves][4][3] float32 (world coordinates).
+ *  qx..nq     queries; grad_w device [nq] float32.
+ *  grad_q     device [nq][3] out, or NULL (NaN for non-finite queries).
+ *  grad_ctrl  device [ncurves][4][3] out, or NULL: fixed-order sums
+ *             (wavefront, workgroup, then float64 over workgroups), bitwise
+ *             reproducible; allocates 48 bytes per (256 queries, curve) on
+ *             the stream.  A control point shared by two curves gets one
+ *             entry per curve; the caller adds them.
+ * Errors: INVALID_ARGUMENT, UNSUPPORTED, OUT_OF_MEMORY, HIP.
+ * ------------------------------------------------------------------------- */
+wn_status wn_backward_curves(const float* ctrl, int64_t ncurves,
+                             const float* qx, const float* qy, const float* qz, int64_t nq,
+                             const float* grad_w, float* grad_q, float* grad_ctrl, void* stream);
+
+/* ---------------------------------------------------------------------------
  * wn_eval_3d_patches -- w of a parametric surface made of bicubic Bezier
  * patches, without tessellation: chi_d from the exact ray-patch crossings
  * (Eq. chi; Sec. 4, parametric surfaces) plus the boundary integral along

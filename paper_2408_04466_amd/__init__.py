@@ -10,7 +10,9 @@ from .api import (  # noqa: F401
     Batch2D,
     WindingNumber2D,
     WindingNumber3D,
+    WindingNumberCurves,
     backward_2d,
+    backward_curves,
     backward,
     boundary_loops,
     crossings_3d,
@@ -23,5 +25,6 @@ from .api import (  # noqa: F401
     eval_3d_grid,
     winding_number,
     winding_number_2d,
+    winding_number_curves,
 )
 from ._lib import WN_CHI_INVALID, WN_MAX_LOOPS, WnError, lib  # noqa: F401

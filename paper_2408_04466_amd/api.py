@@ -9,7 +9,8 @@ import torch
 
 from ._lib import CurveSet2D, check, lib, WN_MAX_LOOPS
 
-__all__ = ["boundary_loops", "BVH", "eval_3d", "eval_3d_boundary", "eval_3d_grid", "eval_3d_curves", "eval_3d_patches", "crossings_3d",
+__all__ = ["boundary_loops", "BVH", "eval_3d", "eval_3d_boundary", "eval_3d_grid", "eval_3d_curves", "eval_3d_patches", "backward_curves",
+           "WindingNumberCurves", "winding_number_curves", "crossings_3d",
            "backward", "WindingNumber3D", "winding_number", "eval_2d", "eval_2d_batched", "Batch2D", "backward_2d",
            "WindingNumber2D", "winding_number_2d", "Batch"]
 
@@ -438,6 +439,54 @@ class WindingNumber2D(torch.autograd.Function):
 
 def winding_number_2d(ctrl, loop_off, loop_closed, x, y):
     return WindingNumber2D.apply(ctrl, x, y, loop_off, loop_closed)
+
+
+def backward_curves(ctrl: torch.Tensor, qx, qy, qz, grad_w: torch.Tensor, want_q: bool = True,
+                    want_ctrl: bool = True, stream=None):
+    """(dL/dp [nq, 3], dL/dctrl [nc, 4, 3]) for dL/dw = grad_w of the curve
+    boundary term (``wn_backward_curves``); either may be None.  A control
+    point shared by two curves gets one entry per curve."""
+    nc = ctrl.shape[0]
+    pcv = _dev(ctrl, torch.float32, "ctrl", (nc, 4, 3))
+    px, py, pz, nq = _queries(qx, qy, qz)
+    pg = _dev(grad_w, torch.float32, "grad_w", (nq,))
+    gq = torch.empty((nq, 3), dtype=torch.float32, device=qx.device) if want_q else None
+    gc = torch.empty((nc, 4, 3), dtype=torch.float32, device=qx.device) if want_ctrl else None
+    if gq is None and gc is None:
+        return None, None
+    check(lib().wn_backward_curves(pcv, nc, px, py, pz, nq, pg,
+                                   _dev(gq, torch.float32, "grad_q") if gq is not None else None,
+                                   _dev(gc, torch.float32, "grad_ctrl") if gc is not None else None,
+                                   _stream(stream)), "wn_backward_curves")
+    return gq, gc
+
+
+class WindingNumberCurves(torch.autograd.Function):
+    """w of a surface bounded by Bezier curves (chi_d from the BVH of its
+    tessellation, or from ``chi`` if given); gradients flow to the control
+    points and the queries through the curve boundary term."""
+
+    @staticmethod
+    def forward(ctx, ctrl, qx, qy, qz, bvh, chi):
+        w, _ = eval_3d_curves(bvh, ctrl.detach(), qx.detach(), qy.detach(), qz.detach(), chi_in=chi,
+                              want_chi=False)
+        ctx.save_for_backward(ctrl, qx, qy, qz)
+        return w
+
+    @staticmethod
+    def backward(ctx, grad_w):
+        ctrl, qx, qy, qz = ctx.saved_tensors
+        need_c = ctx.needs_input_grad[0]
+        need_q = any(ctx.needs_input_grad[1:4])
+        gq, gc = backward_curves(ctrl.detach(), qx.detach(), qy.detach(), qz.detach(),
+                                 grad_w.contiguous().float(), want_q=need_q, want_ctrl=need_c)
+        if gq is None:
+            return gc, None, None, None, None, None
+        return gc, gq[:, 0], gq[:, 1], gq[:, 2], None, None
+
+
+def winding_number_curves(bvh, ctrl, qx, qy, qz, chi=None):
+    return WindingNumberCurves.apply(ctrl, qx, qy, qz, bvh, chi)
 
 
 class Batch:

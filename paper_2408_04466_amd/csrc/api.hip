@@ -468,6 +468,21 @@ wn_status wn_eval_3d_curves(const wn_bvh* h, const float* ctrl, int64_t ncurves,
   return WN_OK;
 }
 
+wn_status wn_backward_curves(const float* ctrl, int64_t ncurves, const float* qx, const float* qy, const float* qz,
+                             int64_t nq, const float* grad_w, float* grad_q, float* grad_ctrl, void* stream) {
+  g_err.clear();
+  if (ncurves < 0) return fail(WN_ERR_INVALID_ARGUMENT, "ncurves must be >= 0");
+  if (ncurves > INT32_MAX / 12) return fail(WN_ERR_UNSUPPORTED, "too many curves");
+  if (ncurves > 0 && !ctrl) return fail(WN_ERR_INVALID_ARGUMENT, "ctrl is NULL");
+  wn_status st = check_queries(qx, qy, qz, nq);
+  if (st) return st;
+  if (nq > 0 && !grad_w) return fail(WN_ERR_INVALID_ARGUMENT, "grad_w is NULL");
+  if (!grad_q && !grad_ctrl) return WN_OK;
+  WN_HIP(wn::backward_curves(ctrl, ncurves, qx, qy, qz, nq, grad_w, grad_q, grad_ctrl, as_stream(stream)),
+         "wn_backward_curves");
+  return WN_OK;
+}
+
 wn_status wn_eval_3d_patches(const double dir[3], const float* nets, int64_t npatch, const float* curves,
                              int64_t ncurves, const float* qx, const float* qy, const float* qz, int64_t nq,
                              float* w_out, int32_t* chi_out, void* stream) {
