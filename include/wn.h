@@ -385,9 +385,10 @@ wn_status wn_eval_2d_batched(const wn_batch2d* batch, const void* ctrl, const vo
  *  grad_q     device [n][2] of dtype out, or NULL (NaN for non-finite
  *             queries).
  *  grad_ctrl  device [nseg][4][2] of dtype out (fully written), or NULL.
- * The end-point sums are reduced in float64 in a fixed order (bitwise
- * reproducible).  Allocates 32 bytes per (open loop, 256 queries) on the
- * stream.  Errors as wn_eval_2d.
+ * The end-point sums are reduced in float64 in a fixed order (wavefront
+ * butterfly, workgroup, chunks of workgroups, chunks; bitwise
+ * reproducible).  Allocates about 32 bytes per (open loop, 256 queries) on
+ * the stream.  Errors as wn_eval_2d.
  * ------------------------------------------------------------------------- */
 wn_status wn_backward_2d(wn_dtype dtype, const void* ctrl, int64_t nseg,
                          const int64_t* loop_off, const uint8_t* loop_closed,

@@ -581,11 +581,38 @@ __global__ __launch_bounds__(kThreads) void k_rows_batched(const Set2D* __restri
 // with the open loops' end-point angles; with A(v) = (-v_y, v_x)/|v|^2 (the
 // gradient of the angle of v) and c = g/(2 pi) per query:
 //   dL/dp += c (A(s - p) - A(e - p)),  dL/ds -= c A(s - p),  dL/de += c A(e - p).
-// Interior control points and closed loops get zero.  Per workgroup the
-// end-point sums are reduced in LDS by a fixed-order tree in float64 and
-// stored value-major (part[value][block]); a second kernel adds the blocks
-// in a fixed order, so grad_ctrl is bitwise reproducible.
+// Interior control points and closed loops get zero.  Per wavefront the
+// end-point sums are reduced by DPP moves in T (a fixed pattern), the
+// workgroup adds its wavefronts in float64 in order after one barrier and stores its
+// partials value-major (part[value][workgroup]); two more kernels add the
+// workgroup partials in chunks and then the chunks, each in a fixed order,
+// so grad_ctrl is bitwise reproducible.
 // ---------------------------------------------------------------------------
+
+// Sum over the 64 lanes of a wavefront, left in lane 63, by DPP moves (no
+// LDS traffic): butterflies inside quads, rotations inside rows of 16, then
+// the row broadcasts of lanes 15 and 31.  Doubles move as two halves.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_t(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_t(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <class T>
+__device__ __forceinline__ T wave_sum_last(T v) {
+  v += dpp_t<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  v += dpp_t<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  v += dpp_t<0x124, 0xF>(v);   // row_ror:4
+  v += dpp_t<0x128, 0xF>(v);   // row_ror:8: every lane holds its row's sum
+  v += dpp_t<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_t<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+  return v;
+}
 
 template <class T>
 __device__ __forceinline__ void angle_grad(T vx, T vy, T& ax, T& ay) {
@@ -599,14 +626,27 @@ template <class T>
 __global__ __launch_bounds__(kThreads) void k_back2d(const T* __restrict__ ctrl, Loops2D L, int32_t kind,
                                                      const T* __restrict__ x, const T* __restrict__ y, int64_t nx,
                                                      int64_t n, const T* __restrict__ gw, T* __restrict__ gq,
-                                                     double* __restrict__ part, int64_t nblocks) {
-  __shared__ double red[4][kThreads];
+                                                     double* __restrict__ part, int64_t nslots) {
+  // [4 open loops][kThreads / 64] wavefront partials (dynamic, sized by the host)
+  extern __shared__ __align__(16) unsigned char dyn_b[];
+  double* wpart = reinterpret_cast<double*>(dyn_b);
   const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const bool ok = q < n;
   T px = (T)0, py = (T)0, g = (T)0;
   if (ok) {
-    px = kind == 0 ? x[q] : x[q % nx];
-    py = kind == 0 ? y[q] : y[q / nx];
+    int64_t row, col;
+    if (kind == 0) {
+      row = col = q;
+    } else if (n <= (int64_t)UINT32_MAX) {   // 32-bit division where it suffices
+      const uint32_t q32 = (uint32_t)q, nx32 = (uint32_t)nx;
+      row = q32 / nx32;
+      col = q32 - (uint32_t)row * nx32;
+    } else {
+      row = q / nx;
+      col = q - row * nx;
+    }
+    px = x[col];
+    py = y[row];
     g = gw[q];
   }
   const bool fin = ok && isfinite(px) && isfinite(py);
@@ -625,21 +665,28 @@ __global__ __launch_bounds__(kThreads) void k_back2d(const T* __restrict__ ctrl,
       gpy += asy - aey;
     }
     if (part) {   // uniform: end-point gradients requested
-      red[0][threadIdx.x] = -(double)(c * asx);
-      red[1][threadIdx.x] = -(double)(c * asy);
-      red[2][threadIdx.x] = (double)(c * aex);
-      red[3][threadIdx.x] = (double)(c * aey);
-      __syncthreads();
-      for (int h = kThreads / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h)
+      // wavefront sums by DPP moves (a fixed pattern, in T), parked in LDS
+      // per (open loop, wavefront)
+      T v[4] = {-(c * asx), -(c * asy), c * aex, c * aey};
 #pragma unroll
-          for (int j = 0; j < 4; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + h];
-        __syncthreads();
+      for (int j = 0; j < 4; ++j) v[j] = wave_sum_last(v[j]);
+      if ((threadIdx.x & 63) == 63) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) wpart[(k * 4 + j) * (kThreads / 64) + (threadIdx.x >> 6)] = (double)v[j];
       }
-      if (threadIdx.x < 4) part[((int64_t)k * 4 + threadIdx.x) * nblocks + blockIdx.x] = red[threadIdx.x][0];
-      __syncthreads();
     }
     ++k;
+  }
+  if (part) {
+    // one barrier: the workgroup's partial of every end-point value is the
+    // sum of its wavefronts' in order
+    __syncthreads();
+    for (int t = threadIdx.x; t < 4 * k; t += kThreads) {
+      double a = wpart[t * (kThreads / 64)];
+#pragma unroll
+      for (int wv = 1; wv < kThreads / 64; ++wv) a += wpart[t * (kThreads / 64) + wv];
+      part[(int64_t)t * nslots + blockIdx.x] = a;
+    }
   }
   if (ok && gq) {
     if (fin) {
@@ -651,16 +698,35 @@ __global__ __launch_bounds__(kThreads) void k_back2d(const T* __restrict__ ctrl,
   }
 }
 
-// One workgroup per end-point value v = 4 k + j (k-th open loop; j: start x,
-// start y, end x, end y): fixed-order sum over the blocks, into its grad_ctrl
-// entry.
+// Fixed-order sums of the end-point partials part[value][nslots]: first
+// over chunks of kSumChunk workgroup partials (grid: chunks x values, into
+// tmp[value][chunk]), then over the chunks (one workgroup per value), into
+// the value's grad_ctrl entry.
+constexpr int kSumChunk = 2048;
+
+__global__ __launch_bounds__(kThreads) void k_back2d_chunks(const double* __restrict__ part, int64_t nslots,
+                                                           int64_t nchunks, double* __restrict__ tmp) {
+  __shared__ double red[kThreads];
+  const int64_t v = blockIdx.y, c0 = (int64_t)blockIdx.x * kSumChunk;
+  const double* p = part + v * nslots;
+  double a = 0.0;
+  for (int i = threadIdx.x; i < kSumChunk && c0 + i < nslots; i += kThreads) a += p[c0 + i];
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int h = kThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) tmp[v * nchunks + blockIdx.x] = red[0];
+}
+
 template <class T>
-__global__ __launch_bounds__(kThreads) void k_back2d_sum(const double* __restrict__ part, int64_t nblocks,
+__global__ __launch_bounds__(kThreads) void k_back2d_sum(const double* __restrict__ tmp, int64_t nchunks,
                                                          Loops2D L, T* __restrict__ gc) {
   __shared__ double red[kThreads];
-  const double* p = part + (int64_t)blockIdx.x * nblocks;
+  const double* p = tmp + (int64_t)blockIdx.x * nchunks;
   double sacc = 0.0;
-  for (int64_t b = threadIdx.x; b < nblocks; b += kThreads) sacc += p[b];
+  for (int64_t b = threadIdx.x; b < nchunks; b += kThreads) sacc += p[b];
   red[threadIdx.x] = sacc;
   __syncthreads();
   for (int h = kThreads / 2; h > 0; h >>= 1) {
@@ -698,17 +764,25 @@ hipError_t back2d(const T* ctrl, int64_t nseg, const Loops2D& L, int32_t kind, c
   for (int l = 0; l < L.n; ++l)
     if (!L.closed[l] && L.off[l + 1] > L.off[l]) ++nopen;
   const int64_t nblocks = (n + kThreads - 1) / kThreads;
-  double* part = nullptr;   // [4 nopen][nblocks] float64 partial sums
+  const int64_t nchunks = (nblocks + kSumChunk - 1) / kSumChunk;
+  double* part = nullptr;   // [4 nopen][nblocks] workgroup partials, then [4 nopen][nchunks]
   if (gc && nopen > 0) {
-    e = hipMallocAsync((void**)&part, (size_t)nopen * 4 * nblocks * sizeof(double), s);
+    e = hipMallocAsync((void**)&part, (size_t)nopen * 4 * (nblocks + nchunks) * sizeof(double), s);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_back2d<T>, dim3((unsigned)nblocks), dim3(kThreads), 0, s, ctrl, L, kind, x, y, nx, n, gw, gq,
-                     part, nblocks);
+  const size_t lds = part ? (size_t)nopen * 4 * (kThreads / 64) * sizeof(double) : 0;
+  hipLaunchKernelGGL(k_back2d<T>, dim3((unsigned)nblocks), dim3(kThreads), lds, s, ctrl, L, kind, x, y, nx, n, gw,
+                     gq, part, nblocks);
   e = hipGetLastError();
   if (e == hipSuccess && part) {
-    hipLaunchKernelGGL(k_back2d_sum<T>, dim3((unsigned)(4 * nopen)), dim3(kThreads), 0, s, part, nblocks, L, gc);
+    double* tmp = part + (size_t)nopen * 4 * nblocks;
+    hipLaunchKernelGGL(k_back2d_chunks, dim3((unsigned)nchunks, (unsigned)(4 * nopen)), dim3(kThreads), 0, s, part,
+                       nblocks, nchunks, tmp);
     e = hipGetLastError();
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_back2d_sum<T>, dim3((unsigned)(4 * nopen)), dim3(kThreads), 0, s, tmp, nchunks, L, gc);
+      e = hipGetLastError();
+    }
   }
   if (part) hipFreeAsync(part, s);
   return e;
