@@ -458,6 +458,16 @@ def run_others(torch, W, T, others, d3, args, dev):
     netc = torch.from_numpy(np.ascontiguousarray(MC.info["net"][None].astype(np.float32))).to(dev)
     ms_pc = T.ms(lambda: W.eval_3d_patches(dmc, netc, None, *qc, want_w=False), reps)
     ms_pw = T.ms(lambda: W.eval_3d_patches(dmc, netc, ctrlc, *qc), reps)
+    # the same queries once put in Morton order (results are the same values, permuted)
+    ms_ord = T.ms(lambda: W.spatial_order(*qc), reps)
+    oc = W.spatial_order(*qc).long()
+    qs = [t[oc].contiguous() for t in qc]
+    ms_cws = T.ms(lambda: W.eval_3d_curves(bvhc, ctrlc, *qs), reps)
+    ms_pws = T.ms(lambda: W.eval_3d_patches(dmc, netc, ctrlc, *qs), reps)
+    ms_tws = T.ms(lambda: W.eval_3d(bvhc, bndc, offc, *qs), reps)
+    res["3d_spatial_order_2p20"] = {
+        "order_ms": ms_ord, "curves_w_sorted_ms": ms_cws, "patches_w_sorted_ms": ms_pws,
+        "tessellated_w_sorted_ms_1M_triangles": ms_tws}
     res["3d_parametric_coons_2p20"] = {
         "patches": 1, "curves": 4, "crossings_ms": ms_pc, "w_ms": ms_pw,
         "tessellated_w_ms_1M_triangles": ms_tw, "queries_per_s": (1 << 20) / (ms_pw * 1e-3)}

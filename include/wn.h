@@ -264,6 +264,24 @@ wn_status wn_eval_3d_patches(const double dir[3], const float* nets, int64_t npa
                              float* w_out, int32_t* chi_out, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * wn_spatial_order -- a query order that groups nearby queries into the same
+ * wavefront (a utility, not a step of the method).  Every query kernel runs
+ * one query per lane, so a wavefront waits for its slowest lane; queries in
+ * this order walk similar BVH paths and similar panel refinements.
+ *  qx..nq     queries as in wn_eval_3d (nq <= INT32_MAX).
+ *  order_out  device [nq] int32 out: a permutation of 0..nq-1 sorting the
+ *             queries by the Morton code of their cell in a 1024^3 grid over
+ *             the finite queries' bounding box; ties keep index order, so
+ *             the result is deterministic; non-finite queries come last.
+ * Evaluating q[order] gives w[order] bit for bit: results depend on the
+ * query alone, not on its position.  Allocates about 13 bytes per query on
+ * the stream for the keys and the radix sort.
+ * Errors: INVALID_ARGUMENT, UNSUPPORTED, OUT_OF_MEMORY, HIP.
+ * ------------------------------------------------------------------------- */
+wn_status wn_spatial_order(const float* qx, const float* qy, const float* qz, int64_t nq,
+                           int32_t* order_out, void* stream);
+
+/* ---------------------------------------------------------------------------
  * wn_crossings_3d -- chi_d only (Eq. chi; the ray-casting step of Alg. 1) through the BVH.
  *  chi_out device [nq] int32 out.
  * ------------------------------------------------------------------------- */

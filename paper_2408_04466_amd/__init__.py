@@ -23,6 +23,7 @@ from .api import (  # noqa: F401
     eval_3d_curves,
     eval_3d_patches,
     eval_3d_grid,
+    spatial_order,
     winding_number,
     winding_number_2d,
     winding_number_curves,

@@ -45,6 +45,7 @@ SIGNATURES = {
     "wn_eval_3d_curves": (I32, [P, P, I64, P, P, P, I64, P, P, P, P]),
     "wn_eval_3d_patches": (I32, [PD, P, I64, P, I64, P, P, P, I64, P, P, P]),
     "wn_backward_curves": (I32, [P, I64, P, P, P, I64, P, P, P, P]),
+    "wn_spatial_order": (I32, [P, P, P, I64, P, P]),
     "wn_crossings_3d": (I32, [P, P, P, P, I64, P, P]),
     "wn_backward": (I32, [P, PI64, I32, P, P, P, I64, P, P, P, P]),
     "wn_eval_2d": (I32, [I32, P, I64, PI64, P, I32, I32, P, P, I64, I64, P, P, P]),

@@ -9,7 +9,7 @@ import torch
 
 from ._lib import CurveSet2D, check, lib, WN_MAX_LOOPS
 
-__all__ = ["boundary_loops", "BVH", "eval_3d", "eval_3d_boundary", "eval_3d_grid", "eval_3d_curves", "eval_3d_patches", "backward_curves",
+__all__ = ["boundary_loops", "BVH", "eval_3d", "eval_3d_boundary", "eval_3d_grid", "eval_3d_curves", "eval_3d_patches", "backward_curves", "spatial_order",
            "WindingNumberCurves", "winding_number_curves", "crossings_3d",
            "backward", "WindingNumber3D", "winding_number", "eval_2d", "eval_2d_batched", "Batch2D", "backward_2d",
            "WindingNumber2D", "winding_number_2d", "Batch"]
@@ -170,6 +170,18 @@ def eval_3d_patches(direction, nets: torch.Tensor, curves, qx, qy, qz, want_w: b
                                    _dev(chi, torch.int32, "chi") if chi is not None else None, _stream(stream)),
           "wn_eval_3d_patches")
     return w, chi
+
+
+def spatial_order(qx, qy, qz, stream=None) -> torch.Tensor:
+    """int32 permutation [nq] that sorts the queries by Morton code over their
+    bounding box (``wn_spatial_order``): deterministic, non-finite queries
+    last.  Evaluating the permuted queries gives the permuted results bit for
+    bit, and neighbouring lanes then take similar paths."""
+    px, py, pz, nq = _queries(qx, qy, qz)
+    order = torch.empty(nq, dtype=torch.int32, device=qx.device)
+    check(lib().wn_spatial_order(px, py, pz, nq, _dev(order, torch.int32, "order"), _stream(stream)),
+          "wn_spatial_order")
+    return order
 
 
 def eval_3d_grid(bvh: BVH, bnd_xyz: torch.Tensor, loop_off, gx, gy, gz, want_chi: bool = True, stream=None):

@@ -524,6 +524,18 @@ wn_status wn_eval_3d_patches(const double dir[3], const float* nets, int64_t npa
   return WN_OK;
 }
 
+wn_status wn_spatial_order(const float* qx, const float* qy, const float* qz, int64_t nq, int32_t* order_out,
+                           void* stream) {
+  g_err.clear();
+  wn_status st = check_queries(qx, qy, qz, nq);
+  if (st) return st;
+  if (nq > INT32_MAX) return fail(WN_ERR_UNSUPPORTED, "nq must be <= INT32_MAX");
+  if (nq == 0) return WN_OK;
+  if (!order_out) return fail(WN_ERR_INVALID_ARGUMENT, "order_out is NULL");
+  WN_HIP(wn::spatial_order(qx, qy, qz, nq, order_out, as_stream(stream)), "wn_spatial_order");
+  return WN_OK;
+}
+
 wn_status wn_eval_3d_grid(const wn_bvh* h, const float* bnd_xyz, const int64_t* loop_off, int32_t nloops,
                           const float* gx, const float* gy, const float* gz, int64_t nx, int64_t ny, int64_t nz,
                           float* w_out, int32_t* chi_out, void* stream) {

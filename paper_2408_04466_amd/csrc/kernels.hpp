@@ -75,6 +75,9 @@ hipError_t launch_cross3d(const CrossArgs& a, hipStream_t s);
 // 3D grid mode (grid3d.hip): fused forward per query, z fastest.
 hipError_t launch_patches3d(const Frame& F, const float* nets, int64_t np, const float* qx, const float* qy,
                             const float* qz, int64_t nq, int32_t* chi_out, hipStream_t s);
+// Morton-order permutation of the queries (order.hip).
+hipError_t spatial_order(const float* qx, const float* qy, const float* qz, int64_t n, int32_t* order,
+                         hipStream_t s);
 hipError_t backward_curves(const float* ctrl, int64_t nc, const float* qx, const float* qy, const float* qz,
                            int64_t nq, const float* gw, float* gq, float* gc, hipStream_t s);
 hipError_t launch_curves3d(const CrossArgs& c, const float* ctrl, int64_t nc, const int32_t* chi_in, float* w_out,

@@ -1,0 +1,125 @@
+// Spatial order of query points.
+//
+// The per-query kernels run one query per lane, so a wavefront is as fast as
+// its slowest lane: random query sets make neighbouring lanes walk different
+// BVH paths and different numbers of curve or patch panels.  Sorting the
+// queries once by their Morton codes (10 bits per axis over the queries'
+// bounding box) puts spatially close queries in the same wavefront.  The sort
+// is the stable LSD radix sort of the BVH build, so the order is
+// deterministic (ties by query index); non-finite queries go last.
+#include "bvh_build.hpp"
+#include "kernels.hpp"
+
+namespace wn {
+
+namespace {
+
+__device__ __forceinline__ unsigned ord_key(float f) {
+  const unsigned u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float ord_float(unsigned o) {
+  return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
+}
+
+// Bounding box of the finite queries as order-preserving integers:
+// box[2c] = min, box[2c + 1] = max of coordinate c.
+__global__ void k_qbox(const float* __restrict__ qx, const float* __restrict__ qy, const float* __restrict__ qz,
+                       int64_t n, unsigned* __restrict__ box) {
+  __shared__ unsigned red[6][256];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float p[3] = {0.f, 0.f, 0.f};
+  bool fin = false;
+  if (i < n) {
+    p[0] = qx[i];
+    p[1] = qy[i];
+    p[2] = qz[i];
+    fin = isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]);
+  }
+  for (int c = 0; c < 3; ++c) {
+    red[2 * c][threadIdx.x] = fin ? ord_key(p[c]) : 0xffffffffu;
+    red[2 * c + 1][threadIdx.x] = fin ? ord_key(p[c]) : 0u;
+  }
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+      for (int c = 0; c < 3; ++c) {
+        red[2 * c][threadIdx.x] = min(red[2 * c][threadIdx.x], red[2 * c][threadIdx.x + h]);
+        red[2 * c + 1][threadIdx.x] = max(red[2 * c + 1][threadIdx.x], red[2 * c + 1][threadIdx.x + h]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) {
+    if (threadIdx.x % 2 == 0) atomicMin(&box[threadIdx.x], red[threadIdx.x][0]);
+    else atomicMax(&box[threadIdx.x], red[threadIdx.x][0]);
+  }
+}
+
+__device__ __forceinline__ unsigned spread10(unsigned x) {
+  x &= 0x3ffu;
+  x = (x | (x << 16)) & 0x030000ffu;
+  x = (x | (x << 8)) & 0x0300f00fu;
+  x = (x | (x << 4)) & 0x030c30c3u;
+  x = (x | (x << 2)) & 0x09249249u;
+  return x;
+}
+
+__global__ void k_qmorton(const float* __restrict__ qx, const float* __restrict__ qy, const float* __restrict__ qz,
+                          int64_t n, const unsigned* __restrict__ box, unsigned* __restrict__ keys,
+                          int32_t* __restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float p[3] = {qx[i], qy[i], qz[i]};
+  vals[i] = (int32_t)i;
+  if (!(isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]))) {
+    keys[i] = 0xffffffffu;
+    return;
+  }
+  unsigned code = 0;
+  for (int c = 0; c < 3; ++c) {
+    const float lo = ord_float(box[2 * c]), hi = ord_float(box[2 * c + 1]);
+    const float ext = hi - lo;
+    const float t = ext > 0.f ? (p[c] - lo) / ext : 0.f;
+    const unsigned cell = (unsigned)fminf(fmaxf(t * 1024.f, 0.f), 1023.f);
+    code |= spread10(cell) << c;
+  }
+  keys[i] = code;
+}
+
+}  // namespace
+
+hipError_t spatial_order(const float* qx, const float* qy, const float* qz, int64_t n, int32_t* order,
+                         hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t b_box = up(6 * sizeof(unsigned));
+  const size_t b_keys = up((size_t)n * sizeof(unsigned));
+  const size_t b_tmp = up(radix_sort_tmp_bytes(n));
+  unsigned char* ws = nullptr;
+  hipError_t e = hipMallocAsync((void**)&ws, b_box + 3 * b_keys + b_tmp, s);
+  if (e != hipSuccess) return e;
+  unsigned* box = (unsigned*)ws;
+  unsigned* keys = (unsigned*)(ws + b_box);
+  unsigned* keys2 = (unsigned*)(ws + b_box + b_keys);
+  int32_t* vals2 = (int32_t*)(ws + b_box + 2 * b_keys);
+  void* tmp = ws + b_box + 3 * b_keys;
+  for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+    e = fill_u32(box + 2 * c, 1, 0xffffffffu, s);
+    if (e == hipSuccess) e = fill_u32(box + 2 * c + 1, 1, 0u, s);
+  }
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_qbox, dim3(blocks), dim3(256), 0, s, qx, qy, qz, n, box);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_qmorton, dim3(blocks), dim3(256), 0, s, qx, qy, qz, n, box, keys, order);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = radix_sort_pairs(keys, order, keys2, vals2, n, tmp, s);
+  const hipError_t e2 = hipFreeAsync(ws, s);
+  return e != hipSuccess ? e : e2;
+}
+
+}  // namespace wn

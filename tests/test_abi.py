@@ -143,6 +143,12 @@ def test_validation_happens_on_the_host(W):
     assert L.wn_eval_3d_patches(d1, fake, 1, None, 0, fake, fake, fake, 4, None, None, None) == 1
     assert L.wn_eval_3d_patches(d1, fake, 1, None, 0, fake, fake, fake, 0, None, None, None) == 0
     assert L.wn_eval_3d_curves(None, fake, 1, fake, fake, fake, 4, None, fake, None, None) == 1
+    # spatial order: NULL output, too many queries, negative and empty counts
+    assert L.wn_spatial_order(fake, fake, fake, 4, None, None) == 1
+    assert "order_out" in _err(W)
+    assert L.wn_spatial_order(fake, fake, fake, 1 << 31, fake, None) == 2
+    assert L.wn_spatial_order(fake, fake, fake, -1, fake, None) == 1
+    assert L.wn_spatial_order(None, None, None, 0, None, None) == 0
 
 
 def test_missing_library_fails_loudly(tmp_path):
