@@ -476,6 +476,33 @@ def run_others(torch, W, T, others, d3, args, dev):
         "polyline_512_boundary_ms": ms_pb, "curves_backward_ms": ms_cbw,
         "queries_per_s": (1 << 20) / (ms_cw * 1e-3)}
     del bvhc
+    # --- 64 parametric surfaces (1 patch + 4 boundary curves each, own
+    # direction, 2^14 queries each): one batched launch vs 64 single calls
+    ps_nets, ps_curves, ps_q, ps_desc = [], [], [], []
+    for k in range(64):
+        Mk = synth.coons_surface(1000 + k, 300, 16)
+        dk = synth.random_direction(2000 + k)
+        ps_nets.append(Mk.info["net"][None])
+        ps_curves.append(Mk.info["curves"])
+        ps_q.append(synth.box_queries(Mk.V, 1 << 14, 3000 + k))
+        ps_desc.append((1, 4, 1 << 14, dk))
+    pb = W.PatchBatch(ps_desc)
+    pnets = torch.from_numpy(np.ascontiguousarray(np.concatenate(ps_nets).astype(np.float32))).to(dev)
+    pcurv = torch.from_numpy(np.ascontiguousarray(np.concatenate(ps_curves).astype(np.float32))).to(dev)
+    pq = np.concatenate(ps_q).astype(np.float32)
+    pqs = [torch.from_numpy(np.ascontiguousarray(pq[:, k])).to(dev) for k in range(3)]
+    ms_pbat = T.ms(lambda: pb.eval(pnets, pcurv, *pqs), reps)
+    views = [(pnets[k:k + 1], pcurv[4 * k:4 * k + 4], [t[k << 14:(k + 1) << 14] for t in pqs], ps_desc[k][3])
+             for k in range(64)]
+
+    def loop_ps():
+        for n_k, c_k, q_k, d_k in views:
+            W.eval_3d_patches(d_k, n_k, c_k, *q_k)
+
+    ms_ploop = T.ms(loop_ps, reps)
+    res["3d_parametric_batched_64x2p14"] = {
+        "surfaces": 64, "queries": 1 << 20, "batched_ms": ms_pbat, "loop_of_single_calls_ms": ms_ploop,
+        "queries_per_s": (1 << 20) / (ms_pbat * 1e-3)}
     # --- the 2D experiment's shape: 1000 random cubics, each on its own 250^2
     # grid, float64; one batched launch vs a loop of single-set calls
     E1 = synth.random_cubics(seed=5, n=1000, res=250, dtype=np.float64)

@@ -264,6 +264,53 @@ wn_status wn_eval_3d_patches(const double dir[3], const float* nets, int64_t npa
                              float* w_out, int32_t* chi_out, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Batched parametric surfaces: many surfaces, each made of bicubic Bezier
+ * patches with cubic Bezier boundary curves, its own ray direction and its
+ * own queries, evaluated in one launch (w = chi_d + Theta/2pi as in
+ * wn_eval_3d_patches; Sec. 4, parametric surfaces).
+ *
+ * One surface of such a batch: its patch, curve and query counts and its
+ * direction.  The surfaces' patches are consecutive in the nets array, their
+ * curves in the curves array and their queries in qx/qy/qz and the outputs,
+ * in surface order.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int64_t npatch;
+  int64_t ncurves;
+  int64_t nq;
+  double dir[3];
+} wn_patch_surface;
+
+typedef struct wn_patch_batch wn_patch_batch;
+
+/* ---------------------------------------------------------------------------
+ * wn_patch_batch_create -- copy the surfaces' frames and a table of which
+ * surface each workgroup of 256 queries belongs to to the device.
+ * Synchronises `stream`.  Errors: INVALID_ARGUMENT (naming the surface:
+ * negative count, non-finite or zero direction), UNSUPPORTED (more than
+ * 2^31 - 1 workgroups, patches or curves beyond 32-bit indexing),
+ * OUT_OF_MEMORY, HIP.
+ * ------------------------------------------------------------------------- */
+wn_status wn_patch_batch_create(const wn_patch_surface* surfs, int32_t nsurf, void* stream,
+                                wn_patch_batch** out);
+wn_status wn_patch_batch_free(wn_patch_batch* batch);
+
+/* ---------------------------------------------------------------------------
+ * wn_eval_3d_patches_batched -- wn_eval_3d_patches for every surface of the
+ * batch in one launch.
+ *  nets       device [sum npatch][4][4][3] float32 (or NULL if none).
+ *  curves     device [sum ncurves][4][3] float32 (or NULL if none).
+ *  qx..qz     device [sum nq] float32 queries.
+ *  w_out      device [sum nq] float32 out, or NULL (crossings only).
+ *  chi_out    device [sum nq] int32 out, or NULL; not both NULL.
+ * Each result equals, bit for bit, that of wn_eval_3d_patches called for
+ * the surface alone.  Allocates nothing.  Errors: INVALID_ARGUMENT, HIP.
+ * ------------------------------------------------------------------------- */
+wn_status wn_eval_3d_patches_batched(const wn_patch_batch* batch, const float* nets, const float* curves,
+                                     const float* qx, const float* qy, const float* qz,
+                                     float* w_out, int32_t* chi_out, void* stream);
+
+/* ---------------------------------------------------------------------------
  * wn_spatial_order -- a query order that groups nearby queries into the same
  * wavefront (a utility, not a step of the method).  Every query kernel runs
  * one query per lane, so a wavefront waits for its slowest lane; queries in

@@ -8,6 +8,7 @@ from .api import (  # noqa: F401
     BVH,
     Batch,
     Batch2D,
+    PatchBatch,
     WindingNumber2D,
     WindingNumber3D,
     WindingNumberCurves,

@@ -46,6 +46,9 @@ SIGNATURES = {
     "wn_eval_3d_patches": (I32, [PD, P, I64, P, I64, P, P, P, I64, P, P, P]),
     "wn_backward_curves": (I32, [P, I64, P, P, P, I64, P, P, P, P]),
     "wn_spatial_order": (I32, [P, P, P, I64, P, P]),
+    "wn_patch_batch_create": (I32, [P, I32, P, P]),
+    "wn_patch_batch_free": (I32, [P]),
+    "wn_eval_3d_patches_batched": (I32, [P, P, P, P, P, P, P, P, P]),
     "wn_crossings_3d": (I32, [P, P, P, P, I64, P, P]),
     "wn_backward": (I32, [P, PI64, I32, P, P, P, I64, P, P, P, P]),
     "wn_eval_2d": (I32, [I32, P, I64, PI64, P, I32, I32, P, P, I64, I64, P, P, P]),
@@ -71,6 +74,11 @@ class CurveSet2D(C.Structure):
     """Mirror of ``wn_curveset_2d`` in include/wn.h."""
     _fields_ = [("nseg", I64), ("loop_off", PI64), ("loop_closed", P), ("nloops", I32),
                 ("nx", I64), ("ny", I64)]
+
+
+class PatchSurface(C.Structure):
+    """Mirror of ``wn_patch_surface`` in include/wn.h."""
+    _fields_ = [("npatch", I64), ("ncurves", I64), ("nq", I64), ("dir", C.c_double * 3)]
 
 
 def lib():

@@ -7,9 +7,9 @@ import ctypes as C
 import numpy as np
 import torch
 
-from ._lib import CurveSet2D, check, lib, WN_MAX_LOOPS
+from ._lib import CurveSet2D, PatchSurface, check, lib, WN_MAX_LOOPS
 
-__all__ = ["boundary_loops", "BVH", "eval_3d", "eval_3d_boundary", "eval_3d_grid", "eval_3d_curves", "eval_3d_patches", "backward_curves", "spatial_order",
+__all__ = ["boundary_loops", "BVH", "eval_3d", "eval_3d_boundary", "eval_3d_grid", "eval_3d_curves", "eval_3d_patches", "backward_curves", "spatial_order", "PatchBatch",
            "WindingNumberCurves", "winding_number_curves", "crossings_3d",
            "backward", "WindingNumber3D", "winding_number", "eval_2d", "eval_2d_batched", "Batch2D", "backward_2d",
            "WindingNumber2D", "winding_number_2d", "Batch"]
@@ -380,6 +380,65 @@ class Batch2D:
         for ny, nx in self.shapes:
             views.append(flat[o:o + ny * nx].view(ny, nx))
             o += ny * nx
+        return views
+
+
+class PatchBatch:
+    """Many parametric surfaces (bicubic patches + boundary curves), each with
+    its own ray direction and queries, evaluated in one launch.
+
+    ``surfaces`` is a sequence of ``(npatch, ncurves, nq, direction)``.
+    ``eval`` takes every surface's patch nets concatenated (``nets``
+    [sum npatch, 4, 4, 3]), their curves concatenated (``curves``
+    [sum ncurves, 4, 3]) and their queries concatenated; each surface's
+    results equal eval_3d_patches on that surface alone, bit for bit."""
+
+    def __init__(self, surfaces, stream=None):
+        self._h = None
+        n = len(surfaces)
+        desc = (PatchSurface * max(n, 1))()
+        self.counts = []
+        for k, (npatch, ncurves, nq, direction) in enumerate(surfaces):
+            d = desc[k]
+            d.npatch, d.ncurves, d.nq = int(npatch), int(ncurves), int(nq)
+            for j, v in enumerate(direction):
+                d.dir[j] = float(v)
+            self.counts.append((int(npatch), int(ncurves), int(nq)))
+        self.npatch = sum(c[0] for c in self.counts)
+        self.ncurves = sum(c[1] for c in self.counts)
+        self.nq = sum(c[2] for c in self.counts)
+        h = C.c_void_p()
+        check(lib().wn_patch_batch_create(desc if n else None, n, _stream(stream), C.byref(h)),
+              "wn_patch_batch_create")
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().wn_patch_batch_free(self._h)
+            self._h = None
+
+    def eval(self, nets, curves, qx, qy, qz, want_w: bool = True, want_chi: bool = True, stream=None):
+        """(w or None, chi or None) as flat [sum nq] tensors in surface order."""
+        if not (want_w or want_chi):
+            raise ValueError("nothing requested")
+        pn = _dev(nets, torch.float32, "nets", (self.npatch, 4, 4, 3)) if self.npatch else None
+        pc = _dev(curves, torch.float32, "curves", (self.ncurves, 4, 3)) if self.ncurves else None
+        n = self.nq
+        px, py, pz = (_dev(t, torch.float32, name, (n,)) for t, name in ((qx, "qx"), (qy, "qy"), (qz, "qz")))
+        w = torch.empty(n, dtype=torch.float32, device=qx.device) if want_w else None
+        chi = torch.empty(n, dtype=torch.int32, device=qx.device) if want_chi else None
+        check(lib().wn_eval_3d_patches_batched(self._h, pn, pc, px, py, pz,
+                                               _dev(w, torch.float32, "w") if w is not None else None,
+                                               _dev(chi, torch.int32, "chi") if chi is not None else None,
+                                               _stream(stream)), "wn_eval_3d_patches_batched")
+        return w, chi
+
+    def split(self, flat: torch.Tensor):
+        """Per-surface views of a flat output."""
+        views, o = [], 0
+        for _, _, nq in self.counts:
+            views.append(flat[o:o + nq])
+            o += nq
         return views
 
 

@@ -524,6 +524,71 @@ wn_status wn_eval_3d_patches(const double dir[3], const float* nets, int64_t npa
   return WN_OK;
 }
 
+struct wn_patch_batch {
+  wn::PBatch b;
+};
+
+wn_status wn_patch_batch_create(const wn_patch_surface* surfs, int32_t nsurf, void* stream, wn_patch_batch** out) {
+  g_err.clear();
+  if (!out) return fail(WN_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if (nsurf < 0) return fail(WN_ERR_INVALID_ARGUMENT, "nsurf must be >= 0");
+  if (nsurf > 0 && !surfs) return fail(WN_ERR_INVALID_ARGUMENT, "surfs is NULL");
+  std::vector<wn::PSurf> d((size_t)nsurf);
+  int64_t patches = 0, curves = 0, blocks = 0;
+  for (int32_t k = 0; k < nsurf; ++k) {
+    const wn_patch_surface& c = surfs[k];
+    if (c.npatch < 0 || c.ncurves < 0 || c.nq < 0) return fail(WN_ERR_INVALID_ARGUMENT, "surface %d: negative count", k);
+    double dn[3], R[9];
+    if (!make_rotation(c.dir, dn, R))
+      return fail(WN_ERR_INVALID_ARGUMENT, "surface %d: dir must be finite and nonzero", k);
+    if (c.npatch > INT32_MAX / 48 || c.ncurves > INT32_MAX / 12)
+      return fail(WN_ERR_UNSUPPORTED, "surface %d: too many patches or curves", k);
+    patches += c.npatch;
+    curves += c.ncurves;
+    blocks += (c.nq + 255) / 256;
+    if (patches > INT64_MAX / 256 || curves > INT64_MAX / 256 || blocks > INT32_MAX)
+      return fail(WN_ERR_UNSUPPORTED, "batch too large for one launch (split it)");
+    wn::PSurf& p = d[(size_t)k];
+    for (int j = 0; j < 9; ++j) p.F.r[j] = R[j];
+    for (int j = 0; j < 3; ++j) p.F.c[j] = 0.0;
+    p.nq = c.nq;
+    p.npatch = (int32_t)c.npatch;
+    p.ncurve = (int32_t)c.ncurves;
+  }
+  wn_patch_batch* h = new (std::nothrow) wn_patch_batch();
+  if (!h) return fail(WN_ERR_OUT_OF_MEMORY, "host allocation");
+  const hipError_t e = wn::pbatch_create(d.data(), nsurf, as_stream(stream), &h->b);
+  if (e != hipSuccess) {
+    delete h;
+    return hip_fail(e, "wn_patch_batch_create");
+  }
+  *out = h;
+  return WN_OK;
+}
+
+wn_status wn_patch_batch_free(wn_patch_batch* batch) {
+  g_err.clear();
+  delete batch;
+  return WN_OK;
+}
+
+wn_status wn_eval_3d_patches_batched(const wn_patch_batch* batch, const float* nets, const float* curves,
+                                     const float* qx, const float* qy, const float* qz, float* w_out,
+                                     int32_t* chi_out, void* stream) {
+  g_err.clear();
+  if (!batch) return fail(WN_ERR_INVALID_ARGUMENT, "batch is NULL");
+  const wn::PBatch& b = batch->b;
+  if (b.nq == 0) return WN_OK;
+  if (b.npatch > 0 && !nets) return fail(WN_ERR_INVALID_ARGUMENT, "nets is NULL");
+  if (b.ncurve > 0 && w_out && !curves) return fail(WN_ERR_INVALID_ARGUMENT, "curves is NULL");
+  if (!qx || !qy || !qz) return fail(WN_ERR_INVALID_ARGUMENT, "NULL query pointer");
+  if (!w_out && !chi_out) return fail(WN_ERR_INVALID_ARGUMENT, "w_out and chi_out are both NULL");
+  WN_HIP(wn::eval_pbatch(b, nets, curves, qx, qy, qz, w_out, chi_out, as_stream(stream)),
+         "wn_eval_3d_patches_batched");
+  return WN_OK;
+}
+
 wn_status wn_spatial_order(const float* qx, const float* qy, const float* qz, int64_t nq, int32_t* order_out,
                            void* stream) {
   g_err.clear();

@@ -75,6 +75,27 @@ hipError_t launch_cross3d(const CrossArgs& a, hipStream_t s);
 // 3D grid mode (grid3d.hip): fused forward per query, z fastest.
 hipError_t launch_patches3d(const Frame& F, const float* nets, int64_t np, const float* qx, const float* qy,
                             const float* qz, int64_t nq, int32_t* chi_out, hipStream_t s);
+// Parametric surfaces (bicubic patches + boundary curves) with their own
+// directions and query ranges, evaluated in one launch (psurf.hip).  The
+// surfaces' patches, curves and queries are consecutive in the arrays.
+struct PSurf {
+  Frame F;                          // frame of the surface's direction, centre 0
+  int64_t patch0, curve0, q0, blk0; // first patch, curve, query and workgroup
+  int64_t nq;
+  int32_t npatch, ncurve;
+};
+struct PBatch {
+  int32_t nsurf = 0;
+  int64_t npatch = 0, ncurve = 0, nq = 0, nblocks = 0;
+  unsigned char* ws = nullptr;      // the one allocation: descriptors | block -> surface
+  PSurf* desc = nullptr;
+  int32_t* blk_surf = nullptr;
+  ~PBatch();
+};
+// surfs: F, nq, npatch, ncurve filled in; the offsets are computed here.
+hipError_t pbatch_create(const PSurf* surfs, int32_t n, hipStream_t s, PBatch* b);
+hipError_t eval_pbatch(const PBatch& b, const float* nets, const float* curves, const float* qx, const float* qy,
+                       const float* qz, float* w_out, int32_t* chi_out, hipStream_t s);
 // Morton-order permutation of the queries (order.hip).
 hipError_t spatial_order(const float* qx, const float* qy, const float* qz, int64_t n, int32_t* order,
                          hipStream_t s);

@@ -143,6 +143,33 @@ def test_validation_happens_on_the_host(W):
     assert L.wn_eval_3d_patches(d1, fake, 1, None, 0, fake, fake, fake, 4, None, None, None) == 1
     assert L.wn_eval_3d_patches(d1, fake, 1, None, 0, fake, fake, fake, 0, None, None, None) == 0
     assert L.wn_eval_3d_curves(None, fake, 1, fake, fake, fake, 4, None, fake, None, None) == 1
+    # batched parametric surfaces: the failing surface is named; NULL batch;
+    # nothing requested
+    from paper_2408_04466_amd._lib import PatchSurface
+    ps = (PatchSurface * 2)()
+    ps[0].npatch, ps[0].ncurves, ps[0].nq = 1, 4, 10
+    ps[0].dir[2] = 1.0
+    ps[1].npatch, ps[1].ncurves, ps[1].nq = 1, -4, 10
+    ps[1].dir[2] = 1.0
+    h = P()
+    assert L.wn_patch_batch_create(ps, 2, None, C.byref(h)) == 1 and not h.value
+    assert "surface 1" in _err(W)
+    ps[1].ncurves = 4
+    ps[1].dir[2] = 0.0
+    assert L.wn_patch_batch_create(ps, 2, None, C.byref(h)) == 1
+    assert "surface 1" in _err(W) and "dir" in _err(W)
+    ps[1].dir[2] = 1.0
+    ps[1].npatch = 1 << 30
+    assert L.wn_patch_batch_create(ps, 2, None, C.byref(h)) == 2
+    ps[1].npatch = 1
+    ps[1].nq = 1 << 40
+    assert L.wn_patch_batch_create(ps, 2, None, C.byref(h)) == 2
+    assert L.wn_patch_batch_create(ps, -1, None, C.byref(h)) == 1
+    assert L.wn_patch_batch_create(None, 1, None, C.byref(h)) == 1
+    assert L.wn_patch_batch_create(ps, 0, None, None) == 1
+    assert L.wn_eval_3d_patches_batched(None, fake, fake, fake, fake, fake, fake, None, None) == 1
+    assert "batch" in _err(W)
+    assert L.wn_patch_batch_free(None) == 0
     # spatial order: NULL output, too many queries, negative and empty counts
     assert L.wn_spatial_order(fake, fake, fake, 4, None, None) == 1
     assert "order_out" in _err(W)
