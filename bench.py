@@ -243,6 +243,14 @@ def main():
     torch.cuda.synchronize()
     ms_step = e0.elapsed_time(e1) / args.steps
     ms_step_plain = T.ms(step_plain, args.steps, args.warmup)
+    # per-step spread (events around each step; reported beside the value above)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for ea, eb in evs:
+        ea.record(stream)
+        step_batched()
+        eb.record(stream)
+    torch.cuda.synchronize()
+    per_step = sorted(ea.elapsed_time(eb) for ea, eb in evs)
 
     # per-kernel timings on the same stream (HIP events around K launches)
     reps = max(args.steps, 10)
@@ -305,6 +313,8 @@ def main():
                           "plain_fwd_qps": nq / (ms_fwd * 1e-3),
                           "ratio_fwd_bwd": ms_step_plain / ms_step},
             **extra.get("c4", {})},
+        "step_ms": {"mean": ms_step, "median": per_step[len(per_step) // 2], "min": per_step[0]},
+        "device": {**W.device_info(), "name": torch.cuda.get_device_name(dev)},
         "kernels_ms": {"crossings": ms_cross, "boundary": ms_bnd, "plain_forward": ms_fwd,
                        "plain_backward": ms_bwd, "batched_forward": ms_fwd_b, "batched_backward": ms_bwd_b,
                        "bvh_build": build_ms, "batch_create": batch_ms},

@@ -311,6 +311,25 @@ wn_status wn_eval_3d_patches_batched(const wn_patch_batch* batch, const float* n
                                      float* w_out, int32_t* chi_out, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * wn_diagnose -- device counters over a call's outputs (not a step of the
+ * method): counts_out[0] = queries with a non-finite coordinate,
+ * counts_out[1] = finite queries whose chi is WN_CHI_INVALID (a traversal
+ * that found the tree malformed; 0 for every tree wn_build_bvh builds).
+ *  qx..qz, nq  the queries of the call; chi the chi_out it wrote.
+ *  counts_out  device [2] int64 out (overwritten, not accumulated).
+ * Exact integer counts (deterministic).  Errors: INVALID_ARGUMENT, HIP.
+ * ------------------------------------------------------------------------- */
+wn_status wn_diagnose(const float* qx, const float* qy, const float* qz, const int32_t* chi, int64_t nq,
+                      int64_t* counts_out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * wn_device_info -- compute units and peak shader clock (kHz) of the
+ * current HIP device, as the runtime reports them.
+ * Errors: INVALID_ARGUMENT, HIP.
+ * ------------------------------------------------------------------------- */
+wn_status wn_device_info(int32_t* cu_count, int32_t* clock_khz);
+
+/* ---------------------------------------------------------------------------
  * wn_spatial_order -- a query order that groups nearby queries into the same
  * wavefront (a utility, not a step of the method).  Every query kernel runs
  * one query per lane, so a wavefront waits for its slowest lane; queries in

@@ -24,6 +24,8 @@ from .api import (  # noqa: F401
     eval_3d_curves,
     eval_3d_patches,
     eval_3d_grid,
+    diagnose,
+    device_info,
     spatial_order,
     winding_number,
     winding_number_2d,

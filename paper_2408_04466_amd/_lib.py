@@ -46,6 +46,8 @@ SIGNATURES = {
     "wn_eval_3d_patches": (I32, [PD, P, I64, P, I64, P, P, P, I64, P, P, P]),
     "wn_backward_curves": (I32, [P, I64, P, P, P, I64, P, P, P, P]),
     "wn_spatial_order": (I32, [P, P, P, I64, P, P]),
+    "wn_diagnose": (I32, [P, P, P, P, I64, P, P]),
+    "wn_device_info": (I32, [P, P]),
     "wn_patch_batch_create": (I32, [P, I32, P, P]),
     "wn_patch_batch_free": (I32, [P]),
     "wn_eval_3d_patches_batched": (I32, [P, P, P, P, P, P, P, P, P]),

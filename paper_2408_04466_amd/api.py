@@ -9,7 +9,7 @@ import torch
 
 from ._lib import CurveSet2D, PatchSurface, check, lib, WN_MAX_LOOPS
 
-__all__ = ["boundary_loops", "BVH", "eval_3d", "eval_3d_boundary", "eval_3d_grid", "eval_3d_curves", "eval_3d_patches", "backward_curves", "spatial_order", "PatchBatch",
+__all__ = ["boundary_loops", "BVH", "eval_3d", "eval_3d_boundary", "eval_3d_grid", "eval_3d_curves", "eval_3d_patches", "backward_curves", "spatial_order", "PatchBatch", "diagnose", "device_info",
            "WindingNumberCurves", "winding_number_curves", "crossings_3d",
            "backward", "WindingNumber3D", "winding_number", "eval_2d", "eval_2d_batched", "Batch2D", "backward_2d",
            "WindingNumber2D", "winding_number_2d", "Batch"]
@@ -170,6 +170,25 @@ def eval_3d_patches(direction, nets: torch.Tensor, curves, qx, qy, qz, want_w: b
                                    _dev(chi, torch.int32, "chi") if chi is not None else None, _stream(stream)),
           "wn_eval_3d_patches")
     return w, chi
+
+
+def diagnose(qx, qy, qz, chi, stream=None) -> torch.Tensor:
+    """int64 device tensor [2]: queries with a non-finite coordinate, and
+    finite queries whose chi is WN_CHI_INVALID (``wn_diagnose``)."""
+    px, py, pz, nq = _queries(qx, qy, qz)
+    pc = _dev(chi, torch.int32, "chi", (nq,))
+    out = torch.empty(2, dtype=torch.int64, device=qx.device)
+    check(lib().wn_diagnose(px, py, pz, pc, nq, _dev(out, torch.int64, "counts"), _stream(stream)),
+          "wn_diagnose")
+    return out
+
+
+def device_info() -> dict:
+    """Compute units and peak shader clock of the current device, as the HIP
+    runtime reports them."""
+    cus, clk = C.c_int32(), C.c_int32()
+    check(lib().wn_device_info(C.byref(cus), C.byref(clk)), "wn_device_info")
+    return {"compute_units": cus.value, "clock_mhz": clk.value / 1000.0}
 
 
 def spatial_order(qx, qy, qz, stream=None) -> torch.Tensor:

@@ -589,6 +589,29 @@ wn_status wn_eval_3d_patches_batched(const wn_patch_batch* batch, const float* n
   return WN_OK;
 }
 
+wn_status wn_diagnose(const float* qx, const float* qy, const float* qz, const int32_t* chi, int64_t nq,
+                      int64_t* counts_out, void* stream) {
+  g_err.clear();
+  wn_status st = check_queries(qx, qy, qz, nq);
+  if (st) return st;
+  if (!counts_out) return fail(WN_ERR_INVALID_ARGUMENT, "counts_out is NULL");
+  if (nq > 0 && !chi) return fail(WN_ERR_INVALID_ARGUMENT, "chi is NULL");
+  WN_HIP(wn::diagnose(qx, qy, qz, chi, nq, counts_out, as_stream(stream)), "wn_diagnose");
+  return WN_OK;
+}
+
+wn_status wn_device_info(int32_t* cu_count, int32_t* clock_khz) {
+  g_err.clear();
+  if (!cu_count || !clock_khz) return fail(WN_ERR_INVALID_ARGUMENT, "NULL output");
+  int dev = 0, cus = 0, clk = 0;
+  WN_HIP(hipGetDevice(&dev), "hipGetDevice");
+  WN_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
+  WN_HIP(hipDeviceGetAttribute(&clk, hipDeviceAttributeClockRate, dev), "hipDeviceGetAttribute");
+  *cu_count = cus;
+  *clock_khz = clk;
+  return WN_OK;
+}
+
 wn_status wn_spatial_order(const float* qx, const float* qy, const float* qz, int64_t nq, int32_t* order_out,
                            void* stream) {
   g_err.clear();

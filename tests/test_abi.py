@@ -170,6 +170,12 @@ def test_validation_happens_on_the_host(W):
     assert L.wn_eval_3d_patches_batched(None, fake, fake, fake, fake, fake, fake, None, None) == 1
     assert "batch" in _err(W)
     assert L.wn_patch_batch_free(None) == 0
+    # diagnostics: NULL counts, NULL chi with queries, negative count
+    assert L.wn_diagnose(fake, fake, fake, fake, 4, None, None) == 1
+    assert "counts_out" in _err(W)
+    assert L.wn_diagnose(fake, fake, fake, None, 4, fake, None) == 1
+    assert L.wn_diagnose(fake, fake, fake, fake, -1, fake, None) == 1
+    assert L.wn_device_info(None, None) == 1
     # spatial order: NULL output, too many queries, negative and empty counts
     assert L.wn_spatial_order(fake, fake, fake, 4, None, None) == 1
     assert "order_out" in _err(W)
