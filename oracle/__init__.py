@@ -21,6 +21,15 @@ Contents
                piecewise constant, so it contributes nothing).
 - ``grad2d`` : the same for 2D loops: only the open loops' end points (and the
                query) carry a gradient.
+- ``curves3d``   : the boundary term along cubic Bezier boundary curves
+               (Sec. 4, region areas from boundary integrals), adaptive
+               Gauss-Legendre on the form whose edge integral is the polyline
+               edge term.
+- ``patches3d``  : signed ray crossings of bicubic Bezier patches (Eq. chi;
+               Sec. 4 parametric surfaces) by subdivision, convex-hull pruning
+               and Newton, with duplicate roots merged.
+- ``gradcurves`` : derivatives of the curve boundary term with respect to
+               the query and the control points (Biot-Savart integrals).
 
 Every floating-point computation is float64 on inputs promoted exactly from
 the kernel's float32 arrays.  Parity status of each function is stated in its
