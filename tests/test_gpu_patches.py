@@ -135,6 +135,34 @@ def test_many_patches_sum():
     assert np.array_equal(chi.cpu().numpy()[ok], r.chi[ok]) and np.count_nonzero(r.chi[ok]) > 10
 
 
+def test_many_chunks():
+    """80 patches (three LDS chunks of staged patches): the counts equal the
+    oracle's, and bit for bit those of the batched kernel."""
+    nets = []
+    for j in range(80):
+        M = synth.coons_surface(500 + j, 300, 16)
+        nets.append(M.info["net"] + np.array([1.2 * (j % 10), 1.2 * (j // 10), 0.0]))
+    nets = np.array(nets).astype(np.float32).astype(np.float64)
+    d = synth.random_direction(501)
+    lo, hi = nets.reshape(-1, 3).min(0), nets.reshape(-1, 3).max(0)
+    P = (lo + (hi - lo) * synth.rng(502).uniform(0, 1, (20000, 3))).astype(np.float32).astype(np.float64)
+    P[11] = np.nan
+    q = _q(P)
+    _, chi = W.eval_3d_patches(d, _dev(nets), None, *q, want_w=False)
+    b = W.PatchBatch([(80, 0, len(P), d)])
+    _, chi_b = b.eval(_dev(nets), None, *q, want_w=False)
+    torch.cuda.synchronize()
+    chi, chi_b = chi.cpu().numpy(), chi_b.cpu().numpy()
+    assert np.array_equal(chi, chi_b)
+    assert chi[11] == W.WN_CHI_INVALID
+    sample = np.arange(300)
+    sample = sample[sample != 11]
+    r = OP.patch_crossings(nets, P[sample], d)
+    ok = ~r.degenerate
+    assert ok.mean() > 0.95 and np.count_nonzero(r.chi[ok]) > 60
+    assert np.array_equal(chi[sample][ok], r.chi[ok])
+
+
 def test_edge_cases():
     M = synth.coons_surface(31, 300, 16)
     net = _dev(M.info["net"][None])
