@@ -178,7 +178,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
       bnd::Lane<1> s;
       rotate(D.F, px, py, pz, s.Xp[0], s.Yp[0], s.Zp[0]);
       turns_init(s.T[0]);
-      const int chi = (ok && fin) ? traverse<kShortStack>(ca, s.Xp[0], s.Yp[0], s.Zp[0]) : 0;
+      const int chi = (ok && fin) ? traverse<kShortStack, true>(ca, s.Xp[0], s.Yp[0], s.Zp[0]) : 0;
       bnd::boundary_walk(s, stage, D.nb, L, sv, staged);
       if (ok) {
         const bool valid = fin && chi != WN_CHI_INVALID;
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_cross(FwdArgs a) {
       if (isfinite(px) && isfinite(py) && isfinite(pz)) {
         double X, Y, Z;
         rotate(D.F, px, py, pz, X, Y, Z);
-        chi = traverse<kShortStack>(ca, X, Y, Z);
+        chi = traverse<kShortStack, true>(ca, X, Y, Z);
       }
       a.chi_buf[q] = chi;
     }

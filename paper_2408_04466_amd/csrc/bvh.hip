@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void k_cross3d(CrossArgs a) {
   }
   double Xp, Yp, Zp;
   rotate(a.F, px, py, pz, Xp, Yp, Zp);
-  a.chi[q] = traverse<S>(a, Xp, Yp, Zp);
+  a.chi[q] = traverse<S, true>(a, Xp, Yp, Zp);
 }
 
 hipError_t launch_cross3d(const CrossArgs& a, hipStream_t s) {
@@ -182,16 +182,23 @@ __global__ void k_karras(const unsigned* __restrict__ keys, int32_t n, int32_t* 
   if (i == 0) parent_int[0] = -1;
 }
 
-// Sorted triangle records and leaf boxes in sorted order.
+// Sorted triangle records and leaf boxes in sorted order.  Vertex indices
+// are below 2^31, so bit 31 of each is free: it holds the lexicographic order
+// of the edge leaving that vertex (v0->v1, v1->v2, v2->v0), i.e. the sign of
+// the edge's tie offset, which is then not recomputed per crossing test.
 __global__ void k_gather_leaves(const int32_t* __restrict__ Fc, const int32_t* __restrict__ order,
                                 int32_t nf, const float4* __restrict__ box,
-                                const float* __restrict__ zmax, int4* __restrict__ tris,
-                                float4* __restrict__ lbox, float* __restrict__ lz) {
+                                const float* __restrict__ zmax, const double4* __restrict__ Vr,
+                                int4* __restrict__ tris, float4* __restrict__ lbox, float* __restrict__ lz) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nf) return;
   int f = order[i];
   if (f < 0 || f >= nf) f = 0;   // never taken for a permutation
-  tris[i] = make_int4(Fc[3 * f], Fc[3 * f + 1], Fc[3 * f + 2], f);
+  const int32_t i0 = Fc[3 * f], i1 = Fc[3 * f + 1], i2 = Fc[3 * f + 2];
+  const double4 A = Vr[i0], B = Vr[i1], C = Vr[i2];
+  tris[i] = make_int4(tri_index(i0, lex_less(A.x, A.y, A.z, B.x, B.y, B.z)),
+                      tri_index(i1, lex_less(B.x, B.y, B.z, C.x, C.y, C.z)),
+                      tri_index(i2, lex_less(C.x, C.y, C.z, A.x, A.y, A.z)), f);
   lbox[i] = box[f];
   lz[i] = zmax[f];
 }
@@ -300,7 +307,7 @@ hipError_t build_bvh_device(const BuildBufs& b, const Frame& F, const float* V, 
   hipLaunchKernelGGL(k_morton, dim3(bf), dim3(256), 0, s, b.cen, nf, b.cbounds, b.keys, b.vals);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = radix_sort_pairs(b.keys, b.vals, b.keys2, b.vals2, nf, b.sort_tmp, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_gather_leaves, dim3(bf), dim3(256), 0, s, Fc, b.vals, nf, b.box, b.zmax,
+  hipLaunchKernelGGL(k_gather_leaves, dim3(bf), dim3(256), 0, s, Fc, b.vals, nf, b.box, b.zmax, b.Vr,
                      b.tris, b.leafbox, b.leafz);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (nf == 1) return hipSuccess;

@@ -29,7 +29,7 @@ struct alignas(16) BvhNode {
 struct CrossArgs {
   Frame F;
   const BvhNode* nodes;
-  const int4* tris;        // sorted triangles: v0, v1, v2, original face id
+  const int4* tris;        // sorted triangles: v0, v1, v2 (tie bits in bit 31), original face id
   const double4* Vr;       // rotated vertices: X, Y, Z, 0
   const float4* leafbox;   // used when the tree is a single leaf
   const float* leafz;

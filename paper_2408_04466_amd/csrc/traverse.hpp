@@ -10,20 +10,36 @@ namespace wn {
 // Triangle test (shared predicates with the boundary kernel)
 // ---------------------------------------------------------------------------
 
+// A vertex index (below 2^31) with the lexicographic order of the edge that
+// leaves it in bit 31, as the sorted triangle records store it.
+__device__ __forceinline__ int32_t tri_index(int32_t v, bool a_less_b) {
+  return a_less_b ? (int32_t)((uint32_t)v | 0x80000000u) : v;
+}
+
 // +1 / -1 when the ray p + t d (t > 0) passes through the triangle's
-// interior along / against its normal (v1-v0)x(v2-v0), 0 otherwise.
+// interior along / against its normal (v1-v0)x(v2-v0), 0 otherwise.  t holds
+// the vertex indices with the edges' lexicographic order in bit 31
+// (tri_index).
+template <bool STORED_TIES>
 __device__ __forceinline__ int tri_crossing(const int4 t, const double4* __restrict__ Vr,
                                             double Xp, double Yp, double Zp) {
-  const double4 A = Vr[t.x];
-  const double4 B = Vr[t.y];
-  const double4 C = Vr[t.z];
+  // the three tie bits in one register, so that the indices die at once
+  const uint32_t tb = ((uint32_t)t.x >> 31) | (((uint32_t)t.y >> 30) & 2u) | (((uint32_t)t.z >> 29) & 4u);
+  const double4 A = Vr[t.x & 0x7fffffff];
+  const double4 B = Vr[t.y & 0x7fffffff];
+  const double4 C = Vr[t.z & 0x7fffffff];
   float za, zb, zc;
   const VQ a = vertex_q(A.x, A.y, A.z, Xp, Yp, Zp, &za);
   const VQ b = vertex_q(B.x, B.y, B.z, Xp, Yp, Zp, &zb);
   const VQ c = vertex_q(C.x, C.y, C.z, Xp, Yp, Zp, &zc);
-  const double n01 = edge_tie(edge_n(a, b), tie_offset(lex_less(A.x, A.y, A.z, B.x, B.y, B.z)));
-  const double n12 = edge_tie(edge_n(b, c), tie_offset(lex_less(B.x, B.y, B.z, C.x, C.y, C.z)));
-  const double n20 = edge_tie(edge_n(c, a), tie_offset(lex_less(C.x, C.y, C.z, A.x, A.y, A.z)));
+  // the stored bits, or the same comparisons redone (fewer live registers
+  // where the register budget is tight)
+  const bool l01 = STORED_TIES ? (tb & 1u) != 0 : lex_less(A.x, A.y, A.z, B.x, B.y, B.z);
+  const bool l12 = STORED_TIES ? (tb & 2u) != 0 : lex_less(B.x, B.y, B.z, C.x, C.y, C.z);
+  const bool l20 = STORED_TIES ? (tb & 4u) != 0 : lex_less(C.x, C.y, C.z, A.x, A.y, A.z);
+  const double n01 = edge_tie(edge_n(a, b), tie_offset(l01));
+  const double n12 = edge_tie(edge_n(b, c), tie_offset(l12));
+  const double n20 = edge_tie(edge_n(c, a), tie_offset(l20));
   const bool s01 = n01 < 0.0, s12 = n12 < 0.0, s20 = n20 < 0.0;
   if (s01 != s12 || s12 != s20) return 0;
   // Height of the crossing above p: barycentric weights are the edge values
@@ -124,11 +140,12 @@ __device__ __forceinline__ int traverse_leaves(const CrossArgs& a, float x, floa
 }
 
 // chi for one query (WN_CHI_INVALID if the tree is malformed).
-template <int S>
+template <int S, bool STORED_TIES = false>
 __device__ int traverse(const CrossArgs& a, double Xp, double Yp, double Zp) {
   int chi = 0;
-  const int st = traverse_leaves<S>(a, (float)Xp, (float)Yp, (float)Zp,
-                                    [&](int t) { chi += tri_crossing(a.tris[t], a.Vr, Xp, Yp, Zp); });
+  const int st = traverse_leaves<S>(a, (float)Xp, (float)Yp, (float)Zp, [&](int t) {
+    chi += tri_crossing<STORED_TIES>(a.tris[t], a.Vr, Xp, Yp, Zp);
+  });
   return st ? st : chi;
 }
 
