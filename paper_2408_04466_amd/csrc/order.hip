@@ -7,6 +7,8 @@
 // bounding box) puts spatially close queries in the same wavefront.  The sort
 // is the stable LSD radix sort of the BVH build, so the order is
 // deterministic (ties by query index); non-finite queries go last.
+#include <algorithm>
+
 #include "bvh_build.hpp"
 #include "kernels.hpp"
 
@@ -24,35 +26,38 @@ __device__ __forceinline__ float ord_float(unsigned o) {
 }
 
 // Bounding box of the finite queries as order-preserving integers:
-// box[2c] = min, box[2c + 1] = max of coordinate c.
-__global__ void k_qbox(const float* __restrict__ qx, const float* __restrict__ qy, const float* __restrict__ qz,
-                       int64_t n, unsigned* __restrict__ box) {
-  __shared__ unsigned red[6][256];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  float p[3] = {0.f, 0.f, 0.f};
-  bool fin = false;
-  if (i < n) {
-    p[0] = qx[i];
-    p[1] = qy[i];
-    p[2] = qz[i];
-    fin = isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]);
-  }
-  for (int c = 0; c < 3; ++c) {
-    red[2 * c][threadIdx.x] = fin ? ord_key(p[c]) : 0xffffffffu;
-    red[2 * c + 1][threadIdx.x] = fin ? ord_key(p[c]) : 0u;
-  }
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h)
+// box[2c] = min, box[2c + 1] = max of coordinate c.  A grid-stride loop over
+// few workgroups, wavefront shuffles, then one atomic per value and
+// workgroup, so that the atomics on the six words do not serialise.
+constexpr int kBoxBlocks = 256;
+
+__global__ __launch_bounds__(256) void k_qbox(const float* __restrict__ qx, const float* __restrict__ qy,
+                                              const float* __restrict__ qz, int64_t n, unsigned* __restrict__ box) {
+  __shared__ unsigned red[6][4];
+  unsigned v[6] = {0xffffffffu, 0u, 0xffffffffu, 0u, 0xffffffffu, 0u};
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const float p[3] = {qx[i], qy[i], qz[i]};
+    if (isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]))
       for (int c = 0; c < 3; ++c) {
-        red[2 * c][threadIdx.x] = min(red[2 * c][threadIdx.x], red[2 * c][threadIdx.x + h]);
-        red[2 * c + 1][threadIdx.x] = max(red[2 * c + 1][threadIdx.x], red[2 * c + 1][threadIdx.x + h]);
+        const unsigned k = ord_key(p[c]);
+        v[2 * c] = min(v[2 * c], k);
+        v[2 * c + 1] = max(v[2 * c + 1], k);
       }
-    __syncthreads();
   }
+  for (int o = 32; o > 0; o >>= 1)
+    for (int c = 0; c < 3; ++c) {
+      v[2 * c] = min(v[2 * c], (unsigned)__shfl_xor((int)v[2 * c], o, 64));
+      v[2 * c + 1] = max(v[2 * c + 1], (unsigned)__shfl_xor((int)v[2 * c + 1], o, 64));
+    }
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < 6; ++k) red[k][threadIdx.x >> 6] = v[k];
+  __syncthreads();
   if (threadIdx.x < 6) {
-    if (threadIdx.x % 2 == 0) atomicMin(&box[threadIdx.x], red[threadIdx.x][0]);
-    else atomicMax(&box[threadIdx.x], red[threadIdx.x][0]);
+    const int k = threadIdx.x;
+    unsigned r = red[k][0];
+    for (int w = 1; w < 4; ++w) r = (k % 2 == 0) ? min(r, red[k][w]) : max(r, red[k][w]);
+    if (k % 2 == 0) atomicMin(&box[k], r);
+    else atomicMax(&box[k], r);
   }
 }
 
@@ -110,7 +115,8 @@ hipError_t spatial_order(const float* qx, const float* qy, const float* qz, int6
   }
   const unsigned blocks = (unsigned)((n + 255) / 256);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_qbox, dim3(blocks), dim3(256), 0, s, qx, qy, qz, n, box);
+    const unsigned bb = (unsigned)std::min<int64_t>((n + 255) / 256, kBoxBlocks);
+    hipLaunchKernelGGL(k_qbox, dim3(bb), dim3(256), 0, s, qx, qy, qz, n, box);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
