@@ -101,32 +101,31 @@ bool make_rotation(const double dir[3], double d[3], double R[9]) {
 
 namespace {
 
-__global__ void k_bbox_f32(const float* __restrict__ V, int32_t nv, unsigned* __restrict__ out) {
-  __shared__ unsigned red[6][256];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  for (int c = 0; c < 3; ++c) {
-    unsigned lo = 0xffffffffu, hi = 0u;
-    if (i < nv) {
+__global__ __launch_bounds__(256) void k_bbox_f32(const float* __restrict__ V, int32_t nv, unsigned* __restrict__ out) {
+  // grid-stride over few workgroups (one atomic per value and workgroup)
+  __shared__ unsigned red[6][4];
+  unsigned v[6] = {0xffffffffu, 0u, 0xffffffffu, 0u, 0xffffffffu, 0u};
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < nv; i += gridDim.x * 256)
+    for (int c = 0; c < 3; ++c) {
       const unsigned u = __float_as_uint(V[3 * i + c]);
       const unsigned o = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-      lo = o;
-      hi = o;
+      v[2 * c] = min(v[2 * c], o);
+      v[2 * c + 1] = max(v[2 * c + 1], o);
     }
-    red[2 * c][threadIdx.x] = lo;
-    red[2 * c + 1][threadIdx.x] = hi;
-  }
+  for (int o = 32; o > 0; o >>= 1)
+    for (int k = 0; k < 6; ++k) {
+      const unsigned w = (unsigned)__shfl_xor((int)v[k], o, 64);
+      v[k] = (k % 2 == 0) ? min(v[k], w) : max(v[k], w);
+    }
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < 6; ++k) red[k][threadIdx.x >> 6] = v[k];
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s)
-      for (int c = 0; c < 3; ++c) {
-        red[2 * c][threadIdx.x] = min(red[2 * c][threadIdx.x], red[2 * c][threadIdx.x + s]);
-        red[2 * c + 1][threadIdx.x] = max(red[2 * c + 1][threadIdx.x], red[2 * c + 1][threadIdx.x + s]);
-      }
-    __syncthreads();
-  }
   if (threadIdx.x < 6) {
-    if (threadIdx.x & 1) atomicMax(&out[threadIdx.x], red[threadIdx.x][0]);
-    else atomicMin(&out[threadIdx.x], red[threadIdx.x][0]);
+    const int k = threadIdx.x;
+    unsigned r = red[k][0];
+    for (int w = 1; w < 4; ++w) r = (k % 2 == 0) ? min(r, red[k][w]) : max(r, red[k][w]);
+    if (k % 2 == 0) atomicMin(&out[k], r);
+    else atomicMax(&out[k], r);
   }
 }
 
@@ -313,7 +312,8 @@ wn_status wn_build_bvh(const float* V, int64_t nv, const int32_t* F, int64_t nf,
     const unsigned init[6] = {0xffffffffu, 0u, 0xffffffffu, 0u, 0xffffffffu, 0u};
     e = hipMemcpyAsync(dbb, init, sizeof init, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
-      hipLaunchKernelGGL(k_bbox_f32, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, V, (int32_t)nv, dbb);
+      hipLaunchKernelGGL(k_bbox_f32, dim3((unsigned)std::min<int64_t>((nv + 255) / 256, 256)), dim3(256), 0, s, V,
+                         (int32_t)nv, dbb);
       e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipMemcpyAsync(hbb, dbb, sizeof hbb, hipMemcpyDeviceToHost, s);

@@ -10,6 +10,8 @@
 // (Karras 2012) over 2D Morton codes of the projected centroids, built with
 // a project-written LSD radix sort, and traversed with a short stack held in
 // registers.
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "bvh_build.hpp"
 #include "traverse.hpp"
@@ -73,49 +75,55 @@ __global__ void k_rotate_vertices(Frame F, const float* __restrict__ V, int32_t 
   Vr[i] = make_double4(X, Y, Z, 0.0);
 }
 
-// Projected box (+ pad) of each triangle, its centroid, and the centroid
-// bounds of the scene (ordered-int atomics).
+// Projected box (+ pad) of each triangle and its centroid.
 __global__ void k_tri_boxes(const double4* __restrict__ Vr, const int32_t* __restrict__ Fc,
                             int32_t nf, float pad, float4* __restrict__ box,
-                            float* __restrict__ zmax, float2* __restrict__ cen,
-                            unsigned* __restrict__ cb) {
+                            float* __restrict__ zmax, float2* __restrict__ cen) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  float cx = 0.f, cy = 0.f;
-  bool ok = i < nf;
-  if (ok) {
-    const double4 A = Vr[Fc[3 * i]];
-    const double4 B = Vr[Fc[3 * i + 1]];
-    const double4 C = Vr[Fc[3 * i + 2]];
-    const double x0 = fmin(A.x, fmin(B.x, C.x)), x1 = fmax(A.x, fmax(B.x, C.x));
-    const double y0 = fmin(A.y, fmin(B.y, C.y)), y1 = fmax(A.y, fmax(B.y, C.y));
-    const double z1 = fmax(A.z, fmax(B.z, C.z));
-    box[i] = make_float4(f_down(x0) - pad, f_up(x1) + pad, f_down(y0) - pad, f_up(y1) + pad);
-    zmax[i] = f_up(z1) + pad;
-    cx = (float)(0.5 * (x0 + x1));
-    cy = (float)(0.5 * (y0 + y1));
-    cen[i] = make_float2(cx, cy);
+  if (i >= nf) return;
+  const double4 A = Vr[Fc[3 * i]];
+  const double4 B = Vr[Fc[3 * i + 1]];
+  const double4 C = Vr[Fc[3 * i + 2]];
+  const double x0 = fmin(A.x, fmin(B.x, C.x)), x1 = fmax(A.x, fmax(B.x, C.x));
+  const double y0 = fmin(A.y, fmin(B.y, C.y)), y1 = fmax(A.y, fmax(B.y, C.y));
+  const double z1 = fmax(A.z, fmax(B.z, C.z));
+  box[i] = make_float4(f_down(x0) - pad, f_up(x1) + pad, f_down(y0) - pad, f_up(y1) + pad);
+  zmax[i] = f_up(z1) + pad;
+  cen[i] = make_float2((float)(0.5 * (x0 + x1)), (float)(0.5 * (y0 + y1)));
+}
+
+// Workgroups of the grid-stride reductions below: few enough that their one
+// atomic per value and workgroup do not queue up on the same words.
+constexpr int kReduceBlocks = 256;
+
+// Bounds of the centroids as order-preserving integers: cb = {min x, max x,
+// min y, max y}.
+__global__ __launch_bounds__(256) void k_cen_bounds(const float2* __restrict__ cen, int32_t nf,
+                                                    unsigned* __restrict__ cb) {
+  __shared__ unsigned red[4][4];
+  unsigned v[4] = {0xffffffffu, 0u, 0xffffffffu, 0u};
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < nf; i += gridDim.x * 256) {
+    const float2 c = cen[i];
+    const unsigned ox = f2ord(c.x), oy = f2ord(c.y);
+    v[0] = min(v[0], ox);
+    v[1] = max(v[1], ox);
+    v[2] = min(v[2], oy);
+    v[3] = max(v[3], oy);
   }
-  // block reduction of centroid bounds, then one atomic per block
-  __shared__ unsigned red[4][256];
-  red[0][threadIdx.x] = ok ? f2ord(cx) : 0xffffffffu;
-  red[1][threadIdx.x] = ok ? f2ord(cx) : 0u;
-  red[2][threadIdx.x] = ok ? f2ord(cy) : 0xffffffffu;
-  red[3][threadIdx.x] = ok ? f2ord(cy) : 0u;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      red[0][threadIdx.x] = min(red[0][threadIdx.x], red[0][threadIdx.x + s]);
-      red[1][threadIdx.x] = max(red[1][threadIdx.x], red[1][threadIdx.x + s]);
-      red[2][threadIdx.x] = min(red[2][threadIdx.x], red[2][threadIdx.x + s]);
-      red[3][threadIdx.x] = max(red[3][threadIdx.x], red[3][threadIdx.x + s]);
+  for (int o = 32; o > 0; o >>= 1)
+    for (int k = 0; k < 4; ++k) {
+      const unsigned w = (unsigned)__shfl_xor((int)v[k], o, 64);
+      v[k] = (k % 2 == 0) ? min(v[k], w) : max(v[k], w);
     }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    atomicMin(&cb[0], red[0][0]);
-    atomicMax(&cb[1], red[1][0]);
-    atomicMin(&cb[2], red[2][0]);
-    atomicMax(&cb[3], red[3][0]);
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x >> 6] = v[k];
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int k = threadIdx.x;
+    unsigned r = red[k][0];
+    for (int w = 1; w < 4; ++w) r = (k % 2 == 0) ? min(r, red[k][w]) : max(r, red[k][w]);
+    if (k % 2 == 0) atomicMin(&cb[k], r);
+    else atomicMax(&cb[k], r);
   }
 }
 
@@ -230,17 +238,28 @@ __global__ void k_depth_jump(const int32_t* __restrict__ anc_in, const int32_t* 
 }
 
 // res[0] = deepest level, res[1] = 1 if some node has not reached the root.
-__global__ void k_depth_max(const int32_t* __restrict__ anc, const int32_t* __restrict__ dep, int32_t n,
-                            int32_t* res) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int m = i < n ? dep[i] : 0;
-  int open = (i < n && anc[i] >= 0) ? 1 : 0;
-  // wavefront maximum first: one atomic per wavefront
+__global__ __launch_bounds__(256) void k_depth_max(const int32_t* __restrict__ anc, const int32_t* __restrict__ dep,
+                                                   int32_t n, int32_t* res) {
+  __shared__ int red[2][4];
+  int m = 0, open = 0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    m = max(m, dep[i]);
+    open = max(open, anc[i] >= 0 ? 1 : 0);
+  }
   for (int o = 32; o > 0; o >>= 1) {
     m = max(m, __shfl_xor(m, o));
     open = max(open, __shfl_xor(open, o));
   }
   if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = m;
+    red[1][threadIdx.x >> 6] = open;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) {
+      m = max(m, red[0][w]);
+      open = max(open, red[1][w]);
+    }
     atomicMax(&res[0], m);
     if (open) atomicMax(&res[1], 1);
   }
@@ -301,8 +320,10 @@ hipError_t build_bvh_device(const BuildBufs& b, const Frame& F, const float* V, 
   unsigned init[4] = {0xffffffffu, 0u, 0xffffffffu, 0u};
   for (int k = 0; k < 4; ++k)
     if ((e = fill_u32(b.cbounds + k, 1, init[k], s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_tri_boxes, dim3(bf), dim3(256), 0, s, b.Vr, Fc, nf, pad, b.box, b.zmax,
-                     b.cen, b.cbounds);
+  hipLaunchKernelGGL(k_tri_boxes, dim3(bf), dim3(256), 0, s, b.Vr, Fc, nf, pad, b.box, b.zmax, b.cen);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cen_bounds, dim3(std::min<unsigned>(bf, kReduceBlocks)), dim3(256), 0, s, b.cen, nf,
+                     b.cbounds);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_morton, dim3(bf), dim3(256), 0, s, b.cen, nf, b.cbounds, b.keys, b.vals);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -335,7 +356,8 @@ hipError_t build_bvh_device(const BuildBufs& b, const Frame& F, const float* V, 
   }
   int32_t* res = (int32_t*)b.cbounds;
   if ((e = fill_u32(b.cbounds, 2, 0u, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_depth_max, dim3(bi), dim3(256), 0, s, anc[cur], dep[cur], ni, res);
+  hipLaunchKernelGGL(k_depth_max, dim3(std::min<unsigned>(bi, kReduceBlocks)), dim3(256), 0, s, anc[cur], dep[cur],
+                     ni, res);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   int32_t hres[2] = {0, 0};
   if ((e = hipMemcpyAsync(hres, res, sizeof hres, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
