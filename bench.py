@@ -475,9 +475,10 @@ def run_others(torch, W, T, others, d3, args, dev):
     ms_cws = T.ms(lambda: W.eval_3d_curves(bvhc, ctrlc, *qs), reps)
     ms_pws = T.ms(lambda: W.eval_3d_patches(dmc, netc, ctrlc, *qs), reps)
     ms_tws = T.ms(lambda: W.eval_3d(bvhc, bndc, offc, *qs), reps)
+    ms_cbws = T.ms(lambda: W.backward_curves(ctrlc, *qs, gwc), reps)
     res["3d_spatial_order_2p20"] = {
         "order_ms": ms_ord, "curves_w_sorted_ms": ms_cws, "patches_w_sorted_ms": ms_pws,
-        "tessellated_w_sorted_ms_1M_triangles": ms_tws}
+        "tessellated_w_sorted_ms_1M_triangles": ms_tws, "curves_backward_sorted_ms": ms_cbws}
     res["3d_parametric_coons_2p20"] = {
         "patches": 1, "curves": 4, "crossings_ms": ms_pc, "w_ms": ms_pw,
         "tessellated_w_ms_1M_triangles": ms_tw, "queries_per_s": (1 << 20) / (ms_pw * 1e-3)}
