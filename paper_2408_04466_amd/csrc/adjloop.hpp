@@ -98,7 +98,7 @@ __device__ __forceinline__ void park(float* rs, float* pv, int va, int nb, const
 }
 
 struct QState {
-  float px, py, pz, g;
+  float px, py, pz, g;       // g: twice dL/dw (see edge_grad)
   float gx, gy, gz;          // sum_e g c_e (1/|a'| + 1/|b'|)
 };
 
@@ -118,16 +118,19 @@ __device__ __forceinline__ Rel rel(const QState& s, const float4& v) {
   return q;
 }
 
-// Edge a->b for one query: c = g K (a' x b'); adds c (1/|a'| + 1/|b'|) to
-// the query gradient and c/|a'|, c/|b'| to the two vertex accumulators.
-__device__ __forceinline__ void edge_grad(QState& s, const Rel& a, const Rel& b, float* acc_a,
+// Edge a->b (squared length l2) for one query: c = g K (a' x b') with
+// 1/K = |a'||b'| + a'.b' = ((|a'| + |b'|)^2 - |b - a|^2) / 2, since
+// |b - a|^2 = |a'|^2 + |b'|^2 - 2 a'.b' (the factor 2 sits in s.g); adds
+// c (1/|a'| + 1/|b'|) to the query gradient and c/|a'|, c/|b'| to the two
+// vertex accumulators.
+__device__ __forceinline__ void edge_grad(QState& s, const Rel& a, const Rel& b, float l2, float* acc_a,
                                           float* acc_b) {
   const float crx = __fmaf_rn(a.y, b.z, -__fmul_rn(a.z, b.y));
   const float cry = __fmaf_rn(a.z, b.x, -__fmul_rn(a.x, b.z));
   const float crz = __fmaf_rn(a.x, b.y, -__fmul_rn(a.y, b.x));
-  const float dot = __fmaf_rn(a.x, b.x, __fmaf_rn(a.y, b.y, __fmul_rn(a.z, b.z)));
-  const float den = __fmaf_rn(a.r, b.r, dot);
-  const float gk = __fmul_rn(s.g, __builtin_amdgcn_rcpf(den));
+  const float rs = __fadd_rn(a.r, b.r);
+  const float den2 = __fmaf_rn(rs, rs, -l2);
+  const float gk = __fmul_rn(s.g, __builtin_amdgcn_rcpf(den2));
   const float cx = __fmul_rn(gk, crx);
   const float cy = __fmul_rn(gk, cry);
   const float cz = __fmul_rn(gk, crz);
@@ -166,7 +169,7 @@ __device__ __forceinline__ void load_tile(QState* S, const float* qx, const floa
     S[k].px = qx[qi[k]];
     S[k].py = qy[qi[k]];
     S[k].pz = qz[qi[k]];
-    S[k].g = ok[k] ? gw[qi[k]] : 0.0f;      // padding lanes contribute nothing
+    S[k].g = ok[k] ? 2.0f * gw[qi[k]] : 0.0f;   // padding lanes contribute nothing
     S[k].gx = S[k].gy = S[k].gz = 0.0f;
   }
 }
@@ -176,11 +179,11 @@ __device__ __forceinline__ void zero3(float* a) { a[0] = a[1] = a[2] = 0.f; }
 // Edge A->B for every query of the lane; the partial of vertex A is then
 // complete and goes out (summed over the wavefront) to row entry `va`.
 template <int QPL>
-__device__ __forceinline__ void step(QState* S, const Rel* A, const Rel* B, float* accA, float* accB,
+__device__ __forceinline__ void step(QState* S, const Rel* A, const Rel* B, float l2, float* accA, float* accB,
                                      float* pv, float* rs, int va, int nb, int lane) {
   zero3(accB);
 #pragma unroll
-  for (int k = 0; k < QPL; ++k) edge_grad(S[k], A[k], B[k], accA, accB);
+  for (int k = 0; k < QPL; ++k) edge_grad(S[k], A[k], B[k], l2, accA, accB);
   if (pv) park(rs, pv, va, nb, accA, lane);
 }
 
@@ -197,14 +200,21 @@ __device__ __forceinline__ void walk(QState* S, const float* __restrict__ bnd, i
   float* rs = rsw + (threadIdx.x >> 6) * kRowFloats;
   Rel F[QPL], A[QPL], B[QPL];      // loop's first vertex; A = last vertex visited
   float accA[3], accB[3];          // pending partial of vertex A (and scratch for B)
+  float lA = 0.f;                  // squared length of the edge leaving vertex A
   zero3(accA);
   int l = 0;
   for (int c0 = 0; c0 < nb; c0 += kChunk) {
     const int c1 = min(c0 + kChunk, nb);
     __syncthreads();
+    // vertex i and, in .w, the squared length of the edge leaving it
     for (int j = threadIdx.x; j < c1 - c0; j += kThreads) {
       const int i = c0 + j;
-      sv[j] = make_float4(bnd[3 * i], bnd[3 * i + 1], bnd[3 * i + 2], 0.f);
+      const int lp = bnd::loop_of(L, i);
+      const int nx = (i + 1 < L.off(lp + 1)) ? i + 1 : L.off(lp);
+      const float x = bnd[3 * i], y = bnd[3 * i + 1], z = bnd[3 * i + 2];
+      const float ex = __fsub_rn(bnd[3 * nx], x), ey = __fsub_rn(bnd[3 * nx + 1], y),
+                  ez = __fsub_rn(bnd[3 * nx + 2], z);
+      sv[j] = make_float4(x, y, z, __fmaf_rn(ex, ex, __fmaf_rn(ey, ey, __fmul_rn(ez, ez))));
     }
     __syncthreads();
     for (; l < L.n() && L.off(l) < c1; ++l) {
@@ -218,6 +228,7 @@ __device__ __forceinline__ void walk(QState* S, const float* __restrict__ bnd, i
           F[k] = rel(S[k], v);
           A[k] = F[k];
         }
+        lA = v.w;
         zero3(accA);
         ++j;
       }
@@ -226,26 +237,28 @@ __device__ __forceinline__ void walk(QState* S, const float* __restrict__ bnd, i
         const float4 v1 = sv[j + 1 - c0];
 #pragma unroll
         for (int k = 0; k < QPL; ++k) B[k] = rel(S[k], v0);
-        step<QPL>(S, A, B, accA, accB, pv, rs, j - 1, nb, lane);
+        step<QPL>(S, A, B, lA, accA, accB, pv, rs, j - 1, nb, lane);
 #pragma unroll
         for (int k = 0; k < QPL; ++k) A[k] = rel(S[k], v1);
-        step<QPL>(S, B, A, accB, accA, pv, rs, j, nb, lane);
+        step<QPL>(S, B, A, v0.w, accB, accA, pv, rs, j, nb, lane);
+        lA = v1.w;
       }
       if (j < j1) {
         const float4 v0 = sv[j - c0];
 #pragma unroll
         for (int k = 0; k < QPL; ++k) B[k] = rel(S[k], v0);
-        step<QPL>(S, A, B, accA, accB, pv, rs, j - 1, nb, lane);
+        step<QPL>(S, A, B, lA, accA, accB, pv, rs, j - 1, nb, lane);
 #pragma unroll
         for (int k = 0; k < QPL; ++k) A[k] = B[k];
         accA[0] = accB[0]; accA[1] = accB[1]; accA[2] = accB[2];
+        lA = v0.w;
         ++j;
       }
       if (j1 < le) break;            // the loop continues in the next chunk
       // closing edge last -> first: completes the last vertex; the first
       // vertex's share goes to the per-loop row
       float accF[3];
-      step<QPL>(S, A, F, accA, accF, pv, rs, le - 1, nb, lane);
+      step<QPL>(S, A, F, lA, accA, accF, pv, rs, le - 1, nb, lane);
       if (pl) put3(pl + 3 * (int64_t)l, accF, lane);
       zero3(accA);
     }
