@@ -8,7 +8,7 @@
 
 namespace wn {
 
-constexpr int kShortStack = 12;   // traversal stack entries kept in registers
+constexpr int kShortStack = 8;    // traversal stack entries kept in registers
 
 struct BuildBufs {
   double4* Vr;          // [nv]
