@@ -37,6 +37,15 @@ FLOPS_PER_PAIR_FWD = 58      # boundary integral, per (query, boundary edge)
 COUNTERS = os.path.join(ROOT, "profiles", "k_bnd3d_mesh_2p20_counters.md")
 KERNEL_SOURCES = ("paper_2408_04466_amd/csrc/bnd3d.hip", "paper_2408_04466_amd/csrc/bndloop.hpp",
                   "paper_2408_04466_amd/csrc/geom.hpp")
+# sources behind the other committed per-kernel VALU counts (the timed step's kernels)
+STEP_KERNEL_SOURCES = {
+    "k_batch_fwd": ("paper_2408_04466_amd/csrc/batch.hip", "paper_2408_04466_amd/csrc/bndloop.hpp",
+                    "paper_2408_04466_amd/csrc/traverse.hpp", "paper_2408_04466_amd/csrc/geom.hpp",
+                    "paper_2408_04466_amd/csrc/kernels.hpp", "paper_2408_04466_amd/csrc/bvh_build.hpp"),
+    "k_batch_bwd": ("paper_2408_04466_amd/csrc/batch.hip", "paper_2408_04466_amd/csrc/adjloop.hpp",
+                    "paper_2408_04466_amd/csrc/bndloop.hpp", "paper_2408_04466_amd/csrc/geom.hpp",
+                    "paper_2408_04466_amd/csrc/kernels.hpp"),
+}
 FLOPS_PER_PAIR_BWD = 40      # adjoint, per (query, boundary edge)
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak
 VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9   # vector lane-instructions/s without packed FP32
@@ -102,6 +111,27 @@ def measured_counters():
         return None, None
     valu = vals.get("valu_wave_instructions_per_launch k_bnd3d")
     return int(vals["traffic_bytes_per_launch k_bnd3d"]), (int(valu) if valu else None)
+
+
+def step_kernel_valu():
+    """{kernel: VALU wavefront instructions per launch} for the timed step's
+    kernels from the committed counter summary, for those whose sources still
+    hash to the value recorded with the count."""
+    import hashlib
+    try:
+        txt = open(COUNTERS).read()
+    except OSError:
+        return {}
+    vals = dict(line.split(": ", 1) for line in txt.splitlines()
+                if line.startswith(("valu_wave_instructions_per_launch ", "source_sha256 ")))
+    out = {}
+    for k, files in STEP_KERNEL_SOURCES.items():
+        h = hashlib.sha256()
+        for f in files:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if vals.get(f"source_sha256 {k}", "").strip() == h.hexdigest() and f"valu_wave_instructions_per_launch {k}" in vals:
+            out[k] = int(vals[f"valu_wave_instructions_per_launch {k}"])
+    return out
 
 
 class Timer:
@@ -269,6 +299,11 @@ def main():
     if others is not None:
         extra = run_others(torch, W, T, others, d, args, dev)
     traffic, valu = measured_counters()
+    step_valu = step_kernel_valu()
+    step_ms = {"k_batch_fwd": ms_fwd_b, "k_batch_bwd": ms_bwd_b}
+    step_issue = {k: {"ms": step_ms[k], "valu_wave_instructions": v,
+                      "valu_issue_frac": v * 64 / (step_ms[k] * 1e-3) / VALU_ISSUE_PEAK}
+                  for k, v in step_valu.items()}
 
     out = {
         "metric": "winding queries/s fwd+bwd, batched vs plain, 3D mesh 2^20 pts at |err|<=1e-4",
@@ -315,6 +350,8 @@ def main():
             **extra.get("c4", {})},
         "step_ms": {"mean": ms_step, "median": per_step[len(per_step) // 2], "min": per_step[0]},
         "device": {**W.device_info(), "name": torch.cuda.get_device_name(dev)},
+        # the timed step's two kernels against the same vector-issue limit
+        "step_valu_issue": step_issue or None,
         "kernels_ms": {"crossings": ms_cross, "boundary": ms_bnd, "plain_forward": ms_fwd,
                        "plain_backward": ms_bwd, "batched_forward": ms_fwd_b, "batched_backward": ms_bwd_b,
                        "bvh_build": build_ms, "batch_create": batch_ms},
