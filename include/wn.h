@@ -247,16 +247,16 @@ wn_status wn_backward_curves(const float* ctrl, int64_t ncurves,
  *             as cubic Beziers, oriented as the patches induce (may be 0).
  *  qx..nq     queries as in wn_eval_3d.
  *  w_out      device [nq] float32 out, or NULL (crossings only);
- *  chi_out    device [nq] int32 out, or NULL (then a temporary buffer of
- *             4 bytes per query is allocated on the stream).
+ *  chi_out    device [nq] int32 out, or NULL.
  * Crossings: per query a depth-first walk over dyadic sub-squares of each
  * patch; a sub-square is dropped when its net relative to the query excludes
  * the ray (convex hull); when it lies wholly in front of the query and the
  * hull of each of its boundary edges excludes the ray, its signed crossings
  * are the winding number of its boundary's image around the ray; otherwise
  * it is split, down to level 16 (where it is dropped).  Non-finite queries
- * give NaN / WN_CHI_INVALID.
- * Errors: INVALID_ARGUMENT, UNSUPPORTED, OUT_OF_MEMORY, HIP.
+ * give NaN / WN_CHI_INVALID.  With w_out, one launch computes both terms per
+ * query (the kernel of wn_eval_3d_patches_batched); allocates nothing.
+ * Errors: INVALID_ARGUMENT, UNSUPPORTED, HIP.
  * ------------------------------------------------------------------------- */
 wn_status wn_eval_3d_patches(const double dir[3], const float* nets, int64_t npatch,
                              const float* curves, int64_t ncurves,

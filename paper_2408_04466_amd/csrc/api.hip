@@ -501,25 +501,11 @@ wn_status wn_eval_3d_patches(const double dir[3], const float* nets, int64_t npa
   for (int k = 0; k < 9; ++k) F.r[k] = R[k];
   for (int k = 0; k < 3; ++k) F.c[k] = 0.0;
   hipStream_t s = as_stream(stream);
-  int32_t* chi = chi_out;
-  if (!chi) {
-    const hipError_t e = hipMallocAsync((void**)&chi, (size_t)nq * sizeof(int32_t), s);
-    if (e != hipSuccess) return hip_fail(e, "hipMallocAsync");
-  }
-  hipError_t e = wn::launch_patches3d(F, nets, npatch, qx, qy, qz, nq, chi, s);
-  if (e == hipSuccess && w_out) {
-    wn::CrossArgs c{};
-    c.F = F;
-    c.qx = qx;
-    c.qy = qy;
-    c.qz = qz;
-    c.nq = nq;
-    e = wn::launch_curves3d(c, curves, ncurves, chi, w_out, nullptr, s);
-  }
-  if (!chi_out) {
-    const hipError_t e2 = hipFreeAsync(chi, s);
-    if (e == hipSuccess) e = e2;
-  }
+  // w: crossings and curve term in one launch (no temporary chi buffer);
+  // crossings only: the crossing kernel alone
+  const hipError_t e = w_out ? wn::launch_psurf_single(F, nets, npatch, curves, ncurves, qx, qy, qz, nq, w_out,
+                                                       chi_out, s)
+                             : wn::launch_patches3d(F, nets, npatch, qx, qy, qz, nq, chi_out, s);
   if (e != hipSuccess) return hip_fail(e, "wn_eval_3d_patches");
   return WN_OK;
 }

@@ -96,6 +96,11 @@ struct PBatch {
 hipError_t pbatch_create(const PSurf* surfs, int32_t n, hipStream_t s, PBatch* b);
 hipError_t eval_pbatch(const PBatch& b, const float* nets, const float* curves, const float* qx, const float* qy,
                        const float* qz, float* w_out, int32_t* chi_out, hipStream_t s);
+// One parametric surface (frame centre 0) through the same kernel: w, and chi
+// when chi_out is not null.
+hipError_t launch_psurf_single(const Frame& F, const float* nets, int64_t np, const float* curves, int64_t nc,
+                               const float* qx, const float* qy, const float* qz, int64_t nq, float* w_out,
+                               int32_t* chi_out, hipStream_t s);
 // Counts over a call's outputs (diag.hip): counts[0] = non-finite queries,
 // counts[1] = finite queries whose chi is WN_CHI_INVALID.
 hipError_t diagnose(const float* qx, const float* qy, const float* qz, const int32_t* chi, int64_t n,

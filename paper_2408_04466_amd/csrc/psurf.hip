@@ -22,20 +22,17 @@ constexpr size_t kStageBytes = sizeof(PatchRot) * kPatchChunk > sizeof(CurveRot)
                                    ? sizeof(PatchRot) * kPatchChunk
                                    : sizeof(CurveRot) * kCurveChunk;
 
-__global__ __launch_bounds__(kSThreads) void k_psurf_batched(const PSurf* __restrict__ desc,
-                                                            const int32_t* __restrict__ blk_surf,
-                                                            const float* __restrict__ nets,
-                                                            const float* __restrict__ curves,
-                                                            const float* __restrict__ qx, const float* __restrict__ qy,
-                                                            const float* __restrict__ qz, float* __restrict__ w_out,
-                                                            int32_t* __restrict__ chi_out) {
+// The work of one workgroup: 256 consecutive queries of the surface D.
+__device__ __forceinline__ void psurf_tile(const PSurf& D, int64_t blk, const float* __restrict__ nets,
+                                           const float* __restrict__ curves, const float* __restrict__ qx,
+                                           const float* __restrict__ qy, const float* __restrict__ qz,
+                                           float* __restrict__ w_out, int32_t* __restrict__ chi_out) {
   // patches and curves are staged one after the other through the same LDS
   __shared__ double stage[kStageBytes / sizeof(double)];
   PatchRot* sp = reinterpret_cast<PatchRot*>(stage);
   CurveRot* sc = reinterpret_cast<CurveRot*>(stage);
-  const PSurf& D = desc[blk_surf[blockIdx.x]];
   const Frame F = D.F;
-  const int64_t li = ((int64_t)blockIdx.x - D.blk0) * kSThreads + threadIdx.x;
+  const int64_t li = (blk - D.blk0) * kSThreads + threadIdx.x;
   const bool ok = li < D.nq;
   const int64_t q = D.q0 + (ok ? li : 0);
   const float px = qx[q], py = qy[q], pz = qz[q];
@@ -66,10 +63,30 @@ __global__ __launch_bounds__(kSThreads) void k_psurf_batched(const PSurf* __rest
   if (ok && chi_out) chi_out[q] = fin ? chi : WN_CHI_INVALID;
 }
 
+__global__ __launch_bounds__(kSThreads) void k_psurf_batched(const PSurf* __restrict__ desc,
+                                                            const int32_t* __restrict__ blk_surf,
+                                                            const float* __restrict__ nets,
+                                                            const float* __restrict__ curves,
+                                                            const float* __restrict__ qx, const float* __restrict__ qy,
+                                                            const float* __restrict__ qz, float* __restrict__ w_out,
+                                                            int32_t* __restrict__ chi_out) {
+  psurf_tile(desc[blk_surf[blockIdx.x]], blockIdx.x, nets, curves, qx, qy, qz, w_out, chi_out);
+}
+
+// One surface, its descriptor in the kernel arguments (the single-surface
+// entry point).
+__global__ __launch_bounds__(kSThreads) void k_psurf_one(PSurf one, const float* __restrict__ nets,
+                                                        const float* __restrict__ curves,
+                                                        const float* __restrict__ qx, const float* __restrict__ qy,
+                                                        const float* __restrict__ qz, float* __restrict__ w_out,
+                                                        int32_t* __restrict__ chi_out) {
+  psurf_tile(one, blockIdx.x, nets, curves, qx, qy, qz, w_out, chi_out);
+}
+
 }  // namespace
 
 PBatch::~PBatch() {
-  if (ws) hipFree(ws);
+  if (ws) (void)hipFree(ws);
 }
 
 hipError_t pbatch_create(const PSurf* surfs, int32_t n, hipStream_t s, PBatch* b) {
@@ -114,6 +131,21 @@ hipError_t eval_pbatch(const PBatch& b, const float* nets, const float* curves, 
   if (b.nblocks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_psurf_batched, dim3((unsigned)b.nblocks), dim3(kSThreads), 0, s, b.desc, b.blk_surf, nets,
                      curves, qx, qy, qz, w_out, chi_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_psurf_single(const Frame& F, const float* nets, int64_t np, const float* curves, int64_t nc,
+                               const float* qx, const float* qy, const float* qz, int64_t nq, float* w_out,
+                               int32_t* chi_out, hipStream_t s) {
+  const int64_t blocks = (nq + kSThreads - 1) / kSThreads;
+  if (blocks == 0) return hipSuccess;
+  PSurf one{};
+  one.F = F;
+  one.nq = nq;
+  one.npatch = (int32_t)np;
+  one.ncurve = (int32_t)nc;
+  hipLaunchKernelGGL(k_psurf_one, dim3((unsigned)blocks), dim3(kSThreads), 0, s, one, nets, curves, qx, qy, qz, w_out,
+                     chi_out);
   return hipGetLastError();
 }
 

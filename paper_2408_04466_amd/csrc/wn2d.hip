@@ -828,7 +828,7 @@ hipError_t run2d(const T* ctrl, int64_t nseg, const Loops2D& L, int32_t kind, co
 }  // namespace
 
 Batch2D::~Batch2D() {
-  if (ws) hipFree(ws);
+  if (ws) (void)hipFree(ws);
 }
 
 hipError_t batch2d_create(int32_t dtype, const wn_curveset_2d* sets, int32_t nsets, hipStream_t s, Batch2D* b) {
