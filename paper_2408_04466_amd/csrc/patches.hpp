@@ -34,13 +34,14 @@ namespace wn {
 namespace {
 
 constexpr int kPThreads = 256;
-constexpr int kPatchChunk = 32;   // patches per LDS stage: 32 * 384 B = 12 KB
+constexpr int kPatchChunk = 32;   // patches per LDS stage: 32 * 576 B = 18 KB
 constexpr int kMaxLevel = 16;
 
 // Power basis of a staged patch, per frame coordinate: S_c(u, v) =
 // sum a[c][k][l] u^k v^l (float64, rotated frame, not relative).
 struct PatchRot {
   double a[3][4][4];
+  float f[3][4][4];   // the same coefficients rounded to float32 (the walk's Taylor shift)
 };
 
 // Bernstein -> power basis of a cubic: a0 = p0, a1 = 3 (p1 - p0),
@@ -65,7 +66,10 @@ __device__ void stage_patch(const Frame& F, const float* __restrict__ nets, int6
     for (int j = 0; j < 4; ++j) to_power(P[c][0][j], P[c][1][j], P[c][2][j], P[c][3][j]);
     for (int i = 0; i < 4; ++i) to_power(P[c][i][0], P[c][i][1], P[c][i][2], P[c][i][3]);
     for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) out->a[c][i][j] = P[c][i][j];
+      for (int j = 0; j < 4; ++j) {
+        out->a[c][i][j] = P[c][i][j];
+        out->f[c][i][j] = (float)P[c][i][j];
+      }
   }
 }
 
@@ -90,13 +94,13 @@ __device__ __forceinline__ void to_bern(float& a0, float& a1, float& a2, float& 
 
 // Bernstein net o[i][j] (i along u) of one coordinate on the sub-square
 // [u0, u0 + h] x [v0, v0 + h], relative to the query coordinate pc.
-__device__ __forceinline__ void subnet(const double (&a)[4][4], double pc, double u0, double v0, float h,
-                                       float (&o)[4][4]) {
+__device__ __forceinline__ void subnet(const double (&a)[4][4], const float (&af)[4][4], double pc, double u0,
+                                       double v0, float h, float (&o)[4][4]) {
   const float uf = (float)u0, vf = (float)v0;
 #pragma unroll
   for (int k = 0; k < 4; ++k)
 #pragma unroll
-    for (int l = 0; l < 4; ++l) o[k][l] = (float)a[k][l];
+    for (int l = 0; l < 4; ++l) o[k][l] = af[k][l];
   // Taylor shift to (u0, v0)
 #pragma unroll
   for (int l = 0; l < 4; ++l)
@@ -204,14 +208,14 @@ __device__ int patches_chi(const PatchRot* sc, int cnt, double Xp, double Yp, do
     bool descend = false;
     float X[4][4], Y[4][4];
     float lo, hi;
-    subnet(S.a[0], Xp, u0, v0, h, X);
+    subnet(S.a[0], S.f[0], Xp, u0, v0, h, X);
     range16(X, lo, hi);
     if (!one_sign(lo, hi)) {
-      subnet(S.a[1], Yp, u0, v0, h, Y);
+      subnet(S.a[1], S.f[1], Yp, u0, v0, h, Y);
       range16(Y, lo, hi);
       if (!one_sign(lo, hi)) {
         float Zn[4][4];
-        subnet(S.a[2], Zp, u0, v0, h, Zn);
+        subnet(S.a[2], S.f[2], Zp, u0, v0, h, Zn);
         range16(Zn, lo, hi);
         const float tz = 1e-6f * fmaxf(fabsf(lo), fabsf(hi));
         if (hi > -tz) {
