@@ -203,7 +203,11 @@ wn_status wn_eval_3d_boundary(const wn_bvh* bvh, const float* bnd_xyz,
  * stands in).  With chi_d from a tessellation whose boundary vertices lie on
  * the curves, chi_d and Theta jump at slightly different places: w can be
  * off by one where the ray passes between a boundary chord and its curve.
- * Errors: INVALID_ARGUMENT, UNSUPPORTED, HIP.
+ * With chi_in and from 2^16 queries the call works on a copy of the queries
+ * (and chi_in) in a coarse Morton order, as wn_backward_curves, and scatters
+ * the results back, the same values per query; this allocates about 36
+ * bytes per query on the stream.
+ * Errors: INVALID_ARGUMENT, UNSUPPORTED, OUT_OF_MEMORY, HIP.
  * ------------------------------------------------------------------------- */
 wn_status wn_eval_3d_curves(const wn_bvh* bvh, const float* ctrl, int64_t ncurves,
                             const float* qx, const float* qy, const float* qz, int64_t nq,
@@ -228,6 +232,12 @@ wn_status wn_eval_3d_curves(const wn_bvh* bvh, const float* ctrl, int64_t ncurve
  *             reproducible; allocates 48 bytes per (256 queries, curve) on
  *             the stream.  A control point shared by two curves gets one
  *             entry per curve; the caller adds them.
+ * From 2^16 queries the call first puts a copy of the queries in a coarse
+ * Morton order (32^3 cells over their bounding box, as wn_spatial_order
+ * with 5 bits per axis), so that the lanes of a wavefront refine similar
+ * panels; grad_q is scattered back and is the same per query, and
+ * grad_ctrl is summed in that (deterministic) order.  This allocates about
+ * 40 bytes per query more on the stream.
  * Errors: INVALID_ARGUMENT, UNSUPPORTED, OUT_OF_MEMORY, HIP.
  * ------------------------------------------------------------------------- */
 wn_status wn_backward_curves(const float* ctrl, int64_t ncurves,
@@ -255,8 +265,12 @@ wn_status wn_backward_curves(const float* ctrl, int64_t ncurves,
  * are the winding number of its boundary's image around the ray; otherwise
  * it is split, down to level 16 (where it is dropped).  Non-finite queries
  * give NaN / WN_CHI_INVALID.  With w_out, one launch computes both terms per
- * query (the kernel of wn_eval_3d_patches_batched); allocates nothing.
- * Errors: INVALID_ARGUMENT, UNSUPPORTED, HIP.
+ * query (the kernel of wn_eval_3d_patches_batched).  With w_out and from
+ * 2^16 queries the call works on a copy of the queries in a coarse Morton
+ * order (as wn_backward_curves) and scatters the results back, the same
+ * values per query; this allocates about 36 bytes per query on the stream.
+ * Otherwise it allocates nothing.
+ * Errors: INVALID_ARGUMENT, UNSUPPORTED, OUT_OF_MEMORY, HIP.
  * ------------------------------------------------------------------------- */
 wn_status wn_eval_3d_patches(const double dir[3], const float* nets, int64_t npatch,
                              const float* curves, int64_t ncurves,

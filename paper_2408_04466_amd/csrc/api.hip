@@ -462,8 +462,23 @@ wn_status wn_eval_3d_curves(const wn_bvh* h, const float* ctrl, int64_t ncurves,
   if (st) return st;
   if (nq == 0) return WN_OK;
   if (!w_out) return fail(WN_ERR_INVALID_ARGUMENT, "w_out is NULL");
-  WN_HIP(wn::launch_curves3d(cross_args(h, qx, qy, qz, nq, chi_out), ctrl, ncurves, chi_in, w_out, chi_out,
-                             as_stream(stream)),
+  hipStream_t s = as_stream(stream);
+  if (chi_in && nq >= wn::kSortQueriesMin && nq <= INT32_MAX && ncurves > 0) {
+    // the boundary term alone: run on a coarse Morton-ordered copy (chi_in
+    // travels with the queries as 32-bit words) and scatter w back
+    wn::SortedQueries sq;
+    WN_HIP(wn::sort_queries(qx, qy, qz, reinterpret_cast<const float*>(chi_in), nq, chi_out ? 2 : 1, s, &sq),
+           "query order");
+    float* w = (float*)sq.out_block(0);
+    int32_t* chi = chi_out ? (int32_t*)sq.out_block(1) : nullptr;
+    WN_HIP(wn::launch_curves3d(cross_args(h, sq.x, sq.y, sq.z, nq, chi), ctrl, ncurves,
+                               reinterpret_cast<const int32_t*>(sq.g), w, chi, s),
+           "wn_eval_3d_curves");
+    WN_HIP(wn::scatter_rows(w, sq.order, nq, 1, w_out, s), "wn_eval_3d_curves");
+    if (chi_out) WN_HIP(wn::scatter_rows(chi, sq.order, nq, 1, chi_out, s), "wn_eval_3d_curves");
+    return WN_OK;
+  }
+  WN_HIP(wn::launch_curves3d(cross_args(h, qx, qy, qz, nq, chi_out), ctrl, ncurves, chi_in, w_out, chi_out, s),
          "wn_eval_3d_curves");
   return WN_OK;
 }
@@ -478,8 +493,18 @@ wn_status wn_backward_curves(const float* ctrl, int64_t ncurves, const float* qx
   if (st) return st;
   if (nq > 0 && !grad_w) return fail(WN_ERR_INVALID_ARGUMENT, "grad_w is NULL");
   if (!grad_q && !grad_ctrl) return WN_OK;
-  WN_HIP(wn::backward_curves(ctrl, ncurves, qx, qy, qz, nq, grad_w, grad_q, grad_ctrl, as_stream(stream)),
-         "wn_backward_curves");
+  hipStream_t s = as_stream(stream);
+  if (nq >= wn::kSortQueriesMin && nq <= INT32_MAX && ncurves > 0) {
+    // neighbouring lanes then refine the same panels: run on sorted copies
+    // and scatter grad_q back (the workspace is freed on the stream on return)
+    wn::SortedQueries sq;
+    WN_HIP(wn::sort_queries(qx, qy, qz, grad_w, nq, grad_q ? 3 : 0, s, &sq), "query order");
+    float* gq = grad_q ? (float*)sq.out_block(0) : nullptr;
+    WN_HIP(wn::backward_curves(ctrl, ncurves, sq.x, sq.y, sq.z, nq, sq.g, gq, grad_ctrl, s), "wn_backward_curves");
+    if (grad_q) WN_HIP(wn::scatter_rows(gq, sq.order, nq, 3, grad_q, s), "wn_backward_curves");
+    return WN_OK;
+  }
+  WN_HIP(wn::backward_curves(ctrl, ncurves, qx, qy, qz, nq, grad_w, grad_q, grad_ctrl, s), "wn_backward_curves");
   return WN_OK;
 }
 
@@ -501,6 +526,20 @@ wn_status wn_eval_3d_patches(const double dir[3], const float* nets, int64_t npa
   for (int k = 0; k < 9; ++k) F.r[k] = R[k];
   for (int k = 0; k < 3; ++k) F.c[k] = 0.0;
   hipStream_t s = as_stream(stream);
+  if (w_out && nq >= wn::kSortQueriesMin && nq <= INT32_MAX && npatch + ncurves > 0) {
+    // neighbouring lanes then walk the same sub-squares and panels: run on
+    // sorted copies and scatter the results back (every result depends on
+    // its query alone, so the values are the same bits)
+    wn::SortedQueries sq;
+    WN_HIP(wn::sort_queries(qx, qy, qz, nullptr, nq, chi_out ? 2 : 1, s, &sq), "query order");
+    float* w = (float*)sq.out_block(0);
+    int32_t* chi = chi_out ? (int32_t*)sq.out_block(1) : nullptr;
+    WN_HIP(wn::launch_psurf_single(F, nets, npatch, curves, ncurves, sq.x, sq.y, sq.z, nq, w, chi, s),
+           "wn_eval_3d_patches");
+    WN_HIP(wn::scatter_rows(w, sq.order, nq, 1, w_out, s), "wn_eval_3d_patches");
+    if (chi_out) WN_HIP(wn::scatter_rows(chi, sq.order, nq, 1, chi_out, s), "wn_eval_3d_patches");
+    return WN_OK;
+  }
   // w: crossings and curve term in one launch (no temporary chi buffer);
   // crossings only: the crossing kernel alone
   const hipError_t e = w_out ? wn::launch_psurf_single(F, nets, npatch, curves, ncurves, qx, qy, qz, nq, w_out,

@@ -35,8 +35,10 @@ struct BuildBufs {
 };
 
 size_t radix_sort_tmp_bytes(int64_t n);
+// Stable LSD radix sort on the low 8 * passes bits of the keys (passes even:
+// the result ends in keys, vals).
 hipError_t radix_sort_pairs(unsigned* keys, int32_t* vals, unsigned* keys_alt, int32_t* vals_alt,
-                            int64_t n, void* tmp, hipStream_t s);
+                            int64_t n, void* tmp, hipStream_t s, int passes = 4);
 hipError_t fill_u32(unsigned* p, int64_t n, unsigned v, hipStream_t s);
 hipError_t build_bvh_device(const BuildBufs& b, const Frame& F, const float* V, int32_t nv,
                             const int32_t* Fc, int32_t nf, float pad, hipStream_t s);

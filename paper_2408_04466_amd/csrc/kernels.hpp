@@ -108,6 +108,28 @@ hipError_t diagnose(const float* qx, const float* qy, const float* qz, const int
 // Morton-order permutation of the queries (order.hip).
 hipError_t spatial_order(const float* qx, const float* qy, const float* qz, int64_t n, int32_t* order,
                          hipStream_t s);
+// Sorted copies of a query set in a coarse Morton order (32^3 cells; order.hip),
+// for the kernels whose lanes diverge on random query orders: order, the
+// sorted coordinates (and loss weights g when given) and out_words float32 or
+// int32 words per query of output space, all in one stream-ordered
+// allocation released by the destructor (on the same stream).
+struct SortedQueries {
+  unsigned char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int32_t* order = nullptr;
+  float *x = nullptr, *y = nullptr, *z = nullptr, *g = nullptr;
+  uint32_t* out = nullptr;
+  size_t block_words = 0;   // out_block(k): the k-th output array of n words
+  uint32_t* out_block(int k) const { return out + (size_t)k * block_words; }
+  ~SortedQueries();
+};
+hipError_t sort_queries(const float* qx, const float* qy, const float* qz, const float* gw, int64_t n, int out_words,
+                        hipStream_t s, SortedQueries* o);
+// dst row order[i] = src row i (rows of `width` 32-bit words).
+hipError_t scatter_rows(const void* src, const int32_t* order, int64_t n, int width, void* dst, hipStream_t s);
+// Query count from which the curve adjoint and the parametric path sort
+// their queries first.
+constexpr int64_t kSortQueriesMin = 1 << 16;
 hipError_t backward_curves(const float* ctrl, int64_t nc, const float* qx, const float* qy, const float* qz,
                            int64_t nq, const float* gw, float* gq, float* gc, hipStream_t s);
 hipError_t launch_curves3d(const CrossArgs& c, const float* ctrl, int64_t nc, const int32_t* chi_in, float* w_out,

@@ -70,8 +70,10 @@ __device__ __forceinline__ unsigned spread10(unsigned x) {
   return x;
 }
 
+// Morton code of the query's cell in a (2^bits)^3 grid over the box
+// (bits <= 10), or 0xffffffff for a non-finite query.
 __global__ void k_qmorton(const float* __restrict__ qx, const float* __restrict__ qy, const float* __restrict__ qz,
-                          int64_t n, const unsigned* __restrict__ box, unsigned* __restrict__ keys,
+                          int64_t n, const unsigned* __restrict__ box, int bits, unsigned* __restrict__ keys,
                           int32_t* __restrict__ vals) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -86,16 +88,38 @@ __global__ void k_qmorton(const float* __restrict__ qx, const float* __restrict_
     const float lo = ord_float(box[2 * c]), hi = ord_float(box[2 * c + 1]);
     const float ext = hi - lo;
     const float t = ext > 0.f ? (p[c] - lo) / ext : 0.f;
-    const unsigned cell = (unsigned)fminf(fmaxf(t * 1024.f, 0.f), 1023.f);
+    const float cells = (float)(1u << bits);
+    const unsigned cell = (unsigned)fminf(fmaxf(t * cells, 0.f), cells - 1.f);
     code |= spread10(cell) << c;
   }
   keys[i] = code;
 }
 
-}  // namespace
+// dst row order[i] = src row i, rows of `width` 32-bit words.
+__global__ void k_scatter_rows(const uint32_t* __restrict__ src, const int32_t* __restrict__ order, int64_t n,
+                               int width, uint32_t* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t r = order[i];
+  for (int c = 0; c < width; ++c) dst[r * width + c] = src[i * width + c];
+}
 
-hipError_t spatial_order(const float* qx, const float* qy, const float* qz, int64_t n, int32_t* order,
-                         hipStream_t s) {
+// Sorted copies: x[i] = qx[order[i]] (and g[i] = gw[order[i]] when gw is set).
+__global__ void k_gather_queries(const float* __restrict__ qx, const float* __restrict__ qy,
+                                 const float* __restrict__ qz, const float* __restrict__ gw,
+                                 const int32_t* __restrict__ order, int64_t n, float* __restrict__ x,
+                                 float* __restrict__ y, float* __restrict__ z, float* __restrict__ g) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t r = order[i];
+  x[i] = qx[r];
+  y[i] = qy[r];
+  z[i] = qz[r];
+  if (gw) g[i] = gw[r];
+}
+
+hipError_t order_by_cells(const float* qx, const float* qy, const float* qz, int64_t n, int32_t* order, int bits,
+                          hipStream_t s) {
   if (n <= 0) return hipSuccess;
   auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
   const size_t b_box = up(6 * sizeof(unsigned));
@@ -120,12 +144,59 @@ hipError_t spatial_order(const float* qx, const float* qy, const float* qz, int6
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_qmorton, dim3(blocks), dim3(256), 0, s, qx, qy, qz, n, box, keys, order);
+    hipLaunchKernelGGL(k_qmorton, dim3(blocks), dim3(256), 0, s, qx, qy, qz, n, box, bits, keys, order);
     e = hipGetLastError();
   }
-  if (e == hipSuccess) e = radix_sort_pairs(keys, order, keys2, vals2, n, tmp, s);
+  // 3 * bits code bits in whole bytes, an even number of passes
+  const int passes = ((3 * bits + 15) / 16) * 2;
+  if (e == hipSuccess) e = radix_sort_pairs(keys, order, keys2, vals2, n, tmp, s, passes);
   const hipError_t e2 = hipFreeAsync(ws, s);
   return e != hipSuccess ? e : e2;
+}
+
+}  // namespace
+
+hipError_t spatial_order(const float* qx, const float* qy, const float* qz, int64_t n, int32_t* order,
+                         hipStream_t s) {
+  return order_by_cells(qx, qy, qz, n, order, 10, s);
+}
+
+SortedQueries::~SortedQueries() {
+  if (ws) (void)hipFreeAsync(ws, stream);
+}
+
+hipError_t sort_queries(const float* qx, const float* qy, const float* qz, const float* gw, int64_t n, int out_words,
+                        hipStream_t s, SortedQueries* o) {
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t b = up((size_t)n * sizeof(float));
+  const size_t bytes = 4 * b + (gw ? b : 0) + (size_t)out_words * b;
+  hipError_t e = hipMallocAsync((void**)&o->ws, bytes, s);
+  if (e != hipSuccess) {
+    o->ws = nullptr;
+    return e;
+  }
+  o->stream = s;
+  unsigned char* p = o->ws;
+  o->order = (int32_t*)p;
+  o->x = (float*)(p + b);
+  o->y = (float*)(p + 2 * b);
+  o->z = (float*)(p + 3 * b);
+  o->g = gw ? (float*)(p + 4 * b) : nullptr;
+  o->out = (uint32_t*)(p + (gw ? 5 : 4) * b);
+  o->block_words = b / sizeof(uint32_t);
+  // 32^3 cells: two radix passes; about 32 queries per cell at 2^20 queries
+  e = order_by_cells(qx, qy, qz, n, o->order, 5, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gather_queries, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, qx, qy, qz, gw, o->order, n,
+                     o->x, o->y, o->z, o->g);
+  return hipGetLastError();
+}
+
+hipError_t scatter_rows(const void* src, const int32_t* order, int64_t n, int width, void* dst, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (const uint32_t*)src, order, n,
+                     width, (uint32_t*)dst);
+  return hipGetLastError();
 }
 
 }  // namespace wn

@@ -189,7 +189,7 @@ size_t radix_sort_tmp_bytes(int64_t n) {
 }
 
 hipError_t radix_sort_pairs(unsigned* keys, int32_t* vals, unsigned* keys_alt, int32_t* vals_alt,
-                            int64_t n, void* tmp, hipStream_t s) {
+                            int64_t n, void* tmp, hipStream_t s, int passes) {
   if (n <= 1) return hipSuccess;
   const int64_t ntiles = (n + kTile - 1) / kTile;
   const int64_t m = 256 * ntiles;
@@ -200,7 +200,7 @@ hipError_t radix_sort_pairs(unsigned* keys, int32_t* vals, unsigned* keys_alt, i
   int32_t* va = vals;
   unsigned* kb = keys_alt;
   int32_t* vb = vals_alt;
-  for (int pass = 0; pass < 4; ++pass) {
+  for (int pass = 0; pass < passes; ++pass) {
     const int shift = 8 * pass;
     hipLaunchKernelGGL(k_hist, dim3((unsigned)ntiles), dim3(kThreads), 0, s, ka, n, shift, hist, ntiles);
     hipError_t e = hipGetLastError();
@@ -212,7 +212,7 @@ hipError_t radix_sort_pairs(unsigned* keys, int32_t* vals, unsigned* keys_alt, i
     unsigned* tk = ka; ka = kb; kb = tk;
     int32_t* tv = va; va = vb; vb = tv;
   }
-  // four passes: the result is back in (keys, vals)
+  // an even number of passes: the result is back in (keys, vals)
   return hipSuccess;
 }
 

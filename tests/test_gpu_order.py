@@ -108,3 +108,59 @@ def test_results_do_not_depend_on_the_order():
     w2, chi2 = W.eval_3d_patches(d, net, curves, *qo)
     torch.cuda.synchronize()
     assert torch.equal(w2, w[o]) and torch.equal(chi2, chi[o])
+
+
+def test_sorted_entry_points_match_the_unsorted_path():
+    """From 2^16 queries the parametric path and the curve adjoint run on a
+    coarse Morton-ordered copy of the queries: per-query results equal the
+    unsorted kernels' bit for bit (the one-surface batch and calls below the
+    threshold), and grad_ctrl equals the sum over halves to rounding."""
+    M = synth.coons_surface(96, 4000, 64)
+    d = synth.random_direction(97)
+    n = (1 << 16) + 1001
+    P = synth.box_queries(M.V, n, 98)
+    P[17] = np.nan
+    q = _q(P)
+    net = _dev(M.info["net"][None])
+    curves = _dev(M.info["curves"])
+    w, chi = W.eval_3d_patches(d, net, curves, *q)
+    _, chi_only = W.eval_3d_patches(d, net, curves, *q, want_w=False)
+    b = W.PatchBatch([(1, 4, n, d)])
+    wb, chib = b.eval(net, curves, *q)
+    torch.cuda.synchronize()
+    assert torch.equal(w.view(torch.int32), wb.view(torch.int32)) and torch.equal(chi, chib)
+    assert torch.equal(chi_only, chib)
+    gw = torch.from_numpy(synth.rng(99).normal(size=n).astype(np.float32)).cuda()
+    gq, gc = W.backward_curves(curves, *q, gw)
+    h = n // 2
+    gq1, gc1 = W.backward_curves(curves, *(t[:h].contiguous() for t in q), gw[:h].contiguous())
+    gq2, gc2 = W.backward_curves(curves, *(t[h:].contiguous() for t in q), gw[h:].contiguous())
+    torch.cuda.synchronize()
+    full = torch.cat([gq1, gq2])
+    assert torch.equal(torch.isnan(gq), torch.isnan(full))
+    ok = ~torch.isnan(full)
+    assert torch.equal(gq[ok], full[ok])
+    ref = (gc1.double() + gc2.double())
+    assert torch.allclose(gc.double(), ref, rtol=1e-4, atol=1e-6 * ref.abs().max().item())
+
+
+def test_sorted_curve_term_matches_the_unsorted_path():
+    """wn_eval_3d_curves with chi_in from 2^16 queries runs on a sorted copy;
+    per-query w and chi equal those of calls below the threshold."""
+    M = synth.coons_surface(101, 4000, 64)
+    d = synth.random_direction(102)
+    dm = DevMesh(M, d)
+    n = (1 << 16) + 77
+    P = synth.box_queries(M.V, n, 103)
+    P[5] = np.nan
+    q = _q(P)
+    curves = _dev(M.info["curves"])
+    chi_in = W.crossings_3d(dm.bvh, *q)
+    w, chi = W.eval_3d_curves(dm.bvh, curves, *q, chi_in=chi_in)
+    h = n // 2
+    parts = [W.eval_3d_curves(dm.bvh, curves, *(t[a:b].contiguous() for t in q), chi_in=chi_in[a:b].contiguous())
+             for a, b in ((0, h), (h, n))]
+    torch.cuda.synchronize()
+    w2 = torch.cat([p[0] for p in parts])
+    chi2 = torch.cat([p[1] for p in parts])
+    assert torch.equal(w.view(torch.int32), w2.view(torch.int32)) and torch.equal(chi, chi2)
