@@ -164,3 +164,12 @@ def test_sorted_curve_term_matches_the_unsorted_path():
     w2 = torch.cat([p[0] for p in parts])
     chi2 = torch.cat([p[1] for p in parts])
     assert torch.equal(w.view(torch.int32), w2.view(torch.int32)) and torch.equal(chi, chi2)
+    # without chi_in (one kernel at every size): the same crossings and w
+    w3, chi3 = W.eval_3d_curves(dm.bvh, curves, *q)
+    w4, _ = W.eval_3d_curves(dm.bvh, curves, *q, want_chi=False)
+    parts = [W.eval_3d_curves(dm.bvh, curves, *(t[a:b].contiguous() for t in q)) for a, b in ((0, h), (h, n))]
+    torch.cuda.synchronize()
+    w5 = torch.cat([p[0] for p in parts])
+    chi5 = torch.cat([p[1] for p in parts])
+    assert torch.equal(w3.view(torch.int32), w5.view(torch.int32)) and torch.equal(chi3, chi5)
+    assert torch.equal(w4.view(torch.int32), w5.view(torch.int32)) and torch.equal(chi3, chi)
