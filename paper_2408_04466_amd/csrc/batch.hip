@@ -178,8 +178,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
       bnd::Lane<1> s;
       rotate(D.F, px, py, pz, s.Xp[0], s.Yp[0], s.Zp[0]);
       turns_init(s.T[0]);
-      const int chi = (ok && fin) ? traverse<kShortStack, true>(ca, s.Xp[0], s.Yp[0], s.Zp[0]) : 0;
-      bnd::boundary_walk(s, stage, D.nb, L, sv, staged);
+      // odd workgroups walk the boundary first: then waves waiting on node
+      // fetches and waves issuing boundary arithmetic share every SIMD from
+      // the start (each workgroup stays uniform, so its barriers still meet)
+      int chi = 0;
+      if (blockIdx.x & 1) bnd::boundary_walk(s, stage, D.nb, L, sv, staged);
+      if (ok && fin) chi = traverse<kShortStack, true>(ca, s.Xp[0], s.Yp[0], s.Zp[0]);
+      if (!(blockIdx.x & 1)) bnd::boundary_walk(s, stage, D.nb, L, sv, staged);
       if (ok) {
         const bool valid = fin && chi != WN_CHI_INVALID;
         a.w[q] = valid ? turns_to_w(s.T[0], chi) : __int_as_float(0x7fc00000);
