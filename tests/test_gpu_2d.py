@@ -133,3 +133,28 @@ def test_2d_edge_cases():
     # non-finite queries
     w, chi = _eval(C, np.array([np.nan, 0.1]), np.array([0.0, 0.2]), np.float64, grid=False)
     assert np.isnan(w[0]) and chi[0] == W.WN_CHI_INVALID and np.isfinite(w[1])
+
+
+def test_fp64_end_point_angle_to_round_off():
+    """Straight open segments (cubics with collinear control points): w is the
+    signed angle the segment subtends at p over 2 pi, a closed form (the
+    crossing count and the end-point term add up to it), so the float64 path
+    must reproduce it to round-off."""
+    g = synth.rng(120)
+    n_seg = 6
+    S = g.uniform(-1, 1, (n_seg, 2))
+    E = S + g.uniform(-1, 1, (n_seg, 2))
+    ctrl = np.stack([S, (2 * S + E) / 3, (S + 2 * E) / 3, E], 1)          # [n, 4, 2]
+    P = g.uniform(-2, 2, (20000, 2))
+    for k in range(n_seg):
+        a, b = S[k], E[k]
+        d = b - a
+        t = np.clip(((P - a) @ d) / (d @ d), 0, 1)
+        dist = np.linalg.norm(P - (a + t[:, None] * d), axis=1)
+        keep = dist > 1e-3
+        w, _ = W.eval_2d(torch.from_numpy(ctrl[k:k + 1].copy()).cuda(), [0, 1], [0],
+                         torch.from_numpy(P[keep, 0].copy()).cuda(), torch.from_numpy(P[keep, 1].copy()).cuda())
+        torch.cuda.synchronize()
+        u, v = a - P[keep], b - P[keep]
+        ref = np.arctan2(u[:, 0] * v[:, 1] - u[:, 1] * v[:, 0], (u * v).sum(1)) / (2 * np.pi)
+        assert np.abs(w.cpu().numpy() - ref).max() <= 1e-13
