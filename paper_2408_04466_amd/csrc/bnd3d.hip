@@ -53,8 +53,9 @@ __global__ __launch_bounds__(kThreads) void k_bnd3d(BndArgs a, LoopTable L) {
 // Fused forward, one query per lane: the crossing count (BVH traversal),
 // then the boundary walk, then w.  While some waves wait on node fetches,
 // others keep the vector units busy with the boundary arithmetic.
-// Eight waves per SIMD: fits in 64 registers without spilling.
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_fwd3d(CrossArgs c, BndArgs a, LoopTable L, int32_t* chi_out) {
+// Seven waves per SIMD: with the alternating order below, the eight-wave
+// budget of 64 registers spilled.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_fwd3d(CrossArgs c, BndArgs a, LoopTable L, int32_t* chi_out) {
   __shared__ double4 sv[kChunk];
   const int64_t qi = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const bool ok = qi < a.nq;
@@ -64,10 +65,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
   Lane<1> s;
   rotate(a.F, px, py, pz, s.Xp[0], s.Yp[0], s.Zp[0]);
   turns_init(s.T[0]);
-  const int chi = (ok && fin) ? traverse<kShortStack>(c, s.Xp[0], s.Yp[0], s.Zp[0]) : WN_CHI_INVALID;
+  // odd workgroups walk the boundary first (uniform per workgroup, so the
+  // staging barriers still meet): node fetches and boundary arithmetic then
+  // overlap on every SIMD from the start
   int staged = -1;
   const KernargLoops KL{L};
-  boundary_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, staged);
+  if (blockIdx.x & 1) boundary_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, staged);
+  const int chi = (ok && fin) ? traverse<kShortStack>(c, s.Xp[0], s.Yp[0], s.Zp[0]) : WN_CHI_INVALID;
+  if (!(blockIdx.x & 1)) boundary_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, staged);
   if (ok) {
     a.w_out[q] = chi != WN_CHI_INVALID ? turns_to_w(s.T[0], chi) : __int_as_float(0x7fc00000);
     if (chi_out) chi_out[q] = chi;
