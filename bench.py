@@ -15,8 +15,8 @@ Also measured in the same run (reported beside the headline): the plain
 path on the same workload, the 256-surface batch (batched vs a loop of plain
 calls), the adjoint workload, and both 2D workloads.
 
-Prints one JSON line.  ``--gpus N`` with N > 1 exits: this build runs on one
-GPU.
+Prints one JSON line.  ``--gpus N`` with N > 1 exits with status 2: the
+library has no multi-GPU path, so the benchmark measures one GPU.
 """
 from __future__ import annotations
 
@@ -192,8 +192,8 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU (got --gpus {args.gpus}); "
-              "multi-GPU runs are not part of it", file=sys.stderr)
+        print(f"bench.py: measures exactly one GPU (got --gpus {args.gpus}); "
+              "the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     M, P, d, t = workload_c3()

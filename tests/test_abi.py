@@ -192,3 +192,14 @@ def test_missing_library_fails_loudly(tmp_path):
             "try:\n    W.lib()\nexcept RuntimeError as e:\n    print('raised', 'no fallback' in str(e))\n")
     r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=120)
     assert "raised True" in r.stdout, r.stdout + r.stderr
+
+
+def test_bench_measures_one_gpu_only():
+    """bench.py --gpus N with N > 1 exits with status 2 and a message, before
+    any device work (the library has no multi-GPU path)."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2", "--steps", "1"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "exactly one GPU" in r.stderr and r.stdout == ""
