@@ -382,6 +382,12 @@ wn_status wn_crossings_3d(const wn_bvh* bvh, const float* qx, const float* qy,
  *  grad_bnd   device [nb][3] float32 out: dL/d(bnd_xyz), or NULL.  Reduced
  *             over queries in a fixed order (float64 partial sums), so the
  *             result is bitwise reproducible.
+ * Few queries over a boundary of more than 512 vertices (fewer than 2048
+ * workgroups of 256 threads) split the boundary into ranges of whole
+ * 512-vertex chunks, one grid row per range.  grad_q is then summed over the
+ * ranges in a fixed order, from a workspace of ranges x nq x 12 bytes, so it
+ * stays bitwise reproducible.  It can differ from a call that does not split
+ * the boundary in the last bits.
  * Errors: INVALID_ARGUMENT, UNSUPPORTED, OUT_OF_MEMORY (workspace), HIP.
  * ------------------------------------------------------------------------- */
 wn_status wn_backward(const float* bnd_xyz, const int64_t* loop_off, int32_t nloops,

@@ -2,6 +2,7 @@
 // boundary vertices, for a loss L with dL/dw = g per query (one tile of
 // queries per workgroup; the walk is in adjloop.hpp), and the fixed-order
 // float64 reduction of the per-wavefront partials.
+#include "adj3d.hpp"
 #include "adjloop.hpp"
 
 namespace wn {
@@ -31,28 +32,176 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL ==
   store_gq<QPL>(S, qi, ok, a.gq);
 }
 
+// The walk of adjloop.hpp restricted to the edges that start at vertices
+// [cbeg, cend) (whole chunks; a loop's closing edge starts at its last
+// vertex).  Each vertex of the range is parked to pv exactly once, as in the
+// full walk.  A range that starts inside a loop also takes the edge
+// (cbeg - 1 -> cbeg); that edge's share of vertex cbeg - 1 goes to pc, and
+// the previous range parks the rest of that vertex at its end.  The loop's
+// first vertex and vertex cbeg - 1 then come from global memory.
+template <int QPL>
+__device__ __forceinline__ void walk_range(QState* S, const float* __restrict__ bnd, int nb,
+                                           const bnd::KernargLoops& L, int cbeg, int cend, float4* sv,
+                                           float* rsw, float* pv, float* pl, float* pc) {
+  const int lane = threadIdx.x & 63;
+  float* rs = rsw + (threadIdx.x >> 6) * kRowFloats;
+  Rel F[QPL], A[QPL], B[QPL];
+  float accA[3], accB[3];
+  float lA = 0.f;
+  zero3(accA);
+  int l = bnd::loop_of(L, cbeg);
+  bool carry_in = cbeg > L.off(l);
+  if (carry_in) {
+    const int ls = L.off(l), i = cbeg - 1;   // i + 1 = cbeg lies in the same loop
+    const float4 f = make_float4(bnd[3 * ls], bnd[3 * ls + 1], bnd[3 * ls + 2], 0.f);
+    const float x = bnd[3 * i], y = bnd[3 * i + 1], z = bnd[3 * i + 2];
+    const float ex = __fsub_rn(bnd[3 * cbeg], x), ey = __fsub_rn(bnd[3 * cbeg + 1], y),
+                ez = __fsub_rn(bnd[3 * cbeg + 2], z);
+    const float4 v = make_float4(x, y, z, __fmaf_rn(ex, ex, __fmaf_rn(ey, ey, __fmul_rn(ez, ez))));
+#pragma unroll
+    for (int k = 0; k < QPL; ++k) {
+      F[k] = rel(S[k], f);
+      A[k] = rel(S[k], v);
+    }
+    lA = v.w;
+  }
+  for (int c0 = cbeg; c0 < cend; c0 += kChunk) {
+    const int c1 = min(c0 + kChunk, cend);
+    __syncthreads();
+    for (int j = threadIdx.x; j < c1 - c0; j += kThreads) {
+      const int i = c0 + j;
+      const int lp = bnd::loop_of(L, i);
+      const int nx = (i + 1 < L.off(lp + 1)) ? i + 1 : L.off(lp);
+      const float x = bnd[3 * i], y = bnd[3 * i + 1], z = bnd[3 * i + 2];
+      const float ex = __fsub_rn(bnd[3 * nx], x), ey = __fsub_rn(bnd[3 * nx + 1], y),
+                  ez = __fsub_rn(bnd[3 * nx + 2], z);
+      sv[j] = make_float4(x, y, z, __fmaf_rn(ex, ex, __fmaf_rn(ey, ey, __fmul_rn(ez, ez))));
+    }
+    __syncthreads();
+    for (; l < L.n() && L.off(l) < c1; ++l) {
+      const int ls = L.off(l), le = L.off(l + 1);
+      int j = max(ls, c0);
+      const int j1 = min(le, c1);
+      if (j == ls) {
+        const float4 v = sv[j - c0];
+#pragma unroll
+        for (int k = 0; k < QPL; ++k) {
+          F[k] = rel(S[k], v);
+          A[k] = F[k];
+        }
+        lA = v.w;
+        zero3(accA);
+        ++j;
+      } else if (carry_in) {   // edge (cbeg - 1 -> cbeg)
+        carry_in = false;
+        const float4 v0 = sv[j - c0];
+#pragma unroll
+        for (int k = 0; k < QPL; ++k) B[k] = rel(S[k], v0);
+        zero3(accB);
+#pragma unroll
+        for (int k = 0; k < QPL; ++k) edge_grad(S[k], A[k], B[k], lA, accA, accB);
+        if (pc) put3(pc, accA, lane);
+#pragma unroll
+        for (int k = 0; k < QPL; ++k) A[k] = B[k];
+        accA[0] = accB[0]; accA[1] = accB[1]; accA[2] = accB[2];
+        lA = v0.w;
+        ++j;
+      }
+      for (; j + 2 <= j1; j += 2) {
+        const float4 v0 = sv[j - c0];
+        const float4 v1 = sv[j + 1 - c0];
+#pragma unroll
+        for (int k = 0; k < QPL; ++k) B[k] = rel(S[k], v0);
+        step<QPL>(S, A, B, lA, accA, accB, pv, rs, j - 1, nb, lane);
+#pragma unroll
+        for (int k = 0; k < QPL; ++k) A[k] = rel(S[k], v1);
+        step<QPL>(S, B, A, v0.w, accB, accA, pv, rs, j, nb, lane);
+        lA = v1.w;
+      }
+      if (j < j1) {
+        const float4 v0 = sv[j - c0];
+#pragma unroll
+        for (int k = 0; k < QPL; ++k) B[k] = rel(S[k], v0);
+        step<QPL>(S, A, B, lA, accA, accB, pv, rs, j - 1, nb, lane);
+#pragma unroll
+        for (int k = 0; k < QPL; ++k) A[k] = B[k];
+        accA[0] = accB[0]; accA[1] = accB[1]; accA[2] = accB[2];
+        lA = v0.w;
+        ++j;
+      }
+      if (j1 < le) {
+        // the loop goes on: into the next chunk, or past the range, whose
+        // last vertex is then parked with the share this range holds
+        if (c1 == cend && pv) park(rs, pv, c1 - 1, nb, accA, lane);
+        break;
+      }
+      float accF[3];
+      step<QPL>(S, A, F, lA, accA, accF, pv, rs, le - 1, nb, lane);
+      if (pl) put3(pl + 3 * (int64_t)l, accF, lane);
+      zero3(accA);
+    }
+  }
+}
+
+template <int QPL>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL == 4 ? 4 : (QPL == 2 ? 6 : 8)))) void k_adj3d_split(
+    AdjArgs a, LoopTable L, int32_t span, int32_t parts, float* carry, float* gq_part) {
+  __shared__ float4 sv[kChunk];
+  __shared__ float4 rsw[kWaves * kRowFloats / 4];
+  const int wave = threadIdx.x >> 6;
+  const int64_t bw = (int64_t)blockIdx.x * kWaves + wave;
+  const int p = blockIdx.y;
+  float* pv = a.partial ? a.partial + bw * (int64_t)a.nb * 3 : nullptr;
+  float* pl = a.partial_loop ? a.partial_loop + bw * (int64_t)L.n * 3 : nullptr;
+  float* pc = (a.partial && carry) ? carry + (bw * parts + p) * 3 : nullptr;
+  QState S[QPL];
+  int64_t qi[QPL];
+  bool ok[QPL];
+  const int64_t tile = (int64_t)kThreads * QPL;
+  const int64_t q0 = (int64_t)blockIdx.x * tile;
+  load_tile<QPL>(S, a.qx, a.qy, a.qz, a.gw, q0, min(tile, a.nq - q0), qi, ok);
+  const int cbeg = p * span;
+  const int cend = min(a.nb, cbeg + span);
+  walk_range<QPL>(S, a.bnd, a.nb, bnd::KernargLoops{L}, cbeg, cend, sv, reinterpret_cast<float*>(rsw), pv, pl,
+                  pc);
+  if (a.gq) store_gq<QPL>(S, qi, ok, gq_part + (int64_t)p * a.nq * 3);
+}
+
+__global__ void k_sum_parts(const float* __restrict__ part, int32_t parts, int64_t n, float* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  out[t] = (float)ordered_sum(part + t, n, parts, 0.0);
+}
+
 constexpr int kRowsPerGroup = 32;
 
 // Stage 1: g-th group of kRowsPerGroup partial rows, summed per column in
 // float64 (for a loop's first vertex the per-loop closing shares as well).
+// With vertex ranges (pc non-null): the vertex before a range that starts
+// inside a loop adds that range's carry slot as well.
 __global__ void k_reduce_rows(const float* __restrict__ pv, const float* __restrict__ pl,
+                              const float* __restrict__ pc, int32_t parts, int32_t span,
                               int64_t rows, int32_t nb, LoopTable L, double* __restrict__ tmp) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = (int64_t)nb * 3;
   if (t >= n) return;
   const int v = (int)(t / 3), c = (int)(t % 3);
   int lf = -1;
-  for (int l = 0; l < L.n; ++l)
+  int cp = (pc && (v + 1) % span == 0 && v + 1 < nb) ? (v + 1) / span : -1;
+  for (int l = 0; l < L.n; ++l) {
     if (L.off[l] == v && L.off[l + 1] > v) lf = l;
+    if (L.off[l] == v + 1) cp = -1;   // the range starts a loop: no carry
+  }
   const int64_t r0 = (int64_t)blockIdx.y * kRowsPerGroup;
   const int64_t r1 = min(rows, r0 + kRowsPerGroup);
   double s = 0.0;
-  if (lf < 0) {
+  if (lf < 0 && cp < 0) {
     s = ordered_sum(pv + r0 * n + t, n, r1 - r0, 0.0);
   } else {
     for (int64_t r = r0; r < r1; ++r) {
       s += (double)pv[r * n + t];
-      s += (double)pl[(r * L.n + lf) * 3 + c];
+      if (lf >= 0) s += (double)pl[(r * L.n + lf) * 3 + c];
+      if (cp >= 0) s += (double)pc[(r * parts + cp) * 3 + c];
     }
   }
   tmp[(int64_t)blockIdx.y * n + t] = s;
@@ -107,7 +256,69 @@ hipError_t launch_reduce_partials(const float* pv, const float* pl, int64_t rows
   if (n == 0) return hipSuccess;
   const int64_t groups = reduce_groups(rows);
   const unsigned bx = (unsigned)((n + 255) / 256);
-  hipLaunchKernelGGL(k_reduce_rows, dim3(bx, (unsigned)groups), dim3(256), 0, s, pv, pl, rows, nb, L, tmp);
+  hipLaunchKernelGGL(k_reduce_rows, dim3(bx, (unsigned)groups), dim3(256), 0, s, pv, pl, (const float*)nullptr,
+                     0, 0, rows, nb, L, tmp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_groups, dim3(bx), dim3(256), 0, s, tmp, groups, n, out);
+  return hipGetLastError();
+}
+
+// Queries per lane when the boundary spans more than one chunk: then the
+// ranges below keep the grid full, so four queries per lane (the cheapest
+// per pair) from 2^16 queries on.  Measured over 2048 edges: 2^18 queries
+// 0.60 ms, 2^19 1.06 ms, 2^20 1.98 ms (0.66, 1.23, 2.08 ms with adj3d_qpl and
+// no ranges).
+int adj3d_qpl_ranges(int64_t nq, int64_t nb) {
+  if (nb > kChunk && nq >= (int64_t)kThreads * 256) return 4;
+  return adj3d_qpl(nq);
+}
+
+// Vertex ranges for few query tiles: with fewer than 2048 workgroups and more
+// than one chunk, split the chunks into equal ranges until the grid reaches
+// 2048 workgroups (2^16 queries over 2048 edges: 0.26 ms, 0.45 ms unsplit).
+int adj3d_parts(int64_t nblocks, int64_t nb) {
+  const int64_t chunks = (nb + kChunk - 1) / kChunk;
+  if (nblocks <= 0 || nblocks >= 2048 || chunks < 2) return 1;
+  const int64_t want = min(chunks, (2048 + nblocks - 1) / nblocks);
+  const int64_t cpp = (chunks + want - 1) / want;
+  return (int)((chunks + cpp - 1) / cpp);
+}
+
+int32_t adj3d_span(int64_t nb, int parts) {
+  const int64_t chunks = (nb + kChunk - 1) / kChunk;
+  return (int32_t)(((chunks + parts - 1) / parts) * kChunk);
+}
+
+hipError_t launch_adj3d_split(const AdjArgs& a, const LoopTable& L, int64_t nblocks, int qpl, int parts,
+                              int32_t span, float* carry, float* gq_part, hipStream_t s) {
+  if (nblocks == 0 || parts < 1) return hipSuccess;
+  if ((int64_t)(parts - 1) * span >= a.nb) return hipErrorInvalidValue;   // every range non-empty
+  const dim3 grid((unsigned)nblocks, (unsigned)parts);
+  if (qpl == 4)
+    hipLaunchKernelGGL(k_adj3d_split<4>, grid, dim3(kThreads), 0, s, a, L, span, parts, carry, gq_part);
+  else if (qpl == 2)
+    hipLaunchKernelGGL(k_adj3d_split<2>, grid, dim3(kThreads), 0, s, a, L, span, parts, carry, gq_part);
+  else
+    hipLaunchKernelGGL(k_adj3d_split<1>, grid, dim3(kThreads), 0, s, a, L, span, parts, carry, gq_part);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_parts(const float* gq_part, int parts, int64_t n, float* gq, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, gq_part, parts, n, gq);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials_split(const float* pv, const float* pl, const float* carry, int parts,
+                                        int32_t span, int64_t rows, int32_t nb, const LoopTable& L, double* tmp,
+                                        float* out, hipStream_t s) {
+  const int64_t n = (int64_t)nb * 3;
+  if (n == 0) return hipSuccess;
+  const int64_t groups = reduce_groups(rows);
+  const unsigned bx = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_reduce_rows, dim3(bx, (unsigned)groups), dim3(256), 0, s, pv, pl, carry, parts, span, rows,
+                     nb, L, tmp);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce_groups, dim3(bx), dim3(256), 0, s, tmp, groups, n, out);

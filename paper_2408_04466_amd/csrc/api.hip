@@ -10,8 +10,10 @@
 #include <string>
 #include <vector>
 
+#include "adj3d.hpp"
 #include "bvh_build.hpp"
 #include "host.hpp"
+#include "adj3d.hpp"
 #include "kernels.hpp"
 
 namespace wn {
@@ -709,12 +711,17 @@ wn_status wn_backward(const float* bnd_xyz, const int64_t* loop_off, int32_t nlo
   if ((st = check_queries(qx, qy, qz, nq))) return st;
   if (nq > 0 && !grad_w) return fail(WN_ERR_INVALID_ARGUMENT, "grad_w is NULL");
   hipStream_t s = as_stream(stream);
-  const int qpl = wn::adj3d_qpl(nq);
+  const int qpl = wn::adj3d_qpl_ranges(nq, nb);
   const int64_t nblocks = wn::adj3d_blocks(nq, qpl);
   const int64_t rows = wn::adj3d_rows(nblocks);
+  // few query tiles over a long boundary: split the boundary into ranges
+  const int parts = wn::adj3d_parts(nblocks, nb);
+  const int32_t span = wn::adj3d_span(nb, parts);
   float* pv = nullptr;
   float* pl = nullptr;
   double* tmp = nullptr;
+  float* pc = nullptr;   // [rows][parts][3] (parts > 1)
+  float* gqp = nullptr;  // [parts][nq][3] (parts > 1)
   if (grad_bnd && nb > 0) {
     if (rows == 0) {
       WN_HIP(wn::fill_u32(reinterpret_cast<unsigned*>(grad_bnd), nb * 3, 0u, s), "zero grad_bnd");
@@ -723,11 +730,22 @@ wn_status wn_backward(const float* bnd_xyz, const int64_t* loop_off, int32_t nlo
       hipError_t e = hipMallocAsync((void**)&pl, (size_t)(rows * nloops * 3) * sizeof(float), s);
       if (e == hipSuccess)
         e = hipMallocAsync((void**)&tmp, (size_t)(wn::reduce_groups(rows) * nb * 3) * sizeof(double), s);
+      if (e == hipSuccess && parts > 1)
+        e = hipMallocAsync((void**)&pc, (size_t)(rows * parts * 3) * sizeof(float), s);
       if (e != hipSuccess) {
         hipFreeAsync(pv, s);
         if (pl) hipFreeAsync(pl, s);
+        if (tmp) hipFreeAsync(tmp, s);
         return hip_fail(e, "partials");
       }
+    }
+  }
+  if (parts > 1 && grad_q && nq > 0 && nb > 0) {
+    hipError_t e = hipMallocAsync((void**)&gqp, (size_t)(parts * nq * 3) * sizeof(float), s);
+    if (e != hipSuccess) {
+      if (pv) { hipFreeAsync(pv, s); hipFreeAsync(pl, s); hipFreeAsync(tmp, s); }
+      if (pc) hipFreeAsync(pc, s);
+      return hip_fail(e, "query partials");
     }
   }
   if (nq > 0 && (grad_q || pv)) {
@@ -745,9 +763,19 @@ wn_status wn_backward(const float* bnd_xyz, const int64_t* loop_off, int32_t nlo
       a.gq = grad_q;
       a.partial = pv;
       a.partial_loop = pl;
-      hipError_t e = wn::launch_adj3d(a, L, nblocks, qpl, s);
-      if (e == hipSuccess && pv) e = wn::launch_reduce_partials(pv, pl, rows, (int32_t)nb, L, tmp, grad_bnd, s);
+      hipError_t e;
+      if (parts > 1) {
+        e = wn::launch_adj3d_split(a, L, nblocks, qpl, parts, span, pc, gqp, s);
+        if (e == hipSuccess && grad_q) e = wn::launch_sum_parts(gqp, parts, nq * 3, grad_q, s);
+        if (e == hipSuccess && pv)
+          e = wn::launch_reduce_partials_split(pv, pl, pc, parts, span, rows, (int32_t)nb, L, tmp, grad_bnd, s);
+      } else {
+        e = wn::launch_adj3d(a, L, nblocks, qpl, s);
+        if (e == hipSuccess && pv) e = wn::launch_reduce_partials(pv, pl, rows, (int32_t)nb, L, tmp, grad_bnd, s);
+      }
       if (pv) { hipFreeAsync(pv, s); hipFreeAsync(pl, s); hipFreeAsync(tmp, s); }
+      if (pc) hipFreeAsync(pc, s);
+      if (gqp) hipFreeAsync(gqp, s);
       if (e != hipSuccess) return hip_fail(e, "backward");
     }
   }

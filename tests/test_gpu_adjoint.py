@@ -120,3 +120,76 @@ def test_backward_deterministic_and_edge_cases():
     gq, gb = a
     tot = gq.double().sum(0) + gb.double().sum(0)
     assert tot.abs().max().item() <= 1e-3 * gb.double().abs().sum().item()
+
+
+def _seg_dist(P, loops):
+    """Distance from each point to the nearest edge of the closed loops."""
+    A = np.concatenate(loops).astype(np.float64)
+    B = np.concatenate([np.roll(l, -1, 0) for l in loops]).astype(np.float64)
+    E = B - A
+    ee = np.maximum((E * E).sum(1), 1e-30)
+    out = np.empty(len(P))
+    for s in range(0, len(P), 1024):
+        X = P[s:s + 1024, None, :].astype(np.float64) - A[None]
+        t = np.clip((X * E[None]).sum(2) / ee, 0.0, 1.0)
+        out[s:s + 1024] = np.sqrt(((X - t[..., None] * E[None]) ** 2).sum(2)).min(1)
+    return out
+
+
+def test_boundary_ranges_for_few_queries():
+    """Few query tiles over a boundary of several 512-vertex chunks: the
+    boundary is split into ranges of whole chunks (4 ranges up to 90000
+    queries here, 2 at 700000).  Loops start on a range start, straddle range
+    starts and end on the last vertex.  Against the unsplit kernel (the same
+    queries inside a 2^21-query call, the others with dL/dw = 0) to rounding,
+    against the closed-form oracle away from the boundary (grad_bnd up to
+    90000 queries, grad_q of the first 4096 kept queries), and bitwise
+    repeatable."""
+    g = synth.rng(31)
+    lens = [300, 212, 700, 5, 3, 598, 230]   # starts 0, 300, 512, 1212, 1217, 1220, 1818
+    loops = []
+    for n in lens:
+        t = np.sort(g.uniform(0, 2 * np.pi, n))
+        r = 0.5 + 0.2 * g.uniform(size=n)
+        c = g.uniform(-0.3, 0.3, 3)
+        loops.append((np.c_[r * np.cos(t), r * np.sin(t), 0.3 * g.normal(size=n)] + c).astype(np.float32))
+    V = np.concatenate(loops)
+    assert len(V) == 2048
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    bnd = torch.from_numpy(V).cuda()
+    L64 = [l.astype(np.float64) for l in loops]
+    big = 1 << 21
+    for nq in (1, 3000, 90000, 700000):
+        P = g.uniform(-1.2, 1.2, (nq, 3)).astype(np.float32)
+        gw = g.normal(size=nq).astype(np.float32)
+        q = tuple(torch.from_numpy(np.ascontiguousarray(P[:, k])).cuda() for k in range(3))
+        gwt = torch.from_numpy(gw).cuda()
+        gq, gb = W.backward(bnd, off, *q, gwt)
+        gq2, gb2 = W.backward(bnd, off, *q, gwt)
+        Pb = np.concatenate([P, g.uniform(-1.2, 1.2, (big - nq, 3)).astype(np.float32)])
+        qb = tuple(torch.from_numpy(np.ascontiguousarray(Pb[:, k])).cuda() for k in range(3))
+        gwb = torch.zeros(big, dtype=torch.float32, device="cuda")
+        gwb[:nq] = gwt
+        gqb, gbb = W.backward(bnd, off, *qb, gwb)
+        torch.cuda.synchronize()
+        assert torch.equal(gq, gq2) and torch.equal(gb, gb2)
+        assert _rel(gq.cpu().numpy(), gqb[:nq].cpu().numpy()) <= 1e-5, nq
+        assert _rel(gb.cpu().numpy(), gbb.cpu().numpy()) <= 1e-5, nq
+        if nq > 90000:   # grad_q only: each query's row depends on that query alone
+            far = np.nonzero(_seg_dist(P[:6000], loops) >= 0.02)[0][:4096]
+            a, _ = G.grad3d(L64, P[far].astype(np.float64), gw[far].astype(np.float64))
+            assert _rel(gq.cpu().numpy()[far], a) <= 1e-3, nq
+            continue
+        far = _seg_dist(P, loops) >= 0.02
+        Pf, gf = P[far], gw[far]
+        qf = tuple(torch.from_numpy(np.ascontiguousarray(Pf[:, k])).cuda() for k in range(3))
+        gqf, gbf = W.backward(bnd, off, *qf, torch.from_numpy(gf).cuda())
+        torch.cuda.synchronize()
+        rq = np.zeros((len(Pf), 3))
+        rv = np.zeros((len(V), 3))
+        for s in range(0, len(Pf), 2048):
+            a, b = G.grad3d(L64, Pf[s:s + 2048].astype(np.float64), gf[s:s + 2048].astype(np.float64))
+            rq[s:s + 2048] = a
+            rv += np.concatenate(b, 0)
+        assert _rel(gqf.cpu().numpy(), rq) <= 1e-3, nq
+        assert _rel(gbf.cpu().numpy(), rv) <= 1e-3, nq
