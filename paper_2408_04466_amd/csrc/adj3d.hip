@@ -218,11 +218,12 @@ __global__ void k_reduce_groups(const double* __restrict__ tmp, int64_t groups, 
 
 }  // namespace
 
-// Queries per lane for nq queries (measured on a 256-CU MI355X): 4 (the
-// cheapest per pair: the cross-lane sums are shared by four queries) once
-// that leaves four wavefronts per SIMD (nq >= 2^20); 2 down to one wavefront
-// per SIMD (nq >= 2^17; at 2^18 queries x 2048 edges 0.75 ms against 0.87
-// ms with 4 and 0.94 ms with 1); 1 below.
+// Queries per lane for nq queries when the grid cannot be filled by
+// boundary ranges (measured on a 256-CU MI355X, 2048 edges, no ranges): 4
+// (the cheapest per pair: the cross-lane sums are shared by four queries)
+// once that leaves four wavefronts per SIMD (nq >= 2^20); 2 down to one
+// wavefront per SIMD (nq >= 2^17; at 2^18 queries 0.75 ms against 0.87 ms
+// with 4 and 0.94 ms with 1); 1 below.
 int adj3d_qpl(int64_t nq) {
   const int64_t simds = 4 * 256;
   if (nq >= (int64_t)kThreads * 4 * simds) return 4;
