@@ -396,6 +396,30 @@ wn_status wn_backward(const float* bnd_xyz, const int64_t* loop_off, int32_t nlo
                       void* stream);
 
 /* ---------------------------------------------------------------------------
+ * wn_backward_noalloc -- wn_backward for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops or harnesses that
+ * forbid allocation).  Same arguments, kernels, results (bit for bit) and
+ * errors as wn_backward; the call makes no device allocation or free.
+ *
+ * Its workspace (per-wavefront vertex partials, first-stage float64 sums,
+ * per-range query gradients) lives in one library-held device array of
+ * WN_NOALLOC_SCRATCH_BYTES bytes.  Each GPU holds its own copy until the
+ * process ends; its address is looked up on the first call on that device.
+ * A call whose workspace does not fit returns WN_ERR_UNSUPPORTED and
+ * enqueues nothing (the workspace of 2^20 queries over 512 boundary vertices
+ * is about 27 MB, of 2^18 queries over 2048 vertices about 39 MB).
+ * Every call on one GPU uses that GPU's array: calls that overlap in time on
+ * one GPU (other streams, other host threads) race and must be serialised
+ * by the caller.  The array keeps the last call's contents; every entry a
+ * call reads was written by that call first.
+ * ------------------------------------------------------------------------- */
+#define WN_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+wn_status wn_backward_noalloc(const float* bnd_xyz, const int64_t* loop_off, int32_t nloops,
+                              const float* qx, const float* qy, const float* qz, int64_t nq,
+                              const float* grad_w, float* grad_q, float* grad_bnd,
+                              void* stream);
+
+/* ---------------------------------------------------------------------------
  * wn_eval_2d -- w_C(p) for loops of cubic Bezier curves (Sec. 3 2D
  * definition; Sec. 6 2D parametric geometry).  The ray direction is +x.
  *

@@ -53,6 +53,7 @@ SIGNATURES = {
     "wn_eval_3d_patches_batched": (I32, [P, P, P, P, P, P, P, P, P]),
     "wn_crossings_3d": (I32, [P, P, P, P, I64, P, P]),
     "wn_backward": (I32, [P, PI64, I32, P, P, P, I64, P, P, P, P]),
+    "wn_backward_noalloc": (I32, [P, PI64, I32, P, P, P, I64, P, P, P, P]),
     "wn_eval_2d": (I32, [I32, P, I64, PI64, P, I32, I32, P, P, I64, I64, P, P, P]),
     "wn_backward_2d": (I32, [I32, P, I64, PI64, P, I32, I32, P, P, I64, I64, P, P, P, P]),
     "wn_batch2d_create": (I32, [I32, P, I32, P, C.POINTER(P)]),

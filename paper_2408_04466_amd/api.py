@@ -244,20 +244,27 @@ def crossings_3d(bvh: BVH, qx, qy, qz, stream=None):
 
 
 def backward(bnd_xyz, loop_off, qx, qy, qz, grad_w, want_q: bool = True, want_bnd: bool = True,
-             stream=None):
-    """(dL/dq [nq, 3] or None, dL/d bnd_xyz [nb, 3] or None) for dL/dw = grad_w."""
+             stream=None, grad_q=None, grad_bnd=None, noalloc: bool = False):
+    """(dL/dq [nq, 3] or None, dL/d bnd_xyz [nb, 3] or None) for dL/dw = grad_w.
+
+    ``grad_q`` / ``grad_bnd`` may be given as preallocated outputs.  With
+    ``noalloc`` the call goes to ``wn_backward_noalloc``: the library then
+    allocates nothing (its workspace is a library-held device array)."""
     lo, nl = _loops(loop_off)
     nb = int(lo[-1]) if nl else 0
     pb = _dev(bnd_xyz, torch.float32, "bnd_xyz", (nb, 3))
     px, py, pz, nq = _queries(qx, qy, qz)
     pg = _dev(grad_w, torch.float32, "grad_w", (nq,))
     dev = qx.device
-    gq = torch.empty((nq, 3), dtype=torch.float32, device=dev) if want_q else None
-    gb = torch.empty((nb, 3), dtype=torch.float32, device=dev) if want_bnd else None
-    check(lib().wn_backward(pb, _ptr64(lo), nl, px, py, pz, nq, pg,
-                            _dev(gq, torch.float32, "grad_q") if gq is not None else None,
-                            _dev(gb, torch.float32, "grad_bnd") if gb is not None else None,
-                            _stream(stream)), "wn_backward")
+    gq = grad_q if grad_q is not None else (
+        torch.empty((nq, 3), dtype=torch.float32, device=dev) if want_q else None)
+    gb = grad_bnd if grad_bnd is not None else (
+        torch.empty((nb, 3), dtype=torch.float32, device=dev) if want_bnd else None)
+    name = "wn_backward_noalloc" if noalloc else "wn_backward"
+    check(getattr(lib(), name)(pb, _ptr64(lo), nl, px, py, pz, nq, pg,
+                               _dev(gq, torch.float32, "grad_q", (nq, 3)) if gq is not None else None,
+                               _dev(gb, torch.float32, "grad_bnd", (nb, 3)) if gb is not None else None,
+                               _stream(stream)), name)
     return gq, gb
 
 

@@ -63,6 +63,100 @@ wn_status make_loops(const int64_t* loop_off, int32_t nloops, int32_t min_len, i
   return WN_OK;
 }
 
+// Argument checks of the 3D adjoint entry points.
+wn_status check_backward(const float* bnd_xyz, const int64_t* loop_off, int32_t nloops, const float* qx,
+                         const float* qy, const float* qz, int64_t nq, const float* grad_w, LoopTable* L,
+                         int64_t* nb) {
+  wn_status st = make_loops(loop_off, nloops, 3, nb, L);
+  if (st) return st;
+  if (*nb > 0 && !bnd_xyz) return fail(WN_ERR_INVALID_ARGUMENT, "bnd_xyz is NULL");
+  if (nq < 0) return fail(WN_ERR_INVALID_ARGUMENT, "nq must be >= 0");
+  if (nq > 0 && (!qx || !qy || !qz)) return fail(WN_ERR_INVALID_ARGUMENT, "NULL query pointer");
+  if (nq > 0 && !grad_w) return fail(WN_ERR_INVALID_ARGUMENT, "grad_w is NULL");
+  return WN_OK;
+}
+
+AdjPlan plan_backward(int64_t nq, int64_t nb, int32_t nloops, bool want_q, bool want_bnd) {
+  AdjPlan P;
+  P.qpl = wn::adj3d_qpl_ranges(nq, nb);
+  P.nblocks = wn::adj3d_blocks(nq, P.qpl);
+  P.rows = wn::adj3d_rows(P.nblocks);
+  // few query tiles over a long boundary: split the boundary into ranges
+  P.parts = wn::adj3d_parts(P.nblocks, nb);
+  P.span = wn::adj3d_span(nb, P.parts);
+  if (want_bnd && nb > 0 && P.rows > 0) {
+    P.n_pv = (size_t)(P.rows * nb * 3);
+    P.n_pl = (size_t)(P.rows * nloops * 3);
+    P.n_tmp = (size_t)(wn::reduce_groups(P.rows) * nb * 3);
+    if (P.parts > 1) P.n_pc = (size_t)(P.rows * P.parts * 3);
+  }
+  if (P.parts > 1 && want_q && nq > 0 && nb > 0) P.n_gqp = (size_t)(P.parts * nq * 3);
+  return P;
+}
+
+static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t plan_bytes(const AdjPlan& P) {
+  return round256(P.n_pv * sizeof(float)) + round256(P.n_pl * sizeof(float)) +
+         round256(P.n_tmp * sizeof(double)) + round256(P.n_pc * sizeof(float)) +
+         round256(P.n_gqp * sizeof(float));
+}
+
+AdjWork carve_backward(const AdjPlan& P, void* base) {
+  AdjWork W;
+  char* b = static_cast<char*>(base);
+  size_t o = 0;
+  auto take = [&](size_t bytes) -> void* {
+    if (!bytes) return nullptr;
+    void* p = b + o;
+    o += round256(bytes);
+    return p;
+  };
+  W.pv = static_cast<float*>(take(P.n_pv * sizeof(float)));
+  W.pl = static_cast<float*>(take(P.n_pl * sizeof(float)));
+  W.tmp = static_cast<double*>(take(P.n_tmp * sizeof(double)));
+  W.pc = static_cast<float*>(take(P.n_pc * sizeof(float)));
+  W.gqp = static_cast<float*>(take(P.n_gqp * sizeof(float)));
+  return W;
+}
+
+wn_status run_backward(const AdjPlan& P, const float* bnd_xyz, const LoopTable& L, int64_t nb, const float* qx,
+                       const float* qy, const float* qz, int64_t nq, const float* grad_w, float* grad_q,
+                       float* grad_bnd, const AdjWork& W, hipStream_t s) {
+  if (grad_bnd && nb > 0 && P.rows == 0)
+    WN_HIP(wn::fill_u32(reinterpret_cast<unsigned*>(grad_bnd), nb * 3, 0u, s), "zero grad_bnd");
+  float* pv = grad_bnd ? W.pv : nullptr;
+  if (nq == 0 || !(grad_q || pv)) return WN_OK;
+  if (nb == 0) {
+    if (grad_q) WN_HIP(wn::fill_u32(reinterpret_cast<unsigned*>(grad_q), nq * 3, 0u, s), "zero grad_q");
+    return WN_OK;
+  }
+  wn::AdjArgs a;
+  a.bnd = bnd_xyz;
+  a.nb = (int32_t)nb;
+  a.qx = qx;
+  a.qy = qy;
+  a.qz = qz;
+  a.nq = nq;
+  a.gw = grad_w;
+  a.gq = grad_q;
+  a.partial = pv;
+  a.partial_loop = pv ? W.pl : nullptr;
+  hipError_t e;
+  if (P.parts > 1) {
+    e = wn::launch_adj3d_split(a, L, P.nblocks, P.qpl, P.parts, P.span, pv ? W.pc : nullptr, W.gqp, s);
+    if (e == hipSuccess && grad_q) e = wn::launch_sum_parts(W.gqp, P.parts, nq * 3, grad_q, s);
+    if (e == hipSuccess && pv)
+      e = wn::launch_reduce_partials_split(pv, W.pl, W.pc, P.parts, P.span, P.rows, (int32_t)nb, L, W.tmp,
+                                           grad_bnd, s);
+  } else {
+    e = wn::launch_adj3d(a, L, P.nblocks, P.qpl, s);
+    if (e == hipSuccess && pv) e = wn::launch_reduce_partials(pv, W.pl, P.rows, (int32_t)nb, L, W.tmp, grad_bnd, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "backward");
+  return WN_OK;
+}
+
 }  // namespace host
 }  // namespace wn
 
@@ -705,81 +799,28 @@ wn_status wn_backward(const float* bnd_xyz, const int64_t* loop_off, int32_t nlo
   g_err.clear();
   wn::LoopTable L;
   int64_t nb = 0;
-  wn_status st = make_loops(loop_off, nloops, 3, &nb, &L);
+  wn_status st = wn::host::check_backward(bnd_xyz, loop_off, nloops, qx, qy, qz, nq, grad_w, &L, &nb);
   if (st) return st;
-  if (nb > 0 && !bnd_xyz) return fail(WN_ERR_INVALID_ARGUMENT, "bnd_xyz is NULL");
-  if ((st = check_queries(qx, qy, qz, nq))) return st;
-  if (nq > 0 && !grad_w) return fail(WN_ERR_INVALID_ARGUMENT, "grad_w is NULL");
   hipStream_t s = as_stream(stream);
-  const int qpl = wn::adj3d_qpl_ranges(nq, nb);
-  const int64_t nblocks = wn::adj3d_blocks(nq, qpl);
-  const int64_t rows = wn::adj3d_rows(nblocks);
-  // few query tiles over a long boundary: split the boundary into ranges
-  const int parts = wn::adj3d_parts(nblocks, nb);
-  const int32_t span = wn::adj3d_span(nb, parts);
-  float* pv = nullptr;
-  float* pl = nullptr;
-  double* tmp = nullptr;
-  float* pc = nullptr;   // [rows][parts][3] (parts > 1)
-  float* gqp = nullptr;  // [parts][nq][3] (parts > 1)
-  if (grad_bnd && nb > 0) {
-    if (rows == 0) {
-      WN_HIP(wn::fill_u32(reinterpret_cast<unsigned*>(grad_bnd), nb * 3, 0u, s), "zero grad_bnd");
-    } else {
-      WN_HIP(hipMallocAsync((void**)&pv, (size_t)(rows * nb * 3) * sizeof(float), s), "partials");
-      hipError_t e = hipMallocAsync((void**)&pl, (size_t)(rows * nloops * 3) * sizeof(float), s);
-      if (e == hipSuccess)
-        e = hipMallocAsync((void**)&tmp, (size_t)(wn::reduce_groups(rows) * nb * 3) * sizeof(double), s);
-      if (e == hipSuccess && parts > 1)
-        e = hipMallocAsync((void**)&pc, (size_t)(rows * parts * 3) * sizeof(float), s);
-      if (e != hipSuccess) {
-        hipFreeAsync(pv, s);
-        if (pl) hipFreeAsync(pl, s);
-        if (tmp) hipFreeAsync(tmp, s);
-        return hip_fail(e, "partials");
-      }
-    }
+  const wn::host::AdjPlan P = wn::host::plan_backward(nq, nb, nloops, grad_q != nullptr, grad_bnd != nullptr);
+  wn::host::AdjWork W;
+  // each workspace array on the stream, freed on the stream after the launches
+  hipError_t e = hipSuccess;
+  if (P.n_pv) e = hipMallocAsync((void**)&W.pv, P.n_pv * sizeof(float), s);
+  if (e == hipSuccess && P.n_pl) e = hipMallocAsync((void**)&W.pl, P.n_pl * sizeof(float), s);
+  if (e == hipSuccess && P.n_tmp) e = hipMallocAsync((void**)&W.tmp, P.n_tmp * sizeof(double), s);
+  if (e == hipSuccess && P.n_pc) e = hipMallocAsync((void**)&W.pc, P.n_pc * sizeof(float), s);
+  if (e == hipSuccess && P.n_gqp) e = hipMallocAsync((void**)&W.gqp, P.n_gqp * sizeof(float), s);
+  if (e == hipSuccess) {
+    st = wn::host::run_backward(P, bnd_xyz, L, nb, qx, qy, qz, nq, grad_w, grad_q, grad_bnd, W, s);
   }
-  if (parts > 1 && grad_q && nq > 0 && nb > 0) {
-    hipError_t e = hipMallocAsync((void**)&gqp, (size_t)(parts * nq * 3) * sizeof(float), s);
-    if (e != hipSuccess) {
-      if (pv) { hipFreeAsync(pv, s); hipFreeAsync(pl, s); hipFreeAsync(tmp, s); }
-      if (pc) hipFreeAsync(pc, s);
-      return hip_fail(e, "query partials");
-    }
-  }
-  if (nq > 0 && (grad_q || pv)) {
-    if (nb == 0) {
-      if (grad_q) WN_HIP(wn::fill_u32(reinterpret_cast<unsigned*>(grad_q), nq * 3, 0u, s), "zero grad_q");
-    } else {
-      wn::AdjArgs a;
-      a.bnd = bnd_xyz;
-      a.nb = (int32_t)nb;
-      a.qx = qx;
-      a.qy = qy;
-      a.qz = qz;
-      a.nq = nq;
-      a.gw = grad_w;
-      a.gq = grad_q;
-      a.partial = pv;
-      a.partial_loop = pl;
-      hipError_t e;
-      if (parts > 1) {
-        e = wn::launch_adj3d_split(a, L, nblocks, qpl, parts, span, pc, gqp, s);
-        if (e == hipSuccess && grad_q) e = wn::launch_sum_parts(gqp, parts, nq * 3, grad_q, s);
-        if (e == hipSuccess && pv)
-          e = wn::launch_reduce_partials_split(pv, pl, pc, parts, span, rows, (int32_t)nb, L, tmp, grad_bnd, s);
-      } else {
-        e = wn::launch_adj3d(a, L, nblocks, qpl, s);
-        if (e == hipSuccess && pv) e = wn::launch_reduce_partials(pv, pl, rows, (int32_t)nb, L, tmp, grad_bnd, s);
-      }
-      if (pv) { hipFreeAsync(pv, s); hipFreeAsync(pl, s); hipFreeAsync(tmp, s); }
-      if (pc) hipFreeAsync(pc, s);
-      if (gqp) hipFreeAsync(gqp, s);
-      if (e != hipSuccess) return hip_fail(e, "backward");
-    }
-  }
-  return WN_OK;
+  if (W.pv) hipFreeAsync(W.pv, s);
+  if (W.pl) hipFreeAsync(W.pl, s);
+  if (W.tmp) hipFreeAsync(W.tmp, s);
+  if (W.pc) hipFreeAsync(W.pc, s);
+  if (W.gqp) hipFreeAsync(W.gqp, s);
+  if (e != hipSuccess) return hip_fail(e, "backward workspace");
+  return st;
 }
 
 // Checks shared by the 2D entry points (curves, loop table, query layout).

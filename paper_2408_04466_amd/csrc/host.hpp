@@ -18,6 +18,41 @@ wn_status make_loops(const int64_t* loop_off, int32_t nloops, int32_t min_len, i
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Launch plan of the 3D adjoint for nq queries over nb boundary vertices:
+// the tile shape, the boundary ranges and the element counts of the
+// workspace arrays (0 where an array is not needed).
+struct AdjPlan {
+  int qpl = 1;
+  int64_t nblocks = 0, rows = 0;
+  int parts = 1;
+  int32_t span = 0;
+  size_t n_pv = 0;    // float [rows][nb][3]: per-wavefront vertex partials
+  size_t n_pl = 0;    // float [rows][nloops][3]: closing-edge shares of first vertices
+  size_t n_tmp = 0;   // double [groups][nb][3]: first reduction stage
+  size_t n_pc = 0;    // float [rows][parts][3]: carry slots of split ranges
+  size_t n_gqp = 0;   // float [parts][nq][3]: per-range query gradients
+};
+struct AdjWork {
+  float* pv = nullptr;
+  float* pl = nullptr;
+  double* tmp = nullptr;
+  float* pc = nullptr;
+  float* gqp = nullptr;
+};
+
+wn_status check_backward(const float* bnd_xyz, const int64_t* loop_off, int32_t nloops, const float* qx,
+                         const float* qy, const float* qz, int64_t nq, const float* grad_w, LoopTable* L,
+                         int64_t* nb);
+AdjPlan plan_backward(int64_t nq, int64_t nb, int32_t nloops, bool want_q, bool want_bnd);
+// Bytes of one block holding every workspace array of the plan (each
+// 256-byte aligned), and the arrays carved out of such a block.
+size_t plan_bytes(const AdjPlan& P);
+AdjWork carve_backward(const AdjPlan& P, void* base);
+// Enqueue the adjoint kernels and reductions of the plan on s.
+wn_status run_backward(const AdjPlan& P, const float* bnd_xyz, const LoopTable& L, int64_t nb, const float* qx,
+                       const float* qy, const float* qz, int64_t nq, const float* grad_w, float* grad_q,
+                       float* grad_bnd, const AdjWork& W, hipStream_t s);
+
 }  // namespace host
 }  // namespace wn
 
