@@ -36,16 +36,24 @@ A triangle (v0, v1, v2) has normal n = (v1 - v0) x (v2 - v0); a hit counts
 sign(d . n) (+1 when the ray runs along the normal, i.e. enters from the back).
 
 Readings of the paper taken here: strict t > 0 (the paper writes t >= 0 in
-Alg. 1 and t > 0 in Eq. ray_bezier_int; w is undefined on M anyway); a ray
-through an edge or vertex, or a query on M, is *degenerate* and reported
-through the margins below instead of being resolved.
+Alg. 1 and t > 0 in Eq. ray_bezier_int; w is undefined on M anyway).  A query
+is *degenerate* (its chi_d is not compared bit for bit) when the line of its
+ray passes within BAND of the projected boundary, when p lies within BAND of
+the surface, or when a triangle the ray nearly hits has an edge value too
+small for the oracle's own float64 predicates (see BAND).  By Lemma 1 a ray
+close to an interior edge or vertex is not degenerate: any consistent
+evaluation (the two triangles of a shared edge decide it oppositely) gives
+the same chi_d there.
 
 Pinned by (tests/test_oracle_3d.py): the per-triangle solid-angle sum (the
 plain definition of w_M), quadrature of Eq. wn_chi over a spherical Fibonacci
 set, the flat-disk closed form, exact {0, 1} for closed meshes, invariance
 under a change of d, orientation flip, union additivity, Lemma 2 on random
 direction pairs straddling one projected boundary edge, and an independent
-Moller-Trumbore crossing count.
+Moller-Trumbore crossing count.  The distance helpers and the margins
+(tests/test_oracle_margins.py): analytic distances, brute-force sampling of
+segments, triangles and loops, and queries placed at known fractions of
+BAND from a boundary edge, a triangle, and an interior edge.
 """
 from __future__ import annotations
 
@@ -54,13 +62,23 @@ import math
 import numpy as np
 
 TWO_PI = 2.0 * math.pi
-# Relative margin below which a query is degenerate.  Margins are normalised
-# edge values d.(a x b)/(|a_perp||b_perp|), vertex offsets |a_perp|/|a| and
-# depths |t|/max(|a|,|b|,|c|); a float32 evaluation of the same predicates
-# relative to p (coordinates rounded once, two rounded products and one
-# difference) errs by at most about 2^-22 in these units, so a band of 2^-20
-# leaves a factor of four.
+# Degeneracy bands.  A float32/float64 evaluation relative to p decides every
+# ray/triangle predicate exactly on a *perturbed* copy of the mesh: each vertex
+# moved in the plane perpendicular to d by at most 2^-23 |v - p| (coordinates
+# rounded, scale factors rounded) plus 2^-50 of the scene size (the float64
+# frame).  The signed crossing count of that copy equals the exact one unless
+# the perturbation carries the projected boundary across the ray or the
+# surface across p (Lemma 1: chi is constant on the regions cut out by the
+# projected boundary; it also changes where p crosses M).  BAND is the
+# relative distance (ray to projected boundary, p to a triangle) below which
+# a query is degenerate; a factor of eight above the perturbation.
 BAND = 2.0 ** -20
+# The oracle's own float64 predicates are exact for edge values above
+# 2^-40 |a||b| (their rounding error is below 2^-50 |a||b|); a triangle the
+# ray nearly hits with a smaller edge value makes the query degenerate too.
+BAND_SELF = 2.0 ** -40
+# Scene-size term added to every relative scale (covers the float64 frame).
+ABS_REL = 2.0 ** -26
 
 
 # ----------------------------------------------------------------------------
@@ -135,7 +153,67 @@ def frame(d) -> np.ndarray:
 # crossing count (Eq. chi)
 # ----------------------------------------------------------------------------
 
-def crossings(V, F, P, d, margins: bool = False):
+def point_triangle_distance(p, A, B, C) -> np.ndarray:
+    """Euclidean distance from the point p to each triangle (A[i], B[i], C[i])
+    (closest point in the plane when its projection falls inside, else on the
+    nearest edge; degenerate triangles use their edges only)."""
+    p = np.asarray(p, np.float64)
+    A, B, C = (np.atleast_2d(np.asarray(x, np.float64)) for x in (A, B, C))
+    n = np.cross(B - A, C - A)
+    nn = np.einsum("ij,ij->i", n, n)
+    out = np.minimum(np.minimum(segment_distance(p, A, B), segment_distance(p, B, C)),
+                     segment_distance(p, C, A))
+    ok = nn > 0
+    if np.any(ok):
+        a, b, c, m = A[ok] - p, B[ok] - p, C[ok] - p, n[ok]
+        # the projection of p lies inside iff p sees every edge on the side of n
+        s_ab = np.einsum("ij,ij->i", np.cross(a, b), m)
+        s_bc = np.einsum("ij,ij->i", np.cross(b, c), m)
+        s_ca = np.einsum("ij,ij->i", np.cross(c, a), m)
+        inside = (s_ab >= 0) & (s_bc >= 0) & (s_ca >= 0)
+        dplane = np.abs(np.einsum("ij,ij->i", a, m)) / np.sqrt(nn[ok])
+        sub = out[ok]
+        sub[inside] = dplane[inside]
+        out[ok] = sub
+    return out
+
+
+def segment_distance(p, A, B) -> np.ndarray:
+    """Distance from p to each segment [A[i], B[i]] (clamped projection)."""
+    p = np.asarray(p, np.float64)
+    A = np.atleast_2d(np.asarray(A, np.float64))
+    B = np.atleast_2d(np.asarray(B, np.float64))
+    E = B - A
+    ee = np.einsum("ij,ij->i", E, E)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        s = np.einsum("ij,ij->i", p - A, E) / ee
+    s = np.where(ee > 0, np.clip(s, 0.0, 1.0), 0.0)
+    q = A + s[:, None] * E
+    return np.sqrt(np.einsum("ij,ij->i", q - p, q - p))
+
+
+def ray_boundary_margin(loops_xyz, p, d, scene) -> float:
+    """Smallest relative distance between the line p + t d and the boundary:
+    per boundary edge a->b, the distance from the origin to the segment
+    [a_perp, b_perp] of the edge's projection along d (relative to p),
+    divided by max(|a - p|, |b - p|) + ABS_REL * scene.  (Conservative: an
+    edge passing behind p counts as well.)"""
+    best = np.inf
+    for L in loops_xyz:
+        L = np.asarray(L, np.float64)
+        if len(L) == 0:
+            continue
+        a = L - p
+        b = np.roll(a, -1, 0)
+        ap = a - np.outer(a @ d, d)
+        bp = b - np.outer(b @ d, d)
+        dist = segment_distance(np.zeros(3), ap, bp)
+        sc = np.maximum(np.linalg.norm(a, axis=1), np.linalg.norm(b, axis=1)) + ABS_REL * scene
+        best = min(best, float((dist / sc).min()))
+    return best
+
+
+def crossings(V, F, P, d, margins: bool = False, loops=None):
     """Signed number of crossings of the ray p + t d (t > 0) with the mesh.
 
     Brute force over every triangle: the ray meets the triangle's interior iff
@@ -143,12 +221,14 @@ def crossings(V, F, P, d, margins: bool = False):
     relative to p share one strict sign (that sign is then sign(d . n)); it
     meets it in front of p iff t = (n . a)/(d . n) > 0.
 
-    With ``margins`` also returns, per query, over the triangles that the ray
-    hits or misses by less than BAND: the smallest normalised edge value
-    |d.(a x b)| / (|a_perp||b_perp|) (the sine of the angle at the ray between
-    the projected vertices; a_perp is a's component perpendicular to d) or
-    vertex offset |a_perp| / |a|, whichever is smaller, and the smallest
-    |t| / max(|a|,|b|,|c|).
+    With ``margins`` also returns a dict of per-query margins (see BAND):
+      m_ray   distance from the ray's line to the projected boundary
+              (ray_boundary_margin);
+      m_surf  min over triangles of dist(p, T) / (max_k |v_k - p| + ABS_REL
+              * scene): how close p is to the surface;
+      m_self  min |edge value| / (|a||b|) over the triangles the ray hits or
+              misses by less than BAND_SELF (the oracle's own exactness).
+    ``loops`` (boundary vertex loops, default: from F) are needed for m_ray.
     """
     V = np.asarray(V, np.float64)
     F = np.asarray(F, np.int64)
@@ -159,8 +239,14 @@ def crossings(V, F, P, d, margins: bool = False):
     n = np.cross(B - A, C - A)
     dn = n @ d
     chi = np.zeros(len(P), np.int64)
-    m_edge = np.full(len(P), np.inf)
-    m_t = np.full(len(P), np.inf)
+    if margins:
+        if loops is None:
+            loops = boundary_loops(F)
+        Lx = loops_coords(V, loops)
+        m = {k: np.full(len(P), np.inf) for k in ("m_ray", "m_surf", "m_self")}
+        # bounding spheres of the triangles, to find the few that can be near p
+        cen = (A + B + C) / 3.0
+        rad = np.sqrt(np.max(np.stack([np.einsum("ij,ij->i", X - cen, X - cen) for X in (A, B, C)], 1), 1))
     for i, p in enumerate(P):
         a, b, c = A - p, B - p, C - p
         e_ab = np.cross(a, b) @ d
@@ -174,29 +260,37 @@ def crossings(V, F, P, d, margins: bool = False):
         hit = inside & (t > 0)
         chi[i] = int(np.sum(np.sign(dn[hit])))
         if margins:
-            la = np.linalg.norm(a, axis=1)
-            lb = np.linalg.norm(b, axis=1)
-            lc = np.linalg.norm(c, axis=1)
-            # distances of the vertices from the ray's line (projections
-            # perpendicular to d)
-            pa = np.linalg.norm(a - np.outer(a @ d, d), axis=1)
-            pb = np.linalg.norm(b - np.outer(b @ d, d), axis=1)
-            pc = np.linalg.norm(c - np.outer(c @ d, d), axis=1)
-            with np.errstate(divide="ignore", invalid="ignore"):
-                ab = e_ab / (pa * pb)
-                bc = e_bc / (pb * pc)
-                ca = e_ca / (pc * pa)
-            near = (((ab > -BAND) & (bc > -BAND) & (ca > -BAND))
-                    | ((ab < BAND) & (bc < BAND) & (ca < BAND)))
-            near &= np.isfinite(t) & (t > -BAND * np.maximum(np.maximum(la, lb), lc))
-            if np.any(near):
-                em = np.minimum(np.minimum(np.abs(ab[near]), np.abs(bc[near])), np.abs(ca[near]))
-                vm = np.minimum(np.minimum(pa[near] / la[near], pb[near] / lb[near]), pc[near] / lc[near])
-                m_edge[i] = float(min(np.nan_to_num(em, nan=0.0).min(), vm.min()))
-                sc = np.maximum(np.maximum(la[near], lb[near]), lc[near])
-                m_t[i] = float((np.abs(t[near]) / sc).min())
+            scene = float(np.sqrt(np.einsum("ij,ij->i", V - p, V - p).max())) if len(V) else 0.0
+            m["m_ray"][i] = ray_boundary_margin(Lx, p, d, scene)
+            # p near a triangle: candidates from the bounding spheres
+            dc = np.linalg.norm(cen - p, axis=1)
+            cand = np.nonzero(dc - rad <= 4.0 * BAND * (dc + rad) + 4.0 * ABS_REL * scene)[0]
+            if cand.size:
+                dist = point_triangle_distance(p, A[cand], B[cand], C[cand])
+                far = np.maximum(np.maximum(np.linalg.norm(a[cand], axis=1), np.linalg.norm(b[cand], axis=1)),
+                                 np.linalg.norm(c[cand], axis=1))
+                m["m_surf"][i] = float((dist / (far + ABS_REL * scene)).min())
+            # the oracle's own float64 decisions: edge values normalised by
+            # the product of the vertex distances, near-hit triangles only
+            # (|a||b| <= scene^2 bounds the normalisation, which finds them)
+            tol = BAND_SELF * scene * scene
+            cand = np.nonzero(((e_ab > -tol) & (e_bc > -tol) & (e_ca > -tol))
+                              | ((e_ab < tol) & (e_bc < tol) & (e_ca < tol)))[0]
+            if cand.size:
+                la = np.linalg.norm(a[cand], axis=1)
+                lb = np.linalg.norm(b[cand], axis=1)
+                lc = np.linalg.norm(c[cand], axis=1)
+                with np.errstate(divide="ignore", invalid="ignore"):
+                    ab = e_ab[cand] / (la * lb)
+                    bc = e_bc[cand] / (lb * lc)
+                    ca = e_ca[cand] / (lc * la)
+                near = (((ab > -BAND_SELF) & (bc > -BAND_SELF) & (ca > -BAND_SELF))
+                        | ((ab < BAND_SELF) & (bc < BAND_SELF) & (ca < BAND_SELF)))
+                if np.any(near):
+                    em = np.minimum(np.minimum(np.abs(ab[near]), np.abs(bc[near])), np.abs(ca[near]))
+                    m["m_self"][i] = float(np.nan_to_num(em, nan=0.0).min())
     if margins:
-        return chi, m_edge, m_t
+        return chi, m
     return chi
 
 
@@ -233,21 +327,18 @@ def boundary_term(loops_xyz, P, d) -> np.ndarray:
 
 
 def boundary_distance(loops_xyz, P) -> np.ndarray:
-    """Distance from each query to the boundary polyline."""
+    """Distance from each query to the boundary polyline (every edge of every
+    loop, the closing edge last -> first included)."""
     P = np.atleast_2d(np.asarray(P, np.float64))
     best = np.full(len(P), np.inf)
     for L in loops_xyz:
         L = np.asarray(L, np.float64)
+        if len(L) == 0:
+            continue
         A = L
         B = np.roll(L, -1, 0)
-        E = B - A
-        ee = np.einsum("ij,ij->i", E, E)
         for i, p in enumerate(P):
-            with np.errstate(divide="ignore", invalid="ignore"):
-                s = np.clip(np.einsum("ij,ij->i", p - A, E) / ee, 0.0, 1.0)
-            s = np.where(ee > 0, s, 0.0)
-            q = A + s[:, None] * E
-            best[i] = min(best[i], float(np.sqrt(((q - p) ** 2).sum(1)).min()))
+            best[i] = min(best[i], float(segment_distance(p, A, B).min()))
     return best
 
 
@@ -256,11 +347,11 @@ def boundary_distance(loops_xyz, P) -> np.ndarray:
 # ----------------------------------------------------------------------------
 
 class Result(dict):
-    """w, chi, S and the margins m_edge, m_t, m_bnd (all per query)."""
+    """w, chi, S and the margins m_ray, m_surf, m_self, m_bnd (per query)."""
 
     @property
     def degenerate(self):
-        return (self["m_edge"] < BAND) | (self["m_t"] < BAND)
+        return (self["m_ray"] < BAND) | (self["m_surf"] < BAND) | (self["m_self"] < BAND_SELF)
 
 
 def loops_coords(V, loops):
@@ -273,12 +364,13 @@ def wn3d(V, F, P, d, margins: bool = True, loops=None) -> Result:
     if loops is None:
         loops = boundary_loops(F)
     Lx = loops_coords(V, loops)
+    out = {}
     if margins:
-        chi, m_edge, m_t = crossings(V, F, P, d, margins=True)
-        m_bnd = boundary_distance(Lx, P) if Lx else np.full(len(np.atleast_2d(P)), np.inf)
+        chi, m = crossings(V, F, P, d, margins=True, loops=loops)
+        out.update(m)
+        out["m_bnd"] = boundary_distance(Lx, P) if Lx else np.full(len(np.atleast_2d(P)), np.inf)
     else:
         chi = crossings(V, F, P, d)
-        m_edge = m_t = m_bnd = None
     S = boundary_term(Lx, P, d) if Lx else np.zeros(len(chi))
     w = chi + S / TWO_PI
-    return Result(w=w, chi=chi, S=S, m_edge=m_edge, m_t=m_t, m_bnd=m_bnd)
+    return Result(w=w, chi=chi, S=S, **out)

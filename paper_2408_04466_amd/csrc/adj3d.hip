@@ -16,7 +16,7 @@ using namespace adj;
 template <int QPL>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL == 4 ? 4 : (QPL == 2 ? 6 : 8)))) void k_adj3d(
     AdjArgs a, LoopTable L) {
-  __shared__ float4 sv[kChunk];
+  __shared__ float4 sv[2 * kChunk];
   __shared__ float4 rsw[kWaves * kRowFloats / 4];
   const int wave = threadIdx.x >> 6;
   const int64_t bw = (int64_t)blockIdx.x * kWaves + wave;     // partial row
@@ -47,7 +47,7 @@ __device__ __forceinline__ void walk_range(QState* S, const float* __restrict__ 
   float* rs = rsw + (threadIdx.x >> 6) * kRowFloats;
   Rel F[QPL], A[QPL], B[QPL];
   float accA[3], accB[3];
-  float lA = 0.f;
+  float4 eA = make_float4(0.f, 0.f, 0.f, 0.f);
   zero3(accA);
   int l = bnd::loop_of(L, cbeg);
   bool carry_in = cbeg > L.off(l);
@@ -57,26 +57,18 @@ __device__ __forceinline__ void walk_range(QState* S, const float* __restrict__ 
     const float x = bnd[3 * i], y = bnd[3 * i + 1], z = bnd[3 * i + 2];
     const float ex = __fsub_rn(bnd[3 * cbeg], x), ey = __fsub_rn(bnd[3 * cbeg + 1], y),
                 ez = __fsub_rn(bnd[3 * cbeg + 2], z);
-    const float4 v = make_float4(x, y, z, __fmaf_rn(ex, ex, __fmaf_rn(ey, ey, __fmul_rn(ez, ez))));
+    const float4 v = make_float4(x, y, z, 0.f);
 #pragma unroll
     for (int k = 0; k < QPL; ++k) {
       F[k] = rel(S[k], f);
       A[k] = rel(S[k], v);
     }
-    lA = v.w;
+    eA = make_float4(ex, ey, ez, __fmaf_rn(ex, ex, __fmaf_rn(ey, ey, __fmul_rn(ez, ez))));
   }
   for (int c0 = cbeg; c0 < cend; c0 += kChunk) {
     const int c1 = min(c0 + kChunk, cend);
     __syncthreads();
-    for (int j = threadIdx.x; j < c1 - c0; j += kThreads) {
-      const int i = c0 + j;
-      const int lp = bnd::loop_of(L, i);
-      const int nx = (i + 1 < L.off(lp + 1)) ? i + 1 : L.off(lp);
-      const float x = bnd[3 * i], y = bnd[3 * i + 1], z = bnd[3 * i + 2];
-      const float ex = __fsub_rn(bnd[3 * nx], x), ey = __fsub_rn(bnd[3 * nx + 1], y),
-                  ez = __fsub_rn(bnd[3 * nx + 2], z);
-      sv[j] = make_float4(x, y, z, __fmaf_rn(ex, ex, __fmaf_rn(ey, ey, __fmul_rn(ez, ez))));
-    }
+    for (int j = threadIdx.x; j < c1 - c0; j += kThreads) stage_adj(bnd, L, c0 + j, j, sv);
     __syncthreads();
     for (; l < L.n() && L.off(l) < c1; ++l) {
       const int ls = L.off(l), le = L.off(l + 1);
@@ -89,7 +81,7 @@ __device__ __forceinline__ void walk_range(QState* S, const float* __restrict__ 
           F[k] = rel(S[k], v);
           A[k] = F[k];
         }
-        lA = v.w;
+        eA = sv[kChunk + j - c0];
         zero3(accA);
         ++j;
       } else if (carry_in) {   // edge (cbeg - 1 -> cbeg)
@@ -99,34 +91,35 @@ __device__ __forceinline__ void walk_range(QState* S, const float* __restrict__ 
         for (int k = 0; k < QPL; ++k) B[k] = rel(S[k], v0);
         zero3(accB);
 #pragma unroll
-        for (int k = 0; k < QPL; ++k) edge_grad(S[k], A[k], B[k], lA, accA, accB);
+        for (int k = 0; k < QPL; ++k) edge_grad(S[k], A[k], B[k], eA, accA, accB);
         if (pc) put3(pc, accA, lane);
 #pragma unroll
         for (int k = 0; k < QPL; ++k) A[k] = B[k];
         accA[0] = accB[0]; accA[1] = accB[1]; accA[2] = accB[2];
-        lA = v0.w;
+        eA = sv[kChunk + j - c0];
         ++j;
       }
       for (; j + 2 <= j1; j += 2) {
         const float4 v0 = sv[j - c0];
         const float4 v1 = sv[j + 1 - c0];
+        const float4 e0 = sv[kChunk + j - c0];
 #pragma unroll
         for (int k = 0; k < QPL; ++k) B[k] = rel(S[k], v0);
-        step<QPL>(S, A, B, lA, accA, accB, pv, rs, j - 1, nb, lane);
+        step<QPL>(S, A, B, eA, accA, accB, pv, rs, j - 1, nb, lane);
 #pragma unroll
         for (int k = 0; k < QPL; ++k) A[k] = rel(S[k], v1);
-        step<QPL>(S, B, A, v0.w, accB, accA, pv, rs, j, nb, lane);
-        lA = v1.w;
+        step<QPL>(S, B, A, e0, accB, accA, pv, rs, j, nb, lane);
+        eA = sv[kChunk + j + 1 - c0];
       }
       if (j < j1) {
         const float4 v0 = sv[j - c0];
 #pragma unroll
         for (int k = 0; k < QPL; ++k) B[k] = rel(S[k], v0);
-        step<QPL>(S, A, B, lA, accA, accB, pv, rs, j - 1, nb, lane);
+        step<QPL>(S, A, B, eA, accA, accB, pv, rs, j - 1, nb, lane);
 #pragma unroll
         for (int k = 0; k < QPL; ++k) A[k] = B[k];
         accA[0] = accB[0]; accA[1] = accB[1]; accA[2] = accB[2];
-        lA = v0.w;
+        eA = sv[kChunk + j - c0];
         ++j;
       }
       if (j1 < le) {
@@ -136,7 +129,7 @@ __device__ __forceinline__ void walk_range(QState* S, const float* __restrict__ 
         break;
       }
       float accF[3];
-      step<QPL>(S, A, F, lA, accA, accF, pv, rs, le - 1, nb, lane);
+      step<QPL>(S, A, F, eA, accA, accF, pv, rs, le - 1, nb, lane);
       if (pl) put3(pl + 3 * (int64_t)l, accF, lane);
       zero3(accA);
     }
@@ -146,7 +139,7 @@ __device__ __forceinline__ void walk_range(QState* S, const float* __restrict__ 
 template <int QPL>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL == 4 ? 4 : (QPL == 2 ? 6 : 8)))) void k_adj3d_split(
     AdjArgs a, LoopTable L, int32_t span, int32_t parts, float* carry, float* gq_part) {
-  __shared__ float4 sv[kChunk];
+  __shared__ float4 sv[2 * kChunk];
   __shared__ float4 rsw[kWaves * kRowFloats / 4];
   const int wave = threadIdx.x >> 6;
   const int64_t bw = (int64_t)blockIdx.x * kWaves + wave;

@@ -9,7 +9,8 @@
 // (the same field integrated against each vertex's hat function along the
 // straight edge).  These vanish in sum: sum_v dw/dv + dw/dp = 0.
 //
-// A lane holds QPL queries (a template parameter); the workgroup stages the boundary in LDS and
+// A lane holds QPL queries (a template parameter); the workgroup stages the
+// boundary in LDS (each vertex with the edge leaving it) and
 // every lane walks the same vertex sequence.  A vertex's gradient is complete
 // one step after the vertex is visited (its two edges are then done); it is
 // summed over the lane's queries in registers and over each row of 16 lanes
@@ -118,18 +119,20 @@ __device__ __forceinline__ Rel rel(const QState& s, const float4& v) {
   return q;
 }
 
-// Edge a->b (squared length l2) for one query: c = g K (a' x b') with
+// Edge a->b for one query, with e = (b - a, |b - a|^2) taken from the
+// boundary itself: c = g K (a' x b') with a' x b' = a' x (b - a) (no
+// cancellation between the two long relative vectors of a far query) and
 // 1/K = |a'||b'| + a'.b' = ((|a'| + |b'|)^2 - |b - a|^2) / 2, since
 // |b - a|^2 = |a'|^2 + |b'|^2 - 2 a'.b' (the factor 2 sits in s.g); adds
 // c (1/|a'| + 1/|b'|) to the query gradient and c/|a'|, c/|b'| to the two
 // vertex accumulators.
-__device__ __forceinline__ void edge_grad(QState& s, const Rel& a, const Rel& b, float l2, float* acc_a,
+__device__ __forceinline__ void edge_grad(QState& s, const Rel& a, const Rel& b, const float4& e, float* acc_a,
                                           float* acc_b) {
-  const float crx = __fmaf_rn(a.y, b.z, -__fmul_rn(a.z, b.y));
-  const float cry = __fmaf_rn(a.z, b.x, -__fmul_rn(a.x, b.z));
-  const float crz = __fmaf_rn(a.x, b.y, -__fmul_rn(a.y, b.x));
+  const float crx = __fmaf_rn(a.y, e.z, -__fmul_rn(a.z, e.y));
+  const float cry = __fmaf_rn(a.z, e.x, -__fmul_rn(a.x, e.z));
+  const float crz = __fmaf_rn(a.x, e.y, -__fmul_rn(a.y, e.x));
   const float rs = __fadd_rn(a.r, b.r);
-  const float den2 = __fmaf_rn(rs, rs, -l2);
+  const float den2 = __fmaf_rn(rs, rs, -e.w);
   const float gk = __fmul_rn(s.g, __builtin_amdgcn_rcpf(den2));
   const float cx = __fmul_rn(gk, crx);
   const float cy = __fmul_rn(gk, cry);
@@ -144,6 +147,21 @@ __device__ __forceinline__ void edge_grad(QState& s, const Rel& a, const Rel& b,
   acc_b[0] = __fmaf_rn(cx, b.i, acc_b[0]);
   acc_b[1] = __fmaf_rn(cy, b.i, acc_b[1]);
   acc_b[2] = __fmaf_rn(cz, b.i, acc_b[2]);
+}
+
+// Stage boundary vertex i (flat index, loops L) for the adjoint walk: its
+// coordinates at sv[j] and, at sv[kChunk + j], the edge leaving it, v_next -
+// v_i, with its squared length in .w.
+template <class Loops>
+__device__ __forceinline__ void stage_adj(const float* __restrict__ bnd, const Loops& L, int i, int j,
+                                          float4* sv) {
+  const int lp = bnd::loop_of(L, i);
+  const int nx = (i + 1 < L.off(lp + 1)) ? i + 1 : L.off(lp);
+  const float x = bnd[3 * i], y = bnd[3 * i + 1], z = bnd[3 * i + 2];
+  const float ex = __fsub_rn(bnd[3 * nx], x), ey = __fsub_rn(bnd[3 * nx + 1], y),
+              ez = __fsub_rn(bnd[3 * nx + 2], z);
+  sv[j] = make_float4(x, y, z, 0.f);
+  sv[kChunk + j] = make_float4(ex, ey, ez, __fmaf_rn(ex, ex, __fmaf_rn(ey, ey, __fmul_rn(ez, ez))));
 }
 
 __device__ __forceinline__ void put3(float* dst, const float acc[3], int lane) {
@@ -179,11 +197,11 @@ __device__ __forceinline__ void zero3(float* a) { a[0] = a[1] = a[2] = 0.f; }
 // Edge A->B for every query of the lane; the partial of vertex A is then
 // complete and goes out (summed over the wavefront) to row entry `va`.
 template <int QPL>
-__device__ __forceinline__ void step(QState* S, const Rel* A, const Rel* B, float l2, float* accA, float* accB,
-                                     float* pv, float* rs, int va, int nb, int lane) {
+__device__ __forceinline__ void step(QState* S, const Rel* A, const Rel* B, const float4& e, float* accA,
+                                     float* accB, float* pv, float* rs, int va, int nb, int lane) {
   zero3(accB);
 #pragma unroll
-  for (int k = 0; k < QPL; ++k) edge_grad(S[k], A[k], B[k], l2, accA, accB);
+  for (int k = 0; k < QPL; ++k) edge_grad(S[k], A[k], B[k], e, accA, accB);
   if (pv) park(rs, pv, va, nb, accA, lane);
 }
 
@@ -200,22 +218,13 @@ __device__ __forceinline__ void walk(QState* S, const float* __restrict__ bnd, i
   float* rs = rsw + (threadIdx.x >> 6) * kRowFloats;
   Rel F[QPL], A[QPL], B[QPL];      // loop's first vertex; A = last vertex visited
   float accA[3], accB[3];          // pending partial of vertex A (and scratch for B)
-  float lA = 0.f;                  // squared length of the edge leaving vertex A
+  float4 eA = make_float4(0.f, 0.f, 0.f, 0.f);   // the edge leaving vertex A
   zero3(accA);
   int l = 0;
   for (int c0 = 0; c0 < nb; c0 += kChunk) {
     const int c1 = min(c0 + kChunk, nb);
     __syncthreads();
-    // vertex i and, in .w, the squared length of the edge leaving it
-    for (int j = threadIdx.x; j < c1 - c0; j += kThreads) {
-      const int i = c0 + j;
-      const int lp = bnd::loop_of(L, i);
-      const int nx = (i + 1 < L.off(lp + 1)) ? i + 1 : L.off(lp);
-      const float x = bnd[3 * i], y = bnd[3 * i + 1], z = bnd[3 * i + 2];
-      const float ex = __fsub_rn(bnd[3 * nx], x), ey = __fsub_rn(bnd[3 * nx + 1], y),
-                  ez = __fsub_rn(bnd[3 * nx + 2], z);
-      sv[j] = make_float4(x, y, z, __fmaf_rn(ex, ex, __fmaf_rn(ey, ey, __fmul_rn(ez, ez))));
-    }
+    for (int j = threadIdx.x; j < c1 - c0; j += kThreads) stage_adj(bnd, L, c0 + j, j, sv);
     __syncthreads();
     for (; l < L.n() && L.off(l) < c1; ++l) {
       const int ls = L.off(l), le = L.off(l + 1);
@@ -228,37 +237,38 @@ __device__ __forceinline__ void walk(QState* S, const float* __restrict__ bnd, i
           F[k] = rel(S[k], v);
           A[k] = F[k];
         }
-        lA = v.w;
+        eA = sv[kChunk + j - c0];
         zero3(accA);
         ++j;
       }
       for (; j + 2 <= j1; j += 2) {
         const float4 v0 = sv[j - c0];
         const float4 v1 = sv[j + 1 - c0];
+        const float4 e0 = sv[kChunk + j - c0];
 #pragma unroll
         for (int k = 0; k < QPL; ++k) B[k] = rel(S[k], v0);
-        step<QPL>(S, A, B, lA, accA, accB, pv, rs, j - 1, nb, lane);
+        step<QPL>(S, A, B, eA, accA, accB, pv, rs, j - 1, nb, lane);
 #pragma unroll
         for (int k = 0; k < QPL; ++k) A[k] = rel(S[k], v1);
-        step<QPL>(S, B, A, v0.w, accB, accA, pv, rs, j, nb, lane);
-        lA = v1.w;
+        step<QPL>(S, B, A, e0, accB, accA, pv, rs, j, nb, lane);
+        eA = sv[kChunk + j + 1 - c0];
       }
       if (j < j1) {
         const float4 v0 = sv[j - c0];
 #pragma unroll
         for (int k = 0; k < QPL; ++k) B[k] = rel(S[k], v0);
-        step<QPL>(S, A, B, lA, accA, accB, pv, rs, j - 1, nb, lane);
+        step<QPL>(S, A, B, eA, accA, accB, pv, rs, j - 1, nb, lane);
 #pragma unroll
         for (int k = 0; k < QPL; ++k) A[k] = B[k];
         accA[0] = accB[0]; accA[1] = accB[1]; accA[2] = accB[2];
-        lA = v0.w;
+        eA = sv[kChunk + j - c0];
         ++j;
       }
       if (j1 < le) break;            // the loop continues in the next chunk
       // closing edge last -> first: completes the last vertex; the first
       // vertex's share goes to the per-loop row
       float accF[3];
-      step<QPL>(S, A, F, lA, accA, accF, pv, rs, le - 1, nb, lane);
+      step<QPL>(S, A, F, eA, accA, accF, pv, rs, le - 1, nb, lane);
       if (pl) put3(pl + 3 * (int64_t)l, accF, lane);
       zero3(accA);
     }

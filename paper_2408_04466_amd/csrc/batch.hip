@@ -248,7 +248,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_bnd(FwdArgs a) {
 // Four waves per SIMD (128 registers): the few spills are per-item
 // addresses, outside the walk.
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_bwd(BwdArgs a) {
-  __shared__ float4 sv[adj::kChunk];
+  __shared__ float4 sv[2 * adj::kChunk];
   __shared__ float4 rsw[adj::kWaves * adj::kRowFloats / 4];
   __shared__ int s_item;
   const int wave = threadIdx.x >> 6;

@@ -35,15 +35,20 @@ class DevMesh:
 
 
 def compare_3d(dm: DevMesh, P, w_gpu, chi_gpu, sample=None, alt_dir_seed=12345,
-               max_degenerate_frac=0.05):
+               max_degenerate_frac=0.02, label=""):
     """Oracle parity on ``sample`` (indices into P).  chi must match bit for
     bit on non-degenerate queries; w within W_TOL away from the boundary.
     Degenerate queries are checked for w against the oracle with another
-    direction (w does not depend on d)."""
+    direction (w does not depend on d).  Large samples run in the oracle's
+    process pool."""
+    import oracle_pool
     P = np.asarray(P, np.float32)
     idx = np.arange(len(P)) if sample is None else np.asarray(sample)
-    r = O.wn3d(dm.M.V, dm.M.F, P[idx], dm.d)
+    loops = [dm.bnd_idx[dm.loop_off[i]:dm.loop_off[i + 1]] for i in range(len(dm.loop_off) - 1)]
+    r = oracle_pool.wn3d(dm.M.V, dm.M.F, P[idx], dm.d, loops=loops)
     deg = r.degenerate
+    print(f"compare_3d{(' ' + label) if label else ''}: {len(idx)} queries, {int(deg.sum())} degenerate",
+          flush=True)
     assert deg.mean() <= max_degenerate_frac, f"too many degenerate queries: {deg.sum()}/{len(idx)}"
     ok = ~deg
     bad = np.nonzero(chi_gpu[idx][ok] != r["chi"][ok])[0]
@@ -53,7 +58,7 @@ def compare_3d(dm: DevMesh, P, w_gpu, chi_gpu, sample=None, alt_dir_seed=12345,
     if deg.any():
         # w is independent of d: take a direction for which these are regular
         d2 = np.asarray(__import__("synth").random_direction(alt_dir_seed))
-        r2 = O.wn3d(dm.M.V, dm.M.F, P[idx][deg], d2)
+        r2 = oracle_pool.wn3d(dm.M.V, dm.M.F, P[idx][deg], d2, loops=loops)
         assert not r2.degenerate.any()
         wref[deg] = r2["w"]
     err = np.abs(w_gpu[idx] - wref)

@@ -102,11 +102,13 @@ def c3():
 
 
 def test_c3_full_size_sampled_parity(c3):
+    """1024 seeded queries of the 2^20 (plus the first and the last) against
+    the FP64 oracle over all 1,048,064 triangles."""
     dm, P, w, chi = c3
     assert dm.M.F.shape[0] == 1048064 and len(dm.bnd_idx) == 512
-    sample = synth.rng(11).choice(len(P), 40, replace=False)
+    sample = synth.rng(11).choice(len(P), 1024, replace=False)
     sample = np.concatenate([sample, [0, len(P) - 1]])
-    info = compare_3d(dm, P, w, chi, sample)
+    info = compare_3d(dm, P, w, chi, sample, label="mesh 2^20")
     print("c3 sample", info)
 
 

@@ -50,9 +50,26 @@ def test_backward_matches_oracle_small(mesh):
     assert _rel(gb.cpu().numpy(), np.concatenate(rv, 0)) <= 1e-3
 
 
+def _componentwise(got, ref, tol=1e-3):
+    """Largest violation of |got - ref| <= tol max(|ref|, 1e-3 max|ref|),
+    component by component (<= 1 passes)."""
+    bound = tol * np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
+    r = np.abs(got - ref) / bound
+    i = np.unravel_index(np.argmax(r), r.shape)
+    print(f"  worst component {i}: got {got[i]:.8g} oracle {ref[i]:.8g} bound {bound[i]:.3g} "
+          f"(max |oracle| {np.abs(ref).max():.4g})", flush=True)
+    return float(r.max())
+
+
 def test_adjoint_workload_parity_and_fd():
     """C3's surface with its boundary refined to 2048 edges, 2^18 queries,
-    L = sum (w - t)^2 with seeded targets t in {0, 1}."""
+    L = sum (w - t)^2 with seeded targets t in {0, 1} over every query more
+    than 1e-2 from the surface.  Both gradients against the FP64 closed form
+    normwise and component by component; the closed form itself against
+    central differences (h = 1e-4) of the oracle's w in the query (full w on
+    8 queries; the boundary term with chi_d fixed on 256) and in seeded
+    boundary vertices."""
+    import oracle_pool
     M = synth.open_sphere(3, top_refine=4)
     d = synth.random_direction(3)
     dm = DevMesh(M, d)
@@ -64,41 +81,58 @@ def test_adjoint_workload_parity_and_fd():
     qx.requires_grad_(True); qy.requires_grad_(True); qz.requires_grad_(True)
     w = W.winding_number(dm.bvh, bnd, dm.loop_off, qx, qy, qz)
     tt = torch.from_numpy(t).cuda()
-    # the loss covers a seeded subset of 16384 queries away from the surface
-    # (the kernels still process all 2^18; the others get dL/dw = 0)
-    sub = np.zeros(len(P), bool)
-    sub[synth.rng(15).choice(len(P), 16384, replace=False)] = True
-    far = torch.from_numpy(_far_from_surface(M, P, 1e-2) & sub).cuda()
+    farn = _far_from_surface(M, P, 1e-2)
+    far = torch.from_numpy(farn).cuda()
+    print(f"adjoint workload: loss over {int(farn.sum())} of {len(P)} queries", flush=True)
     loss = (((w - tt) ** 2) * far).sum()
     loss.backward()
     torch.cuda.synchronize()
     gq = torch.stack([qx.grad, qy.grad, qz.grad], 1).cpu().numpy()
     gb = bnd.grad.cpu().numpy()
     wn = w.detach().cpu().numpy()
-    farn = far.cpu().numpy()
     g = (2.0 * (wn.astype(np.float64) - t) * farn)
     L = M.V[dm.bnd_idx].astype(np.float64)
-    # oracle gradient for every query (closed form, chunked)
-    rq = np.zeros((len(P), 3))
-    rv = np.zeros((len(L), 3))
-    sel_all = np.nonzero(farn)[0]
-    for s in range(0, len(sel_all), 2048):
-        ii = sel_all[s:s + 2048]
-        a, b = G.grad3d([L], P[ii].astype(np.float64), g[ii])
-        rq[ii] = a
-        rv += b[0]
+    rq, rv = oracle_pool.grad3d([L], P.astype(np.float64), g)
+    rv = rv[0]
     assert _rel(gq[farn], rq[farn]) <= 1e-3
     assert _rel(gb, rv) <= 1e-3
-    # the oracle's closed form against FP64 central differences (h = 1e-4)
-    sel = np.nonzero(farn)[0][:4]
+    cq, cb = _componentwise(gq[farn], rq[farn]), _componentwise(gb, rv)
+    print(f"adjoint workload: componentwise grad_q {cq:.3g}, grad_bnd {cb:.3g} (<= 1 passes)", flush=True)
+    assert cq <= 1.0 and cb <= 1.0
+    assert np.count_nonzero(gq[~farn]) == 0
+
     h = 1e-4
+    sel = np.nonzero(farn)[0]
+    # the full oracle w (crossings over every triangle + boundary term)
+    s8 = sel[:8]
+    Ps = P[s8].astype(np.float64)
+    jobs = [(M.V, M.F, Ps + sg * h * np.eye(3)[k], d, None) for k in range(3) for sg in (1.0, -1.0)]
+    rs = oracle_pool.map_wn3d(jobs)
+    ref8 = G.grad3d([L], Ps)[0]
     for k in range(3):
-        e = np.zeros(3)
-        e[k] = h
-        fd = (O.wn3d(M.V, M.F, P[sel] + e, d, margins=False)["w"]
-              - O.wn3d(M.V, M.F, P[sel] - e, d, margins=False)["w"]) / (2 * h)
-        ref = G.grad3d([L], P[sel].astype(np.float64))[0][:, k]
-        assert np.abs(fd - ref).max() <= 1e-3 * max(np.abs(ref).max(), 1e-6)
+        fd = (rs[2 * k]["w"] - rs[2 * k + 1]["w"]) / (2 * h)
+        assert np.abs(fd - ref8[:, k]).max() <= 1e-3 * max(np.abs(ref8).max(), 1e-6), k
+    # the boundary term on 256 queries whose ray stays away from the boundary
+    # (chi_d is then constant under the step, so dw = dS / 2pi)
+    s256 = sel[synth.rng(16).choice(len(sel), 256, replace=False)]
+    Pq = P[s256].astype(np.float64)
+    scene = float(np.abs(M.V).max()) * 2
+    keep = np.array([O.ray_boundary_margin([L], p, d / np.linalg.norm(d), scene) > 1e-2 for p in Pq])
+    Pq = Pq[keep]
+    refq = G.grad3d([L], Pq)[0]
+    for k in range(3):
+        e = h * np.eye(3)[k]
+        fd = (O.boundary_term([L], Pq + e, d) - O.boundary_term([L], Pq - e, d)) / (2 * h) / (2 * np.pi)
+        assert np.abs(fd - refq[:, k]).max() <= 1e-3 * np.abs(refq).max(), k
+    # boundary vertices: dL/dv for L = sum over these queries of w
+    _, rvq = G.grad3d([L], Pq)
+    for j in synth.rng(17).choice(len(L), 6, replace=False):
+        for k in range(3):
+            Lp, Lm = L.copy(), L.copy()
+            Lp[j, k] += h
+            Lm[j, k] -= h
+            fd = (O.boundary_term([Lp], Pq, d).sum() - O.boundary_term([Lm], Pq, d).sum()) / (2 * h) / (2 * np.pi)
+            assert abs(fd - rvq[0][j, k]) <= 1e-3 * np.abs(rvq[0]).max(), (j, k)
 
 
 def test_backward_deterministic_and_edge_cases():

@@ -25,6 +25,10 @@ def _surfaces(seed, n, scale):
     queries.append(synth.box_queries(meshes[-1].V, 3000, 9))
     meshes.append(synth.bumpy_cap())
     queries.append(np.zeros((0, 3), np.float32))
+    # a long boundary (1200 edges) with few queries: the plain adjoint splits
+    # it into vertex ranges
+    meshes.append(synth.coons_surface(77, 4000, 1200))
+    queries.append(synth.box_queries(meshes[-1].V, 3000, 78))
     return meshes, queries, CB.direction
 
 
@@ -82,19 +86,23 @@ def test_batched_oracle_samples(small_batch):
     w, chi = B.eval(*q)
     torch.cuda.synchronize()
     w, chi = w.cpu().numpy(), chi.cpu().numpy()
-    o = 0
+    import oracle_pool
     g = synth.rng(2)
-    for M, Q in zip(meshes, queries):
-        n = len(Q)
-        if n == 0:
+    offs = np.concatenate([[0], np.cumsum([len(Q) for Q in queries])])
+    sels = [g.choice(len(Q), min(len(Q), 64), replace=False) for Q in queries]
+    rs = oracle_pool.map_wn3d((M.V, M.F, Q[sel], d, None) for M, Q, sel in zip(meshes, queries, sels))
+    n_all = n_deg = 0
+    for k, (r, sel) in enumerate(zip(rs, sels)):
+        if len(sel) == 0:
             continue
-        sel = g.choice(n, min(n, 40), replace=False)
-        r = O.wn3d(M.V, M.F, Q[sel], d)
         ok = ~r.degenerate
-        assert np.array_equal(chi[o + sel][ok], r["chi"][ok])
-        far = ok & (r["m_bnd"] > 1e-5)
-        assert np.abs(w[o + sel][far] - r["w"][far]).max() <= W_TOL
-        o += n
+        n_all, n_deg = n_all + len(sel), n_deg + int((~ok).sum())
+        assert np.array_equal(chi[offs[k] + sel][ok], r["chi"][ok]), k
+        far = r["m_bnd"] > 1e-5
+        wref = r["w"].copy()
+        assert np.abs(w[offs[k] + sel][far & ok] - wref[far & ok]).max(initial=0.0) <= W_TOL, k
+    print(f"batched oracle samples: {n_all} queries, {n_deg} degenerate", flush=True)
+    assert n_deg <= 0.02 * n_all
 
 
 def test_graph_replays_and_pointer_changes(small_batch):
@@ -197,7 +205,12 @@ def test_batched_backward_matches_plain(small_batch):
         if n > 0 and nb > 0:
             pq, pb = W.backward(s["bnd"], s["loop_off"], q[0][o:o + n], q[1][o:o + n], q[2][o:o + n], g[o:o + n])
             torch.cuda.synchronize()
-            assert torch.equal(gq[o:o + n], pq)
+            if nb > 512:
+                # the plain call splits a long boundary over few query tiles
+                # into vertex ranges and sums grad_q over them: equal to rounding
+                assert torch.allclose(gq[o:o + n], pq, rtol=1e-5, atol=1e-6 * float(pq.abs().max()))
+            else:
+                assert torch.equal(gq[o:o + n], pq)
             # the plain adjoint may hold fewer queries per lane for small query
             # counts, so its partial rows group the queries differently: the
             # float64 sums agree to rounding, not bit for bit
@@ -212,8 +225,8 @@ def test_batched_backward_matches_plain(small_batch):
 def test_full_size_batch_autotuned_parity():
     """The 256-surface workload at full size (11.2M triangles, 17.5M queries),
     in the configuration bench.py times (quick autotune, graph replay):
-    crossing counts bit-exact and |dw| <= 1e-4 against the oracle on one
-    seeded query of each of 128 surfaces; batched equals plain bit for bit on
+    crossing counts bit-exact and |dw| <= 1e-4 against the oracle on 16
+    seeded queries of each of the 256 surfaces; batched equals plain bit for bit on
     every 16th surface; the batched backward is finite everywhere."""
     CB = synth.coons_batch(4)
     d = CB.direction
@@ -225,19 +238,20 @@ def test_full_size_batch_autotuned_parity():
     assert torch.equal(w, w2) and torch.equal(chi, chi2)
     wc, cc = w.cpu().numpy(), chi.cpu().numpy()
     offs = np.concatenate([[0], np.cumsum([len(Q) for Q in CB.queries])])
+    import oracle_pool
     g = synth.rng(44)
+    sels = [g.choice(len(Q), 16, replace=False) for Q in CB.queries]
+    print("full batch: oracle on 16 queries of each of 256 surfaces", flush=True)
+    rs = oracle_pool.map_wn3d((M.V, M.F, Q[sel], d, None) for M, Q, sel in zip(CB.meshes, CB.queries, sels))
     n_deg = 0
-    for k in range(0, 256, 2):
-        M, Q = CB.meshes[k], CB.queries[k]
-        i = int(g.integers(len(Q)))
-        r = O.wn3d(M.V, M.F, Q[i:i + 1], d)
-        if r.degenerate[0]:
-            n_deg += 1
-            continue
-        assert cc[offs[k] + i] == r["chi"][0], k
-        if r["m_bnd"][0] > 1e-5:
-            assert abs(wc[offs[k] + i] - r["w"][0]) <= W_TOL, k
-    assert n_deg <= 2
+    for k, (r, sel) in enumerate(zip(rs, sels)):
+        ok = ~r.degenerate
+        n_deg += int((~ok).sum())
+        assert np.array_equal(cc[offs[k] + sel][ok], r["chi"][ok]), k
+        far = ok & (r["m_bnd"] > 1e-5)
+        assert np.abs(wc[offs[k] + sel][far] - r["w"][far]).max(initial=0.0) <= W_TOL, k
+    print(f"full batch: {16 * 256} oracle queries, {n_deg} degenerate", flush=True)
+    assert n_deg <= 0.02 * 16 * 256
     for k in range(0, 256, 16):
         s = surfs[k]
         a, b = int(offs[k]), int(offs[k + 1])

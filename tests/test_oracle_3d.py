@@ -122,8 +122,8 @@ def test_crossings_match_moller_trumbore():
     for _ in range(30):
         p = g.uniform(-1.3, 1.3, 3)
         d = synth.random_direction(int(g.integers(1 << 30)))
-        chi, me, mt = W.crossings(M.V, M.F, p[None], d, margins=True)
-        if me[0] < W.BAND or mt[0] < W.BAND:
+        chi, m = W.crossings(M.V, M.F, p[None], d, margins=True)
+        if m["m_ray"][0] < W.BAND or m["m_surf"][0] < W.BAND or m["m_self"][0] < W.BAND_SELF:
             continue
         assert chi[0] == moller_trumbore_chi(M.V, M.F, p, d[None])[0]
 
