@@ -178,13 +178,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
       bnd::Lane<1> s;
       rotate(D.F, px, py, pz, s.Xp[0], s.Yp[0], s.Zp[0]);
       turns_init(s.T[0]);
+      bnd::lane_range(s);
       // odd workgroups walk the boundary first: then waves waiting on node
       // fetches and waves issuing boundary arithmetic share every SIMD from
       // the start (each workgroup stays uniform, so its barriers still meet)
-      int chi = 0;
-      if (blockIdx.x & 1) bnd::boundary_walk(s, stage, D.nb, L, sv, staged);
+      int chi = 0, pend = 0;
+      if (blockIdx.x & 1) bnd::boundary_walk(s, stage, D.nb, L, sv, staged, pend);
       if (ok && fin) chi = traverse<kShortStack, true>(ca, s.Xp[0], s.Yp[0], s.Zp[0]);
-      if (!(blockIdx.x & 1)) bnd::boundary_walk(s, stage, D.nb, L, sv, staged);
+      if (!(blockIdx.x & 1)) bnd::boundary_walk(s, stage, D.nb, L, sv, staged, pend);
+      bnd::finish_turns(s, pend);
       if (ok) {
         const bool valid = fin && chi != WN_CHI_INVALID;
         a.w[q] = valid ? turns_to_w(s.T[0], chi) : __int_as_float(0x7fc00000);
@@ -236,7 +238,10 @@ __global__ __launch_bounds__(kThreads) void k_batch_bnd(FwdArgs a) {
       bnd::Lane<1> s;
       rotate(D.F, a.qx[q], a.qy[q], a.qz[q], s.Xp[0], s.Yp[0], s.Zp[0]);
       turns_init(s.T[0]);
-      bnd::boundary_walk(s, stage, D.nb, L, sv, staged);
+      bnd::lane_range(s);
+      int pend = 0;
+      bnd::boundary_walk(s, stage, D.nb, L, sv, staged, pend);
+      bnd::finish_turns(s, pend);
       if (ok) {
         const int chi = a.chi_buf[q];
         a.w[q] = chi != WN_CHI_INVALID ? turns_to_w(s.T[0], chi) : __int_as_float(0x7fc00000);

@@ -15,7 +15,7 @@ namespace {
 using namespace bnd;
 
 template <int QPL>
-__global__ __launch_bounds__(kThreads) void k_bnd3d(BndArgs a, LoopTable L) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL == 1 ? 8 : 4))) void k_bnd3d(BndArgs a, LoopTable L) {
   __shared__ double4 sv[kChunk];
 
   Lane<QPL> s;
@@ -30,10 +30,12 @@ __global__ __launch_bounds__(kThreads) void k_bnd3d(BndArgs a, LoopTable L) {
     rotate(a.F, a.qx[q], a.qy[q], a.qz[q], s.Xp[j], s.Yp[j], s.Zp[j]);
     turns_init(s.T[j]);
   }
+  lane_range(s);
 
-  int staged = -1;
+  int staged = -1, pend = 0;
   const KernargLoops KL{L};
-  boundary_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, staged);
+  boundary_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, staged, pend);
+  finish_turns(s, pend);
 
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
@@ -65,14 +67,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
   Lane<1> s;
   rotate(a.F, px, py, pz, s.Xp[0], s.Yp[0], s.Zp[0]);
   turns_init(s.T[0]);
+  lane_range(s);
   // odd workgroups walk the boundary first (uniform per workgroup, so the
   // staging barriers still meet): node fetches and boundary arithmetic then
   // overlap on every SIMD from the start
-  int staged = -1;
+  int staged = -1, pend = 0;
   const KernargLoops KL{L};
-  if (blockIdx.x & 1) boundary_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, staged);
+  if (blockIdx.x & 1) boundary_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, staged, pend);
   const int chi = (ok && fin) ? traverse<kShortStack>(c, s.Xp[0], s.Yp[0], s.Zp[0]) : WN_CHI_INVALID;
-  if (!(blockIdx.x & 1)) boundary_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, staged);
+  if (!(blockIdx.x & 1)) boundary_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, staged, pend);
+  finish_turns(s, pend);
   if (ok) {
     a.w_out[q] = chi != WN_CHI_INVALID ? turns_to_w(s.T[0], chi) : __int_as_float(0x7fc00000);
     if (chi_out) chi_out[q] = chi;

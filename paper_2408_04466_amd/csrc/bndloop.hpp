@@ -27,7 +27,13 @@ namespace bnd {
 
 constexpr int kThreads = 256;
 constexpr int kChunk = 512;      // vertices per LDS stage: 512 * 32 B = 16 KB
-constexpr int kUnroll = 8;       // vertices per main-loop step (one rescale per step)
+constexpr int kStep = 16;        // vertices per main-loop step
+constexpr int kRescale = 8;      // edges between rescales outside the main steps
+// A product of 16 edge factors stays within float64 range when every
+// boundary vertex is within 2^28 of the query (frame units; each factor is
+// at most 5 |a - p| |b - p|): true for queries within 2^26 of the frame's
+// centre, where the scene has size O(1).  Farther queries rescale every 8.
+constexpr double kNear = 67108864.0;   // 2^26
 
 // Loop table accessors: loops in the kernel arguments, or in device memory.
 struct KernargLoops {
@@ -102,7 +108,18 @@ template <int QPL>
 struct Lane {
   double Xp[QPL], Yp[QPL], Zp[QPL];
   Turns T[QPL];
+  bool far;   // uniform: some query of the wavefront lies beyond kNear
 };
+
+// Set once the lane's queries are rotated (every lane of the wavefront).
+template <int QPL>
+__device__ __forceinline__ void lane_range(Lane<QPL>& s) {
+  bool f = false;
+#pragma unroll
+  for (int k = 0; k < QPL; ++k)
+    f |= !(fabs(s.Xp[k]) + fabs(s.Yp[k]) + fabs(s.Zp[k]) < kNear);
+  s.far = __any(f);
+}
 
 template <int QPL>
 __device__ __forceinline__ void vert_q(const Lane<QPL>& s, const double4& v, VQ* out) {
@@ -126,14 +143,63 @@ __device__ __forceinline__ void rescale(Lane<QPL>& s) {
   for (int k = 0; k < QPL; ++k) turns_norm(s.T[k]);
 }
 
+template <int QPL>
+__device__ __forceinline__ void flush(Lane<QPL>& s, int n) {
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) turns_flush(s.T[k], n);
+}
+
+// Decide every pending turn of the lane (before reading its result).
+template <int QPL>
+__device__ __forceinline__ void finish_turns(Lane<QPL>& s, int& pend) {
+  if (pend > 0) flush(s, pend);
+  pend = 0;
+}
+
+// Edges j-1 -> j ... while kStep more vertices of the loop segment [j, j1)
+// remain; returns the next vertex.  FAR: rescale every 8 edges instead of 16.
+template <int QPL, bool FAR>
+__device__ __forceinline__ int main_steps(Lane<QPL>& s, const double4* sv, int c0, int j, int j1, VQ* A, VQ* B,
+                                          double& ptie, int& pend) {
+  for (; j + kStep <= j1; j += kStep) {
+    if (pend > kStep) {
+      flush(s, pend);
+      pend = 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kStep; u += 2) {
+      const double4 v0 = sv[j + u - c0];
+      vert_q(s, v0, B);
+      edge_step(s, A, B, ptie);
+      const double4 v1 = sv[j + u + 1 - c0];
+      vert_q(s, v1, A);
+      edge_step(s, B, A, v0.w);
+      ptie = v1.w;
+      // keep the scheduler from hoisting the LDS reads of later vertex
+      // pairs to the top of the step: that prefetch holds extra vector
+      // registers and cuts occupancy
+      __builtin_amdgcn_sched_barrier(0);
+      if (FAR && u + 2 == kStep / 2) rescale(s);
+    }
+    rescale(s);
+    pend += kStep;
+    if (pend == 2 * kStep) {
+      flush(s, pend);
+      pend = 0;
+    }
+  }
+  return j;
+}
+
 // Multiply every boundary edge factor of the loops into the lane's turn
 // accumulators.  All threads of the workgroup must call this together.
 // `staged` tracks which chunk is in LDS (-1: none) so that a caller walking
 // the same boundary again (next tile of queries) skips restaging when the
-// whole boundary fits in one chunk.
+// whole boundary fits in one chunk.  The turns of the last edges may still
+// be pending on return: call finish_turns before turns_to_w.
 template <int QPL, class Stager, class Loops>
 __device__ __forceinline__ void boundary_walk(Lane<QPL>& s, const Stager& stage, int nb, const Loops& L,
-                                              double4* sv, int& staged) {
+                                              double4* sv, int& staged, int& pend) {
   VQ first[QPL], A[QPL], B[QPL];   // A holds the previous vertex between steps
   double ptie = 0.0;               // uniform: tie offset of the edge leaving A
   int l = 0;
@@ -158,24 +224,14 @@ __device__ __forceinline__ void boundary_walk(Lane<QPL>& s, const Stager& stage,
         ptie = v.w;
         ++j;
       }
-      // kUnroll vertices per step, the roles of A and B alternating
-      for (; j + kUnroll <= j1; j += kUnroll) {
-#pragma unroll
-        for (int u = 0; u < kUnroll; u += 2) {
-          const double4 v0 = sv[j + u - c0];
-          vert_q(s, v0, B);
-          edge_step(s, A, B, ptie);
-          const double4 v1 = sv[j + u + 1 - c0];
-          vert_q(s, v1, A);
-          edge_step(s, B, A, v0.w);
-          ptie = v1.w;
-          // keep the scheduler from hoisting the LDS reads of later vertex
-          // pairs to the top of the step: that prefetch would hold up to
-          // 48 extra vector registers and cut occupancy from 8 to 5 waves
-          __builtin_amdgcn_sched_barrier(0);
-        }
-        rescale(s);
-      }
+      // kStep vertices per step, the roles of A and B alternating; the
+      // turns are decided every second step (32 edges), the product is
+      // rescaled every step (every half step for far queries)
+      if (s.far)
+        j = main_steps<QPL, true>(s, sv, c0, j, j1, A, B, ptie, pend);
+      else
+        j = main_steps<QPL, false>(s, sv, c0, j, j1, A, B, ptie, pend);
+      // the rest one vertex at a time (a rescale every kRescale edges)
       for (; j < j1; ++j) {
         const double4 v = sv[j - c0];
         vert_q(s, v, B);
@@ -183,10 +239,20 @@ __device__ __forceinline__ void boundary_walk(Lane<QPL>& s, const Stager& stage,
 #pragma unroll
         for (int k = 0; k < QPL; ++k) A[k] = B[k];
         ptie = v.w;
+        if (++pend == 32) {
+          flush(s, 32);
+          pend = 0;
+        }
+        if ((pend & (kRescale - 1)) == 0) rescale(s);
       }
       rescale(s);
       if (j1 < le) break;            // the loop continues in the next chunk
       edge_step(s, A, first, ptie);  // closing edge last -> first
+      if (++pend == 32) {
+        flush(s, 32);
+        pend = 0;
+      }
+      rescale(s);
     }
   }
 }

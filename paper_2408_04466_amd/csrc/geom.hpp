@@ -33,50 +33,54 @@ __device__ __forceinline__ void rotate(const Frame& F, float x, float y, float z
 }
 
 // Per (query, vertex) quantities in the frame, relative to the query.
-//   (X, Y, Z) = R (v - p): float64 difference of rotated coordinates, rounded
-//   once to float32 (no cancellation for nearby points).
-//   rho^2 = X^2 + Y^2, r = |v - p|, u = r + |Z|.
-//   alpha = r - Z is the stereographic denominator of the vertex seen from d;
-//   it is evaluated without cancellation by scaling the vertex with
-//   lam = u when Z > 0 (then lam*alpha = rho^2) and lam = 1 otherwise
-//   (alpha = u).  The edge terms are homogeneous of degree one in each
-//   vertex's (X, Y, alpha), so a positive per-vertex scale changes neither
-//   the angle of an edge nor the sign of any predicate.
-// The scaled values are float32 numbers held in float64 registers, so the
-// products of two of them in the edge terms below are exact.
+//   (X, Y, Z) = R (v - p): float64 differences of rotated coordinates (no
+//   cancellation for nearby points).  Every kernel forms them the same way,
+//   so each vertex has one value per query, shared by every edge and
+//   triangle that uses it.
+//   alpha = r - Z, with r = |v - p|: the stereographic denominator of the
+//   vertex seen from d (the region term of Eq. wn_discrete_sum, per edge, is
+//   the angle of alpha_a alpha_b + X_a X_b + Y_a Y_b + i N).  It is evaluated
+//   without cancellation as rho^2 / u + (|Z| - Z) with u = r + |Z| (= rho^2 /
+//   (r + Z) for Z > 0 and r + |Z| for Z <= 0); r and 1/u in float32, the
+//   rest in float64.
 struct VQ {
-  double x, y;  // lam * X, lam * Y
-  double a;     // lam * alpha
+  double x, y;  // X, Y
+  double a;     // alpha
 };
 
-__device__ __forceinline__ VQ vertex_q(double Xv, double Yv, double Zv,
-                                       double Xp, double Yp, double Zp, float* lz = nullptr) {
-  const float X = (float)(Xv - Xp);
-  const float Y = (float)(Yv - Yp);
-  const float Z = (float)(Zv - Zp);
-  const float rho2 = __fmaf_rn(X, X, __fmul_rn(Y, Y));
-  const float s = __fmaf_rn(Z, Z, rho2);
-  const float r = __builtin_amdgcn_sqrtf(s);
-  const float u = __fadd_rn(r, fabsf(Z));
-  const bool front = Z > 0.0f;
-  const float lam = front ? u : 1.0f;
+// The projected offset (X, Y) of a vertex from the ray, as the predicates use it.
+__device__ __forceinline__ VQ vertex_xy(double Xv, double Yv, double Xp, double Yp) {
   VQ q;
-  q.x = (double)__fmul_rn(lam, X);
-  q.y = (double)__fmul_rn(lam, Y);
-  q.a = (double)(front ? rho2 : u);
-  if (lz) *lz = __fmul_rn(lam, Z);
+  q.x = __dsub_rn(Xv, Xp);
+  q.y = __dsub_rn(Yv, Yp);
+  q.a = 0.0;
+  return q;
+}
+
+__device__ __forceinline__ VQ vertex_q(double Xv, double Yv, double Zv,
+                                       double Xp, double Yp, double Zp) {
+  VQ q = vertex_xy(Xv, Yv, Xp, Yp);
+  const double Z = __dsub_rn(Zv, Zp);
+  const double rho2 = __fma_rn(q.x, q.x, __dmul_rn(q.y, q.y));
+  const double s = __fma_rn(Z, Z, rho2);
+  const float r = __builtin_amdgcn_sqrtf((float)s);
+  const float u = __fadd_rn(r, fabsf((float)Z));
+  const double iu = (double)__builtin_amdgcn_rcpf(u);
+  q.a = __fma_rn(rho2, iu, __dsub_rn(fabs(Z), Z));
   return q;
 }
 
 // Edge predicate N(a, b) = Y_a X_b - X_a Y_b of the projected edge a->b
-// relative to the ray (proportional to d.(b' x a')).  The inputs are float32
-// values, so X_a*Y_b is exact in float64 and the fused multiply-add rounds
-// the exact difference once: N is correctly rounded, N(b, a) = -N(a, b) bit
-// for bit, and N == 0 exactly when the two projected vertices are collinear
-// with the ray.  Every triangle edge and every boundary edge goes through
-// this one function followed by `edge_tie`.
+// relative to the ray (proportional to d.(b' x a')): the two products
+// rounded to float64, then their difference (whose sign is exact).  Swapping
+// a and b swaps the two rounded products, so N(b, a) = -N(a, b) bit for bit
+// (zeros aside, which `edge_tie` resolves antisymmetrically).  Its sign is the
+// exact sign of Y_a X_b - X_a Y_b unless that is below 2^-52 (|Y_a X_b| +
+// |X_a Y_b|).  Every triangle edge and every boundary edge goes through this
+// one function followed by `edge_tie`, so the crossing count and the branch
+// of the boundary term flip at the same inputs.
 __device__ __forceinline__ double edge_n(const VQ& a, const VQ& b) {
-  return __fma_rn(a.y, b.x, -__dmul_rn(a.x, b.y));
+  return __dsub_rn(__dmul_rn(a.y, b.x), __dmul_rn(a.x, b.y));
 }
 
 // Lexicographic order of two rotated vertices; distinct float32 vertices
@@ -88,8 +92,9 @@ __device__ __forceinline__ bool lex_less(double ax, double ay, double az,
 
 // Tie offset of the directed edge a->b: -2^-1022 if a precedes b
 // lexicographically, +2^-1022 otherwise (antisymmetric in a, b).  A nonzero
-// N is at least 2^-298 in magnitude (a difference of products of float32
-// values), so adding the offset changes nothing but an exact zero, which
+// N is far above 2^-1022 in magnitude (a difference of two rounded products
+// of coordinate differences), so adding the offset changes nothing but an
+// exact zero, which
 // becomes a value whose sign picks the side of the lexicographically smaller
 // end point.  N(a,b) + tie(a,b) stays exactly antisymmetric, so of two
 // triangles sharing an edge exactly one claims a ray through it, and the
@@ -103,31 +108,44 @@ __device__ __forceinline__ double edge_tie(double n, double tie) {
   return __dadd_rn(n, tie);
 }
 
-// Edge factor D + iN (up to the positive scale lam_a*lam_b): the angle
-// theta_e = atan2(N, D) is half the signed solid angle of the spherical
-// triangle (-d, a - p, b - p), i.e. the per-edge boundary term.
+// Edge factor D + iN: the angle theta_e = atan2(N, D) is half the signed
+// solid angle of the spherical triangle (-d, a - p, b - p), i.e. the
+// per-edge boundary term (D = alpha_a alpha_b + X_a X_b + Y_a Y_b).
 __device__ __forceinline__ double edge_d(const VQ& a, const VQ& b) {
-  return __fma_rn(a.y, b.y, __fma_rn(a.x, b.x, __dmul_rn(a.a, b.a)));
+  return __fma_rn(a.a, b.a, __fma_rn(a.x, b.x, __dmul_rn(a.y, b.y)));
 }
 
 // Running product of the edge factors with an exact count of turns:
-// sum_e theta_e = arg(zr + i zi) + 2 pi k.  The product is kept in float64
-// (its magnitude changes by the factors' magnitudes; float64 range allows
-// rescaling only every few edges).  Multiplying by a factor whose angle lies
-// in (-pi, pi] carries the argument across the negative real axis exactly
-// when the old product and the factor lie in the same closed half plane (by
-// sign bit) and the new product in the other one; the sign bits make the
-// count agree with atan2's branch.  The tie offset keeps N nonzero, so the
-// product starts from 1 without losing the sign of a zero.
+// sum_e theta_e = arg(zr + i zi) + 2 pi (ku - kd).  The product is kept in
+// float64 and rescaled by a power of two every few edges.  Multiplying by a
+// factor whose angle lies in (-pi, pi] carries the argument across the
+// negative real axis exactly when the old product and the factor lie in the
+// same closed half plane (by sign bit) and the new product in the other
+// one; the sign bits make the count agree with atan2's branch.  The tie
+// offset keeps N nonzero, so the product starts from 1 without losing the
+// sign of a zero.
+//
+// The three sign bits of an edge are not combined edge by edge: the sign of
+// each factor's N and of each new product's imaginary part are shifted into
+// two bit registers (bacc, cacc) as the edges go by, and every group of at
+// most 32 edges is decided at once (turns_flush): with the old product's
+// sign a_j = c_(j-1), a turn backward past -pi is a_j & b_j & ~c_j and one
+// forward past pi is ~a_j & ~b_j & c_j, counted by population counts.
 struct Turns {
   double zr, zi;
-  int k;
+  uint32_t bacc, cacc;   // sign bits of the group's N and new zi (newest in bit 0)
+  uint32_t cprev;        // cacc when the last group was decided (bit 0: zi's sign then)
+  int kd, ku;            // turns backward past -pi / forward past pi
 };
 
 __device__ __forceinline__ void turns_init(Turns& t) {
   t.zr = 1.0;
   t.zi = 0.0;
-  t.k = 0;
+  t.bacc = 0u;
+  t.cacc = 0u;
+  t.cprev = 0u;
+  t.kd = 0;
+  t.ku = 0;
 }
 
 __device__ __forceinline__ int hi_word(double x) {
@@ -137,14 +155,25 @@ __device__ __forceinline__ int hi_word(double x) {
 __device__ __forceinline__ void turns_mul(Turns& t, double D, double N) {
   const double nr = __fma_rn(t.zr, D, -__dmul_rn(t.zi, N));
   const double ni = __fma_rn(t.zr, N, __dmul_rn(t.zi, D));
-  const int A = hi_word(t.zi);
-  const int B = hi_word(N);
-  const int C = hi_word(ni);
-  const int up = (~A & ~B & C) >> 31;   // -1: turned forward past pi
-  const int dn = (A & B & ~C) >> 31;    // -1: turned backward past -pi
-  t.k += dn - up;
+  t.bacc = __builtin_amdgcn_alignbit(t.bacc, (uint32_t)hi_word(N), 31);
+  t.cacc = __builtin_amdgcn_alignbit(t.cacc, (uint32_t)hi_word(ni), 31);
   t.zr = nr;
   t.zi = ni;
+}
+
+// Decide the last n (1..32, the same for every lane) edges' turns.  The
+// old sign of edge j of the group is the new sign of edge j - 1, i.e. cacc
+// shifted by one, with the sign from before the group (bit 0 of cprev)
+// entering at the top; bacc restarts, cacc keeps running.
+__device__ __forceinline__ void turns_flush(Turns& t, int n) {
+  const uint32_t m = n >= 32 ? 0xFFFFFFFFu : ((1u << n) - 1u);
+  const uint32_t a = __builtin_amdgcn_alignbit(t.cprev, t.cacc, 1);
+  const uint32_t b = t.bacc;           // zero above bit n - 1
+  const uint32_t c = t.cacc & m;
+  t.kd += __popc(a & b & ~c);
+  t.ku += __popc(~a & ~b & c);
+  t.bacc = 0u;
+  t.cprev = t.cacc;
 }
 
 // Rescale by a power of two (exact; keeps signs and zeros).
@@ -152,20 +181,6 @@ __device__ __forceinline__ void turns_norm(Turns& t) {
   const int e = max(__builtin_amdgcn_frexp_exp(t.zr), __builtin_amdgcn_frexp_exp(t.zi));
   t.zr = __builtin_amdgcn_ldexp(t.zr, -e);
   t.zi = __builtin_amdgcn_ldexp(t.zi, -e);
-}
-
-// Combine two partial products (edge chunks of one query).
-__device__ __forceinline__ void turns_join(Turns& t, const Turns& o) {
-  const double nr = __fma_rn(t.zr, o.zr, -__dmul_rn(t.zi, o.zi));
-  const double ni = __fma_rn(t.zr, o.zi, __dmul_rn(t.zi, o.zr));
-  const int A = hi_word(t.zi);
-  const int B = hi_word(o.zi);
-  const int C = hi_word(ni);
-  const int up = (~A & ~B & C) >> 31;
-  const int dn = (A & B & ~C) >> 31;
-  t.k += o.k + dn - up;
-  t.zr = nr;
-  t.zi = ni;
 }
 
 constexpr float kInv2Pi = 0.15915494309189535f;
@@ -199,7 +214,7 @@ __device__ __forceinline__ float atan2_f32(float y, float x) {
   return copysignf(r, y);
 }
 
-// w = chi + k + atan2(zi, zr) / (2 pi).  After a power-of-two rescale the
+// w = chi + ku - kd + atan2(zi, zr) / (2 pi) (every turn flushed).  After a power-of-two rescale the
 // larger component lies in [0.5, 1), so both round to float32 without
 // overflow; a component that underflows keeps its sign bit, so the branch
 // (+pi or -pi on the negative real axis) is the one the turn count assumed.
@@ -208,7 +223,7 @@ __device__ __forceinline__ float atan2_f32(float y, float x) {
 __device__ __forceinline__ float turns_to_w(Turns t, int chi) {
   turns_norm(t);
   const float ang = atan2_f32((float)t.zi, (float)t.zr);
-  return __fadd_rn((float)(chi + t.k), __fmul_rn(ang, kInv2Pi));
+  return __fadd_rn((float)(chi + t.ku - t.kd), __fmul_rn(ang, kInv2Pi));
 }
 
 }  // namespace wn

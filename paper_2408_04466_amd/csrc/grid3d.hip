@@ -39,10 +39,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
   Lane<1> s;
   rotate(a.F, px, py, pz, s.Xp[0], s.Yp[0], s.Zp[0]);
   turns_init(s.T[0]);
+  lane_range(s);
   const int chi = (ok && fin) ? traverse<kShortStack>(c, s.Xp[0], s.Yp[0], s.Zp[0]) : WN_CHI_INVALID;
-  int staged = -1;
+  int staged = -1, pend = 0;
   const KernargLoops KL{L};
-  boundary_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, staged);
+  boundary_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, staged, pend);
+  finish_turns(s, pend);
   if (ok) {
     a.w_out[q] = chi != WN_CHI_INVALID ? turns_to_w(s.T[0], chi) : __int_as_float(0x7fc00000);
     if (chi_out) chi_out[q] = chi;

@@ -28,10 +28,9 @@ __device__ __forceinline__ int tri_crossing(const int4 t, const double4* __restr
   const double4 A = Vr[t.x & 0x7fffffff];
   const double4 B = Vr[t.y & 0x7fffffff];
   const double4 C = Vr[t.z & 0x7fffffff];
-  float za, zb, zc;
-  const VQ a = vertex_q(A.x, A.y, A.z, Xp, Yp, Zp, &za);
-  const VQ b = vertex_q(B.x, B.y, B.z, Xp, Yp, Zp, &zb);
-  const VQ c = vertex_q(C.x, C.y, C.z, Xp, Yp, Zp, &zc);
+  const VQ a = vertex_xy(A.x, A.y, Xp, Yp);
+  const VQ b = vertex_xy(B.x, B.y, Xp, Yp);
+  const VQ c = vertex_xy(C.x, C.y, Xp, Yp);
   // the stored bits, or the same comparisons redone (fewer live registers
   // where the register budget is tight)
   const bool l01 = STORED_TIES ? (tb & 1u) != 0 : lex_less(A.x, A.y, A.z, B.x, B.y, B.z);
@@ -42,10 +41,11 @@ __device__ __forceinline__ int tri_crossing(const int4 t, const double4* __restr
   const double n20 = edge_tie(edge_n(c, a), tie_offset(l20));
   const bool s01 = n01 < 0.0, s12 = n12 < 0.0, s20 = n20 < 0.0;
   if (s01 != s12 || s12 != s20) return 0;
-  // Height of the crossing above p: barycentric weights are the edge values
-  // opposite each vertex (divided by the vertex scales), so the crossing is
-  // above p iff sum(N_opp * lam * Z) has the sign of the N's.
-  const double num = __fma_rn(n12, (double)za, __fma_rn(n20, (double)zb, __dmul_rn(n01, (double)zc)));
+  // Height of the crossing above p: the barycentric weights are the edge
+  // values opposite each vertex, so the crossing is above p iff
+  // sum(N_opp * Z) has the sign of the N's.
+  const double za = __dsub_rn(A.z, Zp), zb = __dsub_rn(B.z, Zp), zc = __dsub_rn(C.z, Zp);
+  const double num = __fma_rn(n12, za, __fma_rn(n20, zb, __dmul_rn(n01, zc)));
   const bool hit = s01 ? (num < 0.0) : (num > 0.0);
   return hit ? (s01 ? 1 : -1) : 0;
 }
