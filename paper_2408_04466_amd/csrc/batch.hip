@@ -36,7 +36,7 @@ struct SurfDesc {
   Frame F;
   const BvhNode* nodes;
   const int4* tris;
-  const double4* Vr;
+  const RPt* Vr;
   const float4* leafbox;
   const float* leafz;
   int32_t nf;
@@ -79,7 +79,7 @@ struct FwdArgs {
   int32_t direct;          // 1: one workgroup per item (item = blockIdx.x, no counter)
   int32_t* counter;        // [0]: fused or crossing kernel, [1]: boundary kernel
   int32_t* chi_buf;        // split mode: crossing counts (chi_out or a batch buffer)
-  const double4* bndr;     // rotated boundary arena (bnd::stage_vertex of every vertex)
+  const RPt* bndr;         // rotated boundary arena (bnd::stage_vertex of every vertex)
   const int32_t* loops;
   const float* qx;
   const float* qy;
@@ -159,7 +159,7 @@ __device__ __forceinline__ CrossArgs cross_args(const SurfDesc& D) {
 // Fused mode: per query, the crossing count and then the boundary walk.
 // Seven waves per SIMD (71 registers; one 64-bit value spills in the prologue).
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_batch_fwd(FwdArgs a) {
-  __shared__ double4 sv[bnd::kChunk];
+  __shared__ RPt sv[bnd::kChunk];
   __shared__ int s_item;
   for (int pass = 0;; ++pass) {
     const int it = item_for(a.direct, pass, a.n_items, a.counter, &s_item);
@@ -176,7 +176,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
       const float px = a.qx[q], py = a.qy[q], pz = a.qz[q];
       const bool fin = isfinite(px) && isfinite(py) && isfinite(pz);
       bnd::Lane<1> s;
-      rotate(D.F, px, py, pz, s.Xp[0], s.Yp[0], s.Zp[0]);
+      {
+        double X, Y, Z;
+        rotate(D.F, px, py, pz, X, Y, Z);
+        s.p[0] = make_qp(X, Y, Z);
+      }
       turns_init(s.T[0]);
       bnd::lane_range(s);
       // odd workgroups walk the boundary first: then waves waiting on node
@@ -184,7 +188,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
       // the start (each workgroup stays uniform, so its barriers still meet)
       int chi = 0, pend = 0;
       if (blockIdx.x & 1) bnd::boundary_walk(s, stage, D.nb, L, sv, staged, pend);
-      if (ok && fin) chi = traverse<kShortStack, true>(ca, s.Xp[0], s.Yp[0], s.Zp[0]);
+      if (ok && fin) chi = traverse<kShortStack, true>(ca, s.p[0]);
       if (!(blockIdx.x & 1)) bnd::boundary_walk(s, stage, D.nb, L, sv, staged, pend);
       bnd::finish_turns(s, pend);
       if (ok) {
@@ -213,7 +217,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_cross(FwdArgs a) {
       if (isfinite(px) && isfinite(py) && isfinite(pz)) {
         double X, Y, Z;
         rotate(D.F, px, py, pz, X, Y, Z);
-        chi = traverse<kShortStack, true>(ca, X, Y, Z);
+        chi = traverse<kShortStack, true>(ca, make_qp(X, Y, Z));
       }
       a.chi_buf[q] = chi;
     }
@@ -222,7 +226,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_cross(FwdArgs a) {
 
 // Split mode, second kernel: boundary walk, combined with chi_buf into w.
 __global__ __launch_bounds__(kThreads) void k_batch_bnd(FwdArgs a) {
-  __shared__ double4 sv[bnd::kChunk];
+  __shared__ RPt sv[bnd::kChunk];
   __shared__ int s_item;
   for (int pass = 0;; ++pass) {
     const int it = item_for(a.direct, pass, a.n_items, a.counter + 1, &s_item);
@@ -236,7 +240,11 @@ __global__ __launch_bounds__(kThreads) void k_batch_bnd(FwdArgs a) {
       const bool ok = r + (int)threadIdx.x < item.cnt;
       const int64_t q = item.q0 + (ok ? r + (int)threadIdx.x : 0);
       bnd::Lane<1> s;
-      rotate(D.F, a.qx[q], a.qy[q], a.qz[q], s.Xp[0], s.Yp[0], s.Zp[0]);
+      {
+        double X, Y, Z;
+        rotate(D.F, a.qx[q], a.qy[q], a.qz[q], X, Y, Z);
+        s.p[0] = make_qp(X, Y, Z);
+      }
       turns_init(s.T[0]);
       bnd::lane_range(s);
       int pend = 0;
@@ -327,7 +335,7 @@ __global__ void k_batch_groups(const SurfDesc* __restrict__ descs, const int32_t
 // boundaries, staged exactly as the plain kernels stage it.
 __global__ void k_rotate_bnd(const SurfDesc* __restrict__ descs, const int32_t* __restrict__ loops,
                              const float* __restrict__ bnd, const int32_t* __restrict__ surf_of, int64_t nb_tot,
-                             double4* __restrict__ out) {
+                             RPt* __restrict__ out) {
   const int64_t gv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gv >= nb_tot) return;
   const SurfDesc D = descs[surf_of[gv]];
@@ -358,7 +366,7 @@ struct wn_batch {
   wn::SurfDesc* d_desc = nullptr;
   int32_t* d_loops = nullptr;
   float* d_bnd = nullptr;
-  double4* d_bndr = nullptr;          // rotated boundary arena (forward)
+  wn::RPt* d_bndr = nullptr;          // rotated boundary arena (forward)
   int32_t* d_surf_of = nullptr;       // boundary vertex -> surface
   int32_t* d_counter = nullptr;
   // forward work list
@@ -821,7 +829,7 @@ wn_status wn_batch_create(const wn_surface* surfs, int32_t ns, const double dir[
     if (nbs[i] > 0)
       chk(hipMemcpyAsync(b->d_bnd + 3 * b->desc[i].bnd_off, surfs[i].bnd_xyz, (size_t)nbs[i] * 3 * sizeof(float),
                          hipMemcpyDeviceToDevice, s));
-  if (e == hipSuccess) chk(hipMalloc((void**)&b->d_bndr, std::max<int64_t>(1, boff) * sizeof(double4)));
+  if (e == hipSuccess) chk(hipMalloc((void**)&b->d_bndr, std::max<int64_t>(1, boff) * sizeof(wn::RPt)));
   if (e == hipSuccess && boff > 0) {
     hipLaunchKernelGGL(wn::k_rotate_bnd, dim3((unsigned)((boff + 255) / 256)), dim3(256), 0, s, b->d_desc,
                        b->d_loops, b->d_bnd, b->d_surf_of, boff, b->d_bndr);

@@ -16,7 +16,7 @@ using namespace bnd;
 
 template <int QPL>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL == 1 ? 8 : 4))) void k_bnd3d(BndArgs a, LoopTable L) {
-  __shared__ double4 sv[kChunk];
+  __shared__ RPt sv[kChunk];
 
   Lane<QPL> s;
   int64_t qi[QPL];
@@ -27,7 +27,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL ==
     qi[j] = base + (int64_t)j * kThreads;
     ok[j] = qi[j] < a.nq;
     const int64_t q = ok[j] ? qi[j] : 0;
-    rotate(a.F, a.qx[q], a.qy[q], a.qz[q], s.Xp[j], s.Yp[j], s.Zp[j]);
+    double X, Y, Z;
+    rotate(a.F, a.qx[q], a.qy[q], a.qz[q], X, Y, Z);
+    s.p[j] = make_qp(X, Y, Z);
     turns_init(s.T[j]);
   }
   lane_range(s);
@@ -58,14 +60,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL ==
 // Seven waves per SIMD: with the alternating order below, the eight-wave
 // budget of 64 registers spilled.
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_fwd3d(CrossArgs c, BndArgs a, LoopTable L, int32_t* chi_out) {
-  __shared__ double4 sv[kChunk];
+  __shared__ RPt sv[kChunk];
   const int64_t qi = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const bool ok = qi < a.nq;
   const int64_t q = ok ? qi : 0;
   const float px = a.qx[q], py = a.qy[q], pz = a.qz[q];
   const bool fin = isfinite(px) && isfinite(py) && isfinite(pz);
   Lane<1> s;
-  rotate(a.F, px, py, pz, s.Xp[0], s.Yp[0], s.Zp[0]);
+  {
+    double X, Y, Z;
+    rotate(a.F, px, py, pz, X, Y, Z);
+    s.p[0] = make_qp(X, Y, Z);
+  }
   turns_init(s.T[0]);
   lane_range(s);
   // odd workgroups walk the boundary first (uniform per workgroup, so the
@@ -74,7 +80,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
   int staged = -1, pend = 0;
   const KernargLoops KL{L};
   if (blockIdx.x & 1) boundary_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, staged, pend);
-  const int chi = (ok && fin) ? traverse<kShortStack>(c, s.Xp[0], s.Yp[0], s.Zp[0]) : WN_CHI_INVALID;
+  const int chi = (ok && fin) ? traverse<kShortStack>(c, s.p[0]) : WN_CHI_INVALID;
   if (!(blockIdx.x & 1)) boundary_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, staged, pend);
   finish_turns(s, pend);
   if (ok) {

@@ -10,8 +10,9 @@
 // over the boundary (the paper evaluates region areas from boundary
 // integrals as well, Sec. 4 "Exact Computations").
 //
-// Layout: the workgroup stages the boundary loops into LDS (rotated float64
-// coordinates plus the tie offset of the edge leaving each vertex) in chunks
+// Layout: the workgroup stages the boundary loops into LDS (rotated
+// coordinates as float32 pairs plus the tie offset of the edge leaving each
+// vertex, 32 bytes) in chunks
 // of kChunk vertices, and every lane walks the same vertex sequence, so the
 // LDS reads are broadcasts.  Per (query, vertex) the frame quantities are
 // formed once and reused by the two edges that share the vertex.  Instead of
@@ -64,67 +65,67 @@ __device__ __forceinline__ int loop_of(const Loops& L, int i) {
   return lo;
 }
 
-// Boundary vertex i as staged: rotated coordinates and, in .w, the tie
+// Boundary vertex i as staged: rotated coordinates (split) and the tie
 // offset of the edge v_i -> v_next(i).
 template <class Loops>
-__device__ __forceinline__ double4 stage_vertex(const Frame& F, const float* __restrict__ bnd, const Loops& L,
-                                                int i) {
+__device__ __forceinline__ RPt stage_vertex(const Frame& F, const float* __restrict__ bnd, const Loops& L, int i) {
   const int l = loop_of(L, i);
   const int nxt = (i + 1 < L.off(l + 1)) ? i + 1 : L.off(l);
   double X, Y, Z, Xn, Yn, Zn;
   rotate(F, bnd[3 * i], bnd[3 * i + 1], bnd[3 * i + 2], X, Y, Z);
   rotate(F, bnd[3 * nxt], bnd[3 * nxt + 1], bnd[3 * nxt + 2], Xn, Yn, Zn);
-  return make_double4(X, Y, Z, tie_offset(lex_less(X, Y, Z, Xn, Yn, Zn)));
+  const RPt a = make_rpt(X, Y, Z, 0.0), b = make_rpt(Xn, Yn, Zn, 0.0);
+  return make_rpt(X, Y, Z, tie_offset(rpt_less(a, b)));
 }
 
 // Stage vertices [c0, c0 + cnt) into LDS.
 template <class Loops>
 __device__ __forceinline__ void stage_chunk(const Frame& F, const float* __restrict__ bnd, const Loops& L,
-                                            int c0, int cnt, double4* sv) {
+                                            int c0, int cnt, RPt* sv) {
   for (int j = threadIdx.x; j < cnt; j += kThreads) sv[j] = stage_vertex(F, bnd, L, c0 + j);
 }
 
-// Stagers: fill LDS with vertices [c0, c0 + cnt) as (X, Y, Z, tie).
-// StageRotate rotates the float32 boundary on the fly; StageCopy copies a
-// boundary that was rotated beforehand with the same arithmetic (the batched
-// path rotates each surface's boundary once, when the batch is created).
+// Stagers: fill LDS with vertices [c0, c0 + cnt).  StageRotate rotates the
+// float32 boundary on the fly; StageCopy copies a boundary that was rotated
+// beforehand with the same arithmetic (the batched path rotates each
+// surface's boundary once, when the batch is created).
 template <class Loops>
 struct StageRotate {
   const Frame& F;
   const float* __restrict__ bnd;
   const Loops& L;
-  __device__ __forceinline__ void operator()(int c0, int cnt, double4* sv) const {
+  __device__ __forceinline__ void operator()(int c0, int cnt, RPt* sv) const {
     stage_chunk(F, bnd, L, c0, cnt, sv);
   }
 };
 struct StageCopy {
-  const double4* __restrict__ src;
-  __device__ __forceinline__ void operator()(int c0, int cnt, double4* sv) const {
+  const RPt* __restrict__ src;
+  __device__ __forceinline__ void operator()(int c0, int cnt, RPt* sv) const {
     for (int j = threadIdx.x; j < cnt; j += kThreads) sv[j] = src[c0 + j];
   }
 };
 
 template <int QPL>
 struct Lane {
-  double Xp[QPL], Yp[QPL], Zp[QPL];
+  QP p[QPL];
   Turns T[QPL];
   bool far;   // uniform: some query of the wavefront lies beyond kNear
 };
 
-// Set once the lane's queries are rotated (every lane of the wavefront).
+// Set once the lane's queries are in place (every lane of the wavefront).
 template <int QPL>
 __device__ __forceinline__ void lane_range(Lane<QPL>& s) {
   bool f = false;
 #pragma unroll
   for (int k = 0; k < QPL; ++k)
-    f |= !(fabs(s.Xp[k]) + fabs(s.Yp[k]) + fabs(s.Zp[k]) < kNear);
+    f |= !(fabsf(s.p[k].xh) + fabsf(s.p[k].yh) + fabsf(s.p[k].zh) < (float)kNear);
   s.far = __any(f);
 }
 
 template <int QPL>
-__device__ __forceinline__ void vert_q(const Lane<QPL>& s, const double4& v, VQ* out) {
+__device__ __forceinline__ void vert_q(const Lane<QPL>& s, const RPt& v, VQ* out) {
 #pragma unroll
-  for (int k = 0; k < QPL; ++k) out[k] = vertex_q(v.x, v.y, v.z, s.Xp[k], s.Yp[k], s.Zp[k]);
+  for (int k = 0; k < QPL; ++k) out[k] = vertex_q(v, s.p[k]);
 }
 
 template <int QPL>
@@ -132,7 +133,7 @@ __device__ __forceinline__ void edge_step(Lane<QPL>& s, const VQ* a, const VQ* b
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
     const double N = edge_tie(edge_n(a[k], b[k]), tie);
-    const double D = edge_d(a[k], b[k]);
+    const double D = (double)edge_d(a[k], b[k]);
     turns_mul(s.T[k], D, N);
   }
 }
@@ -159,7 +160,7 @@ __device__ __forceinline__ void finish_turns(Lane<QPL>& s, int& pend) {
 // Edges j-1 -> j ... while kStep more vertices of the loop segment [j, j1)
 // remain; returns the next vertex.  FAR: rescale every 8 edges instead of 16.
 template <int QPL, bool FAR>
-__device__ __forceinline__ int main_steps(Lane<QPL>& s, const double4* sv, int c0, int j, int j1, VQ* A, VQ* B,
+__device__ __forceinline__ int main_steps(Lane<QPL>& s, const RPt* sv, int c0, int j, int j1, VQ* A, VQ* B,
                                           double& ptie, int& pend) {
   for (; j + kStep <= j1; j += kStep) {
     if (pend > kStep) {
@@ -168,13 +169,13 @@ __device__ __forceinline__ int main_steps(Lane<QPL>& s, const double4* sv, int c
     }
 #pragma unroll
     for (int u = 0; u < kStep; u += 2) {
-      const double4 v0 = sv[j + u - c0];
+      const RPt v0 = sv[j + u - c0];
       vert_q(s, v0, B);
       edge_step(s, A, B, ptie);
-      const double4 v1 = sv[j + u + 1 - c0];
+      const RPt v1 = sv[j + u + 1 - c0];
       vert_q(s, v1, A);
-      edge_step(s, B, A, v0.w);
-      ptie = v1.w;
+      edge_step(s, B, A, rpt_tie(v0));
+      ptie = rpt_tie(v1);
       // keep the scheduler from hoisting the LDS reads of later vertex
       // pairs to the top of the step: that prefetch holds extra vector
       // registers and cuts occupancy
@@ -199,7 +200,7 @@ __device__ __forceinline__ int main_steps(Lane<QPL>& s, const double4* sv, int c
 // be pending on return: call finish_turns before turns_to_w.
 template <int QPL, class Stager, class Loops>
 __device__ __forceinline__ void boundary_walk(Lane<QPL>& s, const Stager& stage, int nb, const Loops& L,
-                                              double4* sv, int& staged, int& pend) {
+                                              RPt* sv, int& staged, int& pend) {
   VQ first[QPL], A[QPL], B[QPL];   // A holds the previous vertex between steps
   double ptie = 0.0;               // uniform: tie offset of the edge leaving A
   int l = 0;
@@ -217,11 +218,11 @@ __device__ __forceinline__ void boundary_walk(Lane<QPL>& s, const Stager& stage,
       int j = max(ls, c0);
       const int j1 = min(le, c1);
       if (j == ls) {
-        const double4 v = sv[j - c0];
+        const RPt v = sv[j - c0];
         vert_q(s, v, first);
 #pragma unroll
         for (int k = 0; k < QPL; ++k) A[k] = first[k];
-        ptie = v.w;
+        ptie = rpt_tie(v);
         ++j;
       }
       // kStep vertices per step, the roles of A and B alternating; the
@@ -233,12 +234,12 @@ __device__ __forceinline__ void boundary_walk(Lane<QPL>& s, const Stager& stage,
         j = main_steps<QPL, false>(s, sv, c0, j, j1, A, B, ptie, pend);
       // the rest one vertex at a time (a rescale every kRescale edges)
       for (; j < j1; ++j) {
-        const double4 v = sv[j - c0];
+        const RPt v = sv[j - c0];
         vert_q(s, v, B);
         edge_step(s, A, B, ptie);
 #pragma unroll
         for (int k = 0; k < QPL; ++k) A[k] = B[k];
-        ptie = v.w;
+        ptie = rpt_tie(v);
         if (++pend == 32) {
           flush(s, 32);
           pend = 0;

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(256) void k_cross3d(CrossArgs a) {
   }
   double Xp, Yp, Zp;
   rotate(a.F, px, py, pz, Xp, Yp, Zp);
-  a.chi[q] = traverse<S, true>(a, Xp, Yp, Zp);
+  a.chi[q] = traverse<S, true>(a, make_qp(Xp, Yp, Zp));
 }
 
 hipError_t launch_cross3d(const CrossArgs& a, hipStream_t s) {
@@ -66,27 +66,29 @@ __device__ __forceinline__ float f_up(double x) {
   return f;
 }
 
-__global__ void k_rotate_vertices(Frame F, const float* __restrict__ V, int32_t nv,
-                                  double4* __restrict__ Vr) {
+__global__ void k_rotate_vertices(Frame F, const float* __restrict__ V, int32_t nv, RPt* __restrict__ Vr) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nv) return;
   double X, Y, Z;
   rotate(F, V[3 * i], V[3 * i + 1], V[3 * i + 2], X, Y, Z);
-  Vr[i] = make_double4(X, Y, Z, 0.0);
+  Vr[i] = make_rpt(X, Y, Z, 0.0);
 }
 
 // Projected box (+ pad) of each triangle and its centroid.
-__global__ void k_tri_boxes(const double4* __restrict__ Vr, const int32_t* __restrict__ Fc,
+__global__ void k_tri_boxes(const RPt* __restrict__ Vr, const int32_t* __restrict__ Fc,
                             int32_t nf, float pad, float4* __restrict__ box,
                             float* __restrict__ zmax, float2* __restrict__ cen) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nf) return;
-  const double4 A = Vr[Fc[3 * i]];
-  const double4 B = Vr[Fc[3 * i + 1]];
-  const double4 C = Vr[Fc[3 * i + 2]];
-  const double x0 = fmin(A.x, fmin(B.x, C.x)), x1 = fmax(A.x, fmax(B.x, C.x));
-  const double y0 = fmin(A.y, fmin(B.y, C.y)), y1 = fmax(A.y, fmax(B.y, C.y));
-  const double z1 = fmax(A.z, fmax(B.z, C.z));
+  const RPt A = Vr[Fc[3 * i]];
+  const RPt B = Vr[Fc[3 * i + 1]];
+  const RPt C = Vr[Fc[3 * i + 2]];
+  const double ax = hilo(A.xy.x, A.xy.y), bx = hilo(B.xy.x, B.xy.y), cx = hilo(C.xy.x, C.xy.y);
+  const double ay = hilo(A.xy.z, A.xy.w), by = hilo(B.xy.z, B.xy.w), cy = hilo(C.xy.z, C.xy.w);
+  const double az = hilo(A.zt.x, A.zt.y), bz = hilo(B.zt.x, B.zt.y), cz = hilo(C.zt.x, C.zt.y);
+  const double x0 = fmin(ax, fmin(bx, cx)), x1 = fmax(ax, fmax(bx, cx));
+  const double y0 = fmin(ay, fmin(by, cy)), y1 = fmax(ay, fmax(by, cy));
+  const double z1 = fmax(az, fmax(bz, cz));
   box[i] = make_float4(f_down(x0) - pad, f_up(x1) + pad, f_down(y0) - pad, f_up(y1) + pad);
   zmax[i] = f_up(z1) + pad;
   cen[i] = make_float2((float)(0.5 * (x0 + x1)), (float)(0.5 * (y0 + y1)));
@@ -196,17 +198,15 @@ __global__ void k_karras(const unsigned* __restrict__ keys, int32_t n, int32_t* 
 // the edge's tie offset, which is then not recomputed per crossing test.
 __global__ void k_gather_leaves(const int32_t* __restrict__ Fc, const int32_t* __restrict__ order,
                                 int32_t nf, const float4* __restrict__ box,
-                                const float* __restrict__ zmax, const double4* __restrict__ Vr,
+                                const float* __restrict__ zmax, const RPt* __restrict__ Vr,
                                 int4* __restrict__ tris, float4* __restrict__ lbox, float* __restrict__ lz) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nf) return;
   int f = order[i];
   if (f < 0 || f >= nf) f = 0;   // never taken for a permutation
   const int32_t i0 = Fc[3 * f], i1 = Fc[3 * f + 1], i2 = Fc[3 * f + 2];
-  const double4 A = Vr[i0], B = Vr[i1], C = Vr[i2];
-  tris[i] = make_int4(tri_index(i0, lex_less(A.x, A.y, A.z, B.x, B.y, B.z)),
-                      tri_index(i1, lex_less(B.x, B.y, B.z, C.x, C.y, C.z)),
-                      tri_index(i2, lex_less(C.x, C.y, C.z, A.x, A.y, A.z)), f);
+  const RPt A = Vr[i0], B = Vr[i1], C = Vr[i2];
+  tris[i] = make_int4(tri_index(i0, rpt_less(A, B)), tri_index(i1, rpt_less(B, C)), tri_index(i2, rpt_less(C, A)), f);
   lbox[i] = box[f];
   lz[i] = zmax[f];
 }

@@ -11,7 +11,7 @@ namespace wn {
 constexpr int kShortStack = 8;    // traversal stack entries kept in registers
 
 struct BuildBufs {
-  double4* Vr;          // [nv]
+  RPt* Vr;              // [nv]
   float4* box;          // [nf] projected boxes (input order)
   float* zmax;          // [nf]
   float2* cen;          // [nf]

@@ -32,69 +32,124 @@ __device__ __forceinline__ void rotate(const Frame& F, float x, float y, float z
   Z = __fma_rn(F.r[6], dx, __fma_rn(F.r[7], dy, __dmul_rn(F.r[8], dz)));
 }
 
-// Per (query, vertex) quantities in the frame, relative to the query.
-//   (X, Y, Z) = R (v - p): float64 differences of rotated coordinates (no
-//   cancellation for nearby points).  Every kernel forms them the same way,
-//   so each vertex has one value per query, shared by every edge and
-//   triangle that uses it.
+// Rotated points as pairs of float32 (hi, lo): v = hi + lo to 2^-48
+// relative.  A vertex (of the mesh or of the boundary) is stored in 32 bytes:
+// xy = (Xh, Xl, Yh, Yl) and zt = (Zh, Zl, and the two words of a float64 that
+// holds the tie offset of the edge leaving a boundary vertex, else 0).
+struct alignas(16) RPt {
+  float4 xy;
+  float4 zt;
+};
+
+// A query in the frame (the same split).
+struct QP {
+  float xh, xl, yh, yl, zh, zl;
+};
+
+__device__ __forceinline__ float split_lo(double v, float h) { return (float)__dsub_rn(v, (double)h); }
+
+__device__ __forceinline__ RPt make_rpt(double X, double Y, double Z, double tie) {
+  const float xh = (float)X, yh = (float)Y, zh = (float)Z;
+  RPt p;
+  p.xy = make_float4(xh, split_lo(X, xh), yh, split_lo(Y, yh));
+  const long long t = __double_as_longlong(tie);
+  p.zt = make_float4(zh, split_lo(Z, zh), __int_as_float((int)(t & 0xffffffff)), __int_as_float((int)(t >> 32)));
+  return p;
+}
+
+__device__ __forceinline__ QP make_qp(double X, double Y, double Z) {
+  QP q;
+  q.xh = (float)X;
+  q.xl = split_lo(X, q.xh);
+  q.yh = (float)Y;
+  q.yl = split_lo(Y, q.yh);
+  q.zh = (float)Z;
+  q.zl = split_lo(Z, q.zh);
+  return q;
+}
+
+__device__ __forceinline__ double rpt_tie(const RPt& p) {
+  return __hiloint2double(__float_as_int(p.zt.w), __float_as_int(p.zt.z));
+}
+
+// The float64 value of a (hi, lo) pair (exact).
+__device__ __forceinline__ double hilo(float h, float l) { return __dadd_rn((double)h, (double)l); }
+
+// Difference of two split coordinates, rounded to float32: (vh - ph) + (vl -
+// pl).  Relative to the exact difference it errs by at most about 2^-23 of
+// its size, also when v and p are close (no cancellation), and it depends on
+// the two points alone: every kernel and every edge or triangle that uses
+// the vertex for this query sees the same value.
+__device__ __forceinline__ float rel32(float vh, float vl, float ph, float pl) {
+  return __fadd_rn(__fsub_rn(vh, ph), __fsub_rn(vl, pl));
+}
+
+// A vertex seen from a query, in the frame:
+//   (X, Y, Z) relative offsets (float32, rel32), X and Y also as float64 for
+//   the edge predicate (exact products);
 //   alpha = r - Z, with r = |v - p|: the stereographic denominator of the
 //   vertex seen from d (the region term of Eq. wn_discrete_sum, per edge, is
 //   the angle of alpha_a alpha_b + X_a X_b + Y_a Y_b + i N).  It is evaluated
 //   without cancellation as rho^2 / u + (|Z| - Z) with u = r + |Z| (= rho^2 /
-//   (r + Z) for Z > 0 and r + |Z| for Z <= 0); r and 1/u in float32, the
-//   rest in float64.
+//   (r + Z) for Z > 0 and r + |Z| for Z <= 0).
 struct VQ {
-  double x, y;  // X, Y
-  double a;     // alpha
+  float x, y, a;
+  double xd, yd;
 };
 
-// The projected offset (X, Y) of a vertex from the ray, as the predicates use it.
-__device__ __forceinline__ VQ vertex_xy(double Xv, double Yv, double Xp, double Yp) {
+__device__ __forceinline__ VQ vertex_xy(const RPt& v, const QP& p) {
   VQ q;
-  q.x = __dsub_rn(Xv, Xp);
-  q.y = __dsub_rn(Yv, Yp);
-  q.a = 0.0;
+  q.x = rel32(v.xy.x, v.xy.y, p.xh, p.xl);
+  q.y = rel32(v.xy.z, v.xy.w, p.yh, p.yl);
+  q.xd = (double)q.x;
+  q.yd = (double)q.y;
+  q.a = 0.0f;
   return q;
 }
 
-__device__ __forceinline__ VQ vertex_q(double Xv, double Yv, double Zv,
-                                       double Xp, double Yp, double Zp) {
-  VQ q = vertex_xy(Xv, Yv, Xp, Yp);
-  const double Z = __dsub_rn(Zv, Zp);
-  const double rho2 = __fma_rn(q.x, q.x, __dmul_rn(q.y, q.y));
-  const double s = __fma_rn(Z, Z, rho2);
-  const float r = __builtin_amdgcn_sqrtf((float)s);
-  const float u = __fadd_rn(r, fabsf((float)Z));
-  const double iu = (double)__builtin_amdgcn_rcpf(u);
-  q.a = __fma_rn(rho2, iu, __dsub_rn(fabs(Z), Z));
+__device__ __forceinline__ float vertex_z(const RPt& v, const QP& p) { return rel32(v.zt.x, v.zt.y, p.zh, p.zl); }
+
+__device__ __forceinline__ VQ vertex_q(const RPt& v, const QP& p) {
+  VQ q = vertex_xy(v, p);
+  const float Z = vertex_z(v, p);
+  const float rho2 = __fmaf_rn(q.x, q.x, __fmul_rn(q.y, q.y));
+  const float s = __fmaf_rn(Z, Z, rho2);
+  const float r = __builtin_amdgcn_sqrtf(s);
+  const float u = __fadd_rn(r, fabsf(Z));
+  q.a = __fmaf_rn(rho2, __builtin_amdgcn_rcpf(u), __fsub_rn(fabsf(Z), Z));
   return q;
 }
 
 // Edge predicate N(a, b) = Y_a X_b - X_a Y_b of the projected edge a->b
-// relative to the ray (proportional to d.(b' x a')): the two products
-// rounded to float64, then their difference (whose sign is exact).  Swapping
-// a and b swaps the two rounded products, so N(b, a) = -N(a, b) bit for bit
-// (zeros aside, which `edge_tie` resolves antisymmetrically).  Its sign is the
-// exact sign of Y_a X_b - X_a Y_b unless that is below 2^-52 (|Y_a X_b| +
-// |X_a Y_b|).  Every triangle edge and every boundary edge goes through this
-// one function followed by `edge_tie`, so the crossing count and the branch
-// of the boundary term flip at the same inputs.
+// relative to the ray (proportional to d.(b' x a')).  The inputs are float32
+// values, so both products are exact in float64 and the fused multiply-add
+// rounds the exact difference once: N is correctly rounded, N(b, a) = -N(a,
+// b) bit for bit, and N == 0 exactly when the two projected vertices are
+// collinear with the ray.  The crossing count is thus decided exactly on the
+// vertices' float32 offsets, a perturbation of each vertex by about 2^-23 of
+// its distance that every triangle and the boundary share.  Every triangle
+// edge and every boundary edge goes through this one function followed by
+// `edge_tie`, so the crossing count and the branch of the boundary term flip
+// at the same inputs.
 __device__ __forceinline__ double edge_n(const VQ& a, const VQ& b) {
-  return __dsub_rn(__dmul_rn(a.y, b.x), __dmul_rn(a.x, b.y));
+  return __fma_rn(a.yd, b.xd, -__dmul_rn(a.xd, b.yd));
 }
 
-// Lexicographic order of two rotated vertices; distinct float32 vertices
-// have distinct rotated float64 coordinates.
-__device__ __forceinline__ bool lex_less(double ax, double ay, double az,
-                                         double bx, double by, double bz) {
-  return ax < bx || (ax == bx && (ay < by || (ay == by && az < bz)));
+// Lexicographic order of two stored vertices (on their split coordinates);
+// distinct vertices have distinct splits.
+__device__ __forceinline__ bool rpt_less(const RPt& a, const RPt& b) {
+  const float av[6] = {a.xy.x, a.xy.y, a.xy.z, a.xy.w, a.zt.x, a.zt.y};
+  const float bv[6] = {b.xy.x, b.xy.y, b.xy.z, b.xy.w, b.zt.x, b.zt.y};
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    if (av[k] != bv[k]) return av[k] < bv[k];
+  return false;
 }
 
 // Tie offset of the directed edge a->b: -2^-1022 if a precedes b
 // lexicographically, +2^-1022 otherwise (antisymmetric in a, b).  A nonzero
-// N is far above 2^-1022 in magnitude (a difference of two rounded products
-// of coordinate differences), so adding the offset changes nothing but an
-// exact zero, which
+// N is at least 2^-298 in magnitude (a difference of products of float32
+// values), so adding the offset changes nothing but an exact zero, which
 // becomes a value whose sign picks the side of the lexicographically smaller
 // end point.  N(a,b) + tie(a,b) stays exactly antisymmetric, so of two
 // triangles sharing an edge exactly one claims a ray through it, and the
@@ -110,9 +165,10 @@ __device__ __forceinline__ double edge_tie(double n, double tie) {
 
 // Edge factor D + iN: the angle theta_e = atan2(N, D) is half the signed
 // solid angle of the spherical triangle (-d, a - p, b - p), i.e. the
-// per-edge boundary term (D = alpha_a alpha_b + X_a X_b + Y_a Y_b).
-__device__ __forceinline__ double edge_d(const VQ& a, const VQ& b) {
-  return __fma_rn(a.a, b.a, __fma_rn(a.x, b.x, __dmul_rn(a.y, b.y)));
+// per-edge boundary term (D = alpha_a alpha_b + X_a X_b + Y_a Y_b, in
+// float32: only N's sign has to be exact).
+__device__ __forceinline__ float edge_d(const VQ& a, const VQ& b) {
+  return __fmaf_rn(a.a, b.a, __fmaf_rn(a.x, b.x, __fmul_rn(a.y, b.y)));
 }
 
 // Running product of the edge factors with an exact count of turns:

@@ -28,7 +28,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
                                                          const float* __restrict__ gx, const float* __restrict__ gy,
                                                          const float* __restrict__ gz, int64_t ny64, int64_t nz64,
                                                          int32_t* chi_out) {
-  __shared__ double4 sv[kChunk];
+  __shared__ RPt sv[kChunk];
   const int64_t qi = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const bool ok = qi < a.nq;
   const int64_t q = ok ? qi : 0;
@@ -37,10 +37,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
   const float px = gx[col / ny], py = gy[col % ny], pz = gz[qq % nz];
   const bool fin = isfinite(px) && isfinite(py) && isfinite(pz);
   Lane<1> s;
-  rotate(a.F, px, py, pz, s.Xp[0], s.Yp[0], s.Zp[0]);
+  {
+    double X, Y, Z;
+    rotate(a.F, px, py, pz, X, Y, Z);
+    s.p[0] = make_qp(X, Y, Z);
+  }
   turns_init(s.T[0]);
   lane_range(s);
-  const int chi = (ok && fin) ? traverse<kShortStack>(c, s.Xp[0], s.Yp[0], s.Zp[0]) : WN_CHI_INVALID;
+  const int chi = (ok && fin) ? traverse<kShortStack>(c, s.p[0]) : WN_CHI_INVALID;
   int staged = -1, pend = 0;
   const KernargLoops KL{L};
   boundary_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, staged, pend);

@@ -66,7 +66,7 @@ struct wn_bvh {
   wn::Frame F;
   double dir[3];
   int32_t nv = 0, nf = 0;
-  double4* Vr = nullptr;
+  wn::RPt* Vr = nullptr;
   int4* tris = nullptr;
   wn::BvhNode* nodes = nullptr;
   float4* leafbox = nullptr;

@@ -30,7 +30,7 @@ struct CrossArgs {
   Frame F;
   const BvhNode* nodes;
   const int4* tris;        // sorted triangles: v0, v1, v2 (tie bits in bit 31), original face id
-  const double4* Vr;       // rotated vertices: X, Y, Z, 0
+  const RPt* Vr;           // rotated vertices, split into float32 pairs
   const float4* leafbox;   // used when the tree is a single leaf
   const float* leafz;
   int32_t nf;

@@ -21,21 +21,20 @@ __device__ __forceinline__ int32_t tri_index(int32_t v, bool a_less_b) {
 // the vertex indices with the edges' lexicographic order in bit 31
 // (tri_index).
 template <bool STORED_TIES>
-__device__ __forceinline__ int tri_crossing(const int4 t, const double4* __restrict__ Vr,
-                                            double Xp, double Yp, double Zp) {
+__device__ __forceinline__ int tri_crossing(const int4 t, const RPt* __restrict__ Vr, const QP& p) {
   // the three tie bits in one register, so that the indices die at once
   const uint32_t tb = ((uint32_t)t.x >> 31) | (((uint32_t)t.y >> 30) & 2u) | (((uint32_t)t.z >> 29) & 4u);
-  const double4 A = Vr[t.x & 0x7fffffff];
-  const double4 B = Vr[t.y & 0x7fffffff];
-  const double4 C = Vr[t.z & 0x7fffffff];
-  const VQ a = vertex_xy(A.x, A.y, Xp, Yp);
-  const VQ b = vertex_xy(B.x, B.y, Xp, Yp);
-  const VQ c = vertex_xy(C.x, C.y, Xp, Yp);
+  const RPt A = Vr[t.x & 0x7fffffff];
+  const RPt B = Vr[t.y & 0x7fffffff];
+  const RPt C = Vr[t.z & 0x7fffffff];
+  const VQ a = vertex_xy(A, p);
+  const VQ b = vertex_xy(B, p);
+  const VQ c = vertex_xy(C, p);
   // the stored bits, or the same comparisons redone (fewer live registers
   // where the register budget is tight)
-  const bool l01 = STORED_TIES ? (tb & 1u) != 0 : lex_less(A.x, A.y, A.z, B.x, B.y, B.z);
-  const bool l12 = STORED_TIES ? (tb & 2u) != 0 : lex_less(B.x, B.y, B.z, C.x, C.y, C.z);
-  const bool l20 = STORED_TIES ? (tb & 4u) != 0 : lex_less(C.x, C.y, C.z, A.x, A.y, A.z);
+  const bool l01 = STORED_TIES ? (tb & 1u) != 0 : rpt_less(A, B);
+  const bool l12 = STORED_TIES ? (tb & 2u) != 0 : rpt_less(B, C);
+  const bool l20 = STORED_TIES ? (tb & 4u) != 0 : rpt_less(C, A);
   const double n01 = edge_tie(edge_n(a, b), tie_offset(l01));
   const double n12 = edge_tie(edge_n(b, c), tie_offset(l12));
   const double n20 = edge_tie(edge_n(c, a), tie_offset(l20));
@@ -44,7 +43,7 @@ __device__ __forceinline__ int tri_crossing(const int4 t, const double4* __restr
   // Height of the crossing above p: the barycentric weights are the edge
   // values opposite each vertex, so the crossing is above p iff
   // sum(N_opp * Z) has the sign of the N's.
-  const double za = __dsub_rn(A.z, Zp), zb = __dsub_rn(B.z, Zp), zc = __dsub_rn(C.z, Zp);
+  const double za = (double)vertex_z(A, p), zb = (double)vertex_z(B, p), zc = (double)vertex_z(C, p);
   const double num = __fma_rn(n12, za, __fma_rn(n20, zb, __dmul_rn(n01, zc)));
   const bool hit = s01 ? (num < 0.0) : (num > 0.0);
   return hit ? (s01 ? 1 : -1) : 0;
@@ -141,10 +140,10 @@ __device__ __forceinline__ int traverse_leaves(const CrossArgs& a, float x, floa
 
 // chi for one query (WN_CHI_INVALID if the tree is malformed).
 template <int S, bool STORED_TIES = false>
-__device__ int traverse(const CrossArgs& a, double Xp, double Yp, double Zp) {
+__device__ int traverse(const CrossArgs& a, const QP& p) {
   int chi = 0;
-  const int st = traverse_leaves<S>(a, (float)Xp, (float)Yp, (float)Zp, [&](int t) {
-    chi += tri_crossing<STORED_TIES>(a.tris[t], a.Vr, Xp, Yp, Zp);
+  const int st = traverse_leaves<S>(a, p.xh, p.yh, p.zh, [&](int t) {
+    chi += tri_crossing<STORED_TIES>(a.tris[t], a.Vr, p);
   });
   return st ? st : chi;
 }
