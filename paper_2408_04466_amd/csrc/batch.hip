@@ -157,8 +157,8 @@ __device__ __forceinline__ CrossArgs cross_args(const SurfDesc& D) {
 }
 
 // Fused mode: per query, the crossing count and then the boundary walk.
-// Seven waves per SIMD (71 registers; one 64-bit value spills in the prologue).
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_batch_fwd(FwdArgs a) {
+// Six waves per SIMD (80 registers: the walk's loops run without spills).
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_batch_fwd(FwdArgs a) {
   __shared__ RPt sv[bnd::kChunk];
   __shared__ int s_item;
   for (int pass = 0;; ++pass) {
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
       bnd::finish_turns(s, pend);
       if (ok) {
         const bool valid = fin && chi != WN_CHI_INVALID;
-        a.w[q] = valid ? turns_to_w(s.T[0], chi) : __int_as_float(0x7fc00000);
+        a.w[q] = valid ? bnd::lane_w(s, 0, chi) : __int_as_float(0x7fc00000);
         if (a.chi) a.chi[q] = valid ? chi : WN_CHI_INVALID;
       }
     }
@@ -252,7 +252,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_bnd(FwdArgs a) {
       bnd::finish_turns(s, pend);
       if (ok) {
         const int chi = a.chi_buf[q];
-        a.w[q] = chi != WN_CHI_INVALID ? turns_to_w(s.T[0], chi) : __int_as_float(0x7fc00000);
+        a.w[q] = chi != WN_CHI_INVALID ? bnd::lane_w(s, 0, chi) : __int_as_float(0x7fc00000);
       }
     }
   }

@@ -14,8 +14,10 @@ namespace {
 
 using namespace bnd;
 
+// Seven waves per SIMD for one query per lane (72 registers; only the turn
+// counters, touched once per 32 edges, live in scratch).
 template <int QPL>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL == 1 ? 8 : 4))) void k_bnd3d(BndArgs a, LoopTable L) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL == 1 ? 7 : 4))) void k_bnd3d(BndArgs a, LoopTable L) {
   __shared__ RPt sv[kChunk];
 
   Lane<QPL> s;
@@ -48,7 +50,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL ==
     if (chi == WN_CHI_INVALID || !(isfinite(a.qx[q]) && isfinite(a.qy[q]) && isfinite(a.qz[q]))) {
       w = __int_as_float(0x7fc00000);
     } else {
-      w = turns_to_w(s.T[k], chi);
+      w = lane_w(s, k, chi);
     }
     a.w_out[q] = w;
   }
@@ -57,9 +59,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL ==
 // Fused forward, one query per lane: the crossing count (BVH traversal),
 // then the boundary walk, then w.  While some waves wait on node fetches,
 // others keep the vector units busy with the boundary arithmetic.
-// Seven waves per SIMD: with the alternating order below, the eight-wave
-// budget of 64 registers spilled.
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_fwd3d(CrossArgs c, BndArgs a, LoopTable L, int32_t* chi_out) {
+// Six waves per SIMD (80 registers): with the alternating order below, the
+// seven-wave budget of 72 registers spilled inside the boundary walk.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_fwd3d(CrossArgs c, BndArgs a, LoopTable L, int32_t* chi_out) {
   __shared__ RPt sv[kChunk];
   const int64_t qi = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const bool ok = qi < a.nq;
@@ -84,7 +86,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
   if (!(blockIdx.x & 1)) boundary_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, staged, pend);
   finish_turns(s, pend);
   if (ok) {
-    a.w_out[q] = chi != WN_CHI_INVALID ? turns_to_w(s.T[0], chi) : __int_as_float(0x7fc00000);
+    a.w_out[q] = chi != WN_CHI_INVALID ? lane_w(s, 0, chi) : __int_as_float(0x7fc00000);
     if (chi_out) chi_out[q] = chi;
   }
 }

@@ -29,12 +29,16 @@ namespace bnd {
 constexpr int kThreads = 256;
 constexpr int kChunk = 512;      // vertices per LDS stage: 512 * 32 B = 16 KB
 constexpr int kStep = 16;        // vertices per main-loop step
-constexpr int kRescale = 8;      // edges between rescales outside the main steps
-// A product of 16 edge factors stays within float64 range when every
-// boundary vertex is within 2^28 of the query (frame units; each factor is
-// at most 5 |a - p| |b - p|): true for queries within 2^26 of the frame's
-// centre, where the scene has size O(1).  Farther queries rescale every 8.
-constexpr double kNear = 67108864.0;   // 2^26
+// The float32 running product is rescaled every second edge: two factors,
+// each at most 2^1.5 r_a r_b, stay below 2^127 when every boundary vertex is
+// within 2^31 of the query (frame units): true for queries within 2^30 of
+// the frame's centre, where the scene has size O(1).  Wavefronts holding a
+// farther query rescale after every edge, which covers queries out to 2^56
+// (r^2 and a factor stay below 2^115).  Beyond kHuge the boundary subtends
+// less than 2^-50 rad, |w| <= area / (4 pi |p|^2) < 2^-100, and w is
+// returned as 0 (lane_w).
+constexpr float kNear = 1073741824.0f;          // 2^30
+constexpr float kHuge = 72057594037927936.0f;   // 2^56
 
 // Loop table accessors: loops in the kernel arguments, or in device memory.
 struct KernargLoops {
@@ -112,13 +116,16 @@ struct Lane {
   bool far;   // uniform: some query of the wavefront lies beyond kNear
 };
 
+__device__ __forceinline__ float qp_extent(const QP& p) {
+  return fmaxf(fabsf(p.xh), fmaxf(fabsf(p.yh), fabsf(p.zh)));
+}
+
 // Set once the lane's queries are in place (every lane of the wavefront).
 template <int QPL>
 __device__ __forceinline__ void lane_range(Lane<QPL>& s) {
   bool f = false;
 #pragma unroll
-  for (int k = 0; k < QPL; ++k)
-    f |= !(fabsf(s.p[k].xh) + fabsf(s.p[k].yh) + fabsf(s.p[k].zh) < (float)kNear);
+  for (int k = 0; k < QPL; ++k) f |= !(qp_extent(s.p[k]) < kNear);
   s.far = __any(f);
 }
 
@@ -132,9 +139,7 @@ template <int QPL>
 __device__ __forceinline__ void edge_step(Lane<QPL>& s, const VQ* a, const VQ* b, double tie) {
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
-    const double N = edge_tie(edge_n(a[k], b[k]), tie);
-    const double D = (double)edge_d(a[k], b[k]);
-    turns_mul(s.T[k], D, N);
+    turns_edge(s.T[k], a[k], b[k], tie);
   }
 }
 
@@ -157,8 +162,15 @@ __device__ __forceinline__ void finish_turns(Lane<QPL>& s, int& pend) {
   pend = 0;
 }
 
+// w of query k of the lane (every turn decided) for crossing count chi.
+template <int QPL>
+__device__ __forceinline__ float lane_w(const Lane<QPL>& s, int k, int chi) {
+  return qp_extent(s.p[k]) < kHuge ? turns_to_w(s.T[k], chi) : 0.0f;
+}
+
 // Edges j-1 -> j ... while kStep more vertices of the loop segment [j, j1)
-// remain; returns the next vertex.  FAR: rescale every 8 edges instead of 16.
+// remain; returns the next vertex.  The product is rescaled after every
+// second edge, and after every edge for FAR wavefronts.
 template <int QPL, bool FAR>
 __device__ __forceinline__ int main_steps(Lane<QPL>& s, const RPt* sv, int c0, int j, int j1, VQ* A, VQ* B,
                                           double& ptie, int& pend) {
@@ -172,17 +184,17 @@ __device__ __forceinline__ int main_steps(Lane<QPL>& s, const RPt* sv, int c0, i
       const RPt v0 = sv[j + u - c0];
       vert_q(s, v0, B);
       edge_step(s, A, B, ptie);
+      if (FAR) rescale(s);
       const RPt v1 = sv[j + u + 1 - c0];
       vert_q(s, v1, A);
       edge_step(s, B, A, rpt_tie(v0));
       ptie = rpt_tie(v1);
+      rescale(s);
       // keep the scheduler from hoisting the LDS reads of later vertex
       // pairs to the top of the step: that prefetch holds extra vector
       // registers and cuts occupancy
       __builtin_amdgcn_sched_barrier(0);
-      if (FAR && u + 2 == kStep / 2) rescale(s);
     }
-    rescale(s);
     pend += kStep;
     if (pend == 2 * kStep) {
       flush(s, pend);
@@ -226,17 +238,17 @@ __device__ __forceinline__ void boundary_walk(Lane<QPL>& s, const Stager& stage,
         ++j;
       }
       // kStep vertices per step, the roles of A and B alternating; the
-      // turns are decided every second step (32 edges), the product is
-      // rescaled every step (every half step for far queries)
+      // turns are decided every second step (32 edges)
       if (s.far)
         j = main_steps<QPL, true>(s, sv, c0, j, j1, A, B, ptie, pend);
       else
         j = main_steps<QPL, false>(s, sv, c0, j, j1, A, B, ptie, pend);
-      // the rest one vertex at a time (a rescale every kRescale edges)
+      // the rest one vertex at a time, rescaled after every edge
       for (; j < j1; ++j) {
         const RPt v = sv[j - c0];
         vert_q(s, v, B);
         edge_step(s, A, B, ptie);
+        rescale(s);
 #pragma unroll
         for (int k = 0; k < QPL; ++k) A[k] = B[k];
         ptie = rpt_tie(v);
@@ -244,16 +256,14 @@ __device__ __forceinline__ void boundary_walk(Lane<QPL>& s, const Stager& stage,
           flush(s, 32);
           pend = 0;
         }
-        if ((pend & (kRescale - 1)) == 0) rescale(s);
       }
-      rescale(s);
       if (j1 < le) break;            // the loop continues in the next chunk
       edge_step(s, A, first, ptie);  // closing edge last -> first
+      rescale(s);
       if (++pend == 32) {
         flush(s, 32);
         pend = 0;
       }
-      rescale(s);
     }
   }
 }

@@ -85,8 +85,7 @@ __device__ __forceinline__ float rel32(float vh, float vl, float ph, float pl) {
 }
 
 // A vertex seen from a query, in the frame:
-//   (X, Y, Z) relative offsets (float32, rel32), X and Y also as float64 for
-//   the edge predicate (exact products);
+//   (X, Y, Z) relative offsets (float32, rel32);
 //   alpha = r - Z, with r = |v - p|: the stereographic denominator of the
 //   vertex seen from d (the region term of Eq. wn_discrete_sum, per edge, is
 //   the angle of alpha_a alpha_b + X_a X_b + Y_a Y_b + i N).  It is evaluated
@@ -94,23 +93,16 @@ __device__ __forceinline__ float rel32(float vh, float vl, float ph, float pl) {
 //   (r + Z) for Z > 0 and r + |Z| for Z <= 0).
 struct VQ {
   float x, y, a;
-  double xd, yd;
 };
 
-__device__ __forceinline__ VQ vertex_xy(const RPt& v, const QP& p) {
-  VQ q;
-  q.x = rel32(v.xy.x, v.xy.y, p.xh, p.xl);
-  q.y = rel32(v.xy.z, v.xy.w, p.yh, p.yl);
-  q.xd = (double)q.x;
-  q.yd = (double)q.y;
-  q.a = 0.0f;
-  return q;
-}
-
+__device__ __forceinline__ float vertex_x(const RPt& v, const QP& p) { return rel32(v.xy.x, v.xy.y, p.xh, p.xl); }
+__device__ __forceinline__ float vertex_y(const RPt& v, const QP& p) { return rel32(v.xy.z, v.xy.w, p.yh, p.yl); }
 __device__ __forceinline__ float vertex_z(const RPt& v, const QP& p) { return rel32(v.zt.x, v.zt.y, p.zh, p.zl); }
 
 __device__ __forceinline__ VQ vertex_q(const RPt& v, const QP& p) {
-  VQ q = vertex_xy(v, p);
+  VQ q;
+  q.x = vertex_x(v, p);
+  q.y = vertex_y(v, p);
   const float Z = vertex_z(v, p);
   const float rho2 = __fmaf_rn(q.x, q.x, __fmul_rn(q.y, q.y));
   const float s = __fmaf_rn(Z, Z, rho2);
@@ -121,18 +113,19 @@ __device__ __forceinline__ VQ vertex_q(const RPt& v, const QP& p) {
 }
 
 // Edge predicate N(a, b) = Y_a X_b - X_a Y_b of the projected edge a->b
-// relative to the ray (proportional to d.(b' x a')).  The inputs are float32
-// values, so both products are exact in float64 and the fused multiply-add
-// rounds the exact difference once: N is correctly rounded, N(b, a) = -N(a,
-// b) bit for bit, and N == 0 exactly when the two projected vertices are
-// collinear with the ray.  The crossing count is thus decided exactly on the
-// vertices' float32 offsets, a perturbation of each vertex by about 2^-23 of
-// its distance that every triangle and the boundary share.  Every triangle
-// edge and every boundary edge goes through this one function followed by
-// `edge_tie`, so the crossing count and the branch of the boundary term flip
-// at the same inputs.
-__device__ __forceinline__ double edge_n(const VQ& a, const VQ& b) {
-  return __fma_rn(a.yd, b.xd, -__dmul_rn(a.xd, b.yd));
+// relative to the ray (proportional to d.(b' x a')), from the float32
+// offsets of its end points.  Both products are exact in float64 and the
+// fused multiply-add rounds the exact difference once: N is correctly
+// rounded, N(b, a) = -N(a, b) bit for bit, and N == 0 exactly when the two
+// projected vertices are collinear with the ray.  The crossing count is thus
+// decided exactly on the vertices' float32 offsets, a perturbation of each
+// vertex by about 2^-23 of its distance that every triangle and the boundary
+// share.  Every triangle edge goes through this function followed by
+// `edge_tie`; the boundary walk (edge_n_walk) takes the sign from here
+// whenever a float32 evaluation cannot certify it, so the crossing count and
+// the branch of the boundary term flip at the same inputs.
+__device__ __forceinline__ double edge_n(float ax, float ay, float bx, float by) {
+  return __fma_rn((double)ay, (double)bx, -__dmul_rn((double)ax, (double)by));
 }
 
 // Lexicographic order of two stored vertices (on their split coordinates);
@@ -171,48 +164,95 @@ __device__ __forceinline__ float edge_d(const VQ& a, const VQ& b) {
   return __fmaf_rn(a.a, b.a, __fmaf_rn(a.x, b.x, __fmul_rn(a.y, b.y)));
 }
 
+// N of a boundary edge for the walk in float32, with the sign of
+// edge_tie(edge_n(a, b), tie) (the triangles' predicate).  n = fl(Y_a X_b -
+// fl(X_a Y_b)) is within |fl(X_a Y_b) - X_a Y_b| <= 2^-24 |p| (+ half the
+// least subnormal) of a quantity with N's sign, and rounding keeps signs, so
+// |n| > 2^-23 |p| + 2^-126 certifies sign(n) = sign(N) with N != 0.  Other
+// lanes (the query within about 2^-23 of the projected edge's line, rare)
+// take the exact float64 value with the tie offset (edge_n_exact); rounded
+// to float32 it keeps its sign bit, also where it becomes a signed zero.
+struct WalkN {
+  float n;
+  bool sure;
+};
+
+__device__ __forceinline__ WalkN edge_n_walk(const VQ& a, const VQ& b) {
+  const float p = __fmul_rn(a.x, b.y);
+  WalkN r;
+  r.n = __fmaf_rn(a.y, b.x, -p);
+  r.sure = fabsf(r.n) > __fmaf_rn(fabsf(p), 0x1p-23f, 0x1p-126f);
+  return r;
+}
+
+__device__ __forceinline__ float edge_n_exact(const VQ& a, const VQ& b, double tie) {
+  return (float)edge_tie(edge_n(a.x, a.y, b.x, b.y), tie);
+}
+
 // Running product of the edge factors with an exact count of turns:
-// sum_e theta_e = arg(zr + i zi) + 2 pi (ku - kd).  The product is kept in
-// float64 and rescaled by a power of two every few edges.  Multiplying by a
-// factor whose angle lies in (-pi, pi] carries the argument across the
-// negative real axis exactly when the old product and the factor lie in the
-// same closed half plane (by sign bit) and the new product in the other
-// one; the sign bits make the count agree with atan2's branch.  The tie
-// offset keeps N nonzero, so the product starts from 1 without losing the
-// sign of a zero.
+// sum_e theta_e = arg(zr + i zi) + 2 pi k.  The product is kept in
+// float32 and rescaled by a power of two every two edges (every edge for far
+// queries): a factor is at most 2^1.5 r_a r_b in size, and two of them stay
+// inside float32's range unless a factor is below 2^-62, i.e. the query lies
+// within about 1e-19 (frame units) of the boundary, where w has no float32
+// value anyway.  Multiplying by a factor whose angle lies in (-pi, pi]
+// carries the argument across the negative real axis exactly when the old
+// product and the factor lie in the same closed half plane (by sign bit)
+// and the new product in the other one; the sign bits make the count agree
+// with atan2's branch.  A factor with N = +-0 (a tie, or an exact N below
+// float32's range) moves a product with zi != 0 by +-pi as its sign bit
+// says; the product starts from 1 + (+0)i, for which the rule holds as well.
 //
 // The three sign bits of an edge are not combined edge by edge: the sign of
 // each factor's N and of each new product's imaginary part are shifted into
 // two bit registers (bacc, cacc) as the edges go by, and every group of at
 // most 32 edges is decided at once (turns_flush): with the old product's
 // sign a_j = c_(j-1), a turn backward past -pi is a_j & b_j & ~c_j and one
-// forward past pi is ~a_j & ~b_j & c_j, counted by population counts.
+// forward past pi is ~a_j & ~b_j & c_j, counted by population counts into k
+// (forward turns minus backward turns).
 struct Turns {
-  double zr, zi;
+  float zr, zi;
   uint32_t bacc, cacc;   // sign bits of the group's N and new zi (newest in bit 0)
   uint32_t cprev;        // cacc when the last group was decided (bit 0: zi's sign then)
-  int kd, ku;            // turns backward past -pi / forward past pi
+  int k;                 // turns forward past pi minus turns backward past -pi
 };
 
 __device__ __forceinline__ void turns_init(Turns& t) {
-  t.zr = 1.0;
-  t.zi = 0.0;
+  t.zr = 1.0f;
+  t.zi = 0.0f;
   t.bacc = 0u;
   t.cacc = 0u;
   t.cprev = 0u;
-  t.kd = 0;
-  t.ku = 0;
+  t.k = 0;
 }
 
-__device__ __forceinline__ int hi_word(double x) {
-  return (int)(__double_as_longlong(x) >> 32);
+__device__ __forceinline__ void turns_mul(Turns& t, float D, float N) {
+  const float nr = __fmaf_rn(t.zr, D, -__fmul_rn(t.zi, N));
+  const float ni = __fmaf_rn(t.zr, N, __fmul_rn(t.zi, D));
+  t.bacc = __builtin_amdgcn_alignbit(t.bacc, __float_as_uint(N), 31);
+  t.cacc = __builtin_amdgcn_alignbit(t.cacc, __float_as_uint(ni), 31);
+  t.zr = nr;
+  t.zi = ni;
 }
 
-__device__ __forceinline__ void turns_mul(Turns& t, double D, double N) {
-  const double nr = __fma_rn(t.zr, D, -__dmul_rn(t.zi, N));
-  const double ni = __fma_rn(t.zr, N, __dmul_rn(t.zi, D));
-  t.bacc = __builtin_amdgcn_alignbit(t.bacc, (uint32_t)hi_word(N), 31);
-  t.cacc = __builtin_amdgcn_alignbit(t.cacc, (uint32_t)hi_word(ni), 31);
+// One boundary edge a->b into the product.  The factor is multiplied in
+// with the float32 N first; the rare lanes whose N's sign that value cannot
+// certify redo the multiplication from the old product with the exact N
+// (after the product, so that the common path stays one straight block).
+__device__ __forceinline__ void turns_edge(Turns& t, const VQ& a, const VQ& b, double tie) {
+  const WalkN w = edge_n_walk(a, b);
+  const float D = edge_d(a, b);
+  const float zr = t.zr, zi = t.zi;
+  float N = w.n;
+  float nr = __fmaf_rn(zr, D, -__fmul_rn(zi, N));
+  float ni = __fmaf_rn(zr, N, __fmul_rn(zi, D));
+  if (__builtin_expect(!w.sure, 0)) {
+    N = edge_n_exact(a, b, tie);
+    nr = __fmaf_rn(zr, D, -__fmul_rn(zi, N));
+    ni = __fmaf_rn(zr, N, __fmul_rn(zi, D));
+  }
+  t.bacc = __builtin_amdgcn_alignbit(t.bacc, __float_as_uint(N), 31);
+  t.cacc = __builtin_amdgcn_alignbit(t.cacc, __float_as_uint(ni), 31);
   t.zr = nr;
   t.zi = ni;
 }
@@ -226,17 +266,20 @@ __device__ __forceinline__ void turns_flush(Turns& t, int n) {
   const uint32_t a = __builtin_amdgcn_alignbit(t.cprev, t.cacc, 1);
   const uint32_t b = t.bacc;           // zero above bit n - 1
   const uint32_t c = t.cacc & m;
-  t.kd += __popc(a & b & ~c);
-  t.ku += __popc(~a & ~b & c);
+  t.k += __popc(~a & ~b & c) - __popc(a & b & ~c);
   t.bacc = 0u;
   t.cprev = t.cacc;
 }
 
-// Rescale by a power of two (exact; keeps signs and zeros).
+// Rescale by a power of two (exact; keeps signs and zeros): with m = |zr| +
+// |zi| in [2^E, 2^(E+1)), the float with exponent field (254 - (E + 127) -
+// borrow) is 2^(-E) or 2^(-E-1), which brings m into [0.5, 2).  A product
+// that has sunk below the normal range is scaled by at most 2^127.
 __device__ __forceinline__ void turns_norm(Turns& t) {
-  const int e = max(__builtin_amdgcn_frexp_exp(t.zr), __builtin_amdgcn_frexp_exp(t.zi));
-  t.zr = __builtin_amdgcn_ldexp(t.zr, -e);
-  t.zi = __builtin_amdgcn_ldexp(t.zi, -e);
+  const uint32_t m = __float_as_uint(__fadd_rn(fabsf(t.zr), fabsf(t.zi)));
+  const float sc = __uint_as_float((0x7F000000u - m) & 0x7F800000u);
+  t.zr = __fmul_rn(t.zr, sc);
+  t.zi = __fmul_rn(t.zi, sc);
 }
 
 constexpr float kInv2Pi = 0.15915494309189535f;
@@ -270,16 +313,13 @@ __device__ __forceinline__ float atan2_f32(float y, float x) {
   return copysignf(r, y);
 }
 
-// w = chi + ku - kd + atan2(zi, zr) / (2 pi) (every turn flushed).  After a power-of-two rescale the
-// larger component lies in [0.5, 1), so both round to float32 without
-// overflow; a component that underflows keeps its sign bit, so the branch
-// (+pi or -pi on the negative real axis) is the one the turn count assumed.
-// The float32 angle is off by about 1e-7 rad, below the float32 rounding of
-// w itself.
+// w = chi + k + atan2(zi, zr) / (2 pi) (every turn flushed).  The
+// branch on the negative real axis (+pi for zi = +0, -pi for zi = -0) is the
+// one the turn count assumed.
 __device__ __forceinline__ float turns_to_w(Turns t, int chi) {
   turns_norm(t);
-  const float ang = atan2_f32((float)t.zi, (float)t.zr);
-  return __fadd_rn((float)(chi + t.ku - t.kd), __fmul_rn(ang, kInv2Pi));
+  const float ang = atan2_f32(t.zi, t.zr);
+  return __fadd_rn((float)(chi + t.k), __fmul_rn(ang, kInv2Pi));
 }
 
 }  // namespace wn

@@ -24,7 +24,7 @@ using namespace bnd;
 
 // 32-bit index arithmetic (the host limits grids to fewer than 2^32
 // points): 64-bit divisions would be long emulated sequences per query.
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_grid3d_fwd(CrossArgs c, BndArgs a, LoopTable L,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_grid3d_fwd(CrossArgs c, BndArgs a, LoopTable L,
                                                          const float* __restrict__ gx, const float* __restrict__ gy,
                                                          const float* __restrict__ gz, int64_t ny64, int64_t nz64,
                                                          int32_t* chi_out) {
@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
   boundary_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, staged, pend);
   finish_turns(s, pend);
   if (ok) {
-    a.w_out[q] = chi != WN_CHI_INVALID ? turns_to_w(s.T[0], chi) : __int_as_float(0x7fc00000);
+    a.w_out[q] = chi != WN_CHI_INVALID ? lane_w(s, 0, chi) : __int_as_float(0x7fc00000);
     if (chi_out) chi_out[q] = chi;
   }
 }

@@ -27,17 +27,17 @@ __device__ __forceinline__ int tri_crossing(const int4 t, const RPt* __restrict_
   const RPt A = Vr[t.x & 0x7fffffff];
   const RPt B = Vr[t.y & 0x7fffffff];
   const RPt C = Vr[t.z & 0x7fffffff];
-  const VQ a = vertex_xy(A, p);
-  const VQ b = vertex_xy(B, p);
-  const VQ c = vertex_xy(C, p);
+  const float ax = vertex_x(A, p), ay = vertex_y(A, p);
+  const float bx = vertex_x(B, p), by = vertex_y(B, p);
+  const float cx = vertex_x(C, p), cy = vertex_y(C, p);
   // the stored bits, or the same comparisons redone (fewer live registers
   // where the register budget is tight)
   const bool l01 = STORED_TIES ? (tb & 1u) != 0 : rpt_less(A, B);
   const bool l12 = STORED_TIES ? (tb & 2u) != 0 : rpt_less(B, C);
   const bool l20 = STORED_TIES ? (tb & 4u) != 0 : rpt_less(C, A);
-  const double n01 = edge_tie(edge_n(a, b), tie_offset(l01));
-  const double n12 = edge_tie(edge_n(b, c), tie_offset(l12));
-  const double n20 = edge_tie(edge_n(c, a), tie_offset(l20));
+  const double n01 = edge_tie(edge_n(ax, ay, bx, by), tie_offset(l01));
+  const double n12 = edge_tie(edge_n(bx, by, cx, cy), tie_offset(l12));
+  const double n20 = edge_tie(edge_n(cx, cy, ax, ay), tie_offset(l20));
   const bool s01 = n01 < 0.0, s12 = n12 < 0.0, s20 = n20 < 0.0;
   if (s01 != s12 || s12 != s20) return 0;
   // Height of the crossing above p: the barycentric weights are the edge

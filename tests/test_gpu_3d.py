@@ -237,6 +237,47 @@ def test_edge_cases():
     compare_3d(dmt, P, w, chi)
 
 
+def test_far_queries():
+    """Queries 2^10 to 2^100 scene sizes away.  Half sit far below the open
+    cap on vertical rays through its hole (d = +z): each such ray crosses the
+    surface once, so the boundary term has to cancel chi exactly; the others
+    lie in random directions.  They are interleaved with near queries so that
+    wavefronts mix both kinds (the far path rescales after every edge, and
+    beyond 2^56 frame units w is returned as 0).  Far away |w| <= area / (4
+    pi dist^2) (Sec. 3: w is the solid angle over 4 pi); near, the oracle
+    decides.  The fused, split and batched entry points agree bit for bit."""
+    M = synth.bumpy_cap()
+    d = np.array([0.0, 0.0, 1.0])
+    dm = DevMesh(M, d)
+    g = synth.rng(24)
+    n = 384
+    xy = g.uniform(-0.4, 0.4, (n, 2))
+    below = np.stack([xy[:, 0], xy[:, 1], -np.exp2(g.uniform(10.0, 100.0, n))], 1)
+    u = g.normal(size=(n, 3))
+    rand = u / np.linalg.norm(u, axis=1, keepdims=True) * np.exp2(g.uniform(10.0, 100.0, n))[:, None]
+    Pfar = np.concatenate([below, rand]).astype(np.float32)
+    P = np.empty((2 * len(Pfar), 3), np.float32)
+    P[0::2] = Pfar
+    P[1::2] = _rand_queries(M, len(Pfar), 25)
+    qx, qy, qz = dm.queries(P)
+    w, chi = W.eval_3d(dm.bvh, dm.bnd, dm.loop_off, qx, qy, qz)
+    chi3 = W.crossings_3d(dm.bvh, qx, qy, qz)
+    w4 = W.eval_3d_boundary(dm.bvh, dm.bnd, dm.loop_off, qx, qy, qz, chi3)
+    B = W.Batch([{"V": dm.V, "F": dm.F, "bnd": dm.bnd, "loop_off": dm.loop_off, "nq": len(P)}], d)
+    wb, cb = B.eval(qx, qy, qz)
+    torch.cuda.synchronize()
+    w, chi = w.cpu().numpy(), chi.cpu().numpy()
+    assert np.array_equal(w4.cpu().numpy(), w) and np.array_equal(chi3.cpu().numpy(), chi)
+    assert np.array_equal(wb.cpu().numpy(), w) and np.array_equal(cb.cpu().numpy(), chi)
+    far = np.arange(0, len(P), 2)
+    V = M.V.astype(np.float64)
+    area = 0.5 * np.linalg.norm(np.cross(V[M.F[:, 1]] - V[M.F[:, 0]], V[M.F[:, 2]] - V[M.F[:, 0]]), axis=1).sum()
+    dist = np.linalg.norm(P[far].astype(np.float64), axis=1) - np.linalg.norm(V, axis=1).max()
+    assert np.all(np.abs(w[far]) <= area / (4.0 * math.pi * dist * dist) + 2e-7), np.abs(w[far]).max()
+    assert np.all(np.abs(chi[far][:n]) == 1)          # the vertical rays cross the cap once
+    compare_3d(dm, P, w, chi, sample=np.arange(1, len(P), 2), label="near, mixed with far")
+
+
 def test_invalid_arguments_raise():
     M = synth.bumpy_cap()
     dm = DevMesh(M, synth.random_direction(4))
