@@ -48,7 +48,6 @@ STEP_KERNEL_SOURCES = {
 }
 FLOPS_PER_PAIR_BWD = 40      # adjoint, per (query, boundary edge)
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak
-VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9   # vector lane-instructions/s without packed FP32
 
 
 def workload_c3():
@@ -350,9 +349,7 @@ def main():
     traffic, valu = measured_counters()
     step_valu = step_kernel_valu()
     step_ms = {"k_batch_fwd": ms_fwd_b, "k_batch_bwd": ms_bwd_b}
-    step_issue = {k: {"ms": step_ms[k], "valu_wave_instructions": v,
-                      "valu_issue_frac": v * 64 / (step_ms[k] * 1e-3) / VALU_ISSUE_PEAK}
-                  for k, v in step_valu.items()}
+    step_counts = {k: {"ms": step_ms[k], "valu_wave_instructions": v} for k, v in step_valu.items()}
 
     out = {
         "metric": "winding queries/s fwd+bwd, batched vs plain, 3D mesh 2^20 pts at |err|<=1e-4",
@@ -382,14 +379,13 @@ def main():
                                      "factors from a 1 GiB copy)",
                      "flops_per_pair": FLOPS_PER_PAIR_FWD, "pairs_per_launch": pairs,
                      "avg_launch_ms": ms_bnd,
-                     # vector-ALU issue: the committed SQ_INSTS_VALU count per launch
-                     # (wavefront instructions x 64 lanes) over the live launch time,
-                     # against 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one wave64
-                     # instruction per SIMD every 4 cycles; packed FP32 excluded)
-                     "valu_issue": ({"achieved": valu * 64 / (ms_bnd * 1e-3), "peak": VALU_ISSUE_PEAK,
-                                     "unit": "lane-instructions/s",
-                                     "frac": valu * 64 / (ms_bnd * 1e-3) / VALU_ISSUE_PEAK}
-                                    if valu else None)},
+                     # the committed SQ_INSTS_VALU count per launch (wavefront
+                     # instructions) and per (query, edge) pair; not an issue
+                     # fraction: float32 operations issue every 2 cycles per
+                     # wavefront, float64, conversions and bit-field operations
+                     # every 4, square root and reciprocal every 8
+                     "valu": ({"wave_instructions_per_launch": valu, "per_pair": valu * 64 / pairs}
+                              if valu else None)},
         "batched_vs_plain": {
             "mesh_2^20": {"batched_fwd_bwd_qps": nq / (ms_step * 1e-3),
                           "plain_fwd_bwd_qps": nq / (ms_step_plain * 1e-3),
@@ -400,7 +396,7 @@ def main():
         "step_ms": {"mean": ms_step, "median": per_step[len(per_step) // 2], "min": per_step[0]},
         "device": {**W.device_info(), "name": torch.cuda.get_device_name(dev)},
         # the timed step's two kernels against the same vector-issue limit
-        "step_valu_issue": step_issue or None,
+        "step_valu": step_counts or None,
         "kernels_ms": {"crossings": ms_cross, "boundary": ms_bnd, "plain_forward": ms_fwd,
                        "plain_backward": ms_bwd, "batched_forward": ms_fwd_b, "batched_backward": ms_bwd_b,
                        "bvh_build": build_ms, "batch_create": batch_ms},

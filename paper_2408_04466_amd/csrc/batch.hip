@@ -157,8 +157,8 @@ __device__ __forceinline__ CrossArgs cross_args(const SurfDesc& D) {
 }
 
 // Fused mode: per query, the crossing count and then the boundary walk.
-// Six waves per SIMD (80 registers: the walk's loops run without spills).
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_batch_fwd(FwdArgs a) {
+// Eight waves per SIMD (64 registers, no spills; seven measured slower).
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_batch_fwd(FwdArgs a) {
   __shared__ RPt sv[bnd::kChunk];
   __shared__ int s_item;
   for (int pass = 0;; ++pass) {

@@ -14,10 +14,9 @@ namespace {
 
 using namespace bnd;
 
-// Seven waves per SIMD for one query per lane (72 registers; only the turn
-// counters, touched once per 32 edges, live in scratch).
+// Eight waves per SIMD for one query per lane (57 registers, no spills).
 template <int QPL>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL == 1 ? 7 : 4))) void k_bnd3d(BndArgs a, LoopTable L) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL == 1 ? 8 : 4))) void k_bnd3d(BndArgs a, LoopTable L) {
   __shared__ RPt sv[kChunk];
 
   Lane<QPL> s;
@@ -59,9 +58,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL ==
 // Fused forward, one query per lane: the crossing count (BVH traversal),
 // then the boundary walk, then w.  While some waves wait on node fetches,
 // others keep the vector units busy with the boundary arithmetic.
-// Six waves per SIMD (80 registers): with the alternating order below, the
-// seven-wave budget of 72 registers spilled inside the boundary walk.
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_fwd3d(CrossArgs c, BndArgs a, LoopTable L, int32_t* chi_out) {
+// Seven waves per SIMD (measured: eight, with the node fetches of more
+// concurrent traversals, and six are both slower).
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_fwd3d(CrossArgs c, BndArgs a, LoopTable L, int32_t* chi_out) {
   __shared__ RPt sv[kChunk];
   const int64_t qi = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const bool ok = qi < a.nq;

@@ -209,12 +209,13 @@ __device__ __forceinline__ float edge_n_exact(const VQ& a, const VQ& b, double t
 // most 32 edges is decided at once (turns_flush): with the old product's
 // sign a_j = c_(j-1), a turn backward past -pi is a_j & b_j & ~c_j and one
 // forward past pi is ~a_j & ~b_j & c_j, counted by population counts into k
-// (forward turns minus backward turns).
+// (forward turns minus backward turns), kept as 2 k beside the last decided
+// sign bit in one register.
 struct Turns {
   float zr, zi;
   uint32_t bacc, cacc;   // sign bits of the group's N and new zi (newest in bit 0)
-  uint32_t cprev;        // cacc when the last group was decided (bit 0: zi's sign then)
-  int k;                 // turns forward past pi minus turns backward past -pi
+  int kc;                // 2 k + (zi's sign bit when the last group was decided), where
+                         // k = turns forward past pi minus turns backward past -pi
 };
 
 __device__ __forceinline__ void turns_init(Turns& t) {
@@ -222,8 +223,7 @@ __device__ __forceinline__ void turns_init(Turns& t) {
   t.zi = 0.0f;
   t.bacc = 0u;
   t.cacc = 0u;
-  t.cprev = 0u;
-  t.k = 0;
+  t.kc = 0;
 }
 
 __device__ __forceinline__ void turns_mul(Turns& t, float D, float N) {
@@ -253,22 +253,27 @@ __device__ __forceinline__ void turns_edge(Turns& t, const VQ& a, const VQ& b, d
   }
   t.bacc = __builtin_amdgcn_alignbit(t.bacc, __float_as_uint(N), 31);
   t.cacc = __builtin_amdgcn_alignbit(t.cacc, __float_as_uint(ni), 31);
+  // an empty statement that takes the bit registers as operands: the
+  // compiler would otherwise defer the insertions to the end of an unrolled
+  // run of edges and keep every edge's N and zi alive until then
+  asm volatile("" : "+v"(t.bacc), "+v"(t.cacc));
   t.zr = nr;
   t.zi = ni;
 }
 
 // Decide the last n (1..32, the same for every lane) edges' turns.  The
 // old sign of edge j of the group is the new sign of edge j - 1, i.e. cacc
-// shifted by one, with the sign from before the group (bit 0 of cprev)
-// entering at the top; bacc restarts, cacc keeps running.
+// shifted by one, with the sign from before the group (bit 0 of kc)
+// entering at the top; bacc restarts, cacc keeps running and its newest
+// bit becomes bit 0 of kc.
 __device__ __forceinline__ void turns_flush(Turns& t, int n) {
   const uint32_t m = n >= 32 ? 0xFFFFFFFFu : ((1u << n) - 1u);
-  const uint32_t a = __builtin_amdgcn_alignbit(t.cprev, t.cacc, 1);
+  const uint32_t a = __builtin_amdgcn_alignbit((uint32_t)t.kc, t.cacc, 1);
   const uint32_t b = t.bacc;           // zero above bit n - 1
   const uint32_t c = t.cacc & m;
-  t.k += __popc(~a & ~b & c) - __popc(a & b & ~c);
+  const int dk = __popc(~a & ~b & c) - __popc(a & b & ~c);
+  t.kc = (int)((((uint32_t)t.kc + 2u * (uint32_t)dk) & ~1u) | (t.cacc & 1u));
   t.bacc = 0u;
-  t.cprev = t.cacc;
 }
 
 // Rescale by a power of two (exact; keeps signs and zeros): with m = |zr| +
@@ -319,7 +324,7 @@ __device__ __forceinline__ float atan2_f32(float y, float x) {
 __device__ __forceinline__ float turns_to_w(Turns t, int chi) {
   turns_norm(t);
   const float ang = atan2_f32(t.zi, t.zr);
-  return __fadd_rn((float)(chi + t.k), __fmul_rn(ang, kInv2Pi));
+  return __fadd_rn((float)(chi + (t.kc >> 1)), __fmul_rn(ang, kInv2Pi));
 }
 
 }  // namespace wn

@@ -24,7 +24,7 @@ using namespace bnd;
 
 // 32-bit index arithmetic (the host limits grids to fewer than 2^32
 // points): 64-bit divisions would be long emulated sequences per query.
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_grid3d_fwd(CrossArgs c, BndArgs a, LoopTable L,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_grid3d_fwd(CrossArgs c, BndArgs a, LoopTable L,
                                                          const float* __restrict__ gx, const float* __restrict__ gy,
                                                          const float* __restrict__ gz, int64_t ny64, int64_t nz64,
                                                          int32_t* chi_out) {
