@@ -81,7 +81,7 @@ const char* wn_last_error(void);
 /* ---------------------------------------------------------------------------
  * wn_boundary_loops -- boundary of an oriented triangle mesh (host, topology).
  *
- * Sec. 4 "Multiple Boundaries" / Sec. 5 preprocessing: the boundary consists
+ * Sec. 5.1 "Multiple Boundaries" / Sec. 6.1 "Preprocessing": the boundary consists
  * of the edges used by exactly one face.  Each boundary half-edge keeps the
  * orientation it has in its face; half-edges are chained head to tail into
  * closed loops.
@@ -154,7 +154,7 @@ wn_status wn_eval_3d(const wn_bvh* bvh, const float* bnd_xyz,
 /* ---------------------------------------------------------------------------
  * wn_eval_3d_grid -- w_M on a grid whose columns run along the ray: queries
  * (gx[i], gy[j], gz[k]), i < nx, j < ny, k < nz, for a BVH built for the
- * direction +z.  Sec. 4 ("Optimization"): points on one line parallel to
+ * direction +z.  Sec. 5 ("Optimization"): points on one line parallel to
  * the ray share the ray.  The points of a column are consecutive lanes with
  * identical frame coordinates X, Y, so a wavefront walks the tree once for
  * its column and each point applies the exact triangle test at its own
@@ -187,7 +187,7 @@ wn_status wn_eval_3d_boundary(const wn_bvh* bvh, const float* bnd_xyz,
  * wn_eval_3d_curves -- w for a surface whose boundary is a set of closed
  * loops of cubic Bezier curves: w = chi_d + Theta/(2pi), Theta the line
  * integral along the curves of the form whose integral along a straight edge
- * is the polyline path's edge term (Sec. 4: region areas from boundary
+ * is the polyline path's edge term (Sec. 5.1 "Exact Computations": region areas from boundary
  * integrals, Gauss-Bonnet; Bezier boundaries are integrated numerically).
  *  bvh        frame and direction d; also gives chi_d when chi_in is NULL
  *             (the BVH of the surface's tessellation).
@@ -247,7 +247,7 @@ wn_status wn_backward_curves(const float* ctrl, int64_t ncurves,
 /* ---------------------------------------------------------------------------
  * wn_eval_3d_patches -- w of a parametric surface made of bicubic Bezier
  * patches, without tessellation: chi_d from the exact ray-patch crossings
- * (Eq. chi; Sec. 4, parametric surfaces) plus the boundary integral along
+ * (Eq. chi; Sec. 5.1, "Parametric Surfaces") plus the boundary integral along
  * the surface's boundary curves as in wn_eval_3d_curves.
  *  dir        host [3] ray direction d (normalised here).
  *  nets       device [npatch][4][4][3] float32 Bernstein control nets (index
@@ -281,7 +281,7 @@ wn_status wn_eval_3d_patches(const double dir[3], const float* nets, int64_t npa
  * Batched parametric surfaces: many surfaces, each made of bicubic Bezier
  * patches with cubic Bezier boundary curves, its own ray direction and its
  * own queries, evaluated in one launch (w = chi_d + Theta/2pi as in
- * wn_eval_3d_patches; Sec. 4, parametric surfaces).
+ * wn_eval_3d_patches; Sec. 5.1, "Parametric Surfaces").
  *
  * One surface of such a batch: its patch, curve and query counts and its
  * direction.  The surfaces' patches are consecutive in the nets array, their
@@ -421,7 +421,7 @@ wn_status wn_backward_noalloc(const float* bnd_xyz, const int64_t* loop_off, int
 
 /* ---------------------------------------------------------------------------
  * wn_eval_2d -- w_C(p) for loops of cubic Bezier curves (Sec. 3 2D
- * definition; Sec. 6 2D parametric geometry).  The ray direction is +x.
+ * definition; Sec. 7 "2D Parametric Geometry").  The ray direction is +x.
  *
  *  dtype      WN_F32 or WN_F64: type of ctrl, the query coordinates and w.
  *  ctrl       device [nseg][4][2] control points; the segments of a loop are
@@ -434,7 +434,7 @@ wn_status wn_backward_noalloc(const float* bnd_xyz, const int64_t* loop_off, int
  *             counter-clockwise from +x).
  *  kind       0 = points: x[n], y[n] (n = nx, ny ignored);
  *             1 = grid: x[nx] ascending, y[ny]; outputs row-major [ny][nx]
- *             (one ray per row, the paper's one-shot reuse of Sec. 4).
+ *             (one ray per row, the paper's one-shot reuse of Sec. 5).
  *  w_out      device out, dtype, [n] or [ny][nx]; chi_out device int32 or NULL.
  * A point on the ray's line counts as lying above it, so chi and the end
  * point angles change together where a row passes exactly through a joint.
@@ -447,7 +447,7 @@ wn_status wn_eval_2d(wn_dtype dtype, const void* ctrl, int64_t nseg,
 
 /* ---------------------------------------------------------------------------
  * Batched 2D grid mode: many independent curve sets, each on its own grid,
- * in one launch (the 2D experiment of Sec. 6 evaluates 1000 random cubics,
+ * in one launch (the 2D experiment of Sec. 7 evaluates 1000 random cubics,
  * each on a 250 x 250 grid over its bounding box).
  *
  * One set of a batch: nseg segments (taken from the batch's ctrl array in set

@@ -8,7 +8,7 @@ A surface whose boundary is a set of closed loops of cubic Bezier curves has
 w(p) = chi_d(p) + Theta(p) / (2 pi), where Theta is the line integral over the
 boundary of the one-form whose integral along a straight edge a -> b is the
 edge term of ``oracle.wn3d``: half the signed solid angle of the spherical
-triangle (-d, a - p, b - p).  Sec. 4 ("Exact Computations") computes region
+triangle (-d, a - p, b - p).  Sec. 5.1 ("Exact Computations") computes region
 areas from boundary integrals (Gauss-Bonnet) and notes that along Bezier
 boundaries they have to be integrated numerically; Theta is that integral for
 the region decomposition seeded at d.

@@ -7,7 +7,7 @@ What is computed
 ----------------
 chi_d (Eq. chi) for a parametric surface S(u, v), (u, v) in [0, 1]^2: the
 points where the ray p + t d, t > 0, meets S, each counted with
-sign(d . (S_u x S_v)).  Sec. 4 ("Parametric surfaces") finds all roots of
+sign(d . (S_u x S_v)).  Sec. 5.1 ("Parametric Surfaces") finds all roots of
 f(xi) + (q - p) t = 0 with a generic nonlinear solver started on
 subintervals of the ray; for polynomial patches it points to specialised
 techniques.  This oracle isolates the roots by subdivision: in the frame R of

@@ -25,8 +25,8 @@ or an end point; grid rows through a bounding-box extreme hit these exactly):
 a point on the ray's line counts as lying on the side y >= 0, the same side
 that phi in [0, 2pi) gives it, so chi and the end-point term jump together.
 Queries whose y is constant along a ray line (grid rows for d = +x) share
-their roots, as in the paper's one-shot reuse of one ray per row (Sec. 4
-"Optimization"; Sec. 6, 2D results).
+their roots, as in the paper's one-shot reuse of one ray per row (Sec. 5
+"Optimization"; Sec. 7, 2D results).
 
 A query is *degenerate* (margins below BAND) if the ray passes within BAND of
 a curve point it crosses (|x(t*)| small: p on or next to the curve), crosses

@@ -9,7 +9,7 @@ of the signed ray-crossing count chi over all directions (Eq. wn_chi).  By
 Lemma 1 chi is constant on each region A_i cut out of the unit sphere around p
 by the projected boundary, so w = (1/4pi) sum_i Area(A_i) chi_i
 (Eq. wn_discrete_sum).  By Lemma 2 neighbouring regions differ by exactly one,
-the in-sphere normal n x tau pointing to the larger value (Sec. 4).
+the in-sphere normal n x tau pointing to the larger value (Lemma 2, Sec. 5).
 
 Fix one unit direction d for all queries and take d's region as the seed of
 Alg. 1 (the paper picks the largest region only as a heuristic; any seed gives
@@ -19,7 +19,7 @@ boundary crossings between d and region j, and since the areas sum to 4pi,
     w(p) = chi_d(p) + (1/4pi) sum_j Area(A_j) delta_j .
 
 The second term is a line integral over the boundary (the paper computes region
-areas from boundary integrals, Sec. 4 "Exact Computations", Gauss-Bonnet).  For
+areas from boundary integrals, Sec. 5.1 "Exact Computations", Gauss-Bonnet).  For
 a straight boundary edge a->b it is half the signed area of the spherical
 triangle (-d, a-p, b-p), which in the rotated frame R (rows e1, e2, d; det +1)
 with (X, Y, Z) = R (v - p), rho^2 = X^2 + Y^2, r = |v - p| and
@@ -64,9 +64,9 @@ import numpy as np
 TWO_PI = 2.0 * math.pi
 # Degeneracy bands.  A float32/float64 evaluation relative to p decides every
 # ray/triangle predicate exactly on a *perturbed* copy of the mesh: each vertex
-# moved in the plane perpendicular to d by at most 2^-23 |v - p| (coordinates
-# rounded, scale factors rounded) plus 2^-50 of the scene size (the float64
-# frame).  The signed crossing count of that copy equals the exact one unless
+# moved in the plane perpendicular to d by at most 2^-23 |v - p| (its offset
+# from p rounded to float32) plus 2^-47 of the scene size (the frame and the
+# split float32 coordinates it is stored in).  The signed crossing count of that copy equals the exact one unless
 # the perturbation carries the projected boundary across the ray or the
 # surface across p (Lemma 1: chi is constant on the regions cut out by the
 # projected boundary; it also changes where p crosses M).  BAND is the
@@ -89,7 +89,7 @@ def boundary_loops(F) -> list:
     """Boundary of an oriented triangle mesh as closed vertex loops.
 
     A boundary half-edge a->b is an edge {a, b} used by exactly one face, kept
-    in that face's orientation (Sec. 5 preprocessing: boundaries are segments
+    in that face's orientation (Sec. 6.1 "Preprocessing": boundaries are segments
     adjacent to only one loop).  Half-edges are chained head to tail; each loop
     is returned as the vertex sequence v0, v1, ..., v_{n-1} (edges v_i -> v_{i+1}
     and v_{n-1} -> v0).  Raises on a vertex with two outgoing boundary edges.

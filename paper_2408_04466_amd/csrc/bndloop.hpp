@@ -8,7 +8,7 @@
 // Lemma 2 every other region differs from it by the number of boundary
 // crossings in between, so the region areas collapse into one line integral
 // over the boundary (the paper evaluates region areas from boundary
-// integrals as well, Sec. 4 "Exact Computations").
+// integrals as well, Sec. 5.1 "Exact Computations").
 //
 // Layout: the workgroup stages the boundary loops into LDS (rotated
 // coordinates as float32 pairs plus the tie offset of the edge leaving each

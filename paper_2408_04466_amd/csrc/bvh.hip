@@ -6,7 +6,7 @@
 // therefore stores, for each child, the 2D box of the children's projections
 // and the largest Z: a ray can reach the child only if its (X, Y) lies in the
 // box and Z_p is below that largest Z.  The paper uses a k-d tree for its
-// ray/mesh intersections (Sec. 4, Meshes); the tree here is a linear BVH
+// ray/mesh intersections (Sec. 5.1, "Meshes"); the tree here is a linear BVH
 // (Karras 2012) over 2D Morton codes of the projected centroids, built with
 // a project-written LSD radix sort, and traversed with a short stack held in
 // registers.

@@ -5,7 +5,7 @@
 // For a surface bounded by loops of cubic Bezier curves, w = chi_d +
 // Theta / (2 pi) with Theta the line integral over the curves of the form
 // whose integral along a straight edge is the edge term atan2(N, D) of the
-// polyline path (Sec. 4: region areas from boundary integrals, Gauss-Bonnet;
+// polyline path (Sec. 5.1 "Exact Computations": region areas from boundary integrals, Gauss-Bonnet;
 // Bezier boundaries need a numerical integral).  In the frame of d, with
 // (X, Y, Z) the curve point relative to the query and r its distance,
 //

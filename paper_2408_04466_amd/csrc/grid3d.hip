@@ -1,7 +1,7 @@
 // Grid mode in 3D: queries (gx[i], gy[j], gz[k]) for a BVH built for d = +z,
 // one lane per query with z fastest.
 //
-// Sec. 4 ("Optimization") reuses one ray for all points on a line parallel
+// Sec. 5 ("Optimization") reuses one ray for all points on a line parallel
 // to the ray direction.  Here every column (x_i, y_j) is such a line, and its
 // points are consecutive lanes: the 64 lanes of a wavefront lie on one
 // column and have bit-identical frame coordinates X, Y (d = +z leaves the

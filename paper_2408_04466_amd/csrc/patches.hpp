@@ -3,7 +3,7 @@
 // Signed crossings of the ray p + t d (t > 0) with bicubic Bezier patches:
 // chi_d of a parametric surface without tessellating it.
 //
-// Sec. 4 ("Parametric surfaces") intersects each ray with the patch by a
+// Sec. 5.1 ("Parametric Surfaces") intersects each ray with the patch by a
 // generic nonlinear solver, started on subintervals of the ray's clip by the
 // patch's bounding box.  For polynomial patches the roots can be isolated
 // instead (the paper points to specialised techniques there), and that is

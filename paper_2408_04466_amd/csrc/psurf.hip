@@ -2,7 +2,7 @@
 // patches, boundary curves, ray direction and query range; each workgroup
 // takes 256 consecutive queries of one surface and computes chi_d with the
 // patch walk of patches.hpp and, when w is wanted, Theta with the curve walk
-// of curves.hpp, then w = chi_d + Theta / (2 pi) (Sec. 4, parametric surfaces;
+// of curves.hpp, then w = chi_d + Theta / (2 pi) (Sec. 5.1, "Parametric Surfaces";
 // Eq. of the one-shot winding number).  The arithmetic per query is that of
 // the single-surface path, in the same order, so a batched result equals
 // the single call's bit for bit.

@@ -16,7 +16,7 @@
 //    crossing counts if it lies right of p, decided by the piece's x bounds
 //    or, when p_x falls inside them, by solving y(t) = p_y on the piece
 //    (safeguarded Newton) and comparing x(t*).
-//  * grid mode: the paper's one-shot reuse (Sec. 4 "Optimization"; Sec. 6,
+//  * grid mode: the paper's one-shot reuse (Sec. 5 "Optimization"; Sec. 7,
 //    2D results): one workgroup per (row, column tile) solves each piece that
 //    crosses the row once, bins the crossing by the number of grid columns
 //    left of it (an LDS histogram of integer counts), and a suffix scan gives

@@ -9,7 +9,25 @@ import paper_2408_04466_amd as W
 from oracle import wn3d as O
 
 W_TOL = 1e-4          # |w_gpu - w_oracle| for FP32 paths
-NEAR_BND = 1e-5       # queries closer than this to the boundary are exempt
+NEAR_REL = 1e-4       # exempt: closer to the boundary than NEAR_REL x its longest edge
+
+
+def near_band(V, loops):
+    """Distance to the boundary below which w is exempt from W_TOL.  Across
+    the boundary w turns through a full unit within a distance delta, so the
+    float32 offsets of the boundary vertices (each rounded to 2^-24 of its
+    distance, at most about the longest edge L for the edges that matter)
+    perturb it by about 2^-24 L / delta: the float32 problem itself is that
+    ill-conditioned there (measured: |dw| ~ 3e-9 L / delta).  Below
+    NEAR_REL x L the tests check that bound instead
+    (tests/test_gpu_3d.py::test_near_boundary_error_follows_float32_conditioning)."""
+    V = np.asarray(V, np.float64)
+    L = 0.0
+    for lp in loops:
+        lp = np.asarray(lp)
+        if len(lp):
+            L = max(L, float(np.linalg.norm(V[lp] - V[np.roll(lp, -1)], axis=1).max()))
+    return NEAR_REL * L
 
 
 class DevMesh:
@@ -39,7 +57,8 @@ def compare_3d(dm: DevMesh, P, w_gpu, chi_gpu, sample=None, alt_dir_seed=12345,
     """Oracle parity on ``sample`` (indices into P).  chi must match bit for
     bit on non-degenerate queries; w within W_TOL away from the boundary.
     Degenerate queries are checked for w against the oracle with another
-    direction (w does not depend on d).  Large samples run in the oracle's
+    direction (w does not depend on d).  "Away from the boundary": at least
+    near_band() from it.  Large samples run in the oracle's
     process pool."""
     import oracle_pool
     P = np.asarray(P, np.float32)
@@ -53,7 +72,7 @@ def compare_3d(dm: DevMesh, P, w_gpu, chi_gpu, sample=None, alt_dir_seed=12345,
     ok = ~deg
     bad = np.nonzero(chi_gpu[idx][ok] != r["chi"][ok])[0]
     assert bad.size == 0, f"chi mismatch at {idx[ok][bad][:10]}: gpu {chi_gpu[idx][ok][bad][:10]} oracle {r['chi'][ok][bad][:10]}"
-    far = r["m_bnd"] >= NEAR_BND
+    far = r["m_bnd"] >= near_band(dm.M.V, loops)
     wref = r["w"].copy()
     if deg.any():
         # w is independent of d: take a direction for which these are regular

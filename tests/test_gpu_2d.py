@@ -1,7 +1,7 @@
 """GPU parity of the 2D path (cubic Bezier loops, ray +x) against the FP64
 oracle: chi bit-exact on non-degenerate queries; w within 1e-10 (float64
 inputs) or 1e-4 (float32) away from open-curve end points; grid mode (one ray
-per row, Sec. 4 "Optimization") equal bit for bit to points mode."""
+per row, Sec. 5 "Optimization") equal bit for bit to points mode."""
 import numpy as np
 import pytest
 import torch
@@ -97,7 +97,7 @@ def test_c2_random_points_and_points_mode(c2):
 
 @pytest.mark.parametrize("dtype,tol", [(np.float64, 1e-10), (np.float32, 1e-4)])
 def test_rows_through_end_points(dtype, tol):
-    # the paper's 2D setup (Sec. 6): random cubics with control points in the
+    # the paper's 2D setup (Sec. 7): random cubics with control points in the
     # unit square, a regular grid in each curve's bounding box; the first and
     # last rows and columns pass exactly through extremes and end points
     g = synth.rng(5)

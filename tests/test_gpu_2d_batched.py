@@ -3,7 +3,7 @@ bit for bit to its own wn_eval_2d grid call (which runs the workgroup
 histogram kernel, so small sets also check the wavefront kernel against it),
 oracle parity on samples, empty and ragged sets on both kernels, the 21/22
 segment boundary between them, and the full-size input shape of the 2D
-experiment of Sec. 6 (1000 random cubics, each on a 250 x 250 grid over its
+experiment of Sec. 7 (1000 random cubics, each on a 250 x 250 grid over its
 bounding box) with no point off by more than 1e-10 in float64."""
 import numpy as np
 import pytest

@@ -67,7 +67,7 @@ def test_many_loops_across_lds_chunks():
     P = _rand_queries(M, 2000, 24)
     w, chi = dm.eval(P)
     compare_3d(dm, P, w, chi)
-    # and the union equals the sum of the parts (Sec. 6: union = sum of w)
+    # and the union equals the sum of the parts (Sec. 7, Fig. bool: union = sum of w)
     tot = np.zeros(len(P))
     for Mk, o in zip(parts, [(1.3 * k, 0.2 * k, 0.0) for k in range(5)]):
         Mk = synth.Mesh(Mk.V + np.asarray(o, np.float32), Mk.F)
@@ -168,6 +168,54 @@ def test_near_boundary_queries():
     P = np.array(pts, np.float32)
     w, chi = dm.eval(P)
     compare_3d(dm, P, w, chi, max_degenerate_frac=0.2)
+
+
+def test_near_boundary_error_follows_float32_conditioning():
+    """Queries 1e-6 to 1e-2 from boundary edges of meshes whose boundary
+    edges are long (0.07 to 0.8).  Away from the boundary (at least
+    near_band = 1e-4 x the longest edge L) w is within W_TOL of the oracle;
+    closer, the error stays below 2^-24 L / delta, the float32 conditioning of
+    w there (delta: the oracle's distance to the boundary).  chi is bit-exact
+    wherever the oracle calls the query regular."""
+    import oracle_pool
+    from gpu_util import NEAR_REL, near_band
+    cases = [(synth.bumpy_cap(), 3), (synth.coons_surface(11, 300, 40), 4), (synth.random_open_mesh(3, n=5), 5)]
+    for M, seed in cases:
+        d = synth.random_direction(seed)
+        dm = DevMesh(M, d)
+        V = M.V.astype(np.float64)
+        loops = [dm.bnd_idx[dm.loop_off[k]:dm.loop_off[k + 1]] for k in range(len(dm.loop_off) - 1)]
+        L = loops[0]
+        g = synth.rng(30 + seed)
+        pts = []
+        for dl in (1e-6, 1e-5, 3e-5, 1e-4, 3e-4, 1e-3, 1e-2):
+            for _ in range(32):
+                i = int(g.integers(len(L)))
+                a, b = V[L[i]], V[L[(i + 1) % len(L)]]
+                e = (b - a) / np.linalg.norm(b - a)
+                u = g.normal(size=3)
+                u -= (u @ e) * e
+                pts.append(a + g.uniform(0.1, 0.9) * (b - a) + dl * u / np.linalg.norm(u))
+        P = np.asarray(pts, np.float32)
+        w, chi = dm.eval(P)
+        r = oracle_pool.wn3d(M.V, M.F, P, d, loops=loops)
+        deg = r.degenerate
+        assert np.array_equal(chi[~deg], r["chi"][~deg])
+        wref, valid = r["w"].copy(), ~deg
+        if deg.any():
+            r2 = oracle_pool.wn3d(M.V, M.F, P[deg], synth.random_direction(12345), loops=loops)
+            wref[deg] = r2["w"]
+            valid[np.nonzero(deg)[0][~r2.degenerate]] = True
+        err = np.abs(w - wref)
+        band = near_band(M.V, loops)
+        delta = r["m_bnd"]
+        out, near = valid & (delta >= band), valid & (delta < band)
+        print(f"near boundary (L = {band / NEAR_REL:.3g}): {int(out.sum())} queries beyond the band, max err "
+              f"{err[out].max():.2e}; {int(near.sum())} inside, max err x delta / L "
+              f"{(err[near] * delta[near]).max() / (band / NEAR_REL):.2e}", flush=True)
+        assert out.sum() > 100 and near.sum() > 30
+        assert err[out].max() <= W_TOL
+        assert np.all(err[near] <= 2.0 ** -24 * (band / NEAR_REL) / delta[near])
 
 
 def test_w_continuous_across_boundary_crossing():

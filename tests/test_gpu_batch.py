@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 if torch.cuda.is_available():
     import paper_2408_04466_amd as W
-    from gpu_util import W_TOL
+    from gpu_util import W_TOL, near_band
 
 
 def _surfaces(seed, n, scale):
@@ -98,7 +98,7 @@ def test_batched_oracle_samples(small_batch):
         ok = ~r.degenerate
         n_all, n_deg = n_all + len(sel), n_deg + int((~ok).sum())
         assert np.array_equal(chi[offs[k] + sel][ok], r["chi"][ok]), k
-        far = r["m_bnd"] > 1e-5
+        far = r["m_bnd"] > near_band(meshes[k].V, O.boundary_loops(meshes[k].F))
         wref = r["w"].copy()
         assert np.abs(w[offs[k] + sel][far & ok] - wref[far & ok]).max(initial=0.0) <= W_TOL, k
     print(f"batched oracle samples: {n_all} queries, {n_deg} degenerate", flush=True)
@@ -248,7 +248,8 @@ def test_full_size_batch_autotuned_parity():
         ok = ~r.degenerate
         n_deg += int((~ok).sum())
         assert np.array_equal(cc[offs[k] + sel][ok], r["chi"][ok]), k
-        far = ok & (r["m_bnd"] > 1e-5)
+        M = CB.meshes[k]
+        far = ok & (r["m_bnd"] > near_band(M.V, O.boundary_loops(M.F)))
         assert np.abs(wc[offs[k] + sel][far] - r["w"][far]).max(initial=0.0) <= W_TOL, k
     print(f"full batch: {16 * 256} oracle queries, {n_deg} degenerate", flush=True)
     assert n_deg <= 0.02 * 16 * 256

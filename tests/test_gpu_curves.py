@@ -5,7 +5,7 @@ to the curves and rays grazing them; with chi_d from the tessellation's BVH
 against the mesh oracle's chi; straight Beziers against the polyline path;
 edge cases; and a 1M-triangle Coons surface with 2^20 queries on samples.
 Also checks that the curve integral removes the polyline's discretization
-error (the effect Sec. 6 measures for parametric surfaces)."""
+error (the effect Sec. 7 measures for parametric surfaces)."""
 import math
 
 import numpy as np

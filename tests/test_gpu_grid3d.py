@@ -1,5 +1,5 @@
 """GPU tests of the 3D grid mode (queries on lines along the ray share the
-ray, Sec. 4 "Optimization"): bit-identical to the per-query path on the
+ray, Sec. 5 "Optimization"): bit-identical to the per-query path on the
 same float32 points, oracle parity on samples, deep stacks of surfaces,
 edge cases, and the full-size voxel grid over the 1M-triangle mesh."""
 import numpy as np

@@ -214,7 +214,7 @@ def test_full_size_queries():
 
 
 def test_parametric_path_removes_the_discretization_error():
-    """The accuracy experiment of Sec. 6 (parametric surfaces) in miniature:
+    """The accuracy experiment of Sec. 7 (parametric surfaces) in miniature:
     queries on a slice through a curved patch; the tessellated path (mesh
     chi + polyline boundary) against the exact parametric path, both against
     the FP64 oracles (patch crossings + curve integral)."""

@@ -2,7 +2,7 @@
 
 ``oracle.wn2d`` is tied to: adaptive quadrature of dtheta along each cubic
 (the definition of w_C, Sec. 3) to the paper's 1e-10 misclassification bar
-(Sec. 6, 2D parametric geometry), a dense unwrapped angle sum, exact integers
+(Sec. 7, 2D parametric geometry), a dense unwrapped angle sum, exact integers
 for closed loops against a polygon crossing test, the closed form for a
 straight segment, and invariance under a change of d.
 """
@@ -75,7 +75,7 @@ def test_random_loops_match_quadrature():
 
 
 def test_paper_2d_setup_zero_misclassified():
-    # Sec. 6 (2D parametric geometry): random cubics with control points in the
+    # Sec. 7 (2D parametric geometry): random cubics with control points in the
     # unit square, a regular grid in each curve's bounding box, 0 points off by
     # more than 1e-10.  Scaled down: 8 curves, 24 x 24 grid each; rows and
     # columns through the bounding-box extremes hit end points exactly.

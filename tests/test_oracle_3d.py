@@ -4,8 +4,8 @@ Each check ties ``oracle.wn3d`` to something other than itself: the plain
 per-triangle solid-angle sum (the definition of w_M, Sec. 3), quadrature of
 Eq. wn_chi over directions with an independent Moller-Trumbore crossing
 count, the flat-disk closed form, closed surfaces (Sec. 3: inside/outside),
-Lemma 2 (Sec. 4), and invariances (change of d, orientation flip, union as a
-sum of winding numbers as in Sec. 6).
+Lemma 2 (Sec. 5), and invariances (change of d, orientation flip, union as a
+sum of winding numbers as in Sec. 7, Fig. bool).
 """
 import math
 
