@@ -40,7 +40,11 @@ Pinned by (tests/test_oracle_curves.py): straight Beziers of any speed against
 the Van Oosterom-Strackee solid angle of (-d, a - p, b - p); planar regions
 bounded by Bezier loops against fine fan triangulations (sum of triangle solid
 angles, Richardson-extrapolated) with chi_d from a point-in-polygon test, for
-several d; additivity under de Casteljau splits; reversal.
+several d; additivity under de Casteljau splits; reversal.  The margins
+(tests/test_oracle_margins_param.py): straight Beziers of uneven speed against
+the point-segment distance and a million-point angle search, curves behind
+the query, rays offset at known fractions of the band, planted mistakes (an
+unnormalised distance, points behind p counted, |v| for |v_perp|).
 """
 from __future__ import annotations
 

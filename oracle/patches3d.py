@@ -33,7 +33,12 @@ point-in-quadrilateral test; fine tessellations of curved patches against
 the mesh oracle's brute-force crossing count (oracle.wn3d.crossings) away
 from the surface; w = chi_d + Theta / 2pi (Theta from oracle.curves3d along
 the patch's boundary curves) independent of d; and closed two-patch pillows
-(chi in {0, 1} for every d).
+(chi in {0, 1} for every d).  The margin (tests/test_oracle_margins_param.py):
+flat, tilted and stretched bilinear patches against the parameter distance,
+|cos| of the tilt and |S - p| / size in closed form, planted mistakes in
+zero_margin; a ray passing just outside a patch has no crossing margin and is
+flagged by curve_margins of the patch's boundary curves, which the parity
+tests combine with it.
 """
 from __future__ import annotations
 
@@ -116,6 +121,15 @@ class Crossings:
         return self.margin < BAND
 
 
+def zero_margin(u, v, S, n, size):
+    """Margin of one zero (u, v) of the projected map, in the frame where d
+    is +z: its parameter distance to the square's boundary (the ray near a
+    boundary curve), |d . n| / |n| with n = S_u x S_v (the ray nearly
+    tangent) and |S - p| over the patch's size (p on the surface)."""
+    return min(u, 1 - u, v, 1 - v, abs(n[2]) / max(np.linalg.norm(n), 1e-300),
+               np.linalg.norm(S) / max(size, 1e-300))
+
+
 def patch_crossings_one(net, p, d):
     """(chi, margin) of one patch net [4, 4, 3] for one query p."""
     R = frame(d)
@@ -152,9 +166,7 @@ def patch_crossings_one(net, p, d):
             continue
         S, Su, Sv = patch_eval(Q, u, v)
         n = np.cross(Su, Sv)
-        margin = min(margin, u, 1 - u, v, 1 - v,
-                     abs(n[2]) / max(np.linalg.norm(n), 1e-300),
-                     np.linalg.norm(S) / max(size, 1e-300))
+        margin = min(margin, zero_margin(u, v, S, n, size))
         if S[2] > 0:
             chi += 1 if n[2] > 0 else -1
     return chi, margin

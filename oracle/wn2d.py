@@ -37,7 +37,11 @@ points are not degenerate: the convention above decides them.
 Pinned by (tests/test_oracle_2d.py): adaptive quadrature of dtheta/dt
 (scipy.integrate.quad) per segment to 1e-10, a dense unwrapped angle sum,
 exact integers for closed loops against a polygon crossing test, the closed
-form for a straight segment, d-invariance, reversal negation.
+form for a straight segment, d-invariance, reversal negation.  The margins
+(tests/test_oracle_margins_param.py): tangency on straight pieces of any
+speed, brute-force root finding (sign changes refined by bisection) for m_x,
+m_tan and m_joint, queries at known fractions of BAND from a crossing, an end
+point and a nearly tangential crossing, and planted mistakes in each helper.
 """
 from __future__ import annotations
 
@@ -158,6 +162,36 @@ def segment_crossings(ys):
     return fi, ft, fs
 
 
+def tangency(xp, yp):
+    """|sin| of the angle between the curve and the ray's line at a crossing,
+    from the curve's derivative (xp, yp) in the frame of d: |y'| / |B'|."""
+    return np.abs(yp) / np.maximum(np.hypot(xp, yp), 1e-300)
+
+
+def crossing_margins(dx, tang):
+    """(m_x, m_tan) per query from dx [q, roots] = x(t*) - p_x of every root
+    on the query's ray line and the roots' tangency: the distance along the
+    line to the nearest crossing (either side: p next to the curve), and the
+    smallest tangency among the crossings the ray counts (at or right of p,
+    within BAND)."""
+    if dx.shape[1] == 0:
+        return np.full(dx.shape[0], np.inf), np.full(dx.shape[0], np.inf)
+    m_x = np.abs(dx).min(1)
+    m_tan = np.where(dx > -BAND, tang[None, :], np.inf).min(1)
+    return m_x, m_tan
+
+
+def joint_margin(jx, jy, ky, px):
+    """Per query (abscissae px, all on the ray line of ordinate ky): the
+    smallest distance from the line of the joints and open end points
+    (jx, jy) at or right of p (within BAND).  Exact ties (jy == ky) are
+    decided by the y >= 0 convention, so they do not count."""
+    dj = np.abs(jy - ky)
+    dj = np.where(dj == 0.0, np.inf, dj)
+    jd = np.where(jx[None, :] - px[:, None] > -BAND, dj[None, :], np.inf)
+    return jd.min(1) if jd.shape[1] else np.full(len(px), np.inf)
+
+
 class Result2D(dict):
     @property
     def degenerate(self):
@@ -217,24 +251,17 @@ def wn2d(ctrl, loop_off, closed, P, d=(1.0, 0.0), margins: bool = True) -> Resul
         xp = _bez_d(cx[seg], t)
         sgn = sgn.astype(np.int64)
         endpt = (t == 0.0) | (t == 1.0)
-        tang = np.where(endpt, np.inf, np.abs(yp) / np.maximum(np.hypot(xp, yp), 1e-300))
+        tang = np.where(endpt, np.inf, tangency(xp, yp))
         for r in range(len(kk)):
             qs = np.nonzero(inv == k0 + r)[0]
             sel = row == r
             xr_r, s_r, tg_r = xr[sel], sgn[sel], tang[sel]
             dx = xr_r[None, :] - px[qs][:, None]               # [q, roots]
             chi[qs] = np.sum(np.where(dx > 0, s_r[None, :], 0), axis=1)
-            if margins and xr_r.size:
-                m_x[qs] = np.abs(dx).min(1)
-                tg = np.where(dx > -BAND, tg_r[None, :], np.inf)
-                m_tan[qs] = tg.min(1)
             if margins:
+                m_x[qs], m_tan[qs] = crossing_margins(dx, tg_r)
                 # exact ties are resolved by the convention; near ties are not
-                dj = np.abs(jy - kk[r])
-                dj = np.where(dj == 0.0, np.inf, dj)
-                jd = np.where(jx[None, :] - px[qs][:, None] > -BAND, dj[None, :], np.inf)
-                if jd.size:
-                    m_joint[qs] = jd.min(1)
+                m_joint[qs] = joint_margin(jx, jy, kk[r], px[qs])
     # end-point terms of open loops
     E = np.zeros(nq)
     for l in range(len(closed)):
