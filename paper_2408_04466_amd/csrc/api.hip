@@ -773,7 +773,7 @@ wn_status wn_eval_3d_grid(const wn_bvh* h, const float* bnd_xyz, const int64_t* 
   a.nq = nq;
   a.chi_in = nullptr;
   a.w_out = w_out;
-  WN_HIP(wn::launch_grid3d_fwd(ca, a, L, gx, gy, gz, ny, nz, chi_out, s), "grid forward");
+  WN_HIP(wn::launch_grid3d_fwd(ca, a, L, gx, gy, gz, nx, ny, nz, chi_out, s), "grid forward");
   return WN_OK;
 }
 

@@ -135,7 +135,7 @@ hipError_t backward_curves(const float* ctrl, int64_t nc, const float* qx, const
 hipError_t launch_curves3d(const CrossArgs& c, const float* ctrl, int64_t nc, const int32_t* chi_in, float* w_out,
                            int32_t* chi_out, hipStream_t s);
 hipError_t launch_grid3d_fwd(const CrossArgs& c, const BndArgs& a, const LoopTable& L, const float* gx,
-                             const float* gy, const float* gz, int64_t ny, int64_t nz, int32_t* chi_out,
+                             const float* gy, const float* gz, int64_t nx, int64_t ny, int64_t nz, int32_t* chi_out,
                              hipStream_t s);
 int adj3d_qpl(int64_t nq);   // queries per lane the plain adjoint uses for nq queries
 hipError_t launch_adj3d(const AdjArgs& a, const LoopTable& L, int64_t nblocks, int qpl, hipStream_t s);

@@ -16,17 +16,17 @@ __device__ __forceinline__ int32_t tri_index(int32_t v, bool a_less_b) {
   return a_less_b ? (int32_t)((uint32_t)v | 0x80000000u) : v;
 }
 
-// +1 / -1 when the ray p + t d (t > 0) passes through the triangle's
-// interior along / against its normal (v1-v0)x(v2-v0), 0 otherwise.  t holds
-// the vertex indices with the edges' lexicographic order in bit 31
-// (tri_index).
+// The three edge values of a triangle for a query, each with its tie offset
+// (t holds the vertex indices with the edges' lexicographic order in bit 31,
+// tri_index).
+struct TriEdges {
+  double n01, n12, n20;
+};
+
 template <bool STORED_TIES>
-__device__ __forceinline__ int tri_crossing(const int4 t, const RPt* __restrict__ Vr, const QP& p) {
+__device__ __forceinline__ TriEdges tri_edges(const int4 t, const RPt& A, const RPt& B, const RPt& C, const QP& p) {
   // the three tie bits in one register, so that the indices die at once
   const uint32_t tb = ((uint32_t)t.x >> 31) | (((uint32_t)t.y >> 30) & 2u) | (((uint32_t)t.z >> 29) & 4u);
-  const RPt A = Vr[t.x & 0x7fffffff];
-  const RPt B = Vr[t.y & 0x7fffffff];
-  const RPt C = Vr[t.z & 0x7fffffff];
   const float ax = vertex_x(A, p), ay = vertex_y(A, p);
   const float bx = vertex_x(B, p), by = vertex_y(B, p);
   const float cx = vertex_x(C, p), cy = vertex_y(C, p);
@@ -35,18 +35,48 @@ __device__ __forceinline__ int tri_crossing(const int4 t, const RPt* __restrict_
   const bool l01 = STORED_TIES ? (tb & 1u) != 0 : rpt_less(A, B);
   const bool l12 = STORED_TIES ? (tb & 2u) != 0 : rpt_less(B, C);
   const bool l20 = STORED_TIES ? (tb & 4u) != 0 : rpt_less(C, A);
-  const double n01 = edge_tie(edge_n(ax, ay, bx, by), tie_offset(l01));
-  const double n12 = edge_tie(edge_n(bx, by, cx, cy), tie_offset(l12));
-  const double n20 = edge_tie(edge_n(cx, cy, ax, ay), tie_offset(l20));
-  const bool s01 = n01 < 0.0, s12 = n12 < 0.0, s20 = n20 < 0.0;
-  if (s01 != s12 || s12 != s20) return 0;
+  TriEdges e;
+  e.n01 = edge_tie(edge_n(ax, ay, bx, by), tie_offset(l01));
+  e.n12 = edge_tie(edge_n(bx, by, cx, cy), tie_offset(l12));
+  e.n20 = edge_tie(edge_n(cx, cy, ax, ay), tie_offset(l20));
+  return e;
+}
+
+// The line of the ray (both directions) passes through the triangle's
+// interior: the three edge values share a sign.  It depends on the query's
+// X and Y only, so every point of a vertical line gets the same answer.
+__device__ __forceinline__ bool tri_inside(const TriEdges& e) {
+  const bool s01 = e.n01 < 0.0, s12 = e.n12 < 0.0, s20 = e.n20 < 0.0;
+  return s01 == s12 && s12 == s20;
+}
+
+// +1 / -1 when the ray p + t d (t > 0) passes through the triangle's
+// interior along / against its normal (v1-v0)x(v2-v0), 0 otherwise.
+template <bool STORED_TIES>
+__device__ __forceinline__ int tri_crossing(const int4 t, const RPt* __restrict__ Vr, const QP& p) {
+  const RPt A = Vr[t.x & 0x7fffffff];
+  const RPt B = Vr[t.y & 0x7fffffff];
+  const RPt C = Vr[t.z & 0x7fffffff];
+  const TriEdges e = tri_edges<STORED_TIES>(t, A, B, C, p);
+  if (!tri_inside(e)) return 0;
+  const bool s01 = e.n01 < 0.0;
   // Height of the crossing above p: the barycentric weights are the edge
   // values opposite each vertex, so the crossing is above p iff
   // sum(N_opp * Z) has the sign of the N's.
   const double za = (double)vertex_z(A, p), zb = (double)vertex_z(B, p), zc = (double)vertex_z(C, p);
-  const double num = __fma_rn(n12, za, __fma_rn(n20, zb, __dmul_rn(n01, zc)));
+  const double num = __fma_rn(e.n12, za, __fma_rn(e.n20, zb, __dmul_rn(e.n01, zc)));
   const bool hit = s01 ? (num < 0.0) : (num > 0.0);
   return hit ? (s01 ? 1 : -1) : 0;
+}
+
+// The line through p along d (both directions) passes through the
+// triangle's interior.
+template <bool STORED_TIES>
+__device__ __forceinline__ bool tri_on_line(const int4 t, const RPt* __restrict__ Vr, const QP& p) {
+  const RPt A = Vr[t.x & 0x7fffffff];
+  const RPt B = Vr[t.y & 0x7fffffff];
+  const RPt C = Vr[t.z & 0x7fffffff];
+  return tri_inside(tri_edges<STORED_TIES>(t, A, B, C, p));
 }
 
 // ---------------------------------------------------------------------------
