@@ -72,20 +72,18 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Vertex va's partial (three values per lane): row sums into the wavefront's
-// LDS block at [va % kBlk][c][row]; once the block is full (or va is the
-// last vertex), lane t < 3 n adds the four row sums of entry t in row order
-// and stores the block's n vertices to pv with one coalesced store.
-__device__ __forceinline__ void park(float* rs, float* pv, int va, int nb, const float acc[3], int lane) {
-  const float r0 = row_sum(acc[0]);
-  const float r1 = row_sum(acc[1]);
-  const float r2 = row_sum(acc[2]);
+// Vertex va's row sums (r[c], every lane of a row holds its row's sum) into
+// the wavefront's LDS block at [va % kBlk][c][row]; once the block is full
+// (or va is the last vertex), lane t < 3 n adds the four row sums of entry t
+// in row order and stores the block's n vertices to pv with one coalesced
+// store.
+__device__ __forceinline__ void park_sums(float* rs, float* pv, int va, int nb, const float r[3], int lane) {
   const int slot = va % kBlk;
   if ((lane & 15) == 15) {
     float* d = rs + slot * 12 + (lane >> 4);
-    d[0] = r0;
-    d[4] = r1;
-    d[8] = r2;
+    d[0] = r[0];
+    d[4] = r[1];
+    d[8] = r[2];
   }
   if (slot == kBlk - 1 || va == nb - 1) {
     wave_sync();
@@ -96,6 +94,23 @@ __device__ __forceinline__ void park(float* rs, float* pv, int va, int nb, const
     }
     wave_sync();
   }
+}
+
+// Vertex va's partial (three values per lane).
+__device__ __forceinline__ void park(float* rs, float* pv, int va, int nb, const float acc[3], int lane) {
+  const float r[3] = {row_sum(acc[0]), row_sum(acc[1]), row_sum(acc[2])};
+  park_sums(rs, pv, va, nb, r, lane);
+}
+
+// The partials of vertices va and va + 1: the six row sums first (six
+// independent chains of lane moves instead of two runs of three), then the
+// two LDS entries in vertex order.
+__device__ __forceinline__ void park2(float* rs, float* pv, int va, int nb, const float a[3], const float b[3],
+                                      int lane) {
+  const float ra[3] = {row_sum(a[0]), row_sum(a[1]), row_sum(a[2])};
+  const float rb[3] = {row_sum(b[0]), row_sum(b[1]), row_sum(b[2])};
+  park_sums(rs, pv, va, nb, ra, lane);
+  park_sums(rs, pv, va + 1, nb, rb, lane);
 }
 
 struct QState {
@@ -134,19 +149,20 @@ __device__ __forceinline__ void edge_grad(QState& s, const Rel& a, const Rel& b,
   const float rs = __fadd_rn(a.r, b.r);
   const float den2 = __fmaf_rn(rs, rs, -e.w);
   const float gk = __fmul_rn(s.g, __builtin_amdgcn_rcpf(den2));
-  const float cx = __fmul_rn(gk, crx);
-  const float cy = __fmul_rn(gk, cry);
-  const float cz = __fmul_rn(gk, crz);
-  const float h = __fadd_rn(a.i, b.i);
-  s.gx = __fmaf_rn(cx, h, s.gx);
-  s.gy = __fmaf_rn(cy, h, s.gy);
-  s.gz = __fmaf_rn(cz, h, s.gz);
-  acc_a[0] = __fmaf_rn(cx, a.i, acc_a[0]);
-  acc_a[1] = __fmaf_rn(cy, a.i, acc_a[1]);
-  acc_a[2] = __fmaf_rn(cz, a.i, acc_a[2]);
-  acc_b[0] = __fmaf_rn(cx, b.i, acc_b[0]);
-  acc_b[1] = __fmaf_rn(cy, b.i, acc_b[1]);
-  acc_b[2] = __fmaf_rn(cz, b.i, acc_b[2]);
+  // c / |a'| = cr (gk / |a'|), c / |b'| = cr (gk / |b'|), and the query's
+  // c (1/|a'| + 1/|b'|) = cr (ta + tb)
+  const float ta = __fmul_rn(gk, a.i);
+  const float tb = __fmul_rn(gk, b.i);
+  const float h = __fadd_rn(ta, tb);
+  s.gx = __fmaf_rn(crx, h, s.gx);
+  s.gy = __fmaf_rn(cry, h, s.gy);
+  s.gz = __fmaf_rn(crz, h, s.gz);
+  acc_a[0] = __fmaf_rn(crx, ta, acc_a[0]);
+  acc_a[1] = __fmaf_rn(cry, ta, acc_a[1]);
+  acc_a[2] = __fmaf_rn(crz, ta, acc_a[2]);
+  acc_b[0] = __fmaf_rn(crx, tb, acc_b[0]);
+  acc_b[1] = __fmaf_rn(cry, tb, acc_b[1]);
+  acc_b[2] = __fmaf_rn(crz, tb, acc_b[2]);
 }
 
 // Stage boundary vertex i (flat index, loops L) for the adjoint walk: its
@@ -216,7 +232,8 @@ __device__ __forceinline__ void walk(QState* S, const float* __restrict__ bnd, i
                                      float4* sv, float* rsw, float* pv, float* pl) {
   const int lane = threadIdx.x & 63;
   float* rs = rsw + (threadIdx.x >> 6) * kRowFloats;
-  Rel F[QPL], A[QPL], B[QPL];      // loop's first vertex; A = last vertex visited
+  Rel A[QPL], B[QPL];              // A = last vertex visited
+  float4 vF = make_float4(0.f, 0.f, 0.f, 0.f);   // the loop's first vertex (uniform)
   float accA[3], accB[3];          // pending partial of vertex A (and scratch for B)
   float4 eA = make_float4(0.f, 0.f, 0.f, 0.f);   // the edge leaving vertex A
   zero3(accA);
@@ -232,11 +249,13 @@ __device__ __forceinline__ void walk(QState* S, const float* __restrict__ bnd, i
       const int j1 = min(le, c1);
       if (j == ls) {
         const float4 v = sv[j - c0];
+        // kept in scalar registers (every lane reads the same vertex) and
+        // seen from the queries again at the closing edge
+        vF = make_float4(__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v.x))),
+                         __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v.y))),
+                         __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v.z))), 0.f);
 #pragma unroll
-        for (int k = 0; k < QPL; ++k) {
-          F[k] = rel(S[k], v);
-          A[k] = F[k];
-        }
+        for (int k = 0; k < QPL; ++k) A[k] = rel(S[k], v);
         eA = sv[kChunk + j - c0];
         zero3(accA);
         ++j;
@@ -245,12 +264,20 @@ __device__ __forceinline__ void walk(QState* S, const float* __restrict__ bnd, i
         const float4 v0 = sv[j - c0];
         const float4 v1 = sv[j + 1 - c0];
         const float4 e0 = sv[kChunk + j - c0];
+        float accC[3];
 #pragma unroll
         for (int k = 0; k < QPL; ++k) B[k] = rel(S[k], v0);
-        step<QPL>(S, A, B, eA, accA, accB, pv, rs, j - 1, nb, lane);
+        zero3(accB);
+#pragma unroll
+        for (int k = 0; k < QPL; ++k) edge_grad(S[k], A[k], B[k], eA, accA, accB);
 #pragma unroll
         for (int k = 0; k < QPL; ++k) A[k] = rel(S[k], v1);
-        step<QPL>(S, B, A, e0, accB, accA, pv, rs, j, nb, lane);
+        zero3(accC);
+#pragma unroll
+        for (int k = 0; k < QPL; ++k) edge_grad(S[k], B[k], A[k], e0, accB, accC);
+        // vertices j - 1 and j are complete
+        if (pv) park2(rs, pv, j - 1, nb, accA, accB, lane);
+        accA[0] = accC[0]; accA[1] = accC[1]; accA[2] = accC[2];
         eA = sv[kChunk + j + 1 - c0];
       }
       if (j < j1) {
@@ -268,7 +295,9 @@ __device__ __forceinline__ void walk(QState* S, const float* __restrict__ bnd, i
       // closing edge last -> first: completes the last vertex; the first
       // vertex's share goes to the per-loop row
       float accF[3];
-      step<QPL>(S, A, F, eA, accA, accF, pv, rs, le - 1, nb, lane);
+#pragma unroll
+      for (int k = 0; k < QPL; ++k) B[k] = rel(S[k], vF);
+      step<QPL>(S, A, B, eA, accA, accF, pv, rs, le - 1, nb, lane);
       if (pl) put3(pl + 3 * (int64_t)l, accF, lane);
       zero3(accA);
     }
