@@ -300,6 +300,29 @@ __global__ __launch_bounds__(kThreads) void k_points(const Piece<T>* __restrict_
 constexpr int kColTile = kGridColTile2D;
 constexpr int kSolveChunk = 1024;   // pieces examined per pass (LDS list of those needing a solve)
 
+constexpr int kMaxOpen = 64;   // open loops whose end points a grid tile stages in LDS
+
+// Histogram slot c lives at word c + c / 32: threads that own consecutive
+// blocks of 8 columns then read and write different banks.
+__host__ __device__ constexpr int hist_at(int c) { return c + (c >> 5); }
+__host__ __device__ constexpr int hist_words(int tile) { return hist_at(tile) + 1; }
+
+template <class T>
+struct alignas(sizeof(T) * 4) EndPts {
+  T sx, sy, ex, ey;
+};
+
+// Inclusive suffix sum over the lanes of a wavefront (lane i gets the sum of
+// lanes i..63).
+__device__ __forceinline__ int wave_suffix_sum(int v) {
+  const int lane = threadIdx.x & 63;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_down(v, o);
+    if (lane + o < 64) v += u;
+  }
+  return v;
+}
+
 // One workgroup per (row, column tile).  Histogram slot c (0..ncol) counts the
 // crossings with exactly c tile columns left of them; columns at or beyond
 // the tile end get every crossing right of the whole tile through `base`.
@@ -311,9 +334,32 @@ template <class T, class LoopsT>
 __device__ void grid_tile(const Piece<T>* __restrict__ pcs, const typename Vec2<T>::type* __restrict__ yr,
                           int32_t npc, const T* __restrict__ ctrl, const LoopsT& L, const T* __restrict__ x,
                           int64_t nx, T yq, int64_t row, int64_t i0, int ncol, T* __restrict__ w,
-                          int32_t* __restrict__ chi, T* sx, int* hist, int* sscan, int* list, int* nlist) {
+                          int32_t* __restrict__ chi, T* sx, int* hist, int* sscan, int* list, int* nlist,
+                          EndPts<T>* sep, int* snopen) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int i = threadIdx.x; i < ncol; i += kThreads) sx[i] = x[i0 + i];
-  for (int i = threadIdx.x; i <= ncol; i += kThreads) hist[i] = 0;
+  for (int i = threadIdx.x; i < hist_words(ncol); i += kThreads) hist[i] = 0;
+  // the open loops' end points, compacted in loop order by the first
+  // wavefront (the same for every query of the row; -1: more than kMaxOpen,
+  // then each query walks the loop table itself)
+  if (wv == 0) {
+    int cnt = 0;
+    for (int l0 = 0; l0 < L.n; l0 += 64) {
+      const int l = l0 + lane;
+      const bool open = l < L.n && !L.closed[l] && L.off[l + 1] > L.off[l];
+      const uint64_t m = __ballot(open);
+      if (open) {
+        const int at = cnt + __popcll(m & ((1ull << lane) - 1ull));
+        if (at < kMaxOpen) {
+          const T* f0 = ctrl + 8 * (int64_t)L.off[l];
+          const T* f1 = ctrl + 8 * (int64_t)(L.off[l + 1] - 1);
+          sep[at] = EndPts<T>{f0[0], f0[1], f1[6], f1[7]};
+        }
+      }
+      cnt += __popcll(m);
+    }
+    if (lane == 0) *snopen = cnt <= kMaxOpen ? cnt : -1;
+  }
   __syncthreads();
   const T xlo = sx[0], xhi = sx[ncol - 1];
   int base = 0;   // crossings right of every column of the tile
@@ -346,45 +392,43 @@ __device__ void grid_tile(const Piece<T>* __restrict__ pcs, const typename Vec2<
         if (sx[mid] < xe) a = mid + 1; else b = mid;
       }
       if (a == ncol) base += sg;
-      else if (a > 0) atomicAdd(&hist[a], sg);
+      else if (a > 0) atomicAdd(&hist[hist_at(a)], sg);
     }
     __syncthreads();
   }
-  // block-wide sum of `base`
-  sscan[threadIdx.x] = base;
-  __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sscan[threadIdx.x] += sscan[threadIdx.x + s];
-    __syncthreads();
-  }
-  const int btot = sscan[0];
-  __syncthreads();
   // chi(col i) = btot + sum_{c > i} hist[c]: suffix sums over [1, ncol),
-  // each thread owning a contiguous block of columns
+  // each thread owning a contiguous block of columns.  Integer sums, so
+  // their order does not matter: wavefront shuffles, then one exchange of
+  // the four wavefronts' totals (and of `base`) through LDS.
   const int per = (ncol + kThreads - 1) / kThreads;
   const int a0 = threadIdx.x * per;
   const int a1 = min(a0 + per, ncol);
   int part = 0;
-  for (int c = a0 + 1; c <= a1 && c < ncol; ++c) part += hist[c];
-  sscan[threadIdx.x] = part;
-  __syncthreads();
-  // exclusive suffix offsets: sum of parts of later threads
-  for (int s = 1; s < kThreads; s <<= 1) {
-    const int v = ((int)threadIdx.x + s < kThreads) ? sscan[threadIdx.x + s] : 0;
-    __syncthreads();
-    sscan[threadIdx.x] += v;
-    __syncthreads();
+  for (int c = a0 + 1; c <= a1 && c < ncol; ++c) part += hist[hist_at(c)];
+  const int suf = wave_suffix_sum(part);              // parts of lanes >= this one in the wavefront
+  const int bw = wave_suffix_sum(base);               // lane 0: the wavefront's base
+  if (lane == 0) {
+    sscan[wv] = suf;
+    sscan[kThreads / 64 + wv] = bw;
   }
-  int run = btot + (((int)threadIdx.x + 1 < kThreads) ? sscan[threadIdx.x + 1] : 0);
+  __syncthreads();
+  int btot = 0, later = 0;
+#pragma unroll
+  for (int k = 0; k < kThreads / 64; ++k) {
+    btot += sscan[kThreads / 64 + k];
+    if (k > wv) later += sscan[k];
+  }
+  int run = btot + (suf - part) + later;
   // walk this thread's columns from the right; chi(i) replaces hist[i + 1],
   // which no thread reads after this point (thread blocks are disjoint and
   // the slot is read just before it is overwritten)
   for (int i = a1 - 1; i >= a0; --i) {
-    if (i + 1 < ncol) run += hist[i + 1];
-    hist[i + 1] = run;
+    if (i + 1 < ncol) run += hist[hist_at(i + 1)];
+    hist[hist_at(i + 1)] = run;
   }
   __syncthreads();
   // coalesced output: consecutive lanes write consecutive columns
+  const int nopen = *snopen;
   for (int i = threadIdx.x; i < ncol; i += kThreads) {
     const int64_t o = row * nx + i0 + i;
     const T px = sx[i];
@@ -393,8 +437,18 @@ __device__ void grid_tile(const Piece<T>* __restrict__ pcs, const typename Vec2<
       if (chi) chi[o] = WN_CHI_INVALID;
       continue;
     }
-    const int c = hist[i + 1];
-    const T e = endpoint_term(ctrl, L, px, yq);
+    const int c = hist[hist_at(i + 1)];
+    T e;
+    if (nopen >= 0) {
+      // endpoint_term's terms in its order
+      e = (T)0;
+      for (int t = 0; t < nopen; ++t) {
+        const EndPts<T> q = sep[t];
+        e += open_loop_angle(q.sx - px, q.sy - yq, q.ex - px, q.ey - yq);
+      }
+    } else {
+      e = endpoint_term(ctrl, L, px, yq);
+    }
     w[o] = finish_w(c, e);
     if (chi) chi[o] = c;
   }
@@ -418,13 +472,15 @@ __global__ __launch_bounds__(kThreads) void k_grid(const Piece<T>* __restrict__ 
   extern __shared__ __align__(16) unsigned char dyn[];
   T* sx = reinterpret_cast<T*>(dyn);
   int* hist = reinterpret_cast<int*>(sx + tile);
-  __shared__ int sscan[kThreads];
+  __shared__ int sscan[2 * (kThreads / 64)];
   __shared__ int list[kSolveChunk];
-  __shared__ int nlist;
+  __shared__ int nlist, nopen;
+  __shared__ EndPts<T> sep[kMaxOpen];
   const int64_t row = blockIdx.y;
   const int64_t i0 = (int64_t)blockIdx.x * tile;
   const int ncol = (int)min((int64_t)tile, nx - i0);
-  grid_tile(pcs, yr, npc, ctrl, L, x, nx, y[row], row, i0, ncol, w, chi, sx, hist, sscan, list, &nlist);
+  grid_tile(pcs, yr, npc, ctrl, L, x, nx, y[row], row, i0, ncol, w, chi, sx, hist, sscan, list, &nlist, sep,
+            &nopen);
 }
 
 // ---------------------------------------------------------------------------
@@ -466,9 +522,10 @@ __global__ __launch_bounds__(kThreads) void k_grid_batched(const Set2D* __restri
                                                            const T* __restrict__ y, T* __restrict__ w,
                                                            int32_t* __restrict__ chi) {
   extern __shared__ __align__(16) unsigned char dyn[];
-  __shared__ int sscan[kThreads];
+  __shared__ int sscan[2 * (kThreads / 64)];
   __shared__ int list[kSolveChunk];
-  __shared__ int nlist;
+  __shared__ int nlist, nopen;
+  __shared__ EndPts<T> sep[kMaxOpen];
   const int64_t item = blockIdx.x;
   const int k = find_set(sets, nsets, item, [](const Set2D& d) { return d.item_off; });
   const Set2D d = sets[k];
@@ -481,7 +538,7 @@ __global__ __launch_bounds__(kThreads) void k_grid_batched(const Set2D* __restri
   const DevLoops2D L{d.nloops, loop_off + d.off_base, loop_closed + d.closed_base};
   grid_tile(pcs + 3 * (int64_t)d.seg_off, yr + 3 * (int64_t)d.seg_off, 3 * d.nseg, ctrl + 8 * (int64_t)d.seg_off,
             L, x + d.x_off, (int64_t)d.nx, y[d.y_off + row], row, i0, ncol, w + d.out_off,
-            chi ? chi + d.out_off : nullptr, sx, hist, sscan, list, &nlist);
+            chi ? chi + d.out_off : nullptr, sx, hist, sscan, list, &nlist, sep, &nopen);
 }
 
 // Sets with at most 64 monotone pieces (21 segments): one wavefront per
@@ -848,7 +905,7 @@ hipError_t run2d(const T* ctrl, int64_t nseg, const Loops2D& L, int32_t kind, co
       // tiles of at most kColTile columns, as even as possible; LDS sized to the tile
       const int64_t ntiles = (nx + kColTile - 1) / kColTile;
       const int tile = (int)((nx + ntiles - 1) / ntiles);
-      const size_t lds = ((size_t)tile * sizeof(T) + (size_t)(tile + 1) * sizeof(int) + 15) & ~(size_t)15;
+      const size_t lds = ((size_t)tile * sizeof(T) + (size_t)hist_words(tile) * sizeof(int) + 15) & ~(size_t)15;
       hipLaunchKernelGGL(k_grid<T>, dim3((unsigned)ntiles, (unsigned)ny), dim3(kThreads), lds, s, pcs, yr,
                          (int32_t)npc, ctrl, L, x, nx, y, ny, w, chi, tile);
     }
@@ -917,7 +974,7 @@ hipError_t batch2d_create(int32_t dtype, const wn_curveset_2d* sets, int32_t nse
   b->items_g = items_g;
   b->items_w = items_w;
   const size_t tsz = dtype == WN_F64 ? sizeof(double) : sizeof(float);
-  b->lds = ((size_t)max_tile * tsz + (size_t)(max_tile + 1) * sizeof(int) + 15) & ~(size_t)15;
+  b->lds = ((size_t)max_tile * tsz + (size_t)hist_words(max_tile) * sizeof(int) + 15) & ~(size_t)15;
   // set of the first item of every wavefront-kernel workgroup
   std::vector<int32_t> bs((size_t)((items_w + kRowWaves - 1) / kRowWaves));
   for (size_t k = 0, blk = 0; blk < bs.size(); ++blk) {

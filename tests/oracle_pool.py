@@ -88,3 +88,29 @@ def shutdown():
         _pool.terminate()
         _pool.join()
         _pool = None
+
+
+def _wn2d_chunk(args):
+    ctrl, loop_off, closed, P = args
+    from oracle import wn2d as O2
+    return dict(O2.wn2d(ctrl, loop_off, closed, P))
+
+
+def wn2d(ctrl, loop_off, closed, P):
+    """oracle.wn2d over the rows of P split across the workers, queries
+    grouped by ordinate so that the points of one ray line stay together
+    (the oracle solves each line's roots once)."""
+    from oracle import wn2d as O2
+    P = np.atleast_2d(np.asarray(P, np.float64))
+    if len(P) < 2 * WORKERS:
+        return O2.wn2d(ctrl, loop_off, closed, P)
+    order = np.argsort(P[:, 1], kind="stable")
+    chunks = [c for c in np.array_split(order, 4 * WORKERS) if len(c)]
+    parts = _start().map(_wn2d_chunk, [(ctrl, loop_off, closed, P[c]) for c in chunks])
+    out = {}
+    for k in parts[0]:
+        v = np.empty(len(P), dtype=np.asarray(parts[0][k]).dtype)
+        for c, part in zip(chunks, parts):
+            v[c] = part[k]
+        out[k] = v
+    return O2.Result2D(**out)

@@ -39,10 +39,13 @@ def _endpoint_dist(C, P):
     return d
 
 
-def _check(C, P, w, chi, tol):
+def _check(C, P, w, chi, tol, label=""):
+    import oracle_pool
     P = np.asarray(P, np.float64)
-    r = O2.wn2d(C.ctrl.astype(np.float64), C.loop_off, C.closed, P)
+    r = oracle_pool.wn2d(C.ctrl.astype(np.float64), C.loop_off, C.closed, P)
     ok = ~r.degenerate
+    print(f"2D parity{(' ' + label) if label else ''}: {len(P)} queries, {int((~ok).sum())} degenerate",
+          flush=True)
     assert ok.mean() > 0.95
     bad = np.nonzero(chi[ok] != r["chi"][ok])[0]
     assert bad.size == 0, f"chi mismatch at {P[ok][bad][:5]}: {chi[ok][bad][:5]} vs {r['chi'][ok][bad][:5]}"
@@ -77,11 +80,28 @@ def c2():
 
 
 def test_c2_full_rows(c2):
+    """32 full rows of the 2048^2 grid (65,536 points, the first and last
+    rows among them) against the oracle."""
     C, xs, w, chi = c2
     assert w.shape == (2048, 2048)
-    for r in (0, 517, 1024, 2047):
-        P = np.stack([xs.astype(np.float64), np.full(2048, float(xs[r]))], 1)
-        _check(C, P, w[r], chi[r], 1e-4)
+    rows = np.unique(np.r_[0, 2047, synth.rng(7).choice(2048, 30, replace=False)])[:32]
+    P = np.concatenate([np.stack([xs.astype(np.float64), np.full(2048, float(xs[r]))], 1) for r in rows])
+    _check(C, P, w[rows].ravel(), chi[rows].ravel(), 1e-4, "C2 rows")
+
+
+def test_c2_points_next_to_crossings(c2):
+    """Every grid point whose crossing count differs from a horizontal
+    neighbour's: the points a curve passes between, the closest the grid
+    gets to the curves."""
+    C, xs, w, chi = c2
+    edge = np.zeros(chi.shape, bool)
+    step = chi[:, 1:] != chi[:, :-1]
+    edge[:, 1:] |= step
+    edge[:, :-1] |= step
+    ii, jj = np.nonzero(edge)
+    assert len(ii) > 10000
+    P = np.stack([xs[jj].astype(np.float64), xs[ii].astype(np.float64)], 1)
+    _check(C, P, w[ii, jj], chi[ii, jj], 1e-4, "C2 next to crossings")
 
 
 def test_c2_random_points_and_points_mode(c2):
