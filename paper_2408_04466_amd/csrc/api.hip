@@ -367,6 +367,7 @@ wn_status wn_build_bvh(const float* V, int64_t nv, const int32_t* F, int64_t nf,
   unsigned* dbb = nullptr;
   Carve tc;
   tc.add(&dbb, 6);
+  tc.add(&b.Vr, (size_t)nv);
   tc.add(&b.box, (size_t)nf);
   tc.add(&b.zmax, (size_t)nf);
   tc.add(&b.cen, (size_t)nf);
@@ -383,20 +384,19 @@ wn_status wn_build_bvh(const float* V, int64_t nv, const int32_t* F, int64_t nf,
   tc.add(&b.ibox, (size_t)nint);
   tc.add(&b.iz, (size_t)nint);
   tc.add(&b.flags, (size_t)nint);
+  tc.add(&b.nodes, (size_t)nint);
   void* tmp = nullptr;
   hipError_t e = tc.alloc(&tmp);
   if (e != hipSuccess) { delete h; return hip_fail(e, "hipMalloc"); }
   Carve pc;
-  pc.add(&h->Vr, (size_t)nv);
   pc.add(&h->tris, (size_t)nf);
   pc.add(&h->nodes, (size_t)nint);
   pc.add(&h->leafbox, (size_t)nf);
   pc.add(&h->leafz, (size_t)nf);
   e = pc.alloc(&h->mem);
   if (e != hipSuccess) { hipFree(tmp); delete h; return hip_fail(e, "hipMalloc"); }
-  b.Vr = h->Vr;
   b.tris = h->tris;
-  b.nodes = h->nodes;
+  b.nodes4 = h->nodes;
   b.leafbox = h->leafbox;
   b.leafz = h->leafz;
 
@@ -476,7 +476,6 @@ static wn::CrossArgs cross_args(const wn_bvh* h, const float* qx, const float* q
   a.F = h->F;
   a.nodes = h->nodes;
   a.tris = h->tris;
-  a.Vr = h->Vr;
   a.leafbox = h->leafbox;
   a.leafz = h->leafz;
   a.nf = h->nf;

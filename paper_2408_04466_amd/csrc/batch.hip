@@ -34,9 +34,8 @@ namespace {
 
 struct SurfDesc {
   Frame F;
-  const BvhNode* nodes;
-  const int4* tris;
-  const RPt* Vr;
+  const BvhNode4* nodes;
+  const TriRec* tris;
   const float4* leafbox;
   const float* leafz;
   int32_t nf;
@@ -149,7 +148,6 @@ __device__ __forceinline__ CrossArgs cross_args(const SurfDesc& D) {
   ca.F = D.F;
   ca.nodes = D.nodes;
   ca.tris = D.tris;
-  ca.Vr = D.Vr;
   ca.leafbox = D.leafbox;
   ca.leafz = D.leafz;
   ca.nf = D.nf;
@@ -188,7 +186,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
       // the start (each workgroup stays uniform, so its barriers still meet)
       int chi = 0, pend = 0;
       if (blockIdx.x & 1) bnd::boundary_walk(s, stage, D.nb, L, sv, staged, pend);
-      if (ok && fin) chi = traverse<kShortStack, true>(ca, s.p[0]);
+      if (ok && fin) chi = traverse<kShortStack>(ca, s.p[0]);
       if (!(blockIdx.x & 1)) bnd::boundary_walk(s, stage, D.nb, L, sv, staged, pend);
       bnd::finish_turns(s, pend);
       if (ok) {
@@ -217,7 +215,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_cross(FwdArgs a) {
       if (isfinite(px) && isfinite(py) && isfinite(pz)) {
         double X, Y, Z;
         rotate(D.F, px, py, pz, X, Y, Z);
-        chi = traverse<kShortStack, true>(ca, make_qp(X, Y, Z));
+        chi = traverse<kShortStack>(ca, make_qp(X, Y, Z));
       }
       a.chi_buf[q] = chi;
     }
@@ -774,7 +772,6 @@ wn_status wn_batch_create(const wn_surface* surfs, int32_t ns, const double dir[
     D.F = h->F;
     D.nodes = h->nodes;
     D.tris = h->tris;
-    D.Vr = h->Vr;
     D.leafbox = h->leafbox;
     D.leafz = h->leafz;
     D.nf = h->nf;

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(256) void k_cross3d(CrossArgs a) {
   }
   double Xp, Yp, Zp;
   rotate(a.F, px, py, pz, Xp, Yp, Zp);
-  a.chi[q] = traverse<S, true>(a, make_qp(Xp, Yp, Zp));
+  a.chi[q] = traverse<S>(a, make_qp(Xp, Yp, Zp));
 }
 
 hipError_t launch_cross3d(const CrossArgs& a, hipStream_t s) {
@@ -192,21 +192,30 @@ __global__ void k_karras(const unsigned* __restrict__ keys, int32_t n, int32_t* 
   if (i == 0) parent_int[0] = -1;
 }
 
-// Sorted triangle records and leaf boxes in sorted order.  Vertex indices
-// are below 2^31, so bit 31 of each is free: it holds the lexicographic order
-// of the edge leaving that vertex (v0->v1, v1->v2, v2->v0), i.e. the sign of
-// the edge's tie offset, which is then not recomputed per crossing test.
+// Sorted triangle records and leaf boxes in sorted order.  Each record
+// carries its three vertices and the lexicographic order of each edge's end
+// points (the sign of the edge's tie offset), so that a crossing test reads
+// one line and recomputes no comparison.
 __global__ void k_gather_leaves(const int32_t* __restrict__ Fc, const int32_t* __restrict__ order,
                                 int32_t nf, const float4* __restrict__ box,
                                 const float* __restrict__ zmax, const RPt* __restrict__ Vr,
-                                int4* __restrict__ tris, float4* __restrict__ lbox, float* __restrict__ lz) {
+                                TriRec* __restrict__ tris, float4* __restrict__ lbox, float* __restrict__ lz) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nf) return;
   int f = order[i];
   if (f < 0 || f >= nf) f = 0;   // never taken for a permutation
-  const int32_t i0 = Fc[3 * f], i1 = Fc[3 * f + 1], i2 = Fc[3 * f + 2];
-  const RPt A = Vr[i0], B = Vr[i1], C = Vr[i2];
-  tris[i] = make_int4(tri_index(i0, rpt_less(A, B)), tri_index(i1, rpt_less(B, C)), tri_index(i2, rpt_less(C, A)), f);
+  const RPt A = Vr[Fc[3 * f]], B = Vr[Fc[3 * f + 1]], C = Vr[Fc[3 * f + 2]];
+  TriRec r;
+  r.xy[0] = A.xy;
+  r.xy[1] = B.xy;
+  r.xy[2] = C.xy;
+  r.ties = (rpt_less(A, B) ? 1u : 0u) | (rpt_less(B, C) ? 2u : 0u) | (rpt_less(C, A) ? 4u : 0u);
+  r.face = f;
+  r.pad0[0] = r.pad0[1] = 0u;
+  r.zab = make_float4(A.zt.x, A.zt.y, B.zt.x, B.zt.y);
+  r.zc = make_float2(C.zt.x, C.zt.y);
+  for (int k = 0; k < 10; ++k) r.pad1[k] = 0u;
+  tris[i] = r;
   lbox[i] = box[f];
   lz[i] = zmax[f];
 }
@@ -294,6 +303,117 @@ __global__ void k_refit_level(int32_t nf, int32_t level, const int32_t* __restri
   iz[node] = fmaxf(zl, zr);
 }
 
+// ---------------------------------------------------------------------------
+// Four-wide tree
+// ---------------------------------------------------------------------------
+
+// One child slot of a four-wide node before quantisation.
+struct Slot4 {
+  float4 box;
+  float z;
+  int32_t ref;
+};
+
+// Smallest power-of-two step s (as a biased exponent) with
+// fma(255, s, lo) >= hi in float32: the grid of 256 codes from lo covers hi.
+__device__ __forceinline__ uint32_t grid_exponent(float lo, float hi) {
+  const double r = ((double)hi - (double)lo) / 255.0;
+  int e = -126;
+  if (r > 0.0) {
+    int k;
+    frexp(r, &k);            // r < 2^k
+    e = max(k - 1, -126);    // start one below, the loop settles it
+  }
+  while (e < 127 && __fmaf_rn(255.0f, __uint_as_float((uint32_t)(e + 127) << 23), lo) < hi) ++e;
+  return (uint32_t)(e + 127);
+}
+
+__device__ __forceinline__ float grid_value(uint32_t code, float step, float origin) {
+  return __fmaf_rn((float)code, step, origin);
+}
+
+// Largest code whose decoded value is not above v (v >= origin).
+__device__ __forceinline__ uint32_t code_down(float v, float step, float origin) {
+  double q = floor(((double)v - (double)origin) / (double)step);
+  uint32_t c = (uint32_t)fmin(fmax(q, 0.0), 255.0);
+  while (c > 0 && grid_value(c, step, origin) > v) --c;
+  return c;
+}
+
+// Smallest code whose decoded value is not below v (v <= the grid's top).
+__device__ __forceinline__ uint32_t code_up(float v, float step, float origin) {
+  double q = ceil(((double)v - (double)origin) / (double)step);
+  uint32_t c = (uint32_t)fmin(fmax(q, 0.0), 255.0);
+  while (c < 255 && grid_value(c, step, origin) < v) ++c;
+  return c;
+}
+
+// Four-wide node for every binary node at even depth: its children, with an
+// internal child replaced by that child's two children.  A slot whose box
+// can hold no point (a NaN or an empty range, as in unwritten nodes of a
+// malformed tree) stays unoccupied, as the binary test never enters it.
+__global__ void k_collapse4(int32_t nf, const int32_t* __restrict__ dep, const BvhNode* __restrict__ nodes,
+                            BvhNode4* __restrict__ out) {
+  const int node = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t nint = nf - 1;
+  if (node >= nint || (dep[node] & 1)) return;
+  const BvhNode nd = nodes[node];
+  Slot4 sl[4];
+  int n = 0;
+  const int32_t cref[2] = {nd.left, nd.right};
+  const float4 cbox[2] = {nd.lbox, nd.rbox};
+  const float cz[2] = {nd.lzmax, nd.rzmax};
+  for (int k = 0; k < 2; ++k) {
+    const int32_t c = cref[k];
+    if (c < 0 || c >= nint) {
+      // a leaf, or an index out of range that the traversal reports
+      sl[n++] = Slot4{cbox[k], cz[k], c};
+    } else {
+      const BvhNode cn = nodes[c];
+      sl[n++] = Slot4{cn.lbox, cn.lzmax, cn.left};
+      sl[n++] = Slot4{cn.rbox, cn.rzmax, cn.right};
+    }
+  }
+  unsigned mask = 0;
+  float x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY, z0 = INFINITY, z1 = -INFINITY;
+  for (int k = 0; k < n; ++k) {
+    const float4 b = sl[k].box;
+    if (!(b.x <= b.y && b.z <= b.w && sl[k].z == sl[k].z)) continue;
+    mask |= 1u << k;
+    x0 = fminf(x0, b.x);
+    x1 = fmaxf(x1, b.y);
+    y0 = fminf(y0, b.z);
+    y1 = fmaxf(y1, b.w);
+    z0 = fminf(z0, sl[k].z);
+    z1 = fmaxf(z1, sl[k].z);
+  }
+  BvhNode4 q;
+  for (int k = 0; k < 3; ++k) q.pad[k] = 0u;
+  for (int k = 0; k < 4; ++k) q.child[k] = k < n ? sl[k].ref : -1;
+  q.xlo = q.xhi = q.ylo = q.yhi = q.zhi = 0u;
+  if (mask == 0) {
+    q.ox = q.oy = q.oz = 0.0f;
+    q.meta = 127u | (127u << 8) | (127u << 16);
+  } else {
+    const uint32_t ex = grid_exponent(x0, x1), ey = grid_exponent(y0, y1), ez = grid_exponent(z0, z1);
+    const float sx = __uint_as_float(ex << 23), sy = __uint_as_float(ey << 23), sz = __uint_as_float(ez << 23);
+    q.ox = x0;
+    q.oy = y0;
+    q.oz = z0;
+    q.meta = ex | (ey << 8) | (ez << 16) | (mask << 24);
+    for (int k = 0; k < n; ++k) {
+      if (!((mask >> k) & 1u)) continue;
+      const float4 b = sl[k].box;
+      q.xlo |= code_down(b.x, sx, x0) << (8 * k);
+      q.xhi |= code_up(b.y, sx, x0) << (8 * k);
+      q.ylo |= code_down(b.z, sy, y0) << (8 * k);
+      q.yhi |= code_up(b.w, sy, y0) << (8 * k);
+      q.zhi |= code_up(sl[k].z, sz, z0) << (8 * k);
+    }
+  }
+  out[node] = q;
+}
+
 __global__ void k_fill_u32(unsigned* p, int64_t n, unsigned v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -368,7 +488,9 @@ hipError_t build_bvh_device(const BuildBufs& b, const Frame& F, const float* V, 
                        b.leafz, b.ibox, b.iz, b.nodes);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  return hipSuccess;
+  if ((e = fill_u32((unsigned*)b.nodes4, (int64_t)ni * (sizeof(BvhNode4) / 4), 0xffffffffu, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_collapse4, dim3(bi), dim3(256), 0, s, nf, dep[cur], b.nodes, b.nodes4);
+  return hipGetLastError();
 }
 
 }  // namespace wn

@@ -21,7 +21,7 @@ struct BuildBufs {
   unsigned* keys2;      // [nf]
   int32_t* vals2;       // [nf]
   void* sort_tmp;       // radix_sort_tmp_bytes(nf)
-  int4* tris;           // [nf] sorted triangles
+  TriRec* tris;         // [nf] sorted triangle records
   float4* leafbox;      // [nf]
   float* leafz;         // [nf]
   int32_t* left;        // [nf-1]
@@ -31,7 +31,8 @@ struct BuildBufs {
   float4* ibox;         // [nf-1] node bounds
   float* iz;            // [nf-1]
   int32_t* flags;       // [nf-1]
-  BvhNode* nodes;       // [nf-1]
+  BvhNode* nodes;       // [nf-1] binary tree
+  BvhNode4* nodes4;     // [nf-1] four-wide tree (written at even depths)
 };
 
 size_t radix_sort_tmp_bytes(int64_t n);

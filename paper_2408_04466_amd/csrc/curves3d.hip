@@ -21,7 +21,7 @@ __global__ __launch_bounds__(kCThreads) void k_curves3d(CrossArgs ca, Frame F, c
   rotate(F, px, py, pz, Xp, Yp, Zp);
   int chi;
   if (chi_in) chi = chi_in[q];
-  else chi = (ok && fin) ? traverse<kShortStack, true>(ca, make_qp(Xp, Yp, Zp)) : WN_CHI_INVALID;
+  else chi = (ok && fin) ? traverse<kShortStack>(ca, make_qp(Xp, Yp, Zp)) : WN_CHI_INVALID;
   double theta = 0.0;
   for (int c0 = 0; c0 < nc; c0 += kCurveChunk) {
     const int cnt = min(kCurveChunk, nc - c0);

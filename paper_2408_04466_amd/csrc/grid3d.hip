@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
     int32_t* hits = s_hits[threadIdx.x / 64];
     int m = 0;
     const int st = traverse_leaves<kShortStack>(c, pu.xh, pu.yh, zmin, [&](int t) {
-      if (tri_on_line<false>(c.tris[t], c.Vr, pu)) {
+      if (tri_on_line(c.tris, t, pu)) {
         if (m < kColHits) hits[m] = t;
         ++m;
       }
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
     if (n <= kColHits) {
       const int32_t* hits = s_hits[threadIdx.x / 64];
       chi = 0;
-      for (int k = 0; k < n; ++k) chi += tri_crossing<false>(c.tris[hits[k]], c.Vr, s.p[0]);
+      for (int k = 0; k < n; ++k) chi += tri_crossing(c.tris, hits[k], s.p[0]);
     } else {
       chi = traverse<kShortStack>(c, s.p[0]);
     }

@@ -66,9 +66,8 @@ struct wn_bvh {
   wn::Frame F;
   double dir[3];
   int32_t nv = 0, nf = 0;
-  wn::RPt* Vr = nullptr;
-  int4* tris = nullptr;
-  wn::BvhNode* nodes = nullptr;
+  wn::TriRec* tris = nullptr;
+  wn::BvhNode4* nodes = nullptr;   // four-wide tree, indexed like the binary one
   float4* leafbox = nullptr;
   float* leafz = nullptr;
   void* mem = nullptr;   // the one allocation holding the arrays above

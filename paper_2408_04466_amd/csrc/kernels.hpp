@@ -16,9 +16,9 @@ struct LoopTable {
   int32_t off[WN_MAX_LOOPS + 1];
 };
 
-// Binary BVH node: the boxes of both children (projected x/y range and the
-// largest coordinate along d) and the children (>= 0 internal node index,
-// < 0 leaf ~index into the sorted triangle array).  48 bytes.
+// Binary BVH node of the build: the boxes of both children (projected x/y
+// range and the largest coordinate along d) and the children (>= 0 internal
+// node index, < 0 leaf ~index into the sorted triangle array).  48 bytes.
 struct alignas(16) BvhNode {
   float4 lbox;   // xmin, xmax, ymin, ymax of the left child
   float4 rbox;   // same for the right child
@@ -26,11 +26,47 @@ struct alignas(16) BvhNode {
   int32_t left, right;
 };
 
+// Four-wide BVH node, the tree that the traversals walk: the binary tree
+// with every second level folded into its parent, so that a node holds up to
+// four children (its binary children, or theirs where a binary child is
+// internal) and a query needs half the dependent node loads.  The children's
+// boxes are 8-bit codes on a grid of the node: bound = fma(code, 2^e, origin)
+// with a power-of-two step per axis, each code rounded outward at build time
+// with that same float32 arithmetic, so that every decoded box contains the
+// child's float box.  64 bytes, one aligned half cache line.  Nodes keep the
+// index of their binary node (the array is sparse: only binary nodes at even
+// depth are written).
+struct alignas(64) BvhNode4 {
+  float ox, oy, oz;       // grid origin: smallest xmin, ymin and zmax of the children
+  uint32_t meta;          // biased exponents of the x, y, z steps (bits 0-23), occupied slots (bits 24-27)
+  uint32_t xlo, xhi;      // byte k: child k's code of xmin (rounded down), xmax (rounded up)
+  uint32_t ylo, yhi;
+  uint32_t zhi;           // byte k: child k's code of zmax (rounded up)
+  int32_t child[4];       // >= 0 node index, < 0 leaf ~index into the sorted triangles
+  uint32_t pad[3];
+};
+static_assert(sizeof(BvhNode4) == 64, "four-wide node is 64 bytes");
+
+// Sorted triangle of the traversal, one aligned 128-byte line: the three
+// rotated vertices as float32 (hi, lo) pairs.  The first half holds what the
+// projected inside test reads for every triangle the traversal reaches (x
+// and y, the edges' tie signs); the second half the heights, read only when
+// the line passes through the triangle.
+struct alignas(128) TriRec {
+  float4 xy[3];           // vertex k: xh, xl, yh, yl
+  uint32_t ties;          // bit e set: edge e (v0v1, v1v2, v2v0) starts at the lexicographically smaller vertex
+  int32_t face;           // index of the triangle in the input
+  uint32_t pad0[2];
+  float4 zab;             // zh, zl of v0 and v1
+  float2 zc;              // zh, zl of v2
+  uint32_t pad1[10];
+};
+static_assert(sizeof(TriRec) == 128, "triangle record is one 128-byte line");
+
 struct CrossArgs {
   Frame F;
-  const BvhNode* nodes;
-  const int4* tris;        // sorted triangles: v0, v1, v2 (tie bits in bit 31), original face id
-  const RPt* Vr;           // rotated vertices, split into float32 pairs
+  const BvhNode4* nodes;
+  const TriRec* tris;      // sorted triangles
   const float4* leafbox;   // used when the tree is a single leaf
   const float* leafz;
   int32_t nf;

@@ -10,35 +10,21 @@ namespace wn {
 // Triangle test (shared predicates with the boundary kernel)
 // ---------------------------------------------------------------------------
 
-// A vertex index (below 2^31) with the lexicographic order of the edge that
-// leaves it in bit 31, as the sorted triangle records store it.
-__device__ __forceinline__ int32_t tri_index(int32_t v, bool a_less_b) {
-  return a_less_b ? (int32_t)((uint32_t)v | 0x80000000u) : v;
-}
-
-// The three edge values of a triangle for a query, each with its tie offset
-// (t holds the vertex indices with the edges' lexicographic order in bit 31,
-// tri_index).
+// The three edge values of a triangle for a query, each with its tie offset.
 struct TriEdges {
   double n01, n12, n20;
 };
 
-template <bool STORED_TIES>
-__device__ __forceinline__ TriEdges tri_edges(const int4 t, const RPt& A, const RPt& B, const RPt& C, const QP& p) {
-  // the three tie bits in one register, so that the indices die at once
-  const uint32_t tb = ((uint32_t)t.x >> 31) | (((uint32_t)t.y >> 30) & 2u) | (((uint32_t)t.z >> 29) & 4u);
-  const float ax = vertex_x(A, p), ay = vertex_y(A, p);
-  const float bx = vertex_x(B, p), by = vertex_y(B, p);
-  const float cx = vertex_x(C, p), cy = vertex_y(C, p);
-  // the stored bits, or the same comparisons redone (fewer live registers
-  // where the register budget is tight)
-  const bool l01 = STORED_TIES ? (tb & 1u) != 0 : rpt_less(A, B);
-  const bool l12 = STORED_TIES ? (tb & 2u) != 0 : rpt_less(B, C);
-  const bool l20 = STORED_TIES ? (tb & 4u) != 0 : rpt_less(C, A);
+__device__ __forceinline__ TriEdges tri_edges(const TriRec* __restrict__ r, const QP& p) {
+  const float4 A = r->xy[0], B = r->xy[1], C = r->xy[2];
+  const uint32_t tb = r->ties;
+  const float ax = rel32(A.x, A.y, p.xh, p.xl), ay = rel32(A.z, A.w, p.yh, p.yl);
+  const float bx = rel32(B.x, B.y, p.xh, p.xl), by = rel32(B.z, B.w, p.yh, p.yl);
+  const float cx = rel32(C.x, C.y, p.xh, p.xl), cy = rel32(C.z, C.w, p.yh, p.yl);
   TriEdges e;
-  e.n01 = edge_tie(edge_n(ax, ay, bx, by), tie_offset(l01));
-  e.n12 = edge_tie(edge_n(bx, by, cx, cy), tie_offset(l12));
-  e.n20 = edge_tie(edge_n(cx, cy, ax, ay), tie_offset(l20));
+  e.n01 = edge_tie(edge_n(ax, ay, bx, by), tie_offset((tb & 1u) != 0u));
+  e.n12 = edge_tie(edge_n(bx, by, cx, cy), tie_offset((tb & 2u) != 0u));
+  e.n20 = edge_tie(edge_n(cx, cy, ax, ay), tie_offset((tb & 4u) != 0u));
   return e;
 }
 
@@ -50,33 +36,30 @@ __device__ __forceinline__ bool tri_inside(const TriEdges& e) {
   return s01 == s12 && s12 == s20;
 }
 
-// +1 / -1 when the ray p + t d (t > 0) passes through the triangle's
-// interior along / against its normal (v1-v0)x(v2-v0), 0 otherwise.
-template <bool STORED_TIES>
-__device__ __forceinline__ int tri_crossing(const int4 t, const RPt* __restrict__ Vr, const QP& p) {
-  const RPt A = Vr[t.x & 0x7fffffff];
-  const RPt B = Vr[t.y & 0x7fffffff];
-  const RPt C = Vr[t.z & 0x7fffffff];
-  const TriEdges e = tri_edges<STORED_TIES>(t, A, B, C, p);
+// +1 / -1 when the ray p + t d (t > 0) passes through the interior of sorted
+// triangle t along / against its normal (v1-v0)x(v2-v0), 0 otherwise.
+__device__ __forceinline__ int tri_crossing(const TriRec* __restrict__ recs, int32_t t, const QP& p) {
+  const TriRec* r = recs + t;
+  const TriEdges e = tri_edges(r, p);
   if (!tri_inside(e)) return 0;
   const bool s01 = e.n01 < 0.0;
   // Height of the crossing above p: the barycentric weights are the edge
   // values opposite each vertex, so the crossing is above p iff
   // sum(N_opp * Z) has the sign of the N's.
-  const double za = (double)vertex_z(A, p), zb = (double)vertex_z(B, p), zc = (double)vertex_z(C, p);
+  const float4 zab = r->zab;
+  const float2 zc2 = r->zc;
+  const double za = (double)rel32(zab.x, zab.y, p.zh, p.zl);
+  const double zb = (double)rel32(zab.z, zab.w, p.zh, p.zl);
+  const double zc = (double)rel32(zc2.x, zc2.y, p.zh, p.zl);
   const double num = __fma_rn(e.n12, za, __fma_rn(e.n20, zb, __dmul_rn(e.n01, zc)));
   const bool hit = s01 ? (num < 0.0) : (num > 0.0);
   return hit ? (s01 ? 1 : -1) : 0;
 }
 
-// The line through p along d (both directions) passes through the
-// triangle's interior.
-template <bool STORED_TIES>
-__device__ __forceinline__ bool tri_on_line(const int4 t, const RPt* __restrict__ Vr, const QP& p) {
-  const RPt A = Vr[t.x & 0x7fffffff];
-  const RPt B = Vr[t.y & 0x7fffffff];
-  const RPt C = Vr[t.z & 0x7fffffff];
-  return tri_inside(tri_edges<STORED_TIES>(t, A, B, C, p));
+// The line through p along d (both directions) passes through the interior
+// of sorted triangle t.
+__device__ __forceinline__ bool tri_on_line(const TriRec* __restrict__ recs, int32_t t, const QP& p) {
+  return tri_inside(tri_edges(recs + t, p));
 }
 
 // ---------------------------------------------------------------------------
@@ -85,10 +68,11 @@ __device__ __forceinline__ bool tri_on_line(const int4 t, const RPt* __restrict_
 
 // Traversal stack: the top S entries live in registers (push and pop shift
 // them, plain moves, no indexed addressing); deeper entries spill to a
-// separate private array that only overflowing traversals touch.  The LBVH's
-// depth is below 64 (its split keys are 64-bit), which bounds the number of
-// pending siblings.
-constexpr int kSpill = 64;
+// separate private array that only overflowing traversals touch.  A node
+// leaves at most three siblings pending beside the child walked next, and
+// the four-wide tree over a binary LBVH of depth <= 64 (its split keys are
+// 64-bit) has at most 33 levels, which bounds the number of pending entries.
+constexpr int kSpill = 3 * 33;
 
 template <int S>
 struct RegStack {
@@ -120,11 +104,23 @@ __device__ __forceinline__ bool in_box(const float4 b, float bz, float x, float 
   return (x >= b.x) & (x <= b.y) & (y >= b.z) & (y <= b.w) & (z <= bz);
 }
 
+// Decoded bound of child k from a word of four codes (the same float32
+// operation as the build's rounding of the codes).
+__device__ __forceinline__ float grid_bound(uint32_t codes, int k, float step, float origin) {
+  return __fmaf_rn((float)((codes >> (8 * k)) & 0xffu), step, origin);
+}
+
+__device__ __forceinline__ int32_t child_ref(const BvhNode4& nd, int k) {
+  return k == 0 ? nd.child[0] : k == 1 ? nd.child[1] : k == 2 ? nd.child[2] : nd.child[3];
+}
+
 // Walk the tree for the vertical half line above (x, y, z) in the frame of
-// d and call leaf(t) for every sorted triangle t whose padded box contains
-// (x, y) with zmax >= z.  z = -inf visits every triangle whose projection box
-// contains (x, y), whatever its height (the column pass of the grid mode).
-// Returns 0, or WN_CHI_INVALID if the tree is malformed.
+// d and call leaf(t) for every sorted triangle t whose padded box, widened to
+// its node's grid, contains (x, y) with zmax >= z.  z = -inf visits every
+// triangle whose box contains (x, y), whatever its height (the column pass
+// of the grid mode).  The widening only adds triangles whose exact test
+// then finds no crossing.  Returns 0, or WN_CHI_INVALID if the tree is
+// malformed.
 template <int S, class Leaf>
 __device__ __forceinline__ int traverse_leaves(const CrossArgs& a, float x, float y, float z, Leaf&& leaf) {
   if (a.nf == 0) return 0;
@@ -140,26 +136,34 @@ __device__ __forceinline__ int traverse_leaves(const CrossArgs& a, float x, floa
   // a valid tree visits each node at most once per query
   for (int32_t it = 0;; ++it) {
     if (it > nint || (uint32_t)node >= (uint32_t)nint) return WN_CHI_INVALID;
-    const BvhNode nd = a.nodes[node];
-    bool hl = in_box(nd.lbox, nd.lzmax, x, y, z);
-    bool hr = in_box(nd.rbox, nd.rzmax, x, y, z);
-    if (hl && nd.left < 0) {
-      if (~nd.left >= a.nf) return WN_CHI_INVALID;
-      leaf(~nd.left);
-      hl = false;
+    const BvhNode4 nd = a.nodes[node];
+    const float sx = __uint_as_float((nd.meta & 0xffu) << 23);
+    const float sy = __uint_as_float(((nd.meta >> 8) & 0xffu) << 23);
+    const float sz = __uint_as_float(((nd.meta >> 16) & 0xffu) << 23);
+    uint32_t lm = 0, im = 0;   // hit leaves, hit nodes
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const bool h = (x >= grid_bound(nd.xlo, k, sx, nd.ox)) & (x <= grid_bound(nd.xhi, k, sx, nd.ox)) &
+                     (y >= grid_bound(nd.ylo, k, sy, nd.oy)) & (y <= grid_bound(nd.yhi, k, sy, nd.oy)) &
+                     (z <= grid_bound(nd.zhi, k, sz, nd.oz)) & (((nd.meta >> (24 + k)) & 1u) != 0u);
+      if (h) {
+        if (nd.child[k] < 0) lm |= 1u << k;
+        else im |= 1u << k;
+      }
     }
-    if (hr && nd.right < 0) {
-      if (~nd.right >= a.nf) return WN_CHI_INVALID;
-      leaf(~nd.right);
-      hr = false;
+    while (lm) {
+      const int32_t c = child_ref(nd, __builtin_ctz(lm));
+      lm &= lm - 1u;
+      if (~c >= a.nf) return WN_CHI_INVALID;
+      leaf(~c);
     }
-    if (hl && hr) {
-      if (!st.push(nd.right, spill)) return WN_CHI_INVALID;
-      node = nd.left;
-    } else if (hl) {
-      node = nd.left;
-    } else if (hr) {
-      node = nd.right;
+    if (im) {
+      node = child_ref(nd, __builtin_ctz(im));
+      im &= im - 1u;
+      while (im) {
+        if (!st.push(child_ref(nd, __builtin_ctz(im)), spill)) return WN_CHI_INVALID;
+        im &= im - 1u;
+      }
     } else {
       if (st.n == 0) break;
       node = st.pop(spill);
@@ -169,11 +173,11 @@ __device__ __forceinline__ int traverse_leaves(const CrossArgs& a, float x, floa
 }
 
 // chi for one query (WN_CHI_INVALID if the tree is malformed).
-template <int S, bool STORED_TIES = false>
+template <int S>
 __device__ int traverse(const CrossArgs& a, const QP& p) {
   int chi = 0;
   const int st = traverse_leaves<S>(a, p.xh, p.yh, p.zh, [&](int t) {
-    chi += tri_crossing<STORED_TIES>(a.tris[t], a.Vr, p);
+    chi += tri_crossing(a.tris, t, p);
   });
   return st ? st : chi;
 }
