@@ -209,12 +209,12 @@ __global__ void k_gather_leaves(const int32_t* __restrict__ Fc, const int32_t* _
   r.xy[0] = A.xy;
   r.xy[1] = B.xy;
   r.xy[2] = C.xy;
+  r.zch = C.zt.x;
+  r.zcl = C.zt.y;
   r.ties = (rpt_less(A, B) ? 1u : 0u) | (rpt_less(B, C) ? 2u : 0u) | (rpt_less(C, A) ? 4u : 0u);
   r.face = f;
-  r.pad0[0] = r.pad0[1] = 0u;
   r.zab = make_float4(A.zt.x, A.zt.y, B.zt.x, B.zt.y);
-  r.zc = make_float2(C.zt.x, C.zt.y);
-  for (int k = 0; k < 10; ++k) r.pad1[k] = 0u;
+  for (int k = 0; k < 12; ++k) r.pad[k] = 0u;
   tris[i] = r;
   lbox[i] = box[f];
   lz[i] = zmax[f];
@@ -353,7 +353,7 @@ __device__ __forceinline__ uint32_t code_up(float v, float step, float origin) {
 // can hold no point (a NaN or an empty range, as in unwritten nodes of a
 // malformed tree) stays unoccupied, as the binary test never enters it.
 __global__ void k_collapse4(int32_t nf, const int32_t* __restrict__ dep, const BvhNode* __restrict__ nodes,
-                            BvhNode4* __restrict__ out) {
+                            const TriRec* __restrict__ tris, BvhNode4* __restrict__ out) {
   const int node = blockIdx.x * blockDim.x + threadIdx.x;
   const int32_t nint = nf - 1;
   if (node >= nint || (dep[node] & 1)) return;
@@ -388,8 +388,12 @@ __global__ void k_collapse4(int32_t nf, const int32_t* __restrict__ dep, const B
     z1 = fmaxf(z1, sl[k].z);
   }
   BvhNode4 q;
-  for (int k = 0; k < 3; ++k) q.pad[k] = 0u;
-  for (int k = 0; k < 4; ++k) q.child[k] = k < n ? sl[k].ref : -1;
+  q.pad[0] = q.pad[1] = 0u;
+  q.ties = 0u;
+  for (int k = 0; k < 4; ++k) {
+    q.child[k] = k < n ? sl[k].ref : -1;
+    if (k < n && sl[k].ref < 0 && ~sl[k].ref < nf) q.ties |= (tris[~sl[k].ref].ties & 7u) << (3 * k);
+  }
   q.xlo = q.xhi = q.ylo = q.yhi = q.zhi = 0u;
   if (mask == 0) {
     q.ox = q.oy = q.oz = 0.0f;
@@ -489,7 +493,7 @@ hipError_t build_bvh_device(const BuildBufs& b, const Frame& F, const float* V, 
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if ((e = fill_u32((unsigned*)b.nodes4, (int64_t)ni * (sizeof(BvhNode4) / 4), 0xffffffffu, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_collapse4, dim3(bi), dim3(256), 0, s, nf, dep[cur], b.nodes, b.nodes4);
+  hipLaunchKernelGGL(k_collapse4, dim3(bi), dim3(256), 0, s, nf, dep[cur], b.nodes, b.tris, b.nodes4);
   return hipGetLastError();
 }
 

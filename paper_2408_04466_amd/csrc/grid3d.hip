@@ -75,8 +75,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
     zmin = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(zmin)));
     int32_t* hits = s_hits[threadIdx.x / 64];
     int m = 0;
-    const int st = traverse_leaves<kShortStack>(c, pu.xh, pu.yh, zmin, [&](int t) {
-      if (tri_on_line(c.tris, t, pu)) {
+    const int st = traverse_leaves<kShortStack>(c, pu.xh, pu.yh, zmin, [&](int t, uint32_t ties) {
+      if (tri_on_line(c.tris, t, ties, pu)) {
         if (m < kColHits) hits[m] = t;
         ++m;
       }

@@ -43,23 +43,23 @@ struct alignas(64) BvhNode4 {
   uint32_t ylo, yhi;
   uint32_t zhi;           // byte k: child k's code of zmax (rounded up)
   int32_t child[4];       // >= 0 node index, < 0 leaf ~index into the sorted triangles
-  uint32_t pad[3];
+  uint32_t ties;          // bits 3k..3k+2: the edge tie signs of leaf child k (TriRec::ties)
+  uint32_t pad[2];
 };
 static_assert(sizeof(BvhNode4) == 64, "four-wide node is 64 bytes");
 
 // Sorted triangle of the traversal, one aligned 128-byte line: the three
-// rotated vertices as float32 (hi, lo) pairs.  The first half holds what the
-// projected inside test reads for every triangle the traversal reaches (x
-// and y, the edges' tie signs); the second half the heights, read only when
-// the line passes through the triangle.
+// rotated vertices as float32 (hi, lo) pairs.  The first three words hold
+// what the projected inside test reads for every triangle the traversal
+// reaches (x and y; the tree's nodes carry the edges' tie signs too); the
+// heights follow, read only when the line passes through the triangle.
 struct alignas(128) TriRec {
   float4 xy[3];           // vertex k: xh, xl, yh, yl
+  float zch, zcl;         // zh, zl of v2
   uint32_t ties;          // bit e set: edge e (v0v1, v1v2, v2v0) starts at the lexicographically smaller vertex
   int32_t face;           // index of the triangle in the input
-  uint32_t pad0[2];
   float4 zab;             // zh, zl of v0 and v1
-  float2 zc;              // zh, zl of v2
-  uint32_t pad1[10];
+  uint32_t pad[12];
 };
 static_assert(sizeof(TriRec) == 128, "triangle record is one 128-byte line");
 

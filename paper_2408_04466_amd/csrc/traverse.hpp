@@ -15,9 +15,8 @@ struct TriEdges {
   double n01, n12, n20;
 };
 
-__device__ __forceinline__ TriEdges tri_edges(const TriRec* __restrict__ r, const QP& p) {
+__device__ __forceinline__ TriEdges tri_edges(const TriRec* __restrict__ r, uint32_t tb, const QP& p) {
   const float4 A = r->xy[0], B = r->xy[1], C = r->xy[2];
-  const uint32_t tb = r->ties;
   const float ax = rel32(A.x, A.y, p.xh, p.xl), ay = rel32(A.z, A.w, p.yh, p.yl);
   const float bx = rel32(B.x, B.y, p.xh, p.xl), by = rel32(B.z, B.w, p.yh, p.yl);
   const float cx = rel32(C.x, C.y, p.xh, p.xl), cy = rel32(C.z, C.w, p.yh, p.yl);
@@ -37,29 +36,34 @@ __device__ __forceinline__ bool tri_inside(const TriEdges& e) {
 }
 
 // +1 / -1 when the ray p + t d (t > 0) passes through the interior of sorted
-// triangle t along / against its normal (v1-v0)x(v2-v0), 0 otherwise.
-__device__ __forceinline__ int tri_crossing(const TriRec* __restrict__ recs, int32_t t, const QP& p) {
+// triangle t along / against its normal (v1-v0)x(v2-v0), 0 otherwise (ties:
+// the record's tie signs, as its tree node holds them).
+__device__ __forceinline__ int tri_crossing(const TriRec* __restrict__ recs, int32_t t, uint32_t ties, const QP& p) {
   const TriRec* r = recs + t;
-  const TriEdges e = tri_edges(r, p);
+  const TriEdges e = tri_edges(r, ties, p);
   if (!tri_inside(e)) return 0;
   const bool s01 = e.n01 < 0.0;
   // Height of the crossing above p: the barycentric weights are the edge
   // values opposite each vertex, so the crossing is above p iff
   // sum(N_opp * Z) has the sign of the N's.
   const float4 zab = r->zab;
-  const float2 zc2 = r->zc;
   const double za = (double)rel32(zab.x, zab.y, p.zh, p.zl);
   const double zb = (double)rel32(zab.z, zab.w, p.zh, p.zl);
-  const double zc = (double)rel32(zc2.x, zc2.y, p.zh, p.zl);
+  const double zc = (double)rel32(r->zch, r->zcl, p.zh, p.zl);
   const double num = __fma_rn(e.n12, za, __fma_rn(e.n20, zb, __dmul_rn(e.n01, zc)));
   const bool hit = s01 ? (num < 0.0) : (num > 0.0);
   return hit ? (s01 ? 1 : -1) : 0;
 }
 
+// The same with the tie signs read from the record.
+__device__ __forceinline__ int tri_crossing(const TriRec* __restrict__ recs, int32_t t, const QP& p) {
+  return tri_crossing(recs, t, recs[t].ties, p);
+}
+
 // The line through p along d (both directions) passes through the interior
 // of sorted triangle t.
-__device__ __forceinline__ bool tri_on_line(const TriRec* __restrict__ recs, int32_t t, const QP& p) {
-  return tri_inside(tri_edges(recs + t, p));
+__device__ __forceinline__ bool tri_on_line(const TriRec* __restrict__ recs, int32_t t, uint32_t ties, const QP& p) {
+  return tri_inside(tri_edges(recs + t, ties, p));
 }
 
 // ---------------------------------------------------------------------------
@@ -115,7 +119,8 @@ __device__ __forceinline__ int32_t child_ref(const BvhNode4& nd, int k) {
 }
 
 // Walk the tree for the vertical half line above (x, y, z) in the frame of
-// d and call leaf(t) for every sorted triangle t whose padded box, widened to
+// d and call leaf(t, ties) for every sorted triangle t (with its edge tie
+// signs) whose padded box, widened to
 // its node's grid, contains (x, y) with zmax >= z.  z = -inf visits every
 // triangle whose box contains (x, y), whatever its height (the column pass
 // of the grid mode).  The widening only adds triangles whose exact test
@@ -125,7 +130,7 @@ template <int S, class Leaf>
 __device__ __forceinline__ int traverse_leaves(const CrossArgs& a, float x, float y, float z, Leaf&& leaf) {
   if (a.nf == 0) return 0;
   if (a.nf == 1) {
-    if (in_box(a.leafbox[0], a.leafz[0], x, y, z)) leaf(0);
+    if (in_box(a.leafbox[0], a.leafz[0], x, y, z)) leaf(0, a.tris[0].ties);
     return 0;
   }
   RegStack<S> st;
@@ -152,10 +157,11 @@ __device__ __forceinline__ int traverse_leaves(const CrossArgs& a, float x, floa
       }
     }
     while (lm) {
-      const int32_t c = child_ref(nd, __builtin_ctz(lm));
+      const int k = __builtin_ctz(lm);
+      const int32_t c = child_ref(nd, k);
       lm &= lm - 1u;
       if (~c >= a.nf) return WN_CHI_INVALID;
-      leaf(~c);
+      leaf(~c, (nd.ties >> (3 * k)) & 7u);
     }
     if (im) {
       node = child_ref(nd, __builtin_ctz(im));
@@ -176,8 +182,8 @@ __device__ __forceinline__ int traverse_leaves(const CrossArgs& a, float x, floa
 template <int S>
 __device__ int traverse(const CrossArgs& a, const QP& p) {
   int chi = 0;
-  const int st = traverse_leaves<S>(a, p.xh, p.yh, p.zh, [&](int t) {
-    chi += tri_crossing(a.tris, t, p);
+  const int st = traverse_leaves<S>(a, p.xh, p.yh, p.zh, [&](int t, uint32_t ties) {
+    chi += tri_crossing(a.tris, t, ties, p);
   });
   return st ? st : chi;
 }
