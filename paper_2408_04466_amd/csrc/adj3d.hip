@@ -16,10 +16,8 @@ using namespace adj;
 template <int QPL>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL == 4 ? 4 : (QPL == 2 ? 6 : 8)))) void k_adj3d(
     AdjArgs a, LoopTable L) {
-  __shared__ float4 sv[2 * kChunk];
-  __shared__ float4 rsw[kWaves * kRowFloats / 4];
-  const int wave = threadIdx.x >> 6;
-  const int64_t bw = (int64_t)blockIdx.x * kWaves + wave;     // partial row
+  __shared__ AdjLds lds;
+  const int64_t bw = blockIdx.x;     // partial row
   float* pv = a.partial ? a.partial + bw * (int64_t)a.nb * 3 : nullptr;
   float* pl = a.partial_loop ? a.partial_loop + bw * (int64_t)L.n * 3 : nullptr;
   QState S[QPL];
@@ -28,7 +26,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL ==
   const int64_t tile = (int64_t)kThreads * QPL;
   const int64_t q0 = (int64_t)blockIdx.x * tile;
   load_tile<QPL>(S, a.qx, a.qy, a.qz, a.gw, q0, min(tile, a.nq - q0), qi, ok);
-  walk<QPL>(S, a.bnd, a.nb, bnd::KernargLoops{L}, sv, reinterpret_cast<float*>(rsw), pv, pl);
+  walk<QPL>(S, a.bnd, a.nb, bnd::KernargLoops{L}, lds, pv, pl);
   store_gq<QPL>(S, qi, ok, a.gq);
 }
 
@@ -41,10 +39,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL ==
 // first vertex and vertex cbeg - 1 then come from global memory.
 template <int QPL>
 __device__ __forceinline__ void walk_range(QState* S, const float* __restrict__ bnd, int nb,
-                                           const bnd::KernargLoops& L, int cbeg, int cend, float4* sv,
-                                           float* rsw, float* pv, float* pl, float* pc) {
+                                           const bnd::KernargLoops& L, int cbeg, int cend, AdjLds& lds,
+                                           float* pv, float* pl, float* pc) {
   const int lane = threadIdx.x & 63;
-  float* rs = rsw + (threadIdx.x >> 6) * kRowFloats;
+  float4* sv = lds.sv;
+  Parker P = make_parker(lds, pv);
   Rel F[QPL], A[QPL], B[QPL];
   float accA[3], accB[3];
   float4 eA = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -92,7 +91,7 @@ __device__ __forceinline__ void walk_range(QState* S, const float* __restrict__ 
         zero3(accB);
 #pragma unroll
         for (int k = 0; k < QPL; ++k) edge_grad(S[k], A[k], B[k], eA, accA, accB);
-        if (pc) put3(pc, accA, lane);
+        if (pc) put3(pc, accA, lds.sh, lane);
 #pragma unroll
         for (int k = 0; k < QPL; ++k) A[k] = B[k];
         accA[0] = accB[0]; accA[1] = accB[1]; accA[2] = accB[2];
@@ -105,17 +104,17 @@ __device__ __forceinline__ void walk_range(QState* S, const float* __restrict__ 
         const float4 e0 = sv[kChunk + j - c0];
 #pragma unroll
         for (int k = 0; k < QPL; ++k) B[k] = rel(S[k], v0);
-        step<QPL>(S, A, B, eA, accA, accB, pv, rs, j - 1, nb, lane);
+        step<QPL>(S, A, B, eA, accA, accB, P, j - 1, nb, lane);
 #pragma unroll
         for (int k = 0; k < QPL; ++k) A[k] = rel(S[k], v1);
-        step<QPL>(S, B, A, e0, accB, accA, pv, rs, j, nb, lane);
+        step<QPL>(S, B, A, e0, accB, accA, P, j, nb, lane);
         eA = sv[kChunk + j + 1 - c0];
       }
       if (j < j1) {
         const float4 v0 = sv[j - c0];
 #pragma unroll
         for (int k = 0; k < QPL; ++k) B[k] = rel(S[k], v0);
-        step<QPL>(S, A, B, eA, accA, accB, pv, rs, j - 1, nb, lane);
+        step<QPL>(S, A, B, eA, accA, accB, P, j - 1, nb, lane);
 #pragma unroll
         for (int k = 0; k < QPL; ++k) A[k] = B[k];
         accA[0] = accB[0]; accA[1] = accB[1]; accA[2] = accB[2];
@@ -125,24 +124,23 @@ __device__ __forceinline__ void walk_range(QState* S, const float* __restrict__ 
       if (j1 < le) {
         // the loop goes on: into the next chunk, or past the range, whose
         // last vertex is then parked with the share this range holds
-        if (c1 == cend && pv) park(rs, pv, c1 - 1, nb, accA, lane);
+        if (c1 == cend && pv) park(P, c1 - 1, nb, accA, lane);
         break;
       }
       float accF[3];
-      step<QPL>(S, A, F, eA, accA, accF, pv, rs, le - 1, nb, lane);
-      if (pl) put3(pl + 3 * (int64_t)l, accF, lane);
+      step<QPL>(S, A, F, eA, accA, accF, P, le - 1, nb, lane);
+      if (pl) put3(pl + 3 * (int64_t)l, accF, lds.sh, lane);
       zero3(accA);
     }
   }
+  flush_last(P);
 }
 
 template <int QPL>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL == 4 ? 4 : (QPL == 2 ? 6 : 8)))) void k_adj3d_split(
     AdjArgs a, LoopTable L, int32_t span, int32_t parts, float* carry, float* gq_part) {
-  __shared__ float4 sv[2 * kChunk];
-  __shared__ float4 rsw[kWaves * kRowFloats / 4];
-  const int wave = threadIdx.x >> 6;
-  const int64_t bw = (int64_t)blockIdx.x * kWaves + wave;
+  __shared__ AdjLds lds;
+  const int64_t bw = blockIdx.x;     // partial row
   const int p = blockIdx.y;
   float* pv = a.partial ? a.partial + bw * (int64_t)a.nb * 3 : nullptr;
   float* pl = a.partial_loop ? a.partial_loop + bw * (int64_t)L.n * 3 : nullptr;
@@ -155,8 +153,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL ==
   load_tile<QPL>(S, a.qx, a.qy, a.qz, a.gw, q0, min(tile, a.nq - q0), qi, ok);
   const int cbeg = p * span;
   const int cend = min(a.nb, cbeg + span);
-  walk_range<QPL>(S, a.bnd, a.nb, bnd::KernargLoops{L}, cbeg, cend, sv, reinterpret_cast<float*>(rsw), pv, pl,
-                  pc);
+  walk_range<QPL>(S, a.bnd, a.nb, bnd::KernargLoops{L}, cbeg, cend, lds, pv, pl, pc);
   if (a.gq) store_gq<QPL>(S, qi, ok, gq_part + (int64_t)p * a.nq * 3);
 }
 
@@ -166,7 +163,7 @@ __global__ void k_sum_parts(const float* __restrict__ part, int32_t parts, int64
   out[t] = (float)ordered_sum(part + t, n, parts, 0.0);
 }
 
-constexpr int kRowsPerGroup = 32;
+constexpr int kRowsPerGroup = 16;
 
 // Stage 1: g-th group of kRowsPerGroup partial rows, summed per column in
 // float64 (for a loop's first vertex the per-loop closing shares as well).
@@ -229,7 +226,7 @@ int64_t adj3d_blocks(int64_t nq, int qpl) {
   return (nq + per - 1) / per;
 }
 
-int64_t adj3d_rows(int64_t nblocks) { return nblocks * kWaves; }
+int64_t adj3d_rows(int64_t nblocks) { return nblocks; }
 
 hipError_t launch_adj3d(const AdjArgs& a, const LoopTable& L, int64_t nblocks, int qpl, hipStream_t s) {
   if (nblocks == 0) return hipSuccess;

@@ -15,11 +15,14 @@
 // one step after the vertex is visited (its two edges are then done); it is
 // summed over the lane's queries in registers and over each row of 16 lanes
 // with DPP moves; the four row sums wait in LDS until kBlk consecutive
-// vertices are complete, and one coalesced store then writes their sums as
-// float32 partials, one per (tile, wavefront, vertex).  The closing edge's
-// share of each loop's first vertex goes to a separate per-loop partial.  The
-// partials are reduced in a fixed order in float64 by separate kernels, so
-// grad_bnd is bitwise reproducible.
+// vertices are complete, and their sums (one per wavefront and vertex) then
+// go to an LDS window of kWin vertices.  When the walk leaves a window, the
+// workgroup adds the wavefronts' sums in wavefront order and writes them
+// with coalesced stores as float32 partials, one per (tile, vertex).  The
+// closing edge's share of each loop's first vertex goes to a separate
+// per-loop partial, summed over the workgroup the same way.  The partials
+// are reduced in a fixed order in float64 by separate kernels, so grad_bnd
+// is bitwise reproducible.
 #pragma once
 
 #include "bndloop.hpp"
@@ -33,9 +36,20 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kQPL = 4;              // queries per lane of the batched adjoint (plain: 1, 2 or 4)
 constexpr int kChunk = 512;
 constexpr int kTile = kThreads * kQPL;   // queries per batched tile
-constexpr int kBlk = 16;              // vertices per partial store
+constexpr int kBlk = 16;              // vertices per LDS row-sum block
 constexpr int kRowFloats = kBlk * 12; // LDS row sums per wavefront: [kBlk][3][4 rows]
+constexpr int kWin = 256;             // vertices per workgroup window (a multiple of kBlk)
 constexpr float kInv4Pi = 0.07957747154594767f;
+
+// LDS of the adjoint walk: the staged chunk (vertices, then the edges leaving
+// them), each wavefront's row-sum block, the workgroup's window of per-
+// wavefront vertex sums [kWaves][kWin][3], and a small exchange area.
+struct AdjLds {
+  float4 sv[2 * kChunk];
+  float rsw[kWaves * kRowFloats];
+  float ps[kWaves * kWin * 3];
+  float sh[kWaves * 3];
+};
 
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp(float v) {
@@ -72,45 +86,95 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Where a walk's completed vertices go (all fields wavefront-uniform).
+// Vertices complete in increasing order without gaps, so the window holds
+// the run [lo, hi) of them, inside [f0, f0 + kWin).
+struct Parker {
+  float* rs;      // this wavefront's row-sum block [kRowFloats] (LDS)
+  float* ps;      // the workgroup's window [kWaves][kWin][3] (LDS)
+  float* pv;      // the workgroup's partial row [nb][3], or null
+  int f0, lo, hi;
+};
+
+__device__ __forceinline__ Parker make_parker(AdjLds& s, float* pv) {
+  Parker P;
+  P.rs = s.rsw + (threadIdx.x >> 6) * kRowFloats;
+  P.ps = s.ps;
+  P.pv = pv;
+  P.f0 = -2 * kWin;   // no window yet
+  P.lo = P.hi = 0;
+  return P;
+}
+
+// Every thread of the workgroup: the window's vertices, summed over the
+// wavefronts in wavefront order, to the partial row.
+__device__ __forceinline__ void flush_window(Parker& P) {
+  __syncthreads();
+  const int n = 3 * (P.hi - P.lo);
+  const float* x = P.ps + 3 * (P.lo - P.f0);
+  float* d = P.pv + 3 * (int64_t)P.lo;
+  for (int t = threadIdx.x; t < n; t += kThreads) {
+    float s = x[t];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) s = __fadd_rn(s, x[w * kWin * 3 + t]);
+    d[t] = s;
+  }
+  __syncthreads();
+  P.lo = P.hi;
+}
+
+// Every thread of the workgroup, at the end of a walk: the last window.
+__device__ __forceinline__ void flush_last(Parker& P) {
+  if (P.pv && P.hi > P.lo) flush_window(P);
+}
+
 // Vertex va's row sums (r[c], every lane of a row holds its row's sum) into
 // the wavefront's LDS block at [va % kBlk][c][row]; once the block is full
 // (or va is the last vertex), lane t < 3 n adds the four row sums of entry t
-// in row order and stores the block's n vertices to pv with one coalesced
-// store.
-__device__ __forceinline__ void park_sums(float* rs, float* pv, int va, int nb, const float r[3], int lane) {
+// in row order into the workgroup's window, after flushing the window if the
+// block lies beyond it.  Every wavefront of the workgroup parks the same
+// vertices, so the flush's barriers are reached by all of them.
+__device__ __forceinline__ void park_sums(Parker& P, int va, int nb, const float r[3], int lane) {
   const int slot = va % kBlk;
   if ((lane & 15) == 15) {
-    float* d = rs + slot * 12 + (lane >> 4);
+    float* d = P.rs + slot * 12 + (lane >> 4);
     d[0] = r[0];
     d[4] = r[1];
     d[8] = r[2];
   }
   if (slot == kBlk - 1 || va == nb - 1) {
+    const int b0 = va - slot;
+    if (b0 >= P.f0 + kWin) {
+      if (P.hi > P.lo) flush_window(P);
+      P.f0 = b0 - b0 % kWin;
+      P.lo = P.hi = b0;
+    }
     wave_sync();
     const int n = slot + 1;
     if (lane < 3 * n) {
-      const float4 x = reinterpret_cast<const float4*>(rs)[lane];
-      pv[3 * (int64_t)(va - slot) + lane] = __fadd_rn(__fadd_rn(__fadd_rn(x.x, x.y), x.z), x.w);
+      const float4 x = reinterpret_cast<const float4*>(P.rs)[lane];
+      P.ps[(threadIdx.x >> 6) * kWin * 3 + 3 * (b0 - P.f0) + lane] =
+          __fadd_rn(__fadd_rn(__fadd_rn(x.x, x.y), x.z), x.w);
     }
+    P.hi = va + 1;
     wave_sync();
   }
 }
 
 // Vertex va's partial (three values per lane).
-__device__ __forceinline__ void park(float* rs, float* pv, int va, int nb, const float acc[3], int lane) {
+__device__ __forceinline__ void park(Parker& P, int va, int nb, const float acc[3], int lane) {
   const float r[3] = {row_sum(acc[0]), row_sum(acc[1]), row_sum(acc[2])};
-  park_sums(rs, pv, va, nb, r, lane);
+  park_sums(P, va, nb, r, lane);
 }
 
 // The partials of vertices va and va + 1: the six row sums first (six
 // independent chains of lane moves instead of two runs of three), then the
 // two LDS entries in vertex order.
-__device__ __forceinline__ void park2(float* rs, float* pv, int va, int nb, const float a[3], const float b[3],
-                                      int lane) {
+__device__ __forceinline__ void park2(Parker& P, int va, int nb, const float a[3], const float b[3], int lane) {
   const float ra[3] = {row_sum(a[0]), row_sum(a[1]), row_sum(a[2])};
   const float rb[3] = {row_sum(b[0]), row_sum(b[1]), row_sum(b[2])};
-  park_sums(rs, pv, va, nb, ra, lane);
-  park_sums(rs, pv, va + 1, nb, rb, lane);
+  park_sums(P, va, nb, ra, lane);
+  park_sums(P, va + 1, nb, rb, lane);
 }
 
 struct QState {
@@ -180,15 +244,26 @@ __device__ __forceinline__ void stage_adj(const float* __restrict__ bnd, const L
   sv[kChunk + j] = make_float4(ex, ey, ez, __fmaf_rn(ex, ex, __fmaf_rn(ey, ey, __fmul_rn(ez, ez))));
 }
 
-__device__ __forceinline__ void put3(float* dst, const float acc[3], int lane) {
+// Every thread of the workgroup: acc summed over each wavefront, then over
+// the wavefronts in order, to dst[0..2] (sh: kWaves * 3 floats of LDS).
+__device__ __forceinline__ void put3(float* dst, const float acc[3], float* sh, int lane) {
   const float r0 = wave_sum_last(acc[0]);
   const float r1 = wave_sum_last(acc[1]);
   const float r2 = wave_sum_last(acc[2]);
   if (lane == 63) {
-    dst[0] = r0;
-    dst[1] = r1;
-    dst[2] = r2;
+    float* d = sh + 3 * (threadIdx.x >> 6);
+    d[0] = r0;
+    d[1] = r1;
+    d[2] = r2;
   }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    float s = sh[threadIdx.x];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) s = __fadd_rn(s, sh[3 * w + threadIdx.x]);
+    dst[threadIdx.x] = s;
+  }
+  __syncthreads();
 }
 
 // Load the tile's queries [q0, q0 + cnt) into the lane states (QPL per lane).
@@ -214,24 +289,25 @@ __device__ __forceinline__ void zero3(float* a) { a[0] = a[1] = a[2] = 0.f; }
 // complete and goes out (summed over the wavefront) to row entry `va`.
 template <int QPL>
 __device__ __forceinline__ void step(QState* S, const Rel* A, const Rel* B, const float4& e, float* accA,
-                                     float* accB, float* pv, float* rs, int va, int nb, int lane) {
+                                     float* accB, Parker& P, int va, int nb, int lane) {
   zero3(accB);
 #pragma unroll
   for (int k = 0; k < QPL; ++k) edge_grad(S[k], A[k], B[k], e, accA, accB);
-  if (pv) park(rs, pv, va, nb, accA, lane);
+  if (P.pv) park(P, va, nb, accA, lane);
 }
 
-// Walk the boundary for one tile.  pv: this wavefront's partial row
-// [nb][3] (or null), pl: its per-loop row [nloops][3] (the closing edge's
-// share of each loop's first vertex), rsw: the workgroup's LDS row-sum
-// blocks [kWaves][kRowFloats].  Loops are taken as straight vertex ranges
-// (like the forward walk), two vertices per step; vertices complete in
-// increasing order 0 .. nb-1.
+// Walk the boundary for one tile (every thread of the workgroup).  pv: the
+// workgroup's partial row [nb][3] (or null), pl: its per-loop row
+// [nloops][3] (the closing edge's share of each loop's first vertex; null
+// with pv).  Loops are taken as straight vertex ranges (like the forward
+// walk), two vertices per step; vertices complete in increasing order 0 ..
+// nb-1.
 template <int QPL, class Loops>
 __device__ __forceinline__ void walk(QState* S, const float* __restrict__ bnd, int nb, const Loops& L,
-                                     float4* sv, float* rsw, float* pv, float* pl) {
+                                     AdjLds& lds, float* pv, float* pl) {
   const int lane = threadIdx.x & 63;
-  float* rs = rsw + (threadIdx.x >> 6) * kRowFloats;
+  float4* sv = lds.sv;
+  Parker P = make_parker(lds, pv);
   Rel A[QPL], B[QPL];              // A = last vertex visited
   float4 vF = make_float4(0.f, 0.f, 0.f, 0.f);   // the loop's first vertex (uniform)
   float accA[3], accB[3];          // pending partial of vertex A (and scratch for B)
@@ -276,7 +352,7 @@ __device__ __forceinline__ void walk(QState* S, const float* __restrict__ bnd, i
 #pragma unroll
         for (int k = 0; k < QPL; ++k) edge_grad(S[k], B[k], A[k], e0, accB, accC);
         // vertices j - 1 and j are complete
-        if (pv) park2(rs, pv, j - 1, nb, accA, accB, lane);
+        if (pv) park2(P, j - 1, nb, accA, accB, lane);
         accA[0] = accC[0]; accA[1] = accC[1]; accA[2] = accC[2];
         eA = sv[kChunk + j + 1 - c0];
       }
@@ -284,7 +360,7 @@ __device__ __forceinline__ void walk(QState* S, const float* __restrict__ bnd, i
         const float4 v0 = sv[j - c0];
 #pragma unroll
         for (int k = 0; k < QPL; ++k) B[k] = rel(S[k], v0);
-        step<QPL>(S, A, B, eA, accA, accB, pv, rs, j - 1, nb, lane);
+        step<QPL>(S, A, B, eA, accA, accB, P, j - 1, nb, lane);
 #pragma unroll
         for (int k = 0; k < QPL; ++k) A[k] = B[k];
         accA[0] = accB[0]; accA[1] = accB[1]; accA[2] = accB[2];
@@ -297,11 +373,12 @@ __device__ __forceinline__ void walk(QState* S, const float* __restrict__ bnd, i
       float accF[3];
 #pragma unroll
       for (int k = 0; k < QPL; ++k) B[k] = rel(S[k], vF);
-      step<QPL>(S, A, B, eA, accA, accF, pv, rs, le - 1, nb, lane);
-      if (pl) put3(pl + 3 * (int64_t)l, accF, lane);
+      step<QPL>(S, A, B, eA, accA, accF, P, le - 1, nb, lane);
+      if (pl) put3(pl + 3 * (int64_t)l, accF, lds.sh, lane);
       zero3(accA);
     }
   }
+  flush_last(P);
 }
 
 // x[0] + x[stride] + ... + x[(cnt - 1) stride] in float64, added in index

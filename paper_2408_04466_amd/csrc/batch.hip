@@ -61,7 +61,7 @@ struct RBlock {
   int32_t pad;
 };
 
-constexpr int kRowsPerGroup = 32;
+constexpr int kRowsPerGroup = 16;
 
 struct Item {
   int32_t surf;
@@ -259,29 +259,27 @@ __global__ __launch_bounds__(kThreads) void k_batch_bnd(FwdArgs a) {
 // Four waves per SIMD (128 registers): the few spills are per-item
 // addresses, outside the walk.
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_bwd(BwdArgs a) {
-  __shared__ float4 sv[2 * adj::kChunk];
-  __shared__ float4 rsw[adj::kWaves * adj::kRowFloats / 4];
+  __shared__ adj::AdjLds lds;
   __shared__ int s_item;
-  const int wave = threadIdx.x >> 6;
   for (int pass = 0;; ++pass) {
     const int it = item_for(1, pass, a.n_items, a.counter, &s_item);
     if (it >= a.n_items) return;
     const Item item = load_const(a.items, it);
     const SurfDesc D = load_const(a.descs, item.surf);
     const bnd::DeviceLoops L{a.loops + D.loop_off, D.nloops};
-    const int64_t row = (int64_t)item.tile * adj::kWaves + wave;
+    const int64_t row = item.tile;   // partial row
     float* pv = a.pv ? a.pv + D.pv_off + row * (int64_t)D.nb * 3 : nullptr;
     float* pl = a.pv ? a.pl + D.pl_off + row * (int64_t)D.nloops * 3 : nullptr;
     adj::QState S[adj::kQPL];
     int64_t qi[adj::kQPL];
     bool ok[adj::kQPL];
     adj::load_tile<adj::kQPL>(S, a.qx, a.qy, a.qz, a.gw, item.q0, item.cnt, qi, ok);
-    if (D.nb > 0) adj::walk<adj::kQPL>(S, a.bnd + 3 * D.bnd_off, D.nb, L, sv, reinterpret_cast<float*>(rsw), pv, pl);
+    if (D.nb > 0) adj::walk<adj::kQPL>(S, a.bnd + 3 * D.bnd_off, D.nb, L, lds, pv, pl);
     adj::store_gq<adj::kQPL>(S, qi, ok, a.gq);
   }
 }
 
-// Boundary-vertex gradients from the per-(tile, wavefront) partial rows, in
+// Boundary-vertex gradients from the per-tile partial rows, in
 // two fixed-order float64 stages (the same grouping as the single-surface
 // adjoint, so both give identical bits).  Stage 1: one group of
 // kRowsPerGroup rows per column, plus the per-loop closing share at a loop's
@@ -299,7 +297,7 @@ __global__ void k_batch_rows(const SurfDesc* __restrict__ descs, const RBlock* _
   int lf = -1;
   for (int l = 0; l < D.nloops; ++l)
     if (lo[l] == v && lo[l + 1] > v) lf = l;
-  const int64_t rows = (int64_t)D.tiles_bwd * adj::kWaves;
+  const int64_t rows = D.tiles_bwd;
   const int64_t r0 = (int64_t)rb.group * kRowsPerGroup;
   const int64_t r1 = min(rows, r0 + kRowsPerGroup);
   const float* p = pv + D.pv_off;
@@ -797,9 +795,9 @@ wn_status wn_batch_create(const wn_surface* surfs, int32_t ns, const double dir[
     D.tiles_bwd = (int32_t)((D.nq + wn::adj::kTile - 1) / wn::adj::kTile);
     D.pv_off = pv;
     D.pl_off = pl;
-    pv += (int64_t)D.tiles_bwd * wn::adj::kWaves * D.nb * 3;
-    pl += (int64_t)D.tiles_bwd * wn::adj::kWaves * D.nloops * 3;
-    D.groups = (int32_t)(((int64_t)D.tiles_bwd * wn::adj::kWaves + wn::kRowsPerGroup - 1) / wn::kRowsPerGroup);
+    pv += (int64_t)D.tiles_bwd * D.nb * 3;
+    pl += (int64_t)D.tiles_bwd * D.nloops * 3;
+    D.groups = (int32_t)(((int64_t)D.tiles_bwd + wn::kRowsPerGroup - 1) / wn::kRowsPerGroup);
     D.tmp_off = b->n_tmp;
     b->n_tmp += (int64_t)D.groups * D.nb * 3;
   }
@@ -981,8 +979,8 @@ wn_status wn_backward_batched(wn_batch* b, const float* qx, const float* qy, con
   if (grad_bnd && !b->d_pv && b->total_b > 0) {
     int64_t pv = 0, pl = 0;
     for (const auto& D : b->desc) {
-      pv = std::max<int64_t>(pv, D.pv_off + (int64_t)D.tiles_bwd * wn::adj::kWaves * D.nb * 3);
-      pl = std::max<int64_t>(pl, D.pl_off + (int64_t)D.tiles_bwd * wn::adj::kWaves * D.nloops * 3);
+      pv = std::max<int64_t>(pv, D.pv_off + (int64_t)D.tiles_bwd * D.nb * 3);
+      pl = std::max<int64_t>(pl, D.pl_off + (int64_t)D.tiles_bwd * D.nloops * 3);
     }
     WN_HIP(hipMalloc((void**)&b->d_pv, std::max<int64_t>(pv, 1) * sizeof(float)), "backward partials");
     WN_HIP(hipMalloc((void**)&b->d_pl, std::max<int64_t>(pl, 1) * sizeof(float)), "backward partials");
