@@ -21,13 +21,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL ==
   float* pv = a.partial ? a.partial + bw * (int64_t)a.nb * 3 : nullptr;
   float* pl = a.partial_loop ? a.partial_loop + bw * (int64_t)L.n * 3 : nullptr;
   QState S[QPL];
-  int64_t qi[QPL];
-  bool ok[QPL];
   const int64_t tile = (int64_t)kThreads * QPL;
   const int64_t q0 = (int64_t)blockIdx.x * tile;
-  load_tile<QPL>(S, a.qx, a.qy, a.qz, a.gw, q0, min(tile, a.nq - q0), qi, ok);
+  const int64_t cnt = min(tile, a.nq - q0);
+  load_tile<QPL>(S, a.qx, a.qy, a.qz, a.gw, q0, cnt);
   walk<QPL>(S, a.bnd, a.nb, bnd::KernargLoops{L}, lds, pv, pl);
-  store_gq<QPL>(S, qi, ok, a.gq);
+  store_gq<QPL>(S, q0, cnt, a.gq);
 }
 
 // The walk of adjloop.hpp restricted to the edges that start at vertices
@@ -88,9 +87,7 @@ __device__ __forceinline__ void walk_range(QState* S, const float* __restrict__ 
         const float4 v0 = sv[j - c0];
 #pragma unroll
         for (int k = 0; k < QPL; ++k) B[k] = rel(S[k], v0);
-        zero3(accB);
-#pragma unroll
-        for (int k = 0; k < QPL; ++k) edge_grad(S[k], A[k], B[k], eA, accA, accB);
+        edges<QPL>(S, A, B, eA, accA, accB);
         if (pc) put3(pc, accA, lds.sh, lane);
 #pragma unroll
         for (int k = 0; k < QPL; ++k) A[k] = B[k];
@@ -146,15 +143,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL ==
   float* pl = a.partial_loop ? a.partial_loop + bw * (int64_t)L.n * 3 : nullptr;
   float* pc = (a.partial && carry) ? carry + (bw * parts + p) * 3 : nullptr;
   QState S[QPL];
-  int64_t qi[QPL];
-  bool ok[QPL];
   const int64_t tile = (int64_t)kThreads * QPL;
   const int64_t q0 = (int64_t)blockIdx.x * tile;
-  load_tile<QPL>(S, a.qx, a.qy, a.qz, a.gw, q0, min(tile, a.nq - q0), qi, ok);
+  const int64_t cnt = min(tile, a.nq - q0);
+  load_tile<QPL>(S, a.qx, a.qy, a.qz, a.gw, q0, cnt);
   const int cbeg = p * span;
   const int cend = min(a.nb, cbeg + span);
   walk_range<QPL>(S, a.bnd, a.nb, bnd::KernargLoops{L}, cbeg, cend, lds, pv, pl, pc);
-  if (a.gq) store_gq<QPL>(S, qi, ok, gq_part + (int64_t)p * a.nq * 3);
+  if (a.gq) store_gq<QPL>(S, q0, cnt, gq_part + (int64_t)p * a.nq * 3);
 }
 
 __global__ void k_sum_parts(const float* __restrict__ part, int32_t parts, int64_t n, float* __restrict__ out) {

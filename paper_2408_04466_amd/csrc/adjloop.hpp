@@ -13,8 +13,8 @@
 // boundary in LDS (each vertex with the edge leaving it) and
 // every lane walks the same vertex sequence.  A vertex's gradient is complete
 // one step after the vertex is visited (its two edges are then done); it is
-// summed over the lane's queries in registers and over each row of 16 lanes
-// with DPP moves; the four row sums wait in LDS until kBlk consecutive
+// summed over the lane's queries in registers and over each quad of 4 lanes
+// with DPP moves; the sixteen quad sums wait in LDS until kBlk consecutive
 // vertices are complete, and their sums (one per wavefront and vertex) then
 // go to an LDS window of kWin vertices.  When the walk leaves a window, the
 // workgroup adds the wavefronts' sums in wavefront order and writes them
@@ -36,13 +36,13 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kQPL = 4;              // queries per lane of the batched adjoint (plain: 1, 2 or 4)
 constexpr int kChunk = 512;
 constexpr int kTile = kThreads * kQPL;   // queries per batched tile
-constexpr int kBlk = 16;              // vertices per LDS row-sum block
-constexpr int kRowFloats = kBlk * 12; // LDS row sums per wavefront: [kBlk][3][4 rows]
-constexpr int kWin = 256;             // vertices per workgroup window (a multiple of kBlk)
+constexpr int kBlk = 16;              // vertices per LDS quad-sum block
+constexpr int kRowFloats = kBlk * 48; // LDS quad sums per wavefront: [kBlk][3][16 quads]
+constexpr int kWin = 128;             // vertices per workgroup window (a multiple of kBlk)
 constexpr float kInv4Pi = 0.07957747154594767f;
 
 // LDS of the adjoint walk: the staged chunk (vertices, then the edges leaving
-// them), each wavefront's row-sum block, the workgroup's window of per-
+// them), each wavefront's quad-sum block, the workgroup's window of per-
 // wavefront vertex sums [kWaves][kWin][3], and a small exchange area.
 struct AdjLds {
   float4 sv[2 * kChunk];
@@ -69,16 +69,14 @@ __device__ __forceinline__ float wave_sum_last(float v) {
   return v;
 }
 
-// Sum over each row of 16 lanes (every lane of the row holds it).
-__device__ __forceinline__ float row_sum(float v) {
+// Sum over each quad of 4 lanes (every lane of the quad holds it).
+__device__ __forceinline__ float quad_sum(float v) {
   v += dpp<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
   v += dpp<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
-  v += dpp<0x124, 0xF>(v);   // row_ror:4
-  v += dpp<0x128, 0xF>(v);   // row_ror:8
   return v;
 }
 
-// Wavefront-scope ordering of the LDS row-sum block between the lanes that
+// Wavefront-scope ordering of the LDS quad-sum block between the lanes that
 // write it and the lanes that read it.
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -90,7 +88,7 @@ __device__ __forceinline__ void wave_sync() {
 // Vertices complete in increasing order without gaps, so the window holds
 // the run [lo, hi) of them, inside [f0, f0 + kWin).
 struct Parker {
-  float* rs;      // this wavefront's row-sum block [kRowFloats] (LDS)
+  float* rs;      // this wavefront's quad-sum block [kRowFloats] (LDS)
   float* ps;      // the workgroup's window [kWaves][kWin][3] (LDS)
   float* pv;      // the workgroup's partial row [nb][3], or null
   int f0, lo, hi;
@@ -128,19 +126,19 @@ __device__ __forceinline__ void flush_last(Parker& P) {
   if (P.pv && P.hi > P.lo) flush_window(P);
 }
 
-// Vertex va's row sums (r[c], every lane of a row holds its row's sum) into
-// the wavefront's LDS block at [va % kBlk][c][row]; once the block is full
-// (or va is the last vertex), lane t < 3 n adds the four row sums of entry t
-// in row order into the workgroup's window, after flushing the window if the
-// block lies beyond it.  Every wavefront of the workgroup parks the same
+// Vertex va's quad sums (r[c], every lane of a quad holds its quad's sum)
+// into the wavefront's LDS block at [va % kBlk][c][quad]; once the block is
+// full (or va is the last vertex), lane t < 3 n adds the sixteen quad sums of
+// entry t in quad order into the workgroup's window, after flushing the
+// window if the block lies beyond it.  Every wavefront of the workgroup parks the same
 // vertices, so the flush's barriers are reached by all of them.
 __device__ __forceinline__ void park_sums(Parker& P, int va, int nb, const float r[3], int lane) {
   const int slot = va % kBlk;
-  if ((lane & 15) == 15) {
-    float* d = P.rs + slot * 12 + (lane >> 4);
+  if ((lane & 3) == 3) {
+    float* d = P.rs + slot * 48 + (lane >> 2);
     d[0] = r[0];
-    d[4] = r[1];
-    d[8] = r[2];
+    d[16] = r[1];
+    d[32] = r[2];
   }
   if (slot == kBlk - 1 || va == nb - 1) {
     const int b0 = va - slot;
@@ -152,9 +150,15 @@ __device__ __forceinline__ void park_sums(Parker& P, int va, int nb, const float
     wave_sync();
     const int n = slot + 1;
     if (lane < 3 * n) {
-      const float4 x = reinterpret_cast<const float4*>(P.rs)[lane];
-      P.ps[(threadIdx.x >> 6) * kWin * 3 + 3 * (b0 - P.f0) + lane] =
-          __fadd_rn(__fadd_rn(__fadd_rn(x.x, x.y), x.z), x.w);
+      const float4* x = reinterpret_cast<const float4*>(P.rs) + 4 * lane;
+      float s = 0.f;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float4 y = x[k];
+        s = k == 0 ? y.x : __fadd_rn(s, y.x);
+        s = __fadd_rn(__fadd_rn(__fadd_rn(s, y.y), y.z), y.w);
+      }
+      P.ps[(threadIdx.x >> 6) * kWin * 3 + 3 * (b0 - P.f0) + lane] = s;
     }
     P.hi = va + 1;
     wave_sync();
@@ -163,16 +167,16 @@ __device__ __forceinline__ void park_sums(Parker& P, int va, int nb, const float
 
 // Vertex va's partial (three values per lane).
 __device__ __forceinline__ void park(Parker& P, int va, int nb, const float acc[3], int lane) {
-  const float r[3] = {row_sum(acc[0]), row_sum(acc[1]), row_sum(acc[2])};
+  const float r[3] = {quad_sum(acc[0]), quad_sum(acc[1]), quad_sum(acc[2])};
   park_sums(P, va, nb, r, lane);
 }
 
-// The partials of vertices va and va + 1: the six row sums first (six
+// The partials of vertices va and va + 1: the six quad sums first (six
 // independent chains of lane moves instead of two runs of three), then the
 // two LDS entries in vertex order.
 __device__ __forceinline__ void park2(Parker& P, int va, int nb, const float a[3], const float b[3], int lane) {
-  const float ra[3] = {row_sum(a[0]), row_sum(a[1]), row_sum(a[2])};
-  const float rb[3] = {row_sum(b[0]), row_sum(b[1]), row_sum(b[2])};
+  const float ra[3] = {quad_sum(a[0]), quad_sum(a[1]), quad_sum(a[2])};
+  const float rb[3] = {quad_sum(b[0]), quad_sum(b[1]), quad_sum(b[2])};
   park_sums(P, va, nb, ra, lane);
   park_sums(P, va + 1, nb, rb, lane);
 }
@@ -204,7 +208,8 @@ __device__ __forceinline__ Rel rel(const QState& s, const float4& v) {
 // 1/K = |a'||b'| + a'.b' = ((|a'| + |b'|)^2 - |b - a|^2) / 2, since
 // |b - a|^2 = |a'|^2 + |b'|^2 - 2 a'.b' (the factor 2 sits in s.g); adds
 // c (1/|a'| + 1/|b'|) to the query gradient and c/|a'|, c/|b'| to the two
-// vertex accumulators.
+// vertex accumulators (FIRST: acc_b starts here, for the lane's first query).
+template <bool FIRST>
 __device__ __forceinline__ void edge_grad(QState& s, const Rel& a, const Rel& b, const float4& e, float* acc_a,
                                           float* acc_b) {
   const float crx = __fmaf_rn(a.y, e.z, -__fmul_rn(a.z, e.y));
@@ -224,9 +229,19 @@ __device__ __forceinline__ void edge_grad(QState& s, const Rel& a, const Rel& b,
   acc_a[0] = __fmaf_rn(crx, ta, acc_a[0]);
   acc_a[1] = __fmaf_rn(cry, ta, acc_a[1]);
   acc_a[2] = __fmaf_rn(crz, ta, acc_a[2]);
-  acc_b[0] = __fmaf_rn(crx, tb, acc_b[0]);
-  acc_b[1] = __fmaf_rn(cry, tb, acc_b[1]);
-  acc_b[2] = __fmaf_rn(crz, tb, acc_b[2]);
+  acc_b[0] = FIRST ? __fmul_rn(crx, tb) : __fmaf_rn(crx, tb, acc_b[0]);
+  acc_b[1] = FIRST ? __fmul_rn(cry, tb) : __fmaf_rn(cry, tb, acc_b[1]);
+  acc_b[2] = FIRST ? __fmul_rn(crz, tb) : __fmaf_rn(crz, tb, acc_b[2]);
+}
+
+// Edge A->B for every query of the lane: the query gradients, vertex A's
+// accumulator, and vertex B's started afresh.
+template <int QPL>
+__device__ __forceinline__ void edges(QState* S, const Rel* A, const Rel* B, const float4& e, float* accA,
+                                      float* accB) {
+  edge_grad<true>(S[0], A[0], B[0], e, accA, accB);
+#pragma unroll
+  for (int k = 1; k < QPL; ++k) edge_grad<false>(S[k], A[k], B[k], e, accA, accB);
 }
 
 // Stage boundary vertex i (flat index, loops L) for the adjoint walk: its
@@ -257,28 +272,31 @@ __device__ __forceinline__ void put3(float* dst, const float acc[3], float* sh, 
     d[2] = r2;
   }
   __syncthreads();
-  if (threadIdx.x < 3) {
-    float s = sh[threadIdx.x];
+  int t = threadIdx.x;   // a fresh copy: no address kept live across the walk
+  asm volatile("" : "+v"(t));
+  if (t < 3) {
+    float s = sh[t];
 #pragma unroll
-    for (int w = 1; w < kWaves; ++w) s = __fadd_rn(s, sh[3 * w + threadIdx.x]);
-    dst[threadIdx.x] = s;
+    for (int w = 1; w < kWaves; ++w) s = __fadd_rn(s, sh[3 * w + t]);
+    dst[t] = s;
   }
   __syncthreads();
 }
 
-// Load the tile's queries [q0, q0 + cnt) into the lane states (QPL per lane).
+// Load the tile's queries [q0, q0 + cnt) into the lane states (QPL per lane;
+// lane query k is tile entry k * kThreads + threadIdx.x).
 template <int QPL>
 __device__ __forceinline__ void load_tile(QState* S, const float* qx, const float* qy, const float* qz,
-                                          const float* gw, int64_t q0, int64_t cnt, int64_t* qi, bool* ok) {
+                                          const float* gw, int64_t q0, int64_t cnt) {
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
     const int64_t r = (int64_t)k * kThreads + threadIdx.x;
-    ok[k] = r < cnt;
-    qi[k] = q0 + (ok[k] ? r : 0);
-    S[k].px = qx[qi[k]];
-    S[k].py = qy[qi[k]];
-    S[k].pz = qz[qi[k]];
-    S[k].g = ok[k] ? 2.0f * gw[qi[k]] : 0.0f;   // padding lanes contribute nothing
+    const bool ok = r < cnt;
+    const int64_t q = q0 + (ok ? r : 0);
+    S[k].px = qx[q];
+    S[k].py = qy[q];
+    S[k].pz = qz[q];
+    S[k].g = ok ? 2.0f * gw[q] : 0.0f;   // padding lanes contribute nothing
     S[k].gx = S[k].gy = S[k].gz = 0.0f;
   }
 }
@@ -290,9 +308,7 @@ __device__ __forceinline__ void zero3(float* a) { a[0] = a[1] = a[2] = 0.f; }
 template <int QPL>
 __device__ __forceinline__ void step(QState* S, const Rel* A, const Rel* B, const float4& e, float* accA,
                                      float* accB, Parker& P, int va, int nb, int lane) {
-  zero3(accB);
-#pragma unroll
-  for (int k = 0; k < QPL; ++k) edge_grad(S[k], A[k], B[k], e, accA, accB);
+  edges<QPL>(S, A, B, e, accA, accB);
   if (P.pv) park(P, va, nb, accA, lane);
 }
 
@@ -343,14 +359,10 @@ __device__ __forceinline__ void walk(QState* S, const float* __restrict__ bnd, i
         float accC[3];
 #pragma unroll
         for (int k = 0; k < QPL; ++k) B[k] = rel(S[k], v0);
-        zero3(accB);
-#pragma unroll
-        for (int k = 0; k < QPL; ++k) edge_grad(S[k], A[k], B[k], eA, accA, accB);
+        edges<QPL>(S, A, B, eA, accA, accB);
 #pragma unroll
         for (int k = 0; k < QPL; ++k) A[k] = rel(S[k], v1);
-        zero3(accC);
-#pragma unroll
-        for (int k = 0; k < QPL; ++k) edge_grad(S[k], B[k], A[k], e0, accB, accC);
+        edges<QPL>(S, B, A, e0, accB, accC);
         // vertices j - 1 and j are complete
         if (pv) park2(P, j - 1, nb, accA, accB, lane);
         accA[0] = accC[0]; accA[1] = accC[1]; accA[2] = accC[2];
@@ -398,12 +410,19 @@ __device__ __forceinline__ double ordered_sum(const T* __restrict__ x, int64_t s
   return s;
 }
 
+// The query gradients of the tile loaded by load_tile (the indices are
+// recomputed rather than held through the walk).
 template <int QPL>
-__device__ __forceinline__ void store_gq(const QState* S, const int64_t* qi, const bool* ok, float* gq) {
+__device__ __forceinline__ void store_gq(const QState* S, int64_t q0, int64_t cnt, float* gq) {
+  // a fresh copy of the lane index, so that the compiler does not keep the
+  // load's index arithmetic alive through the walk
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
-    if (!ok[k] || !gq) continue;
-    const int64_t q = qi[k];
+    const int64_t r = (int64_t)k * kThreads + t;
+    if (r >= cnt || !gq) continue;
+    const int64_t q = q0 + r;
     gq[3 * q + 0] = S[k].gx * kInv4Pi;
     gq[3 * q + 1] = S[k].gy * kInv4Pi;
     gq[3 * q + 2] = S[k].gz * kInv4Pi;

@@ -271,11 +271,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     float* pv = a.pv ? a.pv + D.pv_off + row * (int64_t)D.nb * 3 : nullptr;
     float* pl = a.pv ? a.pl + D.pl_off + row * (int64_t)D.nloops * 3 : nullptr;
     adj::QState S[adj::kQPL];
-    int64_t qi[adj::kQPL];
-    bool ok[adj::kQPL];
-    adj::load_tile<adj::kQPL>(S, a.qx, a.qy, a.qz, a.gw, item.q0, item.cnt, qi, ok);
+    adj::load_tile<adj::kQPL>(S, a.qx, a.qy, a.qz, a.gw, item.q0, item.cnt);
     if (D.nb > 0) adj::walk<adj::kQPL>(S, a.bnd + 3 * D.bnd_off, D.nb, L, lds, pv, pl);
-    adj::store_gq<adj::kQPL>(S, qi, ok, a.gq);
+    adj::store_gq<adj::kQPL>(S, item.q0, item.cnt, a.gq);
   }
 }
 
