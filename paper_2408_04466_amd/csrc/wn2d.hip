@@ -149,7 +149,10 @@ __device__ T solve_x(const Piece<T>& pc, T yq) {
     const T f = horner(pc.cy, t) - yq;
     if (f >= (T)0) hi = t; else lo = t;
     const T fp = horner_d(pc.cy, t);
-    T tn = (fp != (T)0) ? t - f / fp : (T)0.5 * (lo + hi);
+    // the step needs no correctly rounded quotient (the bracket guards it):
+    // in float32 one reciprocal instead of a full division
+    const T q = sizeof(T) == 4 ? (T)(f * __builtin_amdgcn_rcpf((float)fp)) : f / fp;
+    T tn = (fp != (T)0) ? t - q : (T)0.5 * (lo + hi);
     const T a = fmin(lo, hi), b = fmax(lo, hi);
     if (!(tn > a && tn < b)) tn = (T)0.5 * (lo + hi);
     if (tn == t || b - a <= (T)4 * (sizeof(T) == 4 ? (T)1.2e-7 : (T)2.3e-16) * fmax((T)1, fabs(b))) {
@@ -219,19 +222,19 @@ template <> __device__ __forceinline__ double atan2_t<double>(double y, double x
 // disagree through rounding.  p on the chord between s and e (s x e = 0,
 // s . e < 0) gives -pi when e is in [0, pi) (above, or on the +x side of
 // the line), +pi otherwise.
+// Written with selects only, so that several queries' evaluations can be
+// interleaved without branches.
 template <class T>
 __device__ __forceinline__ T open_loop_angle(T sx, T sy, T ex, T ey) {
   const T cr = fma_t(sx, ey, -(sy * ex));
   const T dt = fma_t(sx, ex, sy * ey);
-  if (cr == (T)0 && dt < (T)0) {
-    const bool e_upper = ey > (T)0 || (ey == (T)0 && ex > (T)0);
-    return e_upper ? -(T)3.141592653589793 : (T)3.141592653589793;
-  }
   const T th = atan2_t(cr, dt);
   const bool s_above = sy >= (T)0, e_above = ey >= (T)0;
-  if (!s_above && e_above && cr > (T)0) return th - (T)6.283185307179586;
-  if (s_above && !e_above && cr < (T)0) return th + (T)6.283185307179586;
-  return th;
+  T r = (!s_above && e_above && cr > (T)0) ? th - (T)6.283185307179586 : th;
+  r = (s_above && !e_above && cr < (T)0) ? th + (T)6.283185307179586 : r;
+  const bool e_upper = ey > (T)0 || (ey == (T)0 && ex > (T)0);
+  const T on_chord = e_upper ? -(T)3.141592653589793 : (T)3.141592653589793;
+  return (cr == (T)0 && dt < (T)0) ? on_chord : r;
 }
 
 // Loop table in device memory (batched calls): same members as Loops2D.
@@ -312,6 +315,39 @@ struct alignas(sizeof(T) * 4) EndPts {
   T sx, sy, ex, ey;
 };
 
+// Number of tile columns with x_i < xe (x ascending, ncol >= 1): first the
+// position xe would have on an evenly spaced axis, then steps of doubling
+// length to a bracket of the answer, then bisection inside it.  On an evenly
+// spaced axis the guess is the answer or next to it (two reads instead of
+// the eleven of a bisection over 2048 columns); any ascending axis gets the
+// exact count.
+template <class T>
+__device__ __forceinline__ int count_below(const T* sx, int ncol, T xe, T xlo, T xscale) {
+  const T f = fmin(fmax((xe - xlo) * xscale, (T)-1), (T)ncol);
+  const int g = min((int)f + 1, ncol);   // f >= -1: g in [0, ncol]
+  int lo, hi;                            // the answer lies in [lo, hi]
+  if (g < ncol && sx[g] < xe) {
+    lo = g + 1;
+    hi = lo;
+    for (int step = 1; hi < ncol && sx[hi] < xe; step <<= 1) {
+      lo = hi + 1;
+      hi = min(ncol, hi + step);
+    }
+  } else {
+    hi = g;
+    lo = hi;
+    for (int step = 1; lo > 0 && !(sx[lo - 1] < xe); step <<= 1) {
+      hi = lo - 1;
+      lo = max(0, lo - step);
+    }
+  }
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (sx[mid] < xe) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
 // Inclusive suffix sum over the lanes of a wavefront (lane i gets the sum of
 // lanes i..63).
 __device__ __forceinline__ int wave_suffix_sum(int v) {
@@ -362,6 +398,8 @@ __device__ void grid_tile(const Piece<T>* __restrict__ pcs, const typename Vec2<
   }
   __syncthreads();
   const T xlo = sx[0], xhi = sx[ncol - 1];
+  // columns per unit of x on an evenly spaced axis (the search's first guess)
+  const T xscale = (xhi > xlo && ncol > 1) ? (T)(ncol - 1) / (xhi - xlo) : (T)0;
   int base = 0;   // crossings right of every column of the tile
   for (int c0 = 0; c0 < npc; c0 += kSolveChunk) {
     const int c1 = min(c0 + kSolveChunk, npc);
@@ -385,12 +423,7 @@ __device__ void grid_tile(const Piece<T>* __restrict__ pcs, const typename Vec2<
       const int sg = yr[j].y >= yq ? 1 : -1;
       const T xs = solve_x(pc, yq);
       const T xe = fmin(fmax(xs, pc.xmin), pc.xmax);
-      // number of tile columns with x_i < xe (x ascending)
-      int a = 0, b = ncol;
-      while (a < b) {
-        const int mid = (a + b) >> 1;
-        if (sx[mid] < xe) a = mid + 1; else b = mid;
-      }
+      const int a = count_below(sx, ncol, xe, xlo, xscale);
       if (a == ncol) base += sg;
       else if (a > 0) atomicAdd(&hist[hist_at(a)], sg);
     }
@@ -427,30 +460,43 @@ __device__ void grid_tile(const Piece<T>* __restrict__ pcs, const typename Vec2<
     hist[hist_at(i + 1)] = run;
   }
   __syncthreads();
-  // coalesced output: consecutive lanes write consecutive columns
+  // coalesced output: consecutive lanes write consecutive columns.  A thread
+  // takes kOutQ of its columns at once, so that each end point is read from
+  // LDS once for all of them and their angle chains interleave.
   const int nopen = *snopen;
-  for (int i = threadIdx.x; i < ncol; i += kThreads) {
-    const int64_t o = row * nx + i0 + i;
-    const T px = sx[i];
-    if (!(isfinite(px) && isfinite(yq))) {
-      w[o] = (T)NAN;
-      if (chi) chi[o] = WN_CHI_INVALID;
-      continue;
+  constexpr int kOutQ = 8;
+  for (int ib = 0; ib < ncol; ib += kOutQ * kThreads) {
+    T px[kOutQ], e[kOutQ];
+#pragma unroll
+    for (int k = 0; k < kOutQ; ++k) {
+      const int i = ib + k * kThreads + threadIdx.x;
+      px[k] = i < ncol ? sx[i] : (T)0;
+      e[k] = (T)0;
     }
-    const int c = hist[hist_at(i + 1)];
-    T e;
-    if (nopen >= 0) {
+    if (nopen > 0) {
       // endpoint_term's terms in its order
-      e = (T)0;
       for (int t = 0; t < nopen; ++t) {
         const EndPts<T> q = sep[t];
-        e += open_loop_angle(q.sx - px, q.sy - yq, q.ex - px, q.ey - yq);
+        const T sy = q.sy - yq, ey = q.ey - yq;
+#pragma unroll
+        for (int k = 0; k < kOutQ; ++k) e[k] += open_loop_angle(q.sx - px[k], sy, q.ex - px[k], ey);
       }
-    } else {
-      e = endpoint_term(ctrl, L, px, yq);
     }
-    w[o] = finish_w(c, e);
-    if (chi) chi[o] = c;
+#pragma unroll
+    for (int k = 0; k < kOutQ; ++k) {
+      const int i = ib + k * kThreads + threadIdx.x;
+      if (i >= ncol) continue;
+      const int64_t o = row * nx + i0 + i;
+      if (!(isfinite(px[k]) && isfinite(yq))) {
+        w[o] = (T)NAN;
+        if (chi) chi[o] = WN_CHI_INVALID;
+        continue;
+      }
+      const int c = hist[hist_at(i + 1)];
+      const T ek = nopen >= 0 ? e[k] : endpoint_term(ctrl, L, px[k], yq);
+      w[o] = finish_w(c, ek);
+      if (chi) chi[o] = c;
+    }
   }
 }
 

@@ -178,3 +178,27 @@ def test_fp64_end_point_angle_to_round_off():
         u, v = a - P[keep], b - P[keep]
         ref = np.arctan2(u[:, 0] * v[:, 1] - u[:, 1] * v[:, 0], (u * v).sum(1)) / (2 * np.pi)
         assert np.abs(w.cpu().numpy() - ref).max() <= 1e-13
+
+
+def test_rows_crossing_every_piece():
+    """An open zig-zag of 800 straight cubics between y = -0.9 and y = 0.9:
+    every row in between crosses all 800 pieces (several solve passes per
+    row).  Grid mode equals points mode bit for bit; chi stays in {-1, 0, 1}
+    (the crossings alternate in direction); oracle parity on a sample."""
+    n = 800
+    xv = np.linspace(-1.0, 1.0, n + 1)
+    yv = np.where(np.arange(n + 1) % 2 == 0, -0.9, 0.9)
+    V = np.stack([xv, yv], 1)
+    a, b = V[:-1], V[1:]
+    ctrl = np.stack([a, a + (b - a) / 3, a + 2 * (b - a) / 3, b], 1)
+    C = synth.Curves2D(ctrl, np.array([0, n], np.int64), np.array([0], np.uint8))
+    xs = synth.grid_axis(-1.1, 1.1, 96)
+    ys = synth.grid_axis(-1.1, 1.1, 40)
+    w, chi = _eval(C, xs, ys, np.float64, grid=True)
+    X, Y = np.meshgrid(xs, ys)
+    P = np.stack([X.ravel(), Y.ravel()], 1)
+    wp, cp = _eval(C, P[:, 0], P[:, 1], np.float64, grid=False)
+    assert np.array_equal(w.ravel(), wp) and np.array_equal(chi.ravel(), cp)
+    assert set(np.unique(cp)) <= {-1, 0, 1} and len(np.unique(cp)) >= 2
+    s = synth.rng(12).choice(len(P), 200, replace=False)
+    _check(C, P[s], wp[s], cp[s], 1e-10, "zig-zag")
