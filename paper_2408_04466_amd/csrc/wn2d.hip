@@ -154,8 +154,17 @@ __device__ T solve_x(const Piece<T>& pc, T yq) {
     const T q = sizeof(T) == 4 ? (T)(f * __builtin_amdgcn_rcpf((float)fp)) : f / fp;
     T tn = (fp != (T)0) ? t - q : (T)0.5 * (lo + hi);
     const T a = fmin(lo, hi), b = fmax(lo, hi);
+    const T tol = (T)4 * (sizeof(T) == 4 ? (T)1.2e-7 : (T)2.3e-16) * fmax((T)1, fabs(b));
+    // converged: a step below the tolerance (also one that lands on the
+    // bracket's end, as it does once f rounds to zero or changes sign
+    // between neighbouring parameters; bisecting then would walk away from
+    // the root)
+    if (fabs(tn - t) <= tol) {
+      if (tn >= a && tn <= b) t = tn;
+      break;
+    }
     if (!(tn > a && tn < b)) tn = (T)0.5 * (lo + hi);
-    if (tn == t || b - a <= (T)4 * (sizeof(T) == 4 ? (T)1.2e-7 : (T)2.3e-16) * fmax((T)1, fabs(b))) {
+    if (b - a <= tol) {
       t = tn;
       break;
     }
