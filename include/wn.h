@@ -105,11 +105,14 @@ wn_status wn_boundary_loops(const int32_t* F, int64_t nf, int64_t nv,
  * wn_build_bvh -- prepare a triangle mesh for chi_d (Eq. chi; the ray-casting step of Alg. 1).
  *
  * Builds, on the GPU, the rotated frame of d (rows e1, e2, d; det +1; scaled
- * by a power of two so that coordinates are O(1)), the float64 rotated
- * vertices and a binary LBVH over the triangles' projections along d (every
- * ray of one call is parallel to d, so a node is a 2D box plus the largest
- * coordinate along d).  The handle owns its device memory and does not keep
- * V or F.
+ * by a power of two so that coordinates are O(1)), the rotated vertices and
+ * a binary LBVH over the triangles' projections along d (every ray of one
+ * call is parallel to d, so a node is a 2D box plus the largest coordinate
+ * along d), then folds every second level of that tree into a four-wide
+ * tree whose child boxes are 8-bit codes rounded outward (no ray loses a
+ * triangle).  The handle keeps that tree and one 128-byte record per sorted
+ * triangle (its rotated vertices as float32 pairs); it owns its device memory
+ * and does not keep V or F.
  *
  *  V    device [nv][3] float32; F device [nf][3] int32 (indices must lie in
  *       [0, nv): they are not checked on the device).
@@ -401,13 +404,13 @@ wn_status wn_backward(const float* bnd_xyz, const int64_t* loop_off, int32_t nlo
  * forbid allocation).  Same arguments, kernels, results (bit for bit) and
  * errors as wn_backward; the call makes no device allocation or free.
  *
- * Its workspace (per-wavefront vertex partials, first-stage float64 sums,
+ * Its workspace (per-workgroup vertex partials, first-stage float64 sums,
  * per-range query gradients) lives in one library-held device array of
  * WN_NOALLOC_SCRATCH_BYTES bytes.  Each GPU holds its own copy until the
  * process ends; its address is looked up on the first call on that device.
  * A call whose workspace does not fit returns WN_ERR_UNSUPPORTED and
  * enqueues nothing (the workspace of 2^20 queries over 512 boundary vertices
- * is about 27 MB, of 2^18 queries over 2048 vertices about 39 MB).
+ * is about 7 MB, of 2^18 queries over 2048 vertices about 20 MB).
  * Every call on one GPU uses that GPU's array: calls that overlap in time on
  * one GPU (other streams, other host threads) race and must be serialised
  * by the caller.  The array keeps the last call's contents; every entry a
