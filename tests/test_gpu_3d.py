@@ -334,3 +334,48 @@ def test_invalid_arguments_raise():
         W.eval_3d(dm.bvh, dm.bnd[:2].contiguous(), np.array([0, 2]), q, q, q)   # a 2-vertex loop
     with pytest.raises(TypeError):
         W.eval_3d(dm.bvh, dm.bnd, dm.loop_off, q.double(), q, q)
+
+
+def test_quantised_tree_on_clustered_and_elongated_meshes():
+    """The four-wide tree stores child boxes as 8-bit codes on each node's
+    grid, rounded outward.  Meshes that stress that grid: a disk of radius
+    1e-3 beside a unit disk 50 units away (nodes near the root span both,
+    so the small disk sits in a handful of codes), and a 100 x 0.002 strip
+    of 400 triangles (boxes of aspect 1e4 to 1e5).  chi must stay
+    bit-exact against the oracle near the small and thin parts, and the
+    fused, split and batched entry points must agree bit for bit."""
+    small = synth.disk_fan(64, radius=1e-3, z=0.0)
+    big = synth.disk_fan(64, radius=1.0, z=0.5)
+    Vb = big.V.copy()
+    Vb[:, :2] += 50.0
+    M1 = synth.Mesh(np.concatenate([small.V, Vb]).astype(np.float32),
+                    np.concatenate([small.F, big.F + len(small.V)]).astype(np.int32))
+    n = 200
+    xs = np.linspace(-50.0, 50.0, n + 1)
+    top = np.stack([xs, np.full(n + 1, 0.001), 0.01 * np.sin(xs)], 1)
+    bot = np.stack([xs, np.full(n + 1, -0.001), 0.01 * np.sin(xs)], 1)
+    V2 = np.concatenate([top, bot]).astype(np.float32)
+    k = np.arange(n)
+    F2 = np.concatenate([np.stack([k, n + 1 + k, k + 1], 1), np.stack([k + 1, n + 1 + k, n + 2 + k], 1)])
+    M2 = synth.Mesh(V2, F2.astype(np.int32))
+    g = synth.rng(31)
+    cases = [
+        (M1, g.uniform([-1.5e-3, -1.5e-3, -1e-3], [1.5e-3, 1.5e-3, 1e-3], (400, 3)), 7),
+        (M2, np.stack([g.uniform(-49.0, 49.0, 400), g.uniform(-0.003, 0.003, 400),
+                       g.uniform(-0.05, 0.05, 400)], 1), 8),
+    ]
+    for M, P, seed in cases:
+        d = synth.random_direction(seed)
+        dm = DevMesh(M, d)
+        P = P.astype(np.float32)
+        qx, qy, qz = dm.queries(P)
+        w, chi = W.eval_3d(dm.bvh, dm.bnd, dm.loop_off, qx, qy, qz)
+        chi3 = W.crossings_3d(dm.bvh, qx, qy, qz)
+        B = W.Batch([{"V": dm.V, "F": dm.F, "bnd": dm.bnd, "loop_off": dm.loop_off, "nq": len(P)}], d)
+        wb, cb = B.eval(qx, qy, qz)
+        torch.cuda.synchronize()
+        w, chi = w.cpu().numpy(), chi.cpu().numpy()
+        assert np.array_equal(chi3.cpu().numpy(), chi)
+        assert np.array_equal(wb.cpu().numpy(), w) and np.array_equal(cb.cpu().numpy(), chi)
+        assert np.any(chi != 0)
+        compare_3d(dm, P, w, chi, max_degenerate_frac=0.05, label=f"quantised tree {seed}")
