@@ -61,8 +61,11 @@ typedef int32_t wn_dtype;
 /* chi value written for a query whose input is not finite */
 #define WN_CHI_INVALID ((int32_t)0x80000000)
 
-/* Most boundary loops one wn_eval_3d / wn_backward / wn_eval_2d call takes
- * (the loop table travels in the kernel arguments). */
+/* Boundary loops whose table travels in the kernel arguments.  The 3D calls
+ * (wn_eval_3d, wn_eval_3d_boundary, wn_eval_3d_grid, wn_backward) take more:
+ * such a table is copied to device memory allocated on the call's stream
+ * (which the call then synchronises once) and freed after the launches.
+ * wn_eval_2d, wn_backward_2d and wn_backward_noalloc take at most this many. */
 #define WN_MAX_LOOPS 256
 
 typedef struct wn_bvh wn_bvh;       /* opaque: frame, rotated vertices, BVH */
@@ -143,11 +146,12 @@ wn_status wn_bvh_direction(const wn_bvh* bvh, double dir[3]);
  *             and the boundary term flip together where the ray meets dM.
  *  loop_off   host [nloops + 1] int64, nondecreasing, loop_off[0] = 0,
  *             every loop with >= 3 vertices; nb = loop_off[nloops].
- *             nloops = 0 (closed mesh) is allowed.  nloops <= WN_MAX_LOOPS.
+ *             nloops = 0 (closed mesh) is allowed; more than WN_MAX_LOOPS
+ *             loops are read from a device copy of the table.
  *  qx, qy, qz device [nq] float32 query coordinates (structure of arrays).
  *  w_out      device [nq] float32 out.
  *  chi_out    device [nq] int32 out (chi_d), or NULL.
- * Errors: INVALID_ARGUMENT, UNSUPPORTED (too many loops), HIP.
+ * Errors: INVALID_ARGUMENT, HIP.
  * ------------------------------------------------------------------------- */
 wn_status wn_eval_3d(const wn_bvh* bvh, const float* bnd_xyz,
                      const int64_t* loop_off, int32_t nloops,
@@ -408,9 +412,11 @@ wn_status wn_backward(const float* bnd_xyz, const int64_t* loop_off, int32_t nlo
  * per-range query gradients) lives in one library-held device array of
  * WN_NOALLOC_SCRATCH_BYTES bytes.  Each GPU holds its own copy until the
  * process ends; its address is looked up on the first call on that device.
- * A call whose workspace does not fit returns WN_ERR_UNSUPPORTED and
- * enqueues nothing (the workspace of 2^20 queries over 512 boundary vertices
- * is about 7 MB, of 2^18 queries over 2048 vertices about 20 MB).
+ * A call whose workspace does not fit, or whose loop table has more than
+ * WN_MAX_LOOPS loops (a longer table would need device memory), returns
+ * WN_ERR_UNSUPPORTED and enqueues nothing (the workspace of 2^20 queries
+ * over 512 boundary vertices is about 7 MB, of 2^18 queries over 2048
+ * vertices about 20 MB).
  * Every call on one GPU uses that GPU's array: calls that overlap in time on
  * one GPU (other streams, other host threads) race and must be serialised
  * by the caller.  The array keeps the last call's contents; every entry a

@@ -33,10 +33,12 @@ def _dev(t: torch.Tensor, dtype, name: str, shape=None):
     return C.c_void_p(t.data_ptr()) if t.numel() else C.c_void_p(0)
 
 
-def _loops(loop_off) -> tuple[np.ndarray, int]:
+def _loops(loop_off, limit: bool = False) -> tuple[np.ndarray, int]:
+    """Host loop offsets as int64 and the loop count (``limit``: the 2D plain
+    calls, whose loop table travels in the kernel arguments only)."""
     lo = np.ascontiguousarray(np.asarray(loop_off, dtype=np.int64))
     n = max(lo.size - 1, 0)
-    if n > WN_MAX_LOOPS:
+    if limit and n > WN_MAX_LOOPS:
         raise ValueError(f"at most {WN_MAX_LOOPS} loops per call")
     return lo, n
 
@@ -311,7 +313,7 @@ def eval_2d(ctrl: torch.Tensor, loop_off, loop_closed, x: torch.Tensor, y: torch
         raise TypeError("ctrl must be float32 or float64")
     nseg = ctrl.shape[0]
     pc = _dev(ctrl, dt, "ctrl", (nseg, 4, 2))
-    lo, nl = _loops(loop_off)
+    lo, nl = _loops(loop_off, limit=True)
     cl = np.ascontiguousarray(np.asarray(loop_closed, np.uint8))
     if cl.size != nl:
         raise ValueError("loop_closed must have one entry per loop")
@@ -491,7 +493,7 @@ def backward_2d(ctrl: torch.Tensor, loop_off, loop_closed, x: torch.Tensor, y: t
         raise TypeError("ctrl must be float32 or float64")
     nseg = ctrl.shape[0]
     pc = _dev(ctrl, dt, "ctrl", (nseg, 4, 2))
-    lo, nl = _loops(loop_off)
+    lo, nl = _loops(loop_off, limit=True)
     cl = np.ascontiguousarray(np.asarray(loop_closed, np.uint8))
     if cl.size != nl:
         raise ValueError("loop_closed must have one entry per loop")

@@ -174,9 +174,11 @@ __global__ void k_reduce_rows(const float* __restrict__ pv, const float* __restr
   const int v = (int)(t / 3), c = (int)(t % 3);
   int lf = -1;
   int cp = (pc && (v + 1) % span == 0 && v + 1 < nb) ? (v + 1) / span : -1;
+  const bnd::KernargLoops KL{L};
   for (int l = 0; l < L.n; ++l) {
-    if (L.off[l] == v && L.off[l + 1] > v) lf = l;
-    if (L.off[l] == v + 1) cp = -1;   // the range starts a loop: no carry
+    const int o = KL.off(l);
+    if (o == v && KL.off(l + 1) > v) lf = l;
+    if (o == v + 1) cp = -1;   // the range starts a loop: no carry
   }
   const int64_t r0 = (int64_t)blockIdx.y * kRowsPerGroup;
   const int64_t r1 = min(rows, r0 + kRowsPerGroup);

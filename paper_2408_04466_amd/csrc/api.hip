@@ -37,12 +37,11 @@ wn_status hip_fail(hipError_t e, const char* what) {
   return fail(WN_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Validate a host loop table and copy it into the kernel-argument form.
+// Validate a host loop table and copy it into the kernel-argument form (a
+// table of more than WN_MAX_LOOPS loops is left for upload_loops).
 wn_status make_loops(const int64_t* loop_off, int32_t nloops, int32_t min_len, int64_t* nb_out,
                      wn::LoopTable* L) {
   if (nloops < 0) return fail(WN_ERR_INVALID_ARGUMENT, "nloops must be >= 0 (got %d)", nloops);
-  if (nloops > WN_MAX_LOOPS)
-    return fail(WN_ERR_UNSUPPORTED, "at most %d boundary loops per call (got %d)", WN_MAX_LOOPS, nloops);
   std::memset(L, 0, sizeof *L);
   L->n = nloops;
   if (nloops == 0) {
@@ -58,8 +57,28 @@ wn_status make_loops(const int64_t* loop_off, int32_t nloops, int32_t min_len, i
   }
   if (loop_off[nloops] > INT32_MAX - 1)
     return fail(WN_ERR_UNSUPPORTED, "too many boundary vertices (%lld)", (long long)loop_off[nloops]);
-  for (int32_t l = 0; l <= nloops; ++l) L->off[l] = (int32_t)loop_off[l];
+  if (nloops <= WN_MAX_LOOPS)
+    for (int32_t l = 0; l <= nloops; ++l) L->off[l] = (int32_t)loop_off[l];
   *nb_out = loop_off[nloops];
+  return WN_OK;
+}
+
+wn_status upload_loops(const int64_t* loop_off, LoopTable* L, hipStream_t s, int32_t** owned) {
+  *owned = nullptr;
+  if (L->n <= WN_MAX_LOOPS) return WN_OK;
+  std::vector<int32_t> h((size_t)L->n + 1);
+  for (int32_t l = 0; l <= L->n; ++l) h[l] = (int32_t)loop_off[l];
+  int32_t* d = nullptr;
+  hipError_t e = hipMallocAsync((void**)&d, h.size() * sizeof(int32_t), s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
+  // the host copy must outlive the transfer
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    if (d) hipFreeAsync(d, s);
+    return hip_fail(e, "loop table");
+  }
+  L->dev = d;
+  *owned = d;
   return WN_OK;
 }
 
@@ -529,6 +548,8 @@ wn_status wn_eval_3d(const wn_bvh* h, const float* bnd_xyz, const int64_t* loop_
   if ((st = check_queries(qx, qy, qz, nq))) return st;
   if (nq == 0) return WN_OK;
   if (!w_out) return fail(WN_ERR_INVALID_ARGUMENT, "w_out is NULL");
+  int32_t* owned = nullptr;
+  if ((st = wn::host::upload_loops(loop_off, &L, as_stream(stream), &owned))) return st;
   // one fused kernel: traversal, boundary walk and combine per query
   wn::BndArgs a;
   a.F = h->F;
@@ -540,8 +561,9 @@ wn_status wn_eval_3d(const wn_bvh* h, const float* bnd_xyz, const int64_t* loop_
   a.nq = nq;
   a.chi_in = nullptr;
   a.w_out = w_out;
-  WN_HIP(wn::launch_fwd3d(cross_args(h, qx, qy, qz, nq, chi_out), a, L, chi_out, as_stream(stream)),
-         "forward");
+  const hipError_t e = wn::launch_fwd3d(cross_args(h, qx, qy, qz, nq, chi_out), a, L, chi_out, as_stream(stream));
+  if (owned) hipFreeAsync(owned, as_stream(stream));
+  WN_HIP(e, "forward");
   return WN_OK;
 }
 
@@ -763,6 +785,8 @@ wn_status wn_eval_3d_grid(const wn_bvh* h, const float* bnd_xyz, const int64_t* 
   if (!gx || !gy || !gz || !w_out) return fail(WN_ERR_INVALID_ARGUMENT, "NULL grid axis or output pointer");
   const int64_t nq = nx * ny * nz;
   hipStream_t s = as_stream(stream);
+  int32_t* owned = nullptr;
+  if ((st = wn::host::upload_loops(loop_off, &L, s, &owned))) return st;
   wn::CrossArgs ca = cross_args(h, nullptr, nullptr, nullptr, 0, nullptr);
   wn::BndArgs a;
   a.F = h->F;
@@ -772,7 +796,9 @@ wn_status wn_eval_3d_grid(const wn_bvh* h, const float* bnd_xyz, const int64_t* 
   a.nq = nq;
   a.chi_in = nullptr;
   a.w_out = w_out;
-  WN_HIP(wn::launch_grid3d_fwd(ca, a, L, gx, gy, gz, nx, ny, nz, chi_out, s), "grid forward");
+  const hipError_t e = wn::launch_grid3d_fwd(ca, a, L, gx, gy, gz, nx, ny, nz, chi_out, s);
+  if (owned) hipFreeAsync(owned, s);
+  WN_HIP(e, "grid forward");
   return WN_OK;
 }
 
@@ -789,7 +815,11 @@ wn_status wn_eval_3d_boundary(const wn_bvh* h, const float* bnd_xyz, const int64
   if ((st = check_queries(qx, qy, qz, nq))) return st;
   if (nq == 0) return WN_OK;
   if (!w_out || !chi_in) return fail(WN_ERR_INVALID_ARGUMENT, "w_out or chi_in is NULL");
-  return eval_boundary(h->F, bnd_xyz, L, nb, qx, qy, qz, nq, chi_in, w_out, as_stream(stream));
+  int32_t* owned = nullptr;
+  if ((st = wn::host::upload_loops(loop_off, &L, as_stream(stream), &owned))) return st;
+  st = eval_boundary(h->F, bnd_xyz, L, nb, qx, qy, qz, nq, chi_in, w_out, as_stream(stream));
+  if (owned) hipFreeAsync(owned, as_stream(stream));
+  return st;
 }
 
 wn_status wn_backward(const float* bnd_xyz, const int64_t* loop_off, int32_t nloops, const float* qx,
@@ -801,6 +831,8 @@ wn_status wn_backward(const float* bnd_xyz, const int64_t* loop_off, int32_t nlo
   wn_status st = wn::host::check_backward(bnd_xyz, loop_off, nloops, qx, qy, qz, nq, grad_w, &L, &nb);
   if (st) return st;
   hipStream_t s = as_stream(stream);
+  int32_t* owned = nullptr;
+  if ((st = wn::host::upload_loops(loop_off, &L, s, &owned))) return st;
   const wn::host::AdjPlan P = wn::host::plan_backward(nq, nb, nloops, grad_q != nullptr, grad_bnd != nullptr);
   wn::host::AdjWork W;
   // each workspace array on the stream, freed on the stream after the launches
@@ -818,6 +850,7 @@ wn_status wn_backward(const float* bnd_xyz, const int64_t* loop_off, int32_t nlo
   if (W.tmp) hipFreeAsync(W.tmp, s);
   if (W.pc) hipFreeAsync(W.pc, s);
   if (W.gqp) hipFreeAsync(W.gqp, s);
+  if (owned) hipFreeAsync(owned, s);
   if (e != hipSuccess) return hip_fail(e, "backward workspace");
   return st;
 }

@@ -775,7 +775,7 @@ wn_status wn_batch_create(const wn_surface* surfs, int32_t ns, const double dir[
     D.bnd_off = boff;
     D.loop_off = (int32_t)loops_h.size();
     D.nloops = S.nloops;
-    for (int l = 0; l <= S.nloops && S.nloops > 0; ++l) loops_h.push_back(lts[i].off[l]);
+    for (int l = 0; l <= S.nloops && S.nloops > 0; ++l) loops_h.push_back((int32_t)S.loop_off[l]);
     if (S.nloops == 0) loops_h.push_back(0);
     D.q_off = b->q_off[i];
     D.nq = S.nq;

@@ -40,19 +40,22 @@ constexpr int kStep = 16;        // vertices per main-loop step
 constexpr float kNear = 1073741824.0f;          // 2^30
 constexpr float kHuge = 72057594037927936.0f;   // 2^56
 
-// Loop table accessors: loops in the kernel arguments, or in device memory.
+// Loop table accessors: loops in the kernel arguments (or, for a long table,
+// in device memory named there), or in device memory.  Device tables are
+// read-only for the whole launch and read through the constant address
+// space, so a uniform index gives a scalar load and the loop bounds stay
+// wave-uniform.
 struct KernargLoops {
   const LoopTable& L;
   __device__ __forceinline__ int n() const { return L.n; }
-  __device__ __forceinline__ int off(int l) const { return L.off[l]; }
+  __device__ __forceinline__ int off(int l) const {
+    return L.dev ? ((const __attribute__((address_space(4))) int32_t*)(L.dev))[l] : L.off[l];
+  }
 };
 struct DeviceLoops {
   const int32_t* o;   // [n + 1], relative to the surface's first vertex
   int nl;
   __device__ __forceinline__ int n() const { return nl; }
-  // The table is read-only for the whole launch: read through the constant
-  // address space, so a uniform index gives a scalar load and the loop
-  // bounds stay wave-uniform.
   __device__ __forceinline__ int off(int l) const {
     return ((const __attribute__((address_space(4))) int32_t*)(o))[l];
   }

@@ -15,6 +15,10 @@ wn_status fail(wn_status s, const char* fmt, ...);
 wn_status hip_fail(hipError_t e, const char* what);
 wn_status make_loops(const int64_t* loop_off, int32_t nloops, int32_t min_len, int64_t* nb_out,
                      LoopTable* L);
+// A table of more than WN_MAX_LOOPS loops (validated by make_loops) copied to
+// device memory allocated on s; *owned is that allocation (null for a short
+// table), to be freed on s after the launches that read it.
+wn_status upload_loops(const int64_t* loop_off, LoopTable* L, hipStream_t s, int32_t** owned);
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 

@@ -10,9 +10,12 @@
 
 namespace wn {
 
-// Boundary loops of one call: loop l covers vertices [off[l], off[l+1]).
+// Boundary loops of one call: loop l covers vertices [off[l], off[l+1]).  Up
+// to WN_MAX_LOOPS loops travel in the kernel arguments; a longer table is
+// read from device memory (dev, [n + 1]; null otherwise).
 struct LoopTable {
   int32_t n;
+  const int32_t* dev;
   int32_t off[WN_MAX_LOOPS + 1];
 };
 

@@ -49,6 +49,9 @@ extern "C" wn_status wn_backward_noalloc(const float* bnd_xyz, const int64_t* lo
   int64_t nb = 0;
   wn_status st = wn::host::check_backward(bnd_xyz, loop_off, nloops, qx, qy, qz, nq, grad_w, &L, &nb);
   if (st) return st;
+  if (nloops > WN_MAX_LOOPS)   // a longer table would have to be copied to device memory
+    return wn::host::fail(WN_ERR_UNSUPPORTED, "wn_backward_noalloc takes at most %d boundary loops (got %d; use "
+                          "wn_backward)", WN_MAX_LOOPS, nloops);
   const wn::host::AdjPlan P = wn::host::plan_backward(nq, nb, nloops, grad_q != nullptr, grad_bnd != nullptr);
   const size_t need = wn::host::plan_bytes(P);
   if (need > kScratchBytes)

@@ -379,3 +379,60 @@ def test_quantised_tree_on_clustered_and_elongated_meshes():
         assert np.array_equal(wb.cpu().numpy(), w) and np.array_equal(cb.cpu().numpy(), chi)
         assert np.any(chi != 0)
         compare_3d(dm, P, w, chi, max_degenerate_frac=0.05, label=f"quantised tree {seed}")
+
+
+def test_more_boundary_loops_than_the_kernel_argument_table():
+    """300 small disks scattered in the unit box: 300 boundary loops, more than
+    the WN_MAX_LOOPS that travel in the kernel arguments, so the plain calls
+    read the loop table from device memory.  The fused, split and batched
+    forward and the grid mode agree bit for bit, and with the oracle on a
+    sample; plain and batched backward agree to rounding; the no-allocation
+    backward refuses the table."""
+    g = synth.rng(33)
+    nd = 300
+    Vs, Fs, o = [], [], 0
+    for k in range(nd):
+        D = synth.disk_fan(6, radius=0.04, z=0.0)
+        V = D.V.astype(np.float64)
+        c, s = np.cos(g.uniform(0, np.pi)), np.sin(g.uniform(0, np.pi))
+        V = V @ np.array([[1, 0, 0], [0, c, -s], [0, s, c]]).T + g.uniform(-1, 1, 3)
+        Vs.append(V)
+        Fs.append(D.F + o)
+        o += len(V)
+    M = synth.Mesh(np.concatenate(Vs).astype(np.float32), np.concatenate(Fs).astype(np.int32))
+    for d in (synth.random_direction(34), np.array([0.0, 0.0, 1.0])):
+        dm = DevMesh(M, d)
+        assert len(dm.loop_off) - 1 == nd > W.WN_MAX_LOOPS
+        P = g.uniform(-1.1, 1.1, (2048, 3)).astype(np.float32)
+        qx, qy, qz = dm.queries(P)
+        w, chi = W.eval_3d(dm.bvh, dm.bnd, dm.loop_off, qx, qy, qz)
+        chi3 = W.crossings_3d(dm.bvh, qx, qy, qz)
+        w3 = W.eval_3d_boundary(dm.bvh, dm.bnd, dm.loop_off, qx, qy, qz, chi3)
+        B = W.Batch([{"V": dm.V, "F": dm.F, "bnd": dm.bnd, "loop_off": dm.loop_off, "nq": len(P)}], d)
+        wb, cb = B.eval(qx, qy, qz)
+        torch.cuda.synchronize()
+        w, chi = w.cpu().numpy(), chi.cpu().numpy()
+        assert np.array_equal(w3.cpu().numpy(), w) and np.array_equal(chi3.cpu().numpy(), chi)
+        assert np.array_equal(wb.cpu().numpy(), w) and np.array_equal(cb.cpu().numpy(), chi)
+        assert np.any(chi != 0)
+        compare_3d(dm, P, w, chi, sample=synth.rng(35).choice(len(P), 200, replace=False),
+                   label="300 loops")
+        gw = torch.from_numpy(g.uniform(-1, 1, len(P)).astype(np.float32)).cuda()
+        gq, gbnd = W.backward(dm.bnd, dm.loop_off, qx, qy, qz, gw)
+        gq2, gbnd2 = B.backward(qx, qy, qz, gw)
+        torch.cuda.synchronize()
+        # few queries over 1800 boundary vertices: the plain call splits the
+        # boundary into ranges, the batch does not, so the sums differ in order
+        for a, b in ((gq, gq2), (gbnd, gbnd2)):
+            assert float((a - b).abs().max()) <= 1e-5 * float(b.abs().max())
+        assert float(gbnd.abs().sum()) > 0
+        with pytest.raises(W.WnError) as ei:
+            W.backward(dm.bnd, dm.loop_off, qx, qy, qz, gw, noalloc=True)
+        assert "at most" in str(ei.value)
+        if d[2] == 1.0:
+            ax = [synth.grid_axis(-1.0, 1.0, n, np.float32) for n in (10, 12, 16)]
+            wg, cg = W.eval_3d_grid(dm.bvh, dm.bnd, dm.loop_off, *[torch.from_numpy(a).cuda() for a in ax])
+            X, Y, Z = np.meshgrid(*ax, indexing="ij")
+            Pg = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1).astype(np.float32)
+            wp, cp = dm.eval(Pg)
+            assert np.array_equal(wg.cpu().numpy().ravel(), wp) and np.array_equal(cg.cpu().numpy().ravel(), cp)
