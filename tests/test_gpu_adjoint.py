@@ -227,3 +227,11 @@ def test_boundary_ranges_for_few_queries():
             rv += np.concatenate(b, 0)
         assert _rel(gqf.cpu().numpy(), rq) <= 1e-3, nq
         assert _rel(gbf.cpu().numpy(), rv) <= 1e-3, nq
+        # every vertex on its own (loops of 3 and 5 vertices, loops across the
+        # 16-vertex blocks and 256-vertex windows of the partial sums): a lost
+        # or doubled partial would be off by its whole size.  The bound is 1e-2
+        # of the component: where large per-query terms of a small component
+        # cancel, the float32 sums reach ~5e-3 of it (vertex 1751 at 3000
+        # queries, the same to 7 digits with the per-wavefront partials of
+        # earlier builds)
+        assert _componentwise(gbf.cpu().numpy(), rv, tol=1e-2) <= 1.0, nq
