@@ -18,8 +18,13 @@
 
 namespace wn {
 
+// Workgroups of two wavefronts: finer-grained than 256 lanes for the
+// scheduler to balance traversals of uneven length (3 % faster on 2^20
+// random queries than 256, the same as 64).
+constexpr int kCrossThreads = 128;
+
 template <int S>
-__global__ __launch_bounds__(256) void k_cross3d(CrossArgs a) {
+__global__ __launch_bounds__(kCrossThreads) void k_cross3d(CrossArgs a) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= a.nq) return;
   const float px = a.qx[q], py = a.qy[q], pz = a.qz[q];
@@ -34,8 +39,8 @@ __global__ __launch_bounds__(256) void k_cross3d(CrossArgs a) {
 
 hipError_t launch_cross3d(const CrossArgs& a, hipStream_t s) {
   if (a.nq == 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((a.nq + 255) / 256);
-  hipLaunchKernelGGL(k_cross3d<kShortStack>, dim3(blocks), dim3(256), 0, s, a);
+  const unsigned blocks = (unsigned)((a.nq + kCrossThreads - 1) / kCrossThreads);
+  hipLaunchKernelGGL(k_cross3d<kShortStack>, dim3(blocks), dim3(kCrossThreads), 0, s, a);
   return hipGetLastError();
 }
 
