@@ -436,3 +436,22 @@ def test_more_boundary_loops_than_the_kernel_argument_table():
             Pg = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1).astype(np.float32)
             wp, cp = dm.eval(Pg)
             assert np.array_equal(wg.cpu().numpy().ravel(), wp) and np.array_equal(cg.cpu().numpy().ravel(), cp)
+
+
+@pytest.mark.parametrize("n_tri", [2, 3, 4, 5, 9])
+def test_trees_of_a_few_triangles(n_tri):
+    """Fans of 2-9 triangles: the four-wide root then holds two to four
+    slots, leaves and nodes mixed; chi and w against the oracle."""
+    if n_tri == 2:   # a fan of two is flat: take a quad
+        D = synth.Mesh(np.array([[-1, -1, 0], [1, -1, 0], [1, 1, 0], [-1, 1, 0]], np.float32),
+                       np.array([[0, 1, 2], [0, 2, 3]], np.int32))
+    else:
+        D = synth.disk_fan(n_tri, radius=1.0, z=0.0)
+    V = D.V.astype(np.float64)
+    V[:, 2] += 0.3 * np.sin(3.0 * V[:, 0]) * np.cos(2.0 * V[:, 1])   # not flat
+    M = synth.Mesh(V.astype(np.float32), D.F)
+    dm = DevMesh(M, synth.random_direction(40 + n_tri))
+    P = synth.rng(41 + n_tri).uniform(-1.2, 1.2, (600, 3)).astype(np.float32)
+    w, chi = dm.eval(P)
+    assert np.any(chi != 0)
+    compare_3d(dm, P, w, chi, max_degenerate_frac=0.05, label=f"{n_tri} triangles")
