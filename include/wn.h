@@ -62,10 +62,11 @@ typedef int32_t wn_dtype;
 #define WN_CHI_INVALID ((int32_t)0x80000000)
 
 /* Boundary loops whose table travels in the kernel arguments.  The 3D calls
- * (wn_eval_3d, wn_eval_3d_boundary, wn_eval_3d_grid, wn_backward) take more:
- * such a table is copied to device memory allocated on the call's stream
- * (which the call then synchronises once) and freed after the launches.
- * wn_eval_2d, wn_backward_2d and wn_backward_noalloc take at most this many. */
+ * (wn_eval_3d, wn_eval_3d_boundary, wn_eval_3d_grid, wn_backward) and
+ * wn_eval_2d take more: such a table is copied to device memory allocated on
+ * the call's stream (which the call then synchronises once) and freed after
+ * the launches.  wn_backward_2d and wn_backward_noalloc take at most this
+ * many. */
 #define WN_MAX_LOOPS 256
 
 typedef struct wn_bvh wn_bvh;       /* opaque: frame, rotated vertices, BVH */
@@ -440,7 +441,8 @@ wn_status wn_backward_noalloc(const float* bnd_xyz, const int64_t* loop_off, int
  *             [nloops] uint8 (nonzero: the loop's last point equals its
  *             first point; zero: open, its two end points add
  *             (phi(end-p) - phi(start-p))/(2pi), phi in [0, 2pi) measured
- *             counter-clockwise from +x).
+ *             counter-clockwise from +x).  Any number of loops (more than
+ *             WN_MAX_LOOPS: a device copy of the table, see there).
  *  kind       0 = points: x[n], y[n] (n = nx, ny ignored);
  *             1 = grid: x[nx] ascending, y[ny]; outputs row-major [ny][nx]
  *             (one ray per row, the paper's one-shot reuse of Sec. 5).

@@ -34,8 +34,8 @@ def _dev(t: torch.Tensor, dtype, name: str, shape=None):
 
 
 def _loops(loop_off, limit: bool = False) -> tuple[np.ndarray, int]:
-    """Host loop offsets as int64 and the loop count (``limit``: the 2D plain
-    calls, whose loop table travels in the kernel arguments only)."""
+    """Host loop offsets as int64 and the loop count (``limit``: the 2D
+    adjoint, whose loop table travels in the kernel arguments only)."""
     lo = np.ascontiguousarray(np.asarray(loop_off, dtype=np.int64))
     n = max(lo.size - 1, 0)
     if limit and n > WN_MAX_LOOPS:
@@ -313,7 +313,7 @@ def eval_2d(ctrl: torch.Tensor, loop_off, loop_closed, x: torch.Tensor, y: torch
         raise TypeError("ctrl must be float32 or float64")
     nseg = ctrl.shape[0]
     pc = _dev(ctrl, dt, "ctrl", (nseg, 4, 2))
-    lo, nl = _loops(loop_off, limit=True)
+    lo, nl = _loops(loop_off)
     cl = np.ascontiguousarray(np.asarray(loop_closed, np.uint8))
     if cl.size != nl:
         raise ValueError("loop_closed must have one entry per loop")

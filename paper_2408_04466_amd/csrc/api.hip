@@ -905,7 +905,6 @@ wn_status wn_eval_2d(wn_dtype dtype, const void* ctrl, int64_t nseg, const int64
   if (nseg > (INT32_MAX - 3) / 3) return fail(WN_ERR_UNSUPPORTED, "too many segments");
   if (nseg > 0 && !ctrl) return fail(WN_ERR_INVALID_ARGUMENT, "ctrl is NULL");
   if (nloops < 0) return fail(WN_ERR_INVALID_ARGUMENT, "nloops must be >= 0");
-  if (nloops > WN_MAX_LOOPS) return fail(WN_ERR_UNSUPPORTED, "at most %d loops per call", WN_MAX_LOOPS);
   if (nloops > 0 && (!loop_off || !loop_closed)) return fail(WN_ERR_INVALID_ARGUMENT, "loop table is NULL");
   if (nloops > 0) {
     if (loop_off[0] != 0) return fail(WN_ERR_INVALID_ARGUMENT, "loop_off[0] must be 0");

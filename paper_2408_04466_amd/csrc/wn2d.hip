@@ -276,9 +276,9 @@ __device__ T endpoint_term(const T* __restrict__ ctrl, const LoopsT& L, T px, T 
 constexpr int kThreads = 256;
 constexpr int kPieceChunk = 256;
 
-template <class T>
+template <class T, class LoopsT>
 __global__ __launch_bounds__(kThreads) void k_points(const Piece<T>* __restrict__ pcs, int32_t npc,
-                                                     const T* __restrict__ ctrl, Loops2D L,
+                                                     const T* __restrict__ ctrl, LoopsT L,
                                                      const T* __restrict__ x, const T* __restrict__ y,
                                                      int64_t n, T* __restrict__ w, int32_t* __restrict__ chi) {
   __shared__ Piece<T> sp[kPieceChunk];
@@ -516,10 +516,10 @@ __device__ void grid_tile(const Piece<T>* __restrict__ pcs, const typename Vec2<
 // the row or lie beside the whole tile and lists the others in LDS, so that
 // the Newton solves run on consecutive lanes without idle lanes in between.
 // All counts are integer additions, so their order does not matter.
-template <class T>
+template <class T, class LoopsT>
 __global__ __launch_bounds__(kThreads) void k_grid(const Piece<T>* __restrict__ pcs,
                                                    const typename Vec2<T>::type* __restrict__ yr, int32_t npc,
-                                                   const T* __restrict__ ctrl, Loops2D L,
+                                                   const T* __restrict__ ctrl, LoopsT L,
                                                    const T* __restrict__ x, int64_t nx,
                                                    const T* __restrict__ y, int64_t ny,
                                                    T* __restrict__ w, int32_t* __restrict__ chi, int tile) {
@@ -936,8 +936,8 @@ hipError_t back2d(const T* ctrl, int64_t nseg, const Loops2D& L, int32_t kind, c
   return e;
 }
 
-template <class T>
-hipError_t run2d(const T* ctrl, int64_t nseg, const Loops2D& L, int32_t kind, const T* x, const T* y,
+template <class T, class LoopsT>
+hipError_t run2d(const T* ctrl, int64_t nseg, const LoopsT& L, int32_t kind, const T* x, const T* y,
                  int64_t nx, int64_t ny, T* w, int32_t* chi, hipStream_t s) {
   using V2 = typename Vec2<T>::type;
   const int64_t npc = 3 * nseg;
@@ -954,15 +954,15 @@ hipError_t run2d(const T* ctrl, int64_t nseg, const Loops2D& L, int32_t kind, co
   }
   if (e == hipSuccess) {
     if (kind == 0) {
-      hipLaunchKernelGGL(k_points<T>, dim3((unsigned)((nx + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
-                         pcs, (int32_t)npc, ctrl, L, x, y, nx, w, chi);
+      hipLaunchKernelGGL((k_points<T, LoopsT>), dim3((unsigned)((nx + kThreads - 1) / kThreads)), dim3(kThreads),
+                         0, s, pcs, (int32_t)npc, ctrl, L, x, y, nx, w, chi);
     } else {
       // tiles of at most kColTile columns, as even as possible; LDS sized to the tile
       const int64_t ntiles = (nx + kColTile - 1) / kColTile;
       const int tile = (int)((nx + ntiles - 1) / ntiles);
       const size_t lds = ((size_t)tile * sizeof(T) + (size_t)hist_words(tile) * sizeof(int) + 15) & ~(size_t)15;
-      hipLaunchKernelGGL(k_grid<T>, dim3((unsigned)ntiles, (unsigned)ny), dim3(kThreads), lds, s, pcs, yr,
-                         (int32_t)npc, ctrl, L, x, nx, y, ny, w, chi, tile);
+      hipLaunchKernelGGL((k_grid<T, LoopsT>), dim3((unsigned)ntiles, (unsigned)ny), dim3(kThreads), lds, s, pcs,
+                         yr, (int32_t)npc, ctrl, L, x, nx, y, ny, w, chi, tile);
     }
     e = hipGetLastError();
   }
@@ -1110,18 +1110,42 @@ hipError_t eval_2d_batched(const Batch2D& b, const void* ctrl, const void* x, co
   return run2d_batched<float>(b, (const float*)ctrl, (const float*)x, (const float*)y, (float*)w, chi, s);
 }
 
-hipError_t eval_2d(int32_t dtype, const void* ctrl, int64_t nseg, const int64_t* loop_off,
-                   const uint8_t* closed, int32_t nloops, int32_t kind, const void* x, const void* y,
-                   int64_t nx, int64_t ny, void* w, int32_t* chi, hipStream_t s) {
-  Loops2D L;
-  L.n = nloops;
-  for (int l = 0; l <= nloops; ++l) L.off[l] = (int32_t)loop_off[l];
-  for (int l = 0; l < nloops; ++l) L.closed[l] = closed[l] ? 1 : 0;
+template <class LoopsT>
+hipError_t run2d_typed(int32_t dtype, const void* ctrl, int64_t nseg, const LoopsT& L, int32_t kind, const void* x,
+                       const void* y, int64_t nx, int64_t ny, void* w, int32_t* chi, hipStream_t s) {
   if (dtype == WN_F64)
     return run2d<double>((const double*)ctrl, nseg, L, kind, (const double*)x, (const double*)y, nx, ny,
                          (double*)w, chi, s);
   return run2d<float>((const float*)ctrl, nseg, L, kind, (const float*)x, (const float*)y, nx, ny, (float*)w,
                       chi, s);
+}
+
+hipError_t eval_2d(int32_t dtype, const void* ctrl, int64_t nseg, const int64_t* loop_off,
+                   const uint8_t* closed, int32_t nloops, int32_t kind, const void* x, const void* y,
+                   int64_t nx, int64_t ny, void* w, int32_t* chi, hipStream_t s) {
+  if (nloops <= WN_MAX_LOOPS) {   // the table in the kernel arguments
+    Loops2D L;
+    L.n = nloops;
+    for (int l = 0; l <= nloops; ++l) L.off[l] = (int32_t)loop_off[l];
+    for (int l = 0; l < nloops; ++l) L.closed[l] = closed[l] ? 1 : 0;
+    return run2d_typed(dtype, ctrl, nseg, L, kind, x, y, nx, ny, w, chi, s);
+  }
+  // a longer table: one device copy (offsets, then flags) for this call
+  std::vector<int32_t> h((size_t)nloops + 1 + ((size_t)nloops + 3) / 4, 0);
+  for (int l = 0; l <= nloops; ++l) h[l] = (int32_t)loop_off[l];
+  uint8_t* hc = reinterpret_cast<uint8_t*>(h.data() + nloops + 1);
+  for (int l = 0; l < nloops; ++l) hc[l] = closed[l] ? 1 : 0;
+  int32_t* d = nullptr;
+  hipError_t e = hipMallocAsync((void**)&d, h.size() * sizeof(int32_t), s);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(d, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);   // the host copy must outlive the transfer
+  if (e == hipSuccess) {
+    const DevLoops2D L{nloops, d, reinterpret_cast<const uint8_t*>(d + nloops + 1)};
+    e = run2d_typed(dtype, ctrl, nseg, L, kind, x, y, nx, ny, w, chi, s);
+  }
+  const hipError_t e2 = hipFreeAsync(d, s);
+  return e != hipSuccess ? e : e2;
 }
 
 hipError_t backward_2d(int32_t dtype, const void* ctrl, int64_t nseg, const int64_t* loop_off,

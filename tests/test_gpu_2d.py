@@ -202,3 +202,42 @@ def test_rows_crossing_every_piece():
     assert set(np.unique(cp)) <= {-1, 0, 1} and len(np.unique(cp)) >= 2
     s = synth.rng(12).choice(len(P), 200, replace=False)
     _check(C, P[s], wp[s], cp[s], 1e-10, "zig-zag")
+
+
+def test_more_loops_than_the_kernel_argument_table():
+    """220 small closed circles (four cubics each) and 80 open cubic arcs:
+    300 loops, more than travel in the kernel arguments (the table is read
+    from device memory), and more open loops than a grid row stages (each
+    point then sums the end-point angles over the table itself).  Grid mode
+    equals points mode bit for bit; oracle parity on a sample."""
+    g = synth.rng(14)
+    k = 0.5522847498
+    segs, off, closed = [], [0], []
+    for _ in range(220):
+        c, r = g.uniform(-1, 1, 2), 0.03
+        pts = [c + r * np.array(p) for p in ((1, 0), (0, 1), (-1, 0), (0, -1))]
+        tan = [np.array(t) for t in ((0, 1), (-1, 0), (0, -1), (1, 0))]
+        for i in range(4):
+            a, b = pts[i], pts[(i + 1) % 4]
+            segs.append([a, a + k * r * tan[i], b - k * r * tan[(i + 1) % 4], b])
+        off.append(len(segs))
+        closed.append(1)
+    for _ in range(80):
+        a = g.uniform(-1, 1, 2)
+        segs.append([a, a + g.uniform(-0.1, 0.1, 2), a + g.uniform(-0.1, 0.1, 2), a + g.uniform(-0.1, 0.1, 2)])
+        off.append(len(segs))
+        closed.append(0)
+    C = synth.Curves2D(np.array(segs), np.array(off, np.int64), np.array(closed, np.uint8))
+    assert len(C.closed) == 300 > W.WN_MAX_LOOPS
+    xs = synth.grid_axis(-1.1, 1.1, 150)
+    ys = synth.grid_axis(-1.1, 1.1, 90)
+    for dtype, tol in ((np.float64, 1e-10), (np.float32, 1e-4)):
+        w, chi = _eval(C, xs, ys, dtype, grid=True)
+        X, Y = np.meshgrid(xs, ys)
+        P = np.stack([X.ravel(), Y.ravel()], 1)
+        wp, cp = _eval(C, P[:, 0], P[:, 1], dtype, grid=False)
+        assert np.array_equal(w.ravel(), wp) and np.array_equal(chi.ravel(), cp)
+        assert np.any(cp != 0)
+        s = synth.rng(15).choice(len(P), 300, replace=False)
+        Ps = P[s].astype(dtype).astype(np.float64)
+        _check(C, Ps, wp[s], cp[s], tol, f"300 loops {np.dtype(dtype).name}")
