@@ -834,22 +834,16 @@ wn_status wn_backward(const float* bnd_xyz, const int64_t* loop_off, int32_t nlo
   int32_t* owned = nullptr;
   if ((st = wn::host::upload_loops(loop_off, &L, s, &owned))) return st;
   const wn::host::AdjPlan P = wn::host::plan_backward(nq, nb, nloops, grad_q != nullptr, grad_bnd != nullptr);
-  wn::host::AdjWork W;
-  // each workspace array on the stream, freed on the stream after the launches
-  hipError_t e = hipSuccess;
-  if (P.n_pv) e = hipMallocAsync((void**)&W.pv, P.n_pv * sizeof(float), s);
-  if (e == hipSuccess && P.n_pl) e = hipMallocAsync((void**)&W.pl, P.n_pl * sizeof(float), s);
-  if (e == hipSuccess && P.n_tmp) e = hipMallocAsync((void**)&W.tmp, P.n_tmp * sizeof(double), s);
-  if (e == hipSuccess && P.n_pc) e = hipMallocAsync((void**)&W.pc, P.n_pc * sizeof(float), s);
-  if (e == hipSuccess && P.n_gqp) e = hipMallocAsync((void**)&W.gqp, P.n_gqp * sizeof(float), s);
+  // the workspace arrays in one block on the stream, freed on the stream
+  // after the launches
+  const size_t bytes = wn::host::plan_bytes(P);
+  void* base = nullptr;
+  hipError_t e = bytes ? hipMallocAsync(&base, bytes, s) : hipSuccess;
   if (e == hipSuccess) {
+    const wn::host::AdjWork W = wn::host::carve_backward(P, base);
     st = wn::host::run_backward(P, bnd_xyz, L, nb, qx, qy, qz, nq, grad_w, grad_q, grad_bnd, W, s);
   }
-  if (W.pv) hipFreeAsync(W.pv, s);
-  if (W.pl) hipFreeAsync(W.pl, s);
-  if (W.tmp) hipFreeAsync(W.tmp, s);
-  if (W.pc) hipFreeAsync(W.pc, s);
-  if (W.gqp) hipFreeAsync(W.gqp, s);
+  if (base) hipFreeAsync(base, s);
   if (owned) hipFreeAsync(owned, s);
   if (e != hipSuccess) return hip_fail(e, "backward workspace");
   return st;
