@@ -213,6 +213,23 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
 
 
+def grid2d_only(args):
+    """The 2D loops workload alone (16 loops x 64 cubics, float32, 2048^2 grid):
+    grid-mode forward and backward, for profiling their kernels in isolation."""
+    import torch
+    import paper_2408_04466_amd as W
+    dev = torch.device("cuda:0")
+    T = Timer(torch, torch.cuda.current_stream())
+    C2 = synth.loops2d()
+    ctrl = torch.from_numpy(C2.ctrl).to(dev)
+    xs = torch.from_numpy(synth.grid_axis(-1.2, 1.2, 2048, np.float32)).to(dev)
+    g = torch.ones(2048, 2048, dtype=torch.float32, device=dev)
+    ms = T.ms(lambda: W.eval_2d(ctrl, C2.loop_off, C2.closed, xs, xs, grid=True), args.steps)
+    msb = T.ms(lambda: W.backward_2d(ctrl, C2.loop_off, C2.closed, xs, xs, g, grid=True), args.steps)
+    print(json.dumps({"workload": "2d_loops_fp32_grid_2048^2", "forward_ms": ms, "backward_ms": msb,
+                      "steps": args.steps}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,12 +238,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--parity-sample", type=int, default=256)
     ap.add_argument("--only-c3", action="store_true", help="skip the other workloads")
+    ap.add_argument("--only-2d", action="store_true",
+                    help="only time the 2D loops workload on its 2048^2 grid (forward and backward) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 3 times (the reference kernel "
                          "for scaling HBM byte counters) and exit")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.only_2d:
+        grid2d_only(args)
         return
     if args.gpus != 1:
         print(f"bench.py: measures exactly one GPU (got --gpus {args.gpus}); "
