@@ -11,8 +11,7 @@ namespace {
 
 using namespace adj;
 
-// QPL queries per lane.  With 4, four waves per SIMD: the register
-// allocator then fits 128 registers, spilling one pointer outside the walk.
+// QPL queries per lane.  With 4, four waves per SIMD (at most 128 registers).
 template <int QPL>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(QPL == 4 ? 4 : (QPL == 2 ? 6 : 8)))) void k_adj3d(
     AdjArgs a, LoopTable L) {
@@ -43,7 +42,8 @@ __device__ __forceinline__ void walk_range(QState* S, const float* __restrict__ 
   const int lane = threadIdx.x & 63;
   float4* sv = lds.sv;
   Parker P = make_parker(lds, pv);
-  Rel F[QPL], A[QPL], B[QPL];
+  Rel A[QPL], B[QPL];
+  float4 vF = make_float4(0.f, 0.f, 0.f, 0.f);   // the loop's first vertex (uniform)
   float accA[3], accB[3];
   float4 eA = make_float4(0.f, 0.f, 0.f, 0.f);
   zero3(accA);
@@ -51,16 +51,13 @@ __device__ __forceinline__ void walk_range(QState* S, const float* __restrict__ 
   bool carry_in = cbeg > L.off(l);
   if (carry_in) {
     const int ls = L.off(l), i = cbeg - 1;   // i + 1 = cbeg lies in the same loop
-    const float4 f = make_float4(bnd[3 * ls], bnd[3 * ls + 1], bnd[3 * ls + 2], 0.f);
+    vF = make_float4(bnd[3 * ls], bnd[3 * ls + 1], bnd[3 * ls + 2], 0.f);
     const float x = bnd[3 * i], y = bnd[3 * i + 1], z = bnd[3 * i + 2];
     const float ex = __fsub_rn(bnd[3 * cbeg], x), ey = __fsub_rn(bnd[3 * cbeg + 1], y),
                 ez = __fsub_rn(bnd[3 * cbeg + 2], z);
     const float4 v = make_float4(x, y, z, 0.f);
 #pragma unroll
-    for (int k = 0; k < QPL; ++k) {
-      F[k] = rel(S[k], f);
-      A[k] = rel(S[k], v);
-    }
+    for (int k = 0; k < QPL; ++k) A[k] = rel(S[k], v);
     eA = make_float4(ex, ey, ez, __fmaf_rn(ex, ex, __fmaf_rn(ey, ey, __fmul_rn(ez, ez))));
   }
   for (int c0 = cbeg; c0 < cend; c0 += kChunk) {
@@ -74,11 +71,13 @@ __device__ __forceinline__ void walk_range(QState* S, const float* __restrict__ 
       const int j1 = min(le, c1);
       if (j == ls) {
         const float4 v = sv[j - c0];
+        // kept in scalar registers (every lane reads the same vertex) and
+        // seen from the queries again at the closing edge
+        vF = make_float4(__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v.x))),
+                         __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v.y))),
+                         __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v.z))), 0.f);
 #pragma unroll
-        for (int k = 0; k < QPL; ++k) {
-          F[k] = rel(S[k], v);
-          A[k] = F[k];
-        }
+        for (int k = 0; k < QPL; ++k) A[k] = rel(S[k], v);
         eA = sv[kChunk + j - c0];
         zero3(accA);
         ++j;
@@ -125,7 +124,9 @@ __device__ __forceinline__ void walk_range(QState* S, const float* __restrict__ 
         break;
       }
       float accF[3];
-      step<QPL>(S, A, F, eA, accA, accF, P, le - 1, nb, lane);
+#pragma unroll
+      for (int k = 0; k < QPL; ++k) B[k] = rel(S[k], vF);
+      step<QPL>(S, A, B, eA, accA, accF, P, le - 1, nb, lane);
       if (pl) put3(pl + 3 * (int64_t)l, accF, lds.sh, lane);
       zero3(accA);
     }

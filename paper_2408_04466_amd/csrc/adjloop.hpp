@@ -111,7 +111,9 @@ __device__ __forceinline__ void flush_window(Parker& P) {
   const int n = 3 * (P.hi - P.lo);
   const float* x = P.ps + 3 * (P.lo - P.f0);
   float* d = P.pv + 3 * (int64_t)P.lo;
-  for (int t = threadIdx.x; t < n; t += kThreads) {
+  int t0 = threadIdx.x;   // a fresh copy: no lane address kept live across the walk
+  asm volatile("" : "+v"(t0));
+  for (int t = t0; t < n; t += kThreads) {
     float s = x[t];
 #pragma unroll
     for (int w = 1; w < kWaves; ++w) s = __fadd_rn(s, x[w * kWin * 3 + t]);
