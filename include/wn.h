@@ -113,8 +113,9 @@ wn_status wn_boundary_loops(const int32_t* F, int64_t nf, int64_t nv,
  * a binary LBVH over the triangles' projections along d (every ray of one
  * call is parallel to d, so a node is a 2D box plus the largest coordinate
  * along d), then folds every second level of that tree into a four-wide
- * tree whose child boxes are 8-bit codes rounded outward (no ray loses a
- * triangle).  The handle keeps that tree and one 128-byte record per sorted
+ * tree whose child boxes are 8-bit cells of a per-node grid, assigned with
+ * the same monotone function the traversal applies to the query (no ray
+ * loses a triangle).  The handle keeps that tree and one 128-byte record per sorted
  * triangle (its rotated vertices as float32 pairs); it owns its device memory
  * and does not keep V or F.
  *

@@ -319,9 +319,13 @@ struct Slot4 {
   int32_t ref;
 };
 
-// Smallest power-of-two step s (as a biased exponent) with
-// fma(255, s, lo) >= hi in float32: the grid of 256 codes from lo covers hi.
-__device__ __forceinline__ uint32_t grid_exponent(float lo, float hi) {
+// Grid of one axis of a four-wide node whose children span [lo, hi]: the
+// inverse cell size i = 2^-e and the offset m of grid_cell, with cell(lo) >= 0
+// and cell(hi) <= 255, so that by monotonicity every bound of a child has a
+// cell in [0, 255].  e is the smallest exponent that fits the span in 256
+// cells, and at least such that m = -lo i stays far inside float32's range;
+// where m's rounding would put lo in cell -1, m is raised by an ulp.
+__device__ __forceinline__ void axis_grid(float lo, float hi, float& i, float& m) {
   const double r = ((double)hi - (double)lo) / 255.0;
   int e = -126;
   if (r > 0.0) {
@@ -329,28 +333,17 @@ __device__ __forceinline__ uint32_t grid_exponent(float lo, float hi) {
     frexp(r, &k);            // r < 2^k
     e = max(k - 1, -126);    // start one below, the loop settles it
   }
-  while (e < 127 && __fmaf_rn(255.0f, __uint_as_float((uint32_t)(e + 127) << 23), lo) < hi) ++e;
-  return (uint32_t)(e + 127);
-}
-
-__device__ __forceinline__ float grid_value(uint32_t code, float step, float origin) {
-  return __fmaf_rn((float)code, step, origin);
-}
-
-// Largest code whose decoded value is not above v (v >= origin).
-__device__ __forceinline__ uint32_t code_down(float v, float step, float origin) {
-  double q = floor(((double)v - (double)origin) / (double)step);
-  uint32_t c = (uint32_t)fmin(fmax(q, 0.0), 255.0);
-  while (c > 0 && grid_value(c, step, origin) > v) --c;
-  return c;
-}
-
-// Smallest code whose decoded value is not below v (v <= the grid's top).
-__device__ __forceinline__ uint32_t code_up(float v, float step, float origin) {
-  double q = ceil(((double)v - (double)origin) / (double)step);
-  uint32_t c = (uint32_t)fmin(fmax(q, 0.0), 255.0);
-  while (c < 255 && grid_value(c, step, origin) < v) ++c;
-  return c;
+  if (lo != 0.0f) {
+    int k;
+    frexp((double)lo, &k);   // |lo| < 2^k
+    e = max(e, k - 100);     // |m| < 2^100
+  }
+  for (;; ++e) {
+    i = __uint_as_float((uint32_t)(127 - e) << 23);
+    m = __fmul_rn(-lo, i);
+    while (grid_cell(lo, i, m) < 0.0f) m = nextafterf(m, INFINITY);
+    if (e >= 126 || grid_cell(hi, i, m) <= 255.0f) break;
+  }
 }
 
 // Four-wide node for every binary node at even depth: its children, with an
@@ -393,32 +386,31 @@ __global__ void k_collapse4(int32_t nf, const int32_t* __restrict__ dep, const B
     z1 = fmaxf(z1, sl[k].z);
   }
   BvhNode4 q;
-  q.pad[0] = q.pad[1] = 0u;
   q.ties = 0u;
   for (int k = 0; k < 4; ++k) {
     q.child[k] = k < n ? sl[k].ref : -1;
     if (k < n && sl[k].ref < 0 && ~sl[k].ref < nf) q.ties |= (tris[~sl[k].ref].ties & 7u) << (3 * k);
   }
   q.xlo = q.xhi = q.ylo = q.yhi = q.zhi = 0u;
-  if (mask == 0) {
-    q.ox = q.oy = q.oz = 0.0f;
-    q.meta = 127u | (127u << 8) | (127u << 16);
-  } else {
-    const uint32_t ex = grid_exponent(x0, x1), ey = grid_exponent(y0, y1), ez = grid_exponent(z0, z1);
-    const float sx = __uint_as_float(ex << 23), sy = __uint_as_float(ey << 23), sz = __uint_as_float(ez << 23);
-    q.ox = x0;
-    q.oy = y0;
-    q.oz = z0;
-    q.meta = ex | (ey << 8) | (ez << 16) | (mask << 24);
-    for (int k = 0; k < n; ++k) {
-      if (!((mask >> k) & 1u)) continue;
-      const float4 b = sl[k].box;
-      q.xlo |= code_down(b.x, sx, x0) << (8 * k);
-      q.xhi |= code_up(b.y, sx, x0) << (8 * k);
-      q.ylo |= code_down(b.z, sy, y0) << (8 * k);
-      q.yhi |= code_up(b.w, sy, y0) << (8 * k);
-      q.zhi |= code_up(sl[k].z, sz, z0) << (8 * k);
+  q.ix = q.iy = q.iz = 1.0f;
+  q.mx = q.my = q.mz = 0.0f;
+  if (mask != 0) {
+    axis_grid(x0, x1, q.ix, q.mx);
+    axis_grid(y0, y1, q.iy, q.my);
+    axis_grid(z0, z1, q.iz, q.mz);
+  }
+  for (int k = 0; k < 4; ++k) {
+    if (!((mask >> k) & 1u)) {
+      q.xlo |= 0xffu << (8 * k);   // xlo 255 > xhi 0: no cell passes
+      continue;
     }
+    const float4 b = sl[k].box;
+    // cells in [0, 255] (axis_grid), exact as integers
+    q.xlo |= (uint32_t)grid_cell(b.x, q.ix, q.mx) << (8 * k);
+    q.xhi |= (uint32_t)grid_cell(b.y, q.ix, q.mx) << (8 * k);
+    q.ylo |= (uint32_t)grid_cell(b.z, q.iy, q.my) << (8 * k);
+    q.yhi |= (uint32_t)grid_cell(b.w, q.iy, q.my) << (8 * k);
+    q.zhi |= (uint32_t)grid_cell(sl[k].z, q.iz, q.mz) << (8 * k);
   }
   out[node] = q;
 }

@@ -33,21 +33,22 @@ struct alignas(16) BvhNode {
 // with every second level folded into its parent, so that a node holds up to
 // four children (its binary children, or theirs where a binary child is
 // internal) and a query needs half the dependent node loads.  The children's
-// boxes are 8-bit codes on a grid of the node: bound = fma(code, 2^e, origin)
-// with a power-of-two step per axis, each code rounded outward at build time
-// with that same float32 arithmetic, so that every decoded box contains the
-// child's float box.  64 bytes, one aligned half cache line.  Nodes keep the
-// index of their binary node (the array is sparse: only binary nodes at even
-// depth are written).
+// boxes are 8-bit cells of an integer grid of the node: along each axis a
+// coordinate v lies in cell floor(fma(v, i, m)) (grid_cell; i a power of
+// two), and a child stores the cells of its float box's bounds, computed with
+// that same function.  The function is monotone in v, so every point of the
+// box has its cells between the stored ones: a query computes its three
+// cells once per node and then needs one comparison per bound, with no
+// decoding of the children's bounds.  64 bytes, one aligned half cache line.  Nodes
+// keep the index of their binary node (the array is sparse: only binary nodes
+// at even depth are written).
 struct alignas(64) BvhNode4 {
-  float ox, oy, oz;       // grid origin: smallest xmin, ymin and zmax of the children
-  uint32_t meta;          // biased exponents of the x, y, z steps (bits 0-23), occupied slots (bits 24-27)
-  uint32_t xlo, xhi;      // byte k: child k's code of xmin (rounded down), xmax (rounded up)
+  float ix, mx, iy, my, iz, mz;  // per axis the grid cell_i(v) = floor(fma(v, i, m)), cells 0..255 spanning the children
+  uint32_t xlo, xhi;      // byte k: child k's cells of xmin and xmax (an empty slot: 255 and 0, which no cell passes)
   uint32_t ylo, yhi;
-  uint32_t zhi;           // byte k: child k's code of zmax (rounded up)
+  uint32_t zhi;           // byte k: child k's cell of zmax
   int32_t child[4];       // >= 0 node index, < 0 leaf ~index into the sorted triangles
   uint32_t ties;          // bits 3k..3k+2: the edge tie signs of leaf child k (TriRec::ties)
-  uint32_t pad[2];
 };
 static_assert(sizeof(BvhNode4) == 64, "four-wide node is 64 bytes");
 

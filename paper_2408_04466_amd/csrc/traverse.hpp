@@ -108,11 +108,15 @@ __device__ __forceinline__ bool in_box(const float4 b, float bz, float x, float 
   return (x >= b.x) & (x <= b.y) & (y >= b.z) & (y <= b.w) & (z <= bz);
 }
 
-// Decoded bound of child k from a word of four codes (the same float32
-// operation as the build's rounding of the codes).
-__device__ __forceinline__ float grid_bound(uint32_t codes, int k, float step, float origin) {
-  return __fmaf_rn((float)((codes >> (8 * k)) & 0xffu), step, origin);
-}
+// Cell of coordinate v on one axis of a four-wide node's grid: floor(fma(v,
+// i, m)), kept as a float (an integer value; +-inf or NaN for such v).
+// Monotone non-decreasing in v (i > 0): the build assigns the children's
+// cells with this same function, and an 8-bit cell converted to float
+// compares with it exactly.  A NaN coordinate passes no comparison.
+__device__ __forceinline__ float grid_cell(float v, float i, float m) { return floorf(__fmaf_rn(v, i, m)); }
+
+// Cell k of a word of four 8-bit cells, as a float.
+__device__ __forceinline__ float cell_of(uint32_t cells, int k) { return (float)((cells >> (8 * k)) & 0xffu); }
 
 __device__ __forceinline__ int32_t child_ref(const BvhNode4& nd, int k) {
   return k == 0 ? nd.child[0] : k == 1 ? nd.child[1] : k == 2 ? nd.child[2] : nd.child[3];
@@ -142,15 +146,12 @@ __device__ __forceinline__ int traverse_leaves(const CrossArgs& a, float x, floa
   for (int32_t it = 0;; ++it) {
     if (it > nint || (uint32_t)node >= (uint32_t)nint) return WN_CHI_INVALID;
     const BvhNode4 nd = a.nodes[node];
-    const float sx = __uint_as_float((nd.meta & 0xffu) << 23);
-    const float sy = __uint_as_float(((nd.meta >> 8) & 0xffu) << 23);
-    const float sz = __uint_as_float(((nd.meta >> 16) & 0xffu) << 23);
+    const float cx = grid_cell(x, nd.ix, nd.mx), cy = grid_cell(y, nd.iy, nd.my), cz = grid_cell(z, nd.iz, nd.mz);
     uint32_t lm = 0, im = 0;   // hit leaves, hit nodes
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const bool h = (x >= grid_bound(nd.xlo, k, sx, nd.ox)) & (x <= grid_bound(nd.xhi, k, sx, nd.ox)) &
-                     (y >= grid_bound(nd.ylo, k, sy, nd.oy)) & (y <= grid_bound(nd.yhi, k, sy, nd.oy)) &
-                     (z <= grid_bound(nd.zhi, k, sz, nd.oz)) & (((nd.meta >> (24 + k)) & 1u) != 0u);
+      const bool h = (cell_of(nd.xlo, k) <= cx) & (cx <= cell_of(nd.xhi, k)) & (cell_of(nd.ylo, k) <= cy) &
+                     (cy <= cell_of(nd.yhi, k)) & (cz <= cell_of(nd.zhi, k));
       if (h) {
         if (nd.child[k] < 0) lm |= 1u << k;
         else im |= 1u << k;
