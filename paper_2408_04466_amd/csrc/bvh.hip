@@ -389,6 +389,7 @@ __global__ void k_collapse4(int32_t nf, const int32_t* __restrict__ dep, const B
   q.ties = 0u;
   for (int k = 0; k < 4; ++k) {
     q.child[k] = k < n ? sl[k].ref : -1;
+    if (q.child[k] < 0) q.ties |= 1u << (12 + k);
     if (k < n && sl[k].ref < 0 && ~sl[k].ref < nf) q.ties |= (tris[~sl[k].ref].ties & 7u) << (3 * k);
   }
   q.xlo = q.xhi = q.ylo = q.yhi = q.zhi = 0u;

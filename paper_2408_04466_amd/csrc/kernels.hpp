@@ -48,7 +48,7 @@ struct alignas(64) BvhNode4 {
   uint32_t ylo, yhi;
   uint32_t zhi;           // byte k: child k's cell of zmax
   int32_t child[4];       // >= 0 node index, < 0 leaf ~index into the sorted triangles
-  uint32_t ties;          // bits 3k..3k+2: the edge tie signs of leaf child k (TriRec::ties)
+  uint32_t ties;          // bits 3k..3k+2: the edge tie signs of leaf child k (TriRec::ties); bit 12 + k: child k is a leaf
 };
 static_assert(sizeof(BvhNode4) == 64, "four-wide node is 64 bytes");
 

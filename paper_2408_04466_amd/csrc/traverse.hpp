@@ -147,15 +147,17 @@ __device__ __forceinline__ int traverse_leaves(const CrossArgs& a, float x, floa
     if (it > nint || (uint32_t)node >= (uint32_t)nint) return WN_CHI_INVALID;
     const BvhNode4 nd = a.nodes[node];
     const float cx = grid_cell(x, nd.ix, nd.mx), cy = grid_cell(y, nd.iy, nd.my), cz = grid_cell(z, nd.iz, nd.mz);
-    uint32_t lm = 0, im = 0;   // hit leaves, hit nodes
+    uint32_t lm = 0, im;   // hit leaves, hit nodes (the hit slots first, split without branches)
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const bool h = (cell_of(nd.xlo, k) <= cx) & (cx <= cell_of(nd.xhi, k)) & (cell_of(nd.ylo, k) <= cy) &
                      (cy <= cell_of(nd.yhi, k)) & (cz <= cell_of(nd.zhi, k));
-      if (h) {
-        if (nd.child[k] < 0) lm |= 1u << k;
-        else im |= 1u << k;
-      }
+      lm |= h ? (1u << k) : 0u;
+    }
+    {
+      const uint32_t leaves = (nd.ties >> 12) & 0xfu;   // bit k: child k is a leaf
+      im = lm & ~leaves;
+      lm &= leaves;
     }
     while (lm) {
       const int k = __builtin_ctz(lm);
