@@ -337,10 +337,11 @@ def test_invalid_arguments_raise():
 
 
 def test_quantised_tree_on_clustered_and_elongated_meshes():
-    """The four-wide tree stores child boxes as 8-bit codes on each node's
-    grid, rounded outward.  Meshes that stress that grid: a disk of radius
+    """The four-wide tree stores child boxes as 8-bit cells of each node's
+    grid, assigned with the monotone cell function the traversal applies to
+    the query.  Meshes that stress that grid: a disk of radius
     1e-3 beside a unit disk 50 units away (nodes near the root span both,
-    so the small disk sits in a handful of codes), and a 100 x 0.002 strip
+    so the small disk sits in a handful of cells), and a 100 x 0.002 strip
     of 400 triangles (boxes of aspect 1e4 to 1e5).  chi must stay
     bit-exact against the oracle near the small and thin parts, and the
     fused, split and batched entry points must agree bit for bit."""
