@@ -182,13 +182,19 @@ __device__ __forceinline__ int main_steps(Lane<QPL>& s, const RPt* sv, int c0, i
       flush(s, pend);
       pend = 0;
     }
+    // the step's vertices through one vector register holding their LDS
+    // address, the reads taking immediate offsets (the compiler otherwise
+    // copies the uniform address into a vector register for every vertex)
+    int vo = (j - c0) * (int)sizeof(RPt);
+    asm volatile("" : "+v"(vo));
+    const RPt* sp = reinterpret_cast<const RPt*>(reinterpret_cast<const char*>(sv) + vo);
 #pragma unroll
     for (int u = 0; u < kStep; u += 2) {
-      const RPt v0 = sv[j + u - c0];
+      const RPt v0 = sp[u];
       vert_q(s, v0, B);
       edge_step(s, A, B, ptie);
       if (FAR) rescale(s);
-      const RPt v1 = sv[j + u + 1 - c0];
+      const RPt v1 = sp[u + 1];
       vert_q(s, v1, A);
       edge_step(s, B, A, rpt_tie(v0));
       ptie = rpt_tie(v1);
