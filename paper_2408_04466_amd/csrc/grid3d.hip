@@ -21,7 +21,8 @@
 // traversed per wavefront rather than once per column: a separate pass over
 // the columns left its traversals' latency exposed (0.99 against 0.76 ms on
 // the 128^3 grid), while here it hides behind the boundary arithmetic of the
-// other wavefronts.
+// other wavefronts.  The boundary walk of such a wavefront shares the
+// column's part of the arithmetic as well (column_walk, below).
 #include "bndloop.hpp"
 #include "bvh_build.hpp"
 #include "traverse.hpp"
@@ -34,14 +35,183 @@ using namespace bnd;
 
 constexpr int kColHits = 16;   // crossings kept per line
 
+// ---------------------------------------------------------------------------
+// Boundary walk of a wavefront whose lanes share one column
+// ---------------------------------------------------------------------------
+// The frame X, Y offsets of a boundary vertex are the same for every point of
+// a column, and so is all that the walk derives from them alone: rho^2 of a
+// vertex, and of an edge its N (certified in float32 or exact, with the tie)
+// and the X, Y part of D.  The wavefront computes these once per staged chunk
+// into LDS; each lane then adds what depends on its height: Z, r, alpha, D
+// and the product.  Each value is the same float operation on the same
+// operands as in vertex_q, edge_d and turns_edge, and the product is rescaled
+// and its turns decided after the same edges as in boundary_walk, so w is
+// bit-identical to the per-query walk.
+
+struct ColLds {
+  float rho2[kThreads / 64][kChunk];
+  float2 ng[kThreads / 64][kChunk];   // edge (j - 1 -> j) of the staged order: N, fma(X_a, X_b, Y_a Y_b)
+};
+
+// The column's data for the staged chunk (cnt vertices), the X, Y offsets
+// taken from pc (the column's split coordinates); prev: the previous chunk's
+// last vertex (used when has_prev).  The edge into a loop's first vertex is
+// computed too and never read.
+__device__ __forceinline__ void column_chunk(const RPt* sv, int cnt, bool has_prev, const RPt& prev, const QP& pc,
+                                             float* rho2, float2* ng) {
+  for (int j = threadIdx.x & 63; j < cnt; j += 64) {
+    const RPt v = sv[j];
+    VQ b;
+    b.x = vertex_x(v, pc);
+    b.y = vertex_y(v, pc);
+    b.a = 0.0f;
+    rho2[j] = __fmaf_rn(b.x, b.x, __fmul_rn(b.y, b.y));
+    if (j > 0 || has_prev) {
+      const RPt u = j > 0 ? sv[j - 1] : prev;
+      VQ a;
+      a.x = vertex_x(u, pc);
+      a.y = vertex_y(u, pc);
+      a.a = 0.0f;
+      const WalkN w = edge_n_walk(a, b);
+      const float N = w.sure ? w.n : edge_n_exact(a, b, rpt_tie(u));
+      ng[j] = make_float2(N, __fmaf_rn(a.x, b.x, __fmul_rn(a.y, b.y)));
+    }
+  }
+}
+
+// turns_mul with the sign registers pinned after the edge, as turns_edge
+// does (the compiler would otherwise defer a step's bit insertions)
+__device__ __forceinline__ void column_mul(Turns& t, float D, float N) {
+  turns_mul(t, D, N);
+  asm volatile("" : "+v"(t.bacc), "+v"(t.cacc));
+}
+
+// alpha of a staged vertex for the lane's query (vertex_q's arithmetic, with
+// the column's rho^2).
+__device__ __forceinline__ float column_alpha(const RPt& v, const QP& p, float rho2) {
+  const float Z = vertex_z(v, p);
+  const float s = __fmaf_rn(Z, Z, rho2);
+  const float r = __builtin_amdgcn_sqrtf(s);
+  const float u = __fadd_rn(r, fabsf(Z));
+  return __fmaf_rn(rho2, __builtin_amdgcn_rcpf(u), __fsub_rn(fabsf(Z), Z));
+}
+
+// main_steps with the column's data (the same edges, rescales and flushes).
+template <bool FAR>
+__device__ __forceinline__ int column_steps(Lane<1>& s, const RPt* sv, const float* rho2, const float2* ng, int c0,
+                                            int j, int j1, float& aA, int& pend) {
+  for (; j + kStep <= j1; j += kStep) {
+    if (pend > kStep) {
+      flush(s, pend);
+      pend = 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kStep; u += 2) {
+      const int i = j + u - c0;
+      const float a0 = column_alpha(sv[i], s.p[0], rho2[i]);
+      const float2 e0 = ng[i];
+      column_mul(s.T[0], __fmaf_rn(aA, a0, e0.y), e0.x);
+      if (FAR) rescale(s);
+      const float a1 = column_alpha(sv[i + 1], s.p[0], rho2[i + 1]);
+      const float2 e1 = ng[i + 1];
+      column_mul(s.T[0], __fmaf_rn(a0, a1, e1.y), e1.x);
+      aA = a1;
+      rescale(s);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    pend += kStep;
+    if (pend == 2 * kStep) {
+      flush(s, pend);
+      pend = 0;
+    }
+  }
+  return j;
+}
+
+// boundary_walk for a wavefront on one column (pc: the column's uniform split
+// X, Y).  Every thread of the workgroup must call this or boundary_walk
+// together: both pass the same barriers.
+template <class Stager, class Loops>
+__device__ __forceinline__ void column_walk(Lane<1>& s, const Stager& stage, int nb, const Loops& L, RPt* sv,
+                                            ColLds& cl, const QP& pc, int& pend) {
+  float* rho2 = cl.rho2[threadIdx.x >> 6];
+  float2* ng = cl.ng[threadIdx.x >> 6];
+  VQ first[1];
+  first[0].x = first[0].y = first[0].a = 0.0f;
+  float aA = 0.0f;                 // alpha of the last vertex visited
+  RPt prev;
+  prev.xy = prev.zt = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  int l = 0;
+  for (int c0 = 0; c0 < nb; c0 += kChunk) {
+    const int c1 = min(c0 + kChunk, nb);
+    if (c0 > 0) prev = sv[kChunk - 1];   // the previous chunk was full
+    __syncthreads();
+    stage(c0, c1 - c0, sv);
+    __syncthreads();
+    column_chunk(sv, c1 - c0, c0 > 0, prev, pc, rho2, ng);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (; l < L.n() && L.off(l) < c1; ++l) {
+      const int ls = L.off(l), le = L.off(l + 1);
+      int j = max(ls, c0);
+      const int j1 = min(le, c1);
+      if (j == ls) {
+        first[0] = vertex_q(sv[j - c0], s.p[0]);
+        aA = first[0].a;
+        ++j;
+      }
+      if (s.far)
+        j = column_steps<true>(s, sv, rho2, ng, c0, j, j1, aA, pend);
+      else
+        j = column_steps<false>(s, sv, rho2, ng, c0, j, j1, aA, pend);
+      for (; j < j1; ++j) {
+        const int i = j - c0;
+        const float a = column_alpha(sv[i], s.p[0], rho2[i]);
+        const float2 e = ng[i];
+        column_mul(s.T[0], __fmaf_rn(aA, a, e.y), e.x);
+        rescale(s);
+        aA = a;
+        if (++pend == 32) {
+          flush(s, 32);
+          pend = 0;
+        }
+      }
+      if (j1 < le) break;            // the loop continues in the next chunk
+      // closing edge last -> first, with the per-query edge arithmetic
+      const RPt v = sv[le - 1 - c0];
+      VQ A[1];
+      A[0].x = vertex_x(v, s.p[0]);
+      A[0].y = vertex_y(v, s.p[0]);
+      A[0].a = aA;
+      edge_step(s, A, first, rpt_tie(v));
+      rescale(s);
+      if (++pend == 32) {
+        flush(s, 32);
+        pend = 0;
+      }
+    }
+  }
+}
+
 // 32-bit index arithmetic (the host limits grids to fewer than 2^32
 // points): 64-bit divisions would be long emulated sequences per query.
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_grid3d_fwd(CrossArgs c, BndArgs a, LoopTable L,
+// COLS: the column data for the shared walk is allocated (24 KB of LDS, four
+// waves per SIMD instead of eight); the host sets it when nz is a multiple
+// of 64, so that every wavefront lies on one column.
+template <bool COLS>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(COLS ? 4 : 8))) void k_grid3d_fwd(CrossArgs c, BndArgs a, LoopTable L,
                                                          const float* __restrict__ gx, const float* __restrict__ gy,
                                                          const float* __restrict__ gz, int64_t ny64, int64_t nz64,
                                                          int32_t* chi_out) {
-  __shared__ RPt sv[kChunk];
-  __shared__ int32_t s_hits[kThreads / 64][kColHits];
+  // the staged boundary, and before it the lines' crossing lists (read
+  // before the walk stages its first chunk)
+  __shared__ union {
+    RPt sv[kChunk];
+    int32_t hits[kThreads / 64][kColHits];
+  } su;
+  RPt* sv = su.sv;
+  auto& s_hits = su.hits;
   const int64_t qi = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const bool ok = qi < a.nq;
   const int64_t q = ok ? qi : 0;
@@ -60,14 +230,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
   // the wavefront's line: one traversal when all its lanes share the column
   const uint32_t col0 = __builtin_amdgcn_readfirstlane(col);
   const bool one_col = __all(col == col0 || !ok);
+  QP pu;   // the column's X, Y (identical in every lane; made uniform)
+  pu.xh = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s.p[0].xh)));
+  pu.xl = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s.p[0].xl)));
+  pu.yh = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s.p[0].yh)));
+  pu.yl = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s.p[0].yl)));
+  pu.zh = pu.zl = 0.0f;
+  // wavefront-uniform: lane 0 is a query of the wavefront's column unless
+  // the wavefront holds none
+  const bool line = one_col && isfinite(pu.xh) && isfinite(pu.yh);
   int n = kColHits + 1;
-  if (one_col && isfinite(px) && isfinite(py)) {
-    QP pu;   // the column's X, Y (identical in every lane; made uniform)
-    pu.xh = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s.p[0].xh)));
-    pu.xl = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s.p[0].xl)));
-    pu.yh = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s.p[0].yh)));
-    pu.yl = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s.p[0].yl)));
-    pu.zh = pu.zl = 0.0f;
+  if (line) {
     // crossings below every lane of the wavefront count for none of them:
     // cull at the lowest query (a weaker cut than each lane's own)
     float zmin = s.p[0].zh;
@@ -95,7 +268,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
   }
   int staged = -1, pend = 0;
   const KernargLoops KL{L};
-  boundary_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, staged, pend);
+  // both walks stage their first chunk after a barrier, which every
+  // wavefront reaches with its crossing list read
+  if constexpr (COLS) {
+    __shared__ ColLds cl;
+    if (line)
+      column_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, cl, pu, pend);
+    else
+      boundary_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, staged, pend);
+  } else {
+    boundary_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, staged, pend);
+  }
   finish_turns(s, pend);
   if (ok) {
     a.w_out[q] = chi != WN_CHI_INVALID ? lane_w(s, 0, chi) : __int_as_float(0x7fc00000);
@@ -112,8 +295,12 @@ hipError_t launch_grid3d_fwd(const CrossArgs& c, const BndArgs& a, const LoopTab
   const int64_t blocks = (a.nq + kThreads - 1) / kThreads;
   if (blocks == 0) return hipSuccess;
   if (a.nq > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_grid3d_fwd, dim3((unsigned)blocks), dim3(kThreads), 0, s, c, a, L, gx, gy, gz, ny, nz,
-                     chi_out);
+  if (nz % 64 == 0)
+    hipLaunchKernelGGL(k_grid3d_fwd<true>, dim3((unsigned)blocks), dim3(kThreads), 0, s, c, a, L, gx, gy, gz, ny, nz,
+                       chi_out);
+  else
+    hipLaunchKernelGGL(k_grid3d_fwd<false>, dim3((unsigned)blocks), dim3(kThreads), 0, s, c, a, L, gx, gy, gz, ny,
+                       nz, chi_out);
   return hipGetLastError();
 }
 

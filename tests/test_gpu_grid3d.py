@@ -45,14 +45,17 @@ def _stack_of_disks(n_layers, n_tri=48):
     return synth.Mesh(np.concatenate(Vs).astype(np.float32), np.concatenate(Fs).astype(np.int32))
 
 
+# nz = 16: wavefronts span several columns (the per-lane walk); nz = 128:
+# each wavefront lies on one column (the column's shared walk)
+@pytest.mark.parametrize("shape", [(24, 20, 16), (6, 5, 128)])
 @pytest.mark.parametrize("name", ["bumpy_cap", "coons", "sphere"])
-def test_grid_equals_per_query_path_and_oracle(name):
+def test_grid_equals_per_query_path_and_oracle(name, shape):
     M = {"bumpy_cap": synth.bumpy_cap(), "coons": synth.coons_surface(3, 3000, 96),
          "sphere": synth.icosphere(3, radius=0.8)}[name]
     dm = DevMesh(M, DZ)
-    ax = _axes(M, (24, 20, 16))
+    ax = _axes(M, shape)
     w, chi = _grid(dm, ax)
-    assert tuple(w.shape) == (24, 20, 16)
+    assert tuple(w.shape) == shape
     P = _points(ax)
     wp, cp = dm.eval(P)
     assert np.array_equal(chi.cpu().numpy().ravel(), cp)
@@ -61,14 +64,19 @@ def test_grid_equals_per_query_path_and_oracle(name):
     compare_3d(dm, P, wp, cp, sample)
 
 
+@pytest.mark.parametrize("shape", [(10, 12, 30), (6, 4, 64)])
 @pytest.mark.parametrize("layers", [12, 40])
-def test_deep_stack_of_surfaces(layers):
+def test_deep_stack_of_surfaces(layers, shape):
     # stacked disks: columns through the stack cross every layer (12: kept in
     # the column lists; 40: more than a list holds, those columns' points
-    # traverse the tree themselves)
+    # traverse the tree themselves).  Their 576 or 1920 boundary vertices in
+    # 12 or 40 loops take two or four staged chunks, with loops running
+    # across chunk ends (nz = 64: the column's shared walk carries the last
+    # vertex of a chunk into the next).  Even x and y counts keep the columns
+    # off the disks' projected edges through the centre.
     M = _stack_of_disks(layers)
     dm = DevMesh(M, DZ)
-    ax = _axes(M, (10, 12, 30))
+    ax = _axes(M, shape)
     w, chi = _grid(dm, ax)
     P = _points(ax)
     wp, cp = dm.eval(P)
@@ -87,17 +95,24 @@ def test_grid_edge_cases():
     g = [torch.from_numpy(a).cuda() for a in ax]
     w, chi = W.eval_3d_grid(dm.bvh, dm.bnd, dm.loop_off, g[0], e, g[2])
     assert tuple(w.shape) == (5, 0, 3)
-    # a non-finite axis value makes exactly its points invalid
-    ax2 = [a.copy() for a in ax]
-    ax2[1][2] = np.nan
-    ax2[2][0] = np.inf
-    w, chi = _grid(dm, ax2)
-    w, chi = w.cpu().numpy(), chi.cpu().numpy()
-    bad = np.zeros((5, 4, 3), bool)
-    bad[:, 2, :] = True
-    bad[:, :, 0] = True
-    assert np.all(np.isnan(w[bad])) and np.all(chi[bad] == W.WN_CHI_INVALID)
-    assert np.all(np.isfinite(w[~bad]))
+    # a non-finite axis value makes exactly its points invalid (nz = 64: a
+    # non-finite x or y takes the column off the shared walk)
+    for nzk in (3, 64):
+        ax2 = _axes(M, (5, 4, nzk))
+        ax2[1][2] = np.nan
+        ax2[2][0] = np.inf
+        w, chi = _grid(dm, ax2)
+        w, chi = w.cpu().numpy(), chi.cpu().numpy()
+        bad = np.zeros((5, 4, nzk), bool)
+        bad[:, 2, :] = True
+        bad[:, :, 0] = True
+        assert np.all(np.isnan(w[bad])) and np.all(chi[bad] == W.WN_CHI_INVALID)
+        assert np.all(np.isfinite(w[~bad]))
+        if nzk == 64:
+            P = _points(ax2)
+            ok = ~bad.ravel()
+            wp, cp = dm.eval(P[ok])
+            assert np.array_equal(w.ravel()[ok], wp) and np.array_equal(chi.ravel()[ok], cp)
     # a BVH for another direction is refused
     dm2 = DevMesh(M, synth.random_direction(2))
     with pytest.raises(W.WnError) as ei:
