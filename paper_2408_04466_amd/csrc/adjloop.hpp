@@ -69,10 +69,14 @@ __device__ __forceinline__ float wave_sum_last(float v) {
   return v;
 }
 
-// Sum over each quad of 4 lanes (every lane of the quad holds it).
+// Sum over each quad of 4 lanes (every lane of the quad holds it).  The
+// empty asm keeps the sum computed in every lane at this point: sunk into the
+// branch of the lanes that store it, the second step would become a move, a
+// DPP move and an add instead of one DPP add.
 __device__ __forceinline__ float quad_sum(float v) {
   v += dpp<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
   v += dpp<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  asm volatile("" : "+v"(v));
   return v;
 }
 
