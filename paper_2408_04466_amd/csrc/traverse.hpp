@@ -82,17 +82,25 @@ template <int S>
 struct RegStack {
   int32_t e[S];   // e[0] = top
   int n;
-  __device__ __forceinline__ void init() { n = 0; }
-  __device__ __forceinline__ bool push(int32_t v, int32_t* spill) {
+  bool lost;
+  __device__ __forceinline__ void init() {
+    n = 0;
+    lost = false;
+  }
+  // Never fails: an entry beyond the spill array (only a malformed tree
+  // gets there) is dropped and recorded in `lost`, which the caller checks
+  // before its next pop.
+  __device__ __forceinline__ void push(int32_t v, int32_t* spill) {
     if (n >= S) {
-      if (n - S >= kSpill) return false;
-      spill[n - S] = e[S - 1];
+      if (n - S < kSpill)
+        spill[n - S] = e[S - 1];
+      else
+        lost = true;
     }
 #pragma unroll
     for (int i = S - 1; i > 0; --i) e[i] = e[i - 1];
     e[0] = v;
     ++n;
-    return true;
   }
   __device__ __forceinline__ int32_t pop(const int32_t* spill) {
     const int32_t v = e[0];
@@ -169,10 +177,16 @@ __device__ __forceinline__ int traverse_leaves(const CrossArgs& a, float x, floa
     if (im) {
       node = child_ref(nd, __builtin_ctz(im));
       im &= im - 1u;
-      while (im) {
-        if (!st.push(child_ref(nd, __builtin_ctz(im)), spill)) return WN_CHI_INVALID;
-        im &= im - 1u;
+      // at most three siblings wait (unrolled: a loop keeps copies of the
+      // register stack alive across its iterations)
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        if (im) {
+          st.push(child_ref(nd, __builtin_ctz(im)), spill);
+          im &= im - 1u;
+        }
       }
+      if (st.lost) return WN_CHI_INVALID;
     } else {
       if (st.n == 0) break;
       node = st.pop(spill);
