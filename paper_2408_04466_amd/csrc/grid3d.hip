@@ -48,18 +48,20 @@ constexpr int kColHits = 16;   // crossings kept per line
 // and its turns decided after the same edges as in boundary_walk, so w is
 // bit-identical to the per-query walk.
 
+// One slot per column of the workgroup (CPW columns of 4 / CPW wavefronts).
+template <int CPW>
 struct ColLds {
-  float rho2[kThreads / 64][kChunk];
-  float2 ng[kThreads / 64][kChunk];   // edge (j - 1 -> j) of the staged order: N, fma(X_a, X_b, Y_a Y_b)
+  float rho2[CPW][kChunk];
+  float2 ng[CPW][kChunk];   // edge (j - 1 -> j) of the staged order: N, fma(X_a, X_b, Y_a Y_b)
 };
 
 // The column's data for the staged chunk (cnt vertices), the X, Y offsets
 // taken from pc (the column's split coordinates); prev: the previous chunk's
 // last vertex (used when has_prev).  The edge into a loop's first vertex is
-// computed too and never read.
+// computed too and never read.  Vertices t0, t0 + stride, ... of the chunk.
 __device__ __forceinline__ void column_chunk(const RPt* sv, int cnt, bool has_prev, const RPt& prev, const QP& pc,
-                                             float* rho2, float2* ng) {
-  for (int j = threadIdx.x & 63; j < cnt; j += 64) {
+                                             float* rho2, float2* ng, int t0, int stride) {
+  for (int j = t0; j < cnt; j += stride) {
     const RPt v = sv[j];
     VQ b;
     b.x = vertex_x(v, pc);
@@ -128,14 +130,17 @@ __device__ __forceinline__ int column_steps(Lane<1>& s, const RPt* sv, const flo
   return j;
 }
 
-// boundary_walk for a wavefront on one column (pc: the column's uniform split
-// X, Y).  Every thread of the workgroup must call this or boundary_walk
-// together: both pass the same barriers.
-template <class Stager, class Loops>
+// boundary_walk for the wavefronts of a workgroup that lie on CPW columns (pc:
+// the split X, Y of the thread's column, the same in all its lanes).  Every
+// thread of the workgroup calls this or every thread calls boundary_walk.
+template <int CPW, class Stager, class Loops>
 __device__ __forceinline__ void column_walk(Lane<1>& s, const Stager& stage, int nb, const Loops& L, RPt* sv,
-                                            ColLds& cl, const QP& pc, int& pend) {
-  float* rho2 = cl.rho2[threadIdx.x >> 6];
-  float2* ng = cl.ng[threadIdx.x >> 6];
+                                            ColLds<CPW>& cl, const QP& pc, int& pend) {
+  constexpr int kWpc = (kThreads / 64) / CPW;   // wavefronts per column
+  const int slot = (threadIdx.x >> 6) / kWpc;
+  float* rho2 = cl.rho2[slot];
+  float2* ng = cl.ng[slot];
+  const int t0 = threadIdx.x % (64 * kWpc);
   VQ first[1];
   first[0].x = first[0].y = first[0].a = 0.0f;
   float aA = 0.0f;                 // alpha of the last vertex visited
@@ -148,10 +153,14 @@ __device__ __forceinline__ void column_walk(Lane<1>& s, const Stager& stage, int
     __syncthreads();
     stage(c0, c1 - c0, sv);
     __syncthreads();
-    column_chunk(sv, c1 - c0, c0 > 0, prev, pc, rho2, ng);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    column_chunk(sv, c1 - c0, c0 > 0, prev, pc, rho2, ng, t0, 64 * kWpc);
+    if constexpr (kWpc == 1) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+      __syncthreads();   // the column's wavefronts wrote its data together
+    }
     for (; l < L.n() && L.off(l) < c1; ++l) {
       const int ls = L.off(l), le = L.off(l + 1);
       int j = max(ls, c0);
@@ -196,11 +205,12 @@ __device__ __forceinline__ void column_walk(Lane<1>& s, const Stager& stage, int
 
 // 32-bit index arithmetic (the host limits grids to fewer than 2^32
 // points): 64-bit divisions would be long emulated sequences per query.
-// COLS: the column data for the shared walk is allocated (24 KB of LDS, four
-// waves per SIMD instead of eight); the host sets it when nz is a multiple
-// of 64, so that every wavefront lies on one column.
-template <bool COLS>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(COLS ? 4 : 8))) void k_grid3d_fwd(CrossArgs c, BndArgs a, LoopTable L,
+// CPW > 0: the workgroup's 256 points lie on CPW columns (the host sets 4, 2
+// or 1 when nz is a multiple of 64, 128 or 256), and their shared walk keeps
+// 6 KB of column data per column in LDS (4: four waves per SIMD, 2: five,
+// 1: seven).  CPW = 0: the per-lane walk at eight waves per SIMD.
+template <int CPW>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(CPW == 4 ? 4 : CPW == 2 ? 5 : CPW == 1 ? 7 : 8))) void k_grid3d_fwd(CrossArgs c, BndArgs a, LoopTable L,
                                                          const float* __restrict__ gx, const float* __restrict__ gy,
                                                          const float* __restrict__ gz, int64_t ny64, int64_t nz64,
                                                          int32_t* chi_out) {
@@ -270,10 +280,32 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(COLS ?
   const KernargLoops KL{L};
   // both walks stage their first chunk after a barrier, which every
   // wavefront reaches with its crossing list read
-  if constexpr (COLS) {
-    __shared__ ColLds cl;
-    if (line)
-      column_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, cl, pu, pend);
+  if constexpr (CPW > 0) {
+    __shared__ ColLds<CPW> cl;
+    // the thread's column: that of the first point of its slot (clamped to
+    // the grid, so that trailing lanes past the last point agree with it)
+    constexpr int kWpc = (kThreads / 64) / CPW;
+    const int64_t qs0 = (int64_t)blockIdx.x * kThreads + (int64_t)((threadIdx.x >> 6) / kWpc) * 64 * kWpc;
+    const uint32_t qs = (uint32_t)min(qs0, a.nq - 1), cs = qs / nz;
+    QP pc;
+    {
+      double X, Y, Z;
+      rotate(a.F, gx[cs / ny], gy[cs % ny], gz[qs % nz], X, Y, Z);
+      const QP t = make_qp(X, Y, Z);
+      pc.xh = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(t.xh)));
+      pc.xl = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(t.xl)));
+      pc.yh = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(t.yh)));
+      pc.yl = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(t.yl)));
+      pc.zh = pc.zl = 0.0f;
+    }
+    // the shared walk, or the per-lane walk for a column with a non-finite x
+    // or y: per wavefront when each has its own column (both walks pass the
+    // same barriers), else for the whole workgroup (the shared walk adds a
+    // barrier after the column data)
+    bool shared = isfinite(pc.xh) && isfinite(pc.yh);
+    if constexpr (kWpc > 1) shared = __syncthreads_and(shared);
+    if (shared)
+      column_walk<CPW>(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, cl, pc, pend);
     else
       boundary_walk(s, StageRotate<KernargLoops>{a.F, a.bnd, KL}, a.nb, KL, sv, staged, pend);
   } else {
@@ -295,12 +327,15 @@ hipError_t launch_grid3d_fwd(const CrossArgs& c, const BndArgs& a, const LoopTab
   const int64_t blocks = (a.nq + kThreads - 1) / kThreads;
   if (blocks == 0) return hipSuccess;
   if (a.nq > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
-  if (nz % 64 == 0)
-    hipLaunchKernelGGL(k_grid3d_fwd<true>, dim3((unsigned)blocks), dim3(kThreads), 0, s, c, a, L, gx, gy, gz, ny, nz,
-                       chi_out);
+  const dim3 g((unsigned)blocks), b(kThreads);
+  if (nz % 256 == 0)
+    hipLaunchKernelGGL(k_grid3d_fwd<1>, g, b, 0, s, c, a, L, gx, gy, gz, ny, nz, chi_out);
+  else if (nz % 128 == 0)
+    hipLaunchKernelGGL(k_grid3d_fwd<2>, g, b, 0, s, c, a, L, gx, gy, gz, ny, nz, chi_out);
+  else if (nz % 64 == 0)
+    hipLaunchKernelGGL(k_grid3d_fwd<4>, g, b, 0, s, c, a, L, gx, gy, gz, ny, nz, chi_out);
   else
-    hipLaunchKernelGGL(k_grid3d_fwd<false>, dim3((unsigned)blocks), dim3(kThreads), 0, s, c, a, L, gx, gy, gz, ny,
-                       nz, chi_out);
+    hipLaunchKernelGGL(k_grid3d_fwd<0>, g, b, 0, s, c, a, L, gx, gy, gz, ny, nz, chi_out);
   return hipGetLastError();
 }
 

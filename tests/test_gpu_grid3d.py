@@ -17,9 +17,10 @@ if torch.cuda.is_available():
 DZ = np.array([0.0, 0.0, 1.0])
 
 
-def _axes(M, n, scale=1.2, seed=0):
+def _axes(M, n, scale=1.2, seed=0, shift=0.0):
     lo, hi = M.V.min(0).astype(np.float64), M.V.max(0).astype(np.float64)
     c, h = (lo + hi) / 2, (hi - lo) / 2 * scale
+    c = c + shift * h   # off the mesh's centre lines (odd point counts)
     return [synth.grid_axis(c[k] - h[k], c[k] + h[k], n[k], np.float32) for k in range(3)]
 
 
@@ -45,15 +46,16 @@ def _stack_of_disks(n_layers, n_tri=48):
     return synth.Mesh(np.concatenate(Vs).astype(np.float32), np.concatenate(Fs).astype(np.int32))
 
 
-# nz = 16: wavefronts span several columns (the per-lane walk); nz = 128:
-# each wavefront lies on one column (the column's shared walk)
-@pytest.mark.parametrize("shape", [(24, 20, 16), (6, 5, 128)])
+# nz = 16: wavefronts span several columns (the per-lane walk); nz = 128 and
+# 256: two and four wavefronts share a column's walk (5 x 3 x 128: the last
+# workgroup holds half a column)
+@pytest.mark.parametrize("shape", [(24, 20, 16), (6, 5, 128), (5, 3, 128), (4, 3, 256)])
 @pytest.mark.parametrize("name", ["bumpy_cap", "coons", "sphere"])
 def test_grid_equals_per_query_path_and_oracle(name, shape):
     M = {"bumpy_cap": synth.bumpy_cap(), "coons": synth.coons_surface(3, 3000, 96),
          "sphere": synth.icosphere(3, radius=0.8)}[name]
     dm = DevMesh(M, DZ)
-    ax = _axes(M, shape)
+    ax = _axes(M, shape, shift=0.0123 if shape[0] % 2 else 0.0)
     w, chi = _grid(dm, ax)
     assert tuple(w.shape) == shape
     P = _points(ax)
@@ -95,9 +97,10 @@ def test_grid_edge_cases():
     g = [torch.from_numpy(a).cuda() for a in ax]
     w, chi = W.eval_3d_grid(dm.bvh, dm.bnd, dm.loop_off, g[0], e, g[2])
     assert tuple(w.shape) == (5, 0, 3)
-    # a non-finite axis value makes exactly its points invalid (nz = 64: a
-    # non-finite x or y takes the column off the shared walk)
-    for nzk in (3, 64):
+    # a non-finite axis value makes exactly its points invalid (nz = 64, 128: a
+    # non-finite x or y takes the wavefront, or the workgroup, off the shared
+    # walk)
+    for nzk in (3, 64, 128):
         ax2 = _axes(M, (5, 4, nzk))
         ax2[1][2] = np.nan
         ax2[2][0] = np.inf
@@ -108,7 +111,7 @@ def test_grid_edge_cases():
         bad[:, :, 0] = True
         assert np.all(np.isnan(w[bad])) and np.all(chi[bad] == W.WN_CHI_INVALID)
         assert np.all(np.isfinite(w[~bad]))
-        if nzk == 64:
+        if nzk >= 64:
             P = _points(ax2)
             ok = ~bad.ravel()
             wp, cp = dm.eval(P[ok])
